@@ -1,0 +1,51 @@
+"""Spill-policy simulator for run generation with early aggregation.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Run generation absorbs input into an ordered in-memory index of unique keys;
+a key already in the index is absorbed, a new key is inserted; when memory is
+full the whole index is written, in key order, as one run and emptied
+(read-sort-write cycles, the policy the paper's product implementation uses:
+Section 3 on run generation with an in-memory index, Section 6.1 on the
+product implementation).  The final index is not written out; it joins the
+final merge as one more input (the paper's analysis likewise ignores the
+in-memory run, Section 3, Example 2).
+
+Batch-granular reading of "memory is full": input is consumed in batches of
+``batch_rows`` consecutive rows.  A batch's distinct keys are absorbed into the
+index if the union fits ``capacity`` keys; otherwise the index is spilled as a
+run and the batch's distinct keys start the next index.  The simulator works on
+key sets only, so it yields the exact run count and spilled-row count for that
+policy, independently of how a batch is sorted.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def simulate(keys, batch_rows: int, capacity: int):
+    if batch_rows <= 0 or capacity <= 0 or batch_rows > capacity:
+        raise ValueError("need 0 < batch_rows <= capacity")
+    keys = np.asarray(keys, dtype=np.uint64)
+    index = np.empty(0, np.uint64)
+    run_sizes = []
+    for start in range(0, keys.shape[0], batch_rows):
+        batch = np.unique(keys[start:start + batch_rows])
+        merged = np.union1d(index, batch)
+        if merged.shape[0] <= capacity:
+            index = merged
+        else:
+            run_sizes.append(int(index.shape[0]))
+            index = batch
+    return {"runs": len(run_sizes), "spilled_rows": int(sum(run_sizes)),
+            "run_sizes": run_sizes, "final_index_rows": int(index.shape[0])}
+
+
+def model_spill_rows(I: float, M: float, O: float) -> float:
+    """Predicted total size of the initial runs with an in-memory index and
+    memory kept full (Section 3, Example 2): zero when the output fits memory,
+    otherwise M + (1 - M/O) * I.  An approximation (it assumes replacement
+    selection and uniformly distributed keys)."""
+    if O <= M:
+        return 0.0
+    return M + (1.0 - M / O) * I
