@@ -1,0 +1,213 @@
+/*
+ * insort.h -- C ABI of a GPU (AMD MI355X, gfx950) implementation of
+ * sort-based duplicate removal, grouping and aggregation for unsorted input
+ * with early aggregation during run generation and wide merging
+ * (Do, Graefe, Naughton, "Efficient sorting, duplicate removal, grouping,
+ * and aggregation").
+ *
+ * Problem statement (Section 1): "select A, count(*), sum(X), min(Z), max(Z)
+ * ... group by A" over an unsorted input, with duplicate removal as the case
+ * without aggregates; the output is sorted on the grouping key (Section 6.1:
+ * sorted output is a by-product of the ordered index).
+ *
+ * Conventions shared by every entry point:
+ *  - All column pointers are DEVICE pointers unless stated otherwise.  The
+ *    caller owns and allocates every buffer passed in; the library allocates
+ *    no device memory.  Host-side bookkeeping uses ordinary host memory.
+ *  - The memory budget of the operator (Section 3, Example 1: a per-operator
+ *    memory allotment) is the device workspace passed in; the library uses
+ *    no other device memory.  Caller-owned input, output and the pinned spill
+ *    buffer do not count toward it.
+ *  - Temporary storage for runs (Section 3, run generation; Section 4, wide
+ *    merging) is a caller-provided pinned host buffer.
+ *  - `stream` is a hipStream_t passed as void*.  Every call is synchronous
+ *    with respect to the host: it returns after its work on `stream` is done.
+ *  - Keys compare as unsigned 64-bit integers; output is ascending by key.
+ *    The int64 sum wraps modulo 2^64.  The float64 sum is accumulated in
+ *    float64 and is accurate to 1e-12 * (sum of |x|) per group.  Min and max
+ *    apply to the int64 value column.
+ *  - On error every output count is 0 unless stated otherwise; no exception
+ *    crosses the ABI.  A context is used by one host thread at a time;
+ *    separate contexts are independent.
+ */
+#ifndef INSORT_H
+#define INSORT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct isa_ctx isa_ctx;
+typedef struct isa_server isa_server;
+
+typedef enum {
+    ISA_OK = 0,
+    ISA_EINVAL = -1,   /* invalid argument (null column for a requested aggregate, ...) */
+    ISA_EBUDGET = -2,  /* workspace below isa_min_workspace_bytes */
+    ISA_ESPILL = -3,   /* pinned spill buffer too small, or too many runs to merge */
+    ISA_ETRUNC = -4,   /* output capacity below the group count; n_groups = required */
+    ISA_EDEVICE = -5,  /* HIP runtime error */
+    ISA_ENOMEM = -6,   /* host allocation failed, or server workspace cap exceeded */
+    ISA_EUNIMPL = -7,
+    ISA_EBUSY = -8     /* server: request not finished / no free slot */
+} isa_status;
+
+/* Aggregate selection bits.  aggs == 0 is duplicate removal (keys only). */
+enum {
+    ISA_COUNT = 1u,    /* count(*) per group                      -> output count   */
+    ISA_SUM_I64 = 2u,  /* sum of the int64 value, mod 2^64        -> output sum_i64 */
+    ISA_SUM_F64 = 4u,  /* sum of the float64 value                -> output sum_f64 */
+    ISA_MIN_I64 = 8u,  /* min of the int64 value                  -> output min_i64 */
+    ISA_MAX_I64 = 16u  /* max of the int64 value                  -> output max_i64 */
+};
+
+/* Input columns (device).  v_i64 is required when any of SUM_I64, MIN_I64,
+ * MAX_I64 is requested, v_f64 when SUM_F64 is; otherwise they may be NULL. */
+typedef struct {
+    const uint64_t* keys;
+    const int64_t* v_i64;
+    const double* v_f64;
+    uint64_t n_rows;
+} isa_input;
+
+/* Output columns (device), capacity rows each.  Columns of aggregates that
+ * were not requested may be NULL and are not written.  On return n_groups is
+ * the number of groups written (or required, with ISA_ETRUNC). */
+typedef struct {
+    uint64_t* keys;
+    uint64_t* count;
+    int64_t* sum_i64;
+    double* sum_f64;
+    int64_t* min_i64;
+    int64_t* max_i64;
+    uint64_t capacity;
+    uint64_t n_groups;
+} isa_output;
+
+/* Device workspace: the operator's memory budget, bytes == mem_budget.
+ * Must be 256-byte aligned. */
+typedef struct {
+    void* dev;
+    uint64_t bytes;
+} isa_workspace;
+
+/* Temporary storage for runs: pinned host memory (hipHostMalloc or a
+ * pin_memory tensor).  host_pinned may be NULL when bytes == 0; then any need
+ * to spill returns ISA_ESPILL.  Spilled rows never exceed the input rows, so
+ * n_rows * isa_state_row_bytes(aggs) bytes always suffice. */
+typedef struct {
+    void* host_pinned;
+    uint64_t bytes;
+} isa_spill;
+
+/* Statistics of one call (Section 6 reports spill volume and run counts). */
+typedef struct {
+    uint64_t runs;            /* sorted runs written to temporary storage         */
+    uint64_t spilled_rows;    /* rows written to temporary storage (= rows read back) */
+    uint64_t spilled_bytes;
+    uint64_t windows;         /* key windows of the wide merge (0 if no merge)    */
+    uint64_t batches;         /* input batches absorbed during run generation     */
+    uint64_t index_capacity;  /* rows the in-memory index may hold                */
+    uint64_t batch_rows;      /* input rows per batch                             */
+    uint64_t peak_ws_bytes;   /* workspace bytes actually used                    */
+    double t_rungen_ms;       /* wall time of run generation                      */
+    double t_merge_ms;        /* wall time of the wide merge and output           */
+} isa_stats;
+
+/* Create a context on HIP device `device`.  Returns ISA_EDEVICE if the device
+ * is not a usable gfx950 GPU.  *out is set to NULL on error. */
+isa_status isa_ctx_create(int device, isa_ctx** out);
+void isa_ctx_destroy(isa_ctx* ctx);
+
+/* Bytes of one intermediate (state) row for the given aggregates: key plus
+ * partial aggregates (Section 3.3: index and runs share one row format). */
+uint64_t isa_state_row_bytes(uint32_t aggs);
+
+/* Smallest workspace isa_group_by accepts for these aggregates. */
+uint64_t isa_min_workspace_bytes(uint32_t aggs);
+
+/*
+ * Group the input on its key and aggregate (Sections 3 and 4).
+ *
+ * Run generation consumes the input in batches; each batch is sorted and its
+ * duplicate keys collapsed, then absorbed into an ordered in-memory index of
+ * unique keys held in the workspace (Section 3.3; Section 6.1: sort the batch,
+ * look its distinct keys up in the ordered index).  When the index cannot
+ * absorb a batch within its capacity it is written whole, in key order, to the
+ * spill buffer as a run (read-sort-write) and a new index starts.  At the end
+ * all runs and the last index are combined in a single wide merge step that
+ * processes one key window at a time (Section 4) and produces the sorted
+ * output.  With no run written the index is the output.
+ *
+ * stats may be NULL.  Errors: ISA_EINVAL (null ctx/in/out, a missing column,
+ * unknown agg bits), ISA_EBUDGET, ISA_ESPILL, ISA_ETRUNC, ISA_EDEVICE.
+ */
+isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs,
+                        isa_workspace ws, isa_spill spill, isa_output* out,
+                        isa_stats* stats, void* stream);
+
+/*
+ * Group on the pair (a, b) of int32 columns for input sorted on a only
+ * (Section 1: with input sorted on a prefix of the grouping key, grouping
+ * proceeds one segment at a time).  Each a-segment is grouped on b
+ * independently; segments are processed together as one batch.  Output is
+ * ordered by (a, b), both signed, in out_a/out_b (device, capacity rows) and
+ * the aggregate columns of out (out->keys is unused and may be NULL).
+ * Requires a to be non-decreasing (ISA_EINVAL if a segment boundary check
+ * fails).  No spilling: every segment's output must fit the workspace
+ * (ISA_EBUDGET otherwise).
+ */
+isa_status isa_group_by_segmented(isa_ctx* ctx, const int32_t* a_sorted,
+                                  const int32_t* b, const int64_t* v,
+                                  uint64_t n_rows, uint32_t aggs, isa_workspace ws,
+                                  int32_t* out_a, int32_t* out_b, isa_output* out,
+                                  void* stream);
+
+/*
+ * Run n_inst independent group-by instances together: every phase of the
+ * device path is launched once for all instances (the launches can be replayed
+ * as one captured graph).  `inst` and `outs` are HOST arrays of n_inst entries
+ * whose column pointers are device pointers.  No spilling: all instances'
+ * intermediate data must fit the workspace together (ISA_EBUDGET otherwise;
+ * isa_batch_workspace_bytes gives the requirement).  On ISA_ETRUNC the
+ * failing instances have n_groups = required and the others are complete.
+ */
+isa_status isa_batch_run(isa_ctx* ctx, uint32_t n_inst, const isa_input* inst,
+                         uint32_t aggs, isa_workspace ws, isa_output* outs,
+                         void* stream);
+uint64_t isa_batch_workspace_bytes(uint32_t n_inst, const isa_input* inst, uint32_t aggs);
+
+/*
+ * Serving: a request loop that admits group-by requests against a device
+ * workspace cap and runs admitted requests together (continuous batching):
+ * requests that arrive while others run are admitted as soon as workspace and
+ * a slot free up, and their device work overlaps.  The server owns a worker
+ * thread; hbm_cap_bytes of workspace are carved from `workspace` (device,
+ * caller-owned, at least hbm_cap_bytes).  Input and output buffers of a
+ * request must stay valid until isa_server_poll reports it done.
+ */
+isa_status isa_server_create(isa_ctx* ctx, void* workspace, uint64_t hbm_cap_bytes,
+                             uint32_t slots, isa_server** out);
+/* Enqueue a request; *ticket identifies it.  ISA_ENOMEM if the request alone
+ * could never fit the cap. */
+isa_status isa_server_submit(isa_server* s, const isa_input* in, uint32_t aggs,
+                             isa_output* out, uint64_t* ticket);
+/* *done = 1 once the request finished; then *latency_ms is arrival-to-ready
+ * time, out->n_groups is set and the return value is the request's status. */
+isa_status isa_server_poll(isa_server* s, uint64_t ticket, int* done, double* latency_ms);
+/* Block until every submitted request finished. */
+isa_status isa_server_drain(isa_server* s);
+void isa_server_destroy(isa_server* s);
+
+const char* isa_status_str(isa_status st);
+
+/* Message describing the last error returned on this context ("" if none).
+ * The string is owned by the context and valid until its next call. */
+const char* isa_last_error(isa_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* INSORT_H */

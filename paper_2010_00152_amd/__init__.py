@@ -1,0 +1,206 @@
+"""Python binding of libinsort.so: sort-based duplicate removal, grouping and
+aggregation on AMD MI355X (gfx950).
+
+The C ABI (include/insort.h) is exposed under the same names (``isa_*``);
+this module only marshals arguments.  Every step of the grouping runs in the
+library's HIP kernels; PyTorch is used to allocate device and pinned memory
+and to name streams.  There is no fallback: if the library is missing or the
+device is not a gfx950 GPU, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libinsort.so")
+
+ISA_OK = 0
+ISA_EINVAL = -1
+ISA_EBUDGET = -2
+ISA_ESPILL = -3
+ISA_ETRUNC = -4
+ISA_EDEVICE = -5
+ISA_ENOMEM = -6
+ISA_EUNIMPL = -7
+ISA_EBUSY = -8
+
+ISA_COUNT = 1
+ISA_SUM_I64 = 2
+ISA_SUM_F64 = 4
+ISA_MIN_I64 = 8
+ISA_MAX_I64 = 16
+ISA_ALL = ISA_COUNT | ISA_SUM_I64 | ISA_SUM_F64 | ISA_MIN_I64 | ISA_MAX_I64
+ISA_INT_AGGS = ISA_COUNT | ISA_SUM_I64 | ISA_MIN_I64 | ISA_MAX_I64
+
+P = ctypes.c_void_p
+U64 = ctypes.c_uint64
+U32 = ctypes.c_uint32
+
+
+class isa_input(ctypes.Structure):
+    _fields_ = [("keys", P), ("v_i64", P), ("v_f64", P), ("n_rows", U64)]
+
+
+class isa_output(ctypes.Structure):
+    _fields_ = [("keys", P), ("count", P), ("sum_i64", P), ("sum_f64", P),
+                ("min_i64", P), ("max_i64", P), ("capacity", U64), ("n_groups", U64)]
+
+
+class isa_workspace(ctypes.Structure):
+    _fields_ = [("dev", P), ("bytes", U64)]
+
+
+class isa_spill(ctypes.Structure):
+    _fields_ = [("host_pinned", P), ("bytes", U64)]
+
+
+class isa_stats(ctypes.Structure):
+    _fields_ = [("runs", U64), ("spilled_rows", U64), ("spilled_bytes", U64), ("windows", U64),
+                ("batches", U64), ("index_capacity", U64), ("batch_rows", U64),
+                ("peak_ws_bytes", U64), ("t_rungen_ms", ctypes.c_double),
+                ("t_merge_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# Every function the header declares: name -> (restype, argtypes)
+SIGNATURES = {
+    "isa_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(P)]),
+    "isa_ctx_destroy": (None, [P]),
+    "isa_state_row_bytes": (U64, [U32]),
+    "isa_min_workspace_bytes": (U64, [U32]),
+    "isa_group_by": (ctypes.c_int, [P, ctypes.POINTER(isa_input), U32, isa_workspace, isa_spill,
+                                    ctypes.POINTER(isa_output), ctypes.POINTER(isa_stats), P]),
+    "isa_group_by_segmented": (ctypes.c_int, [P, P, P, P, U64, U32, isa_workspace, P, P,
+                                              ctypes.POINTER(isa_output), P]),
+    "isa_batch_run": (ctypes.c_int, [P, U32, ctypes.POINTER(isa_input), U32, isa_workspace,
+                                     ctypes.POINTER(isa_output), P]),
+    "isa_batch_workspace_bytes": (U64, [U32, ctypes.POINTER(isa_input), U32]),
+    "isa_server_create": (ctypes.c_int, [P, P, U64, U32, ctypes.POINTER(P)]),
+    "isa_server_submit": (ctypes.c_int, [P, ctypes.POINTER(isa_input), U32,
+                                         ctypes.POINTER(isa_output), ctypes.POINTER(U64)]),
+    "isa_server_poll": (ctypes.c_int, [P, U64, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_double)]),
+    "isa_server_drain": (ctypes.c_int, [P]),
+    "isa_server_destroy": (None, [P]),
+    "isa_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "isa_last_error": (ctypes.c_char_p, [P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libinsort.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libinsort.so is not built; run paper_2010_00152_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class InsortError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__("%s (%d)%s" % (lib().isa_status_str(status).decode(), status,
+                                        (": " + msg) if msg else ""))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A library context bound to one GPU."""
+
+    def __init__(self, device: int = 0):
+        h = P()
+        st = lib().isa_ctx_create(device, ctypes.byref(h))
+        if st != ISA_OK:
+            raise InsortError(st, "isa_ctx_create(%d)" % device)
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().isa_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return lib().isa_last_error(self.handle).decode()
+
+
+def _alloc_outputs(torch, cap, aggs, dev, with_keys=True):
+    o = {}
+    if with_keys:
+        o["keys"] = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)  # uint64 bits
+    if aggs & ISA_COUNT:
+        o["count"] = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)  # uint64 bits
+    if aggs & ISA_SUM_I64:
+        o["sum_i64"] = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+    if aggs & ISA_SUM_F64:
+        o["sum_f64"] = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+    if aggs & ISA_MIN_I64:
+        o["min_i64"] = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+    if aggs & ISA_MAX_I64:
+        o["max_i64"] = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+    return o
+
+
+def _output_struct(o, cap):
+    return isa_output(_ptr(o.get("keys")), _ptr(o.get("count")), _ptr(o.get("sum_i64")),
+                      _ptr(o.get("sum_f64")), _ptr(o.get("min_i64")), _ptr(o.get("max_i64")),
+                      cap, 0)
+
+
+def group_by(ctx: Context, keys, v_i64=None, v_f64=None, aggs: int = ISA_ALL,
+             mem_budget: int = 256 << 20, capacity: int | None = None, spill_bytes: int | None = None,
+             workspace=None, spill=None, stream=None, check: bool = True):
+    """group_by(keys, values, aggs, mem_budget) -> sorted (key, count, sum, min, max).
+
+    keys: CUDA tensor of uint64 key bits (int64 or uint64 dtype); v_i64: int64;
+    v_f64: float64 (same length).  Output keys and counts are int64 tensors
+    holding uint64 bits.
+    Returns (dict of output tensors trimmed to n_groups, stats dict, status)."""
+    import torch
+    dev = keys.device
+    n = keys.numel()
+    cap = n if capacity is None else capacity
+    if workspace is None:
+        workspace = torch.empty(mem_budget, dtype=torch.uint8, device=dev)
+    if spill is None:
+        sb = spill_bytes if spill_bytes is not None else n * lib().isa_state_row_bytes(aggs)
+        spill = torch.empty(max(sb, 1), dtype=torch.uint8, pin_memory=True) if sb else None
+    o = _alloc_outputs(torch, cap, aggs, dev)
+    out = _output_struct(o, cap)
+    inp = isa_input(_ptr(keys), _ptr(v_i64), _ptr(v_f64), n)
+    ws = isa_workspace(_ptr(workspace), workspace.numel())
+    sp = isa_spill(_ptr(spill), spill.numel() if spill is not None else 0)
+    st = isa_stats()
+    status = lib().isa_group_by(ctx.handle, ctypes.byref(inp), aggs, ws, sp, ctypes.byref(out),
+                                ctypes.byref(st), _stream_ptr(stream))
+    if check and status not in (ISA_OK,):
+        raise InsortError(status, ctx.last_error())
+    g = out.n_groups
+    res = {k: v[:min(g, cap)] for k, v in o.items()}
+    return res, st.as_dict(), status, g

@@ -1,0 +1,506 @@
+// C ABI of the grouping library (include/insort.h): argument checking, the
+// run-generation loop with spilling, and the wide merge.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/insort.h"
+#include "isa_engine.h"
+
+using namespace isa;
+
+struct isa_ctx {
+    int device = 0;
+    Engine eng;
+    std::string last_error;
+    std::mutex mu;
+};
+
+namespace {
+
+void ck(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw Fail{ISA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool valid_aggs(uint32_t aggs) {
+    return (aggs & ~(uint32_t)(ISA_COUNT | ISA_SUM_I64 | ISA_SUM_F64 | ISA_MIN_I64 | ISA_MAX_I64)) == 0;
+}
+
+Cols cols_of(uint32_t aggs) {
+    Cols k;
+    k.c = (aggs & ISA_COUNT) != 0;
+    k.v = (aggs & (ISA_SUM_I64 | ISA_MIN_I64 | ISA_MAX_I64)) != 0;
+    k.f = (aggs & ISA_SUM_F64) != 0;
+    return k;
+}
+
+// Raw input rows viewed column-wise.
+ColView input_view(const isa_input& in, const Cols& k) {
+    ColView v;
+    v.key = in.keys;
+    v.cnt = nullptr;
+    v.sum = v.mn = v.mx = k.v ? in.v_i64 : nullptr;
+    v.fs = k.f ? in.v_f64 : nullptr;
+    v.stride = 1;
+    return v;
+}
+
+// Caller's output columns; unrequested columns are not written.
+OutView output_view(const isa_output& o, uint32_t aggs, uint64_t shift) {
+    OutView v;
+    v.key = o.keys ? o.keys + shift : nullptr;
+    v.cnt = (aggs & ISA_COUNT) && o.count ? o.count + shift : nullptr;
+    v.sum = (aggs & ISA_SUM_I64) && o.sum_i64 ? o.sum_i64 + shift : nullptr;
+    v.mn = (aggs & ISA_MIN_I64) && o.min_i64 ? o.min_i64 + shift : nullptr;
+    v.mx = (aggs & ISA_MAX_I64) && o.max_i64 ? o.max_i64 + shift : nullptr;
+    v.fs = (aggs & ISA_SUM_F64) && o.sum_f64 ? o.sum_f64 + shift : nullptr;
+    v.stride = 1;
+    return v;
+}
+
+isa_status check_output(const isa_output* out, uint32_t aggs, bool need_keys) {
+    if (!out) return ISA_EINVAL;
+    if (need_keys && !out->keys) return ISA_EINVAL;
+    if ((aggs & ISA_COUNT) && !out->count) return ISA_EINVAL;
+    if ((aggs & ISA_SUM_I64) && !out->sum_i64) return ISA_EINVAL;
+    if ((aggs & ISA_SUM_F64) && !out->sum_f64) return ISA_EINVAL;
+    if ((aggs & ISA_MIN_I64) && !out->min_i64) return ISA_EINVAL;
+    if ((aggs & ISA_MAX_I64) && !out->max_i64) return ISA_EINVAL;
+    return ISA_OK;
+}
+
+isa_status check_input(const isa_input* in, uint32_t aggs) {
+    if (!in) return ISA_EINVAL;
+    if (in->n_rows == 0) return ISA_OK;
+    if (!in->keys) return ISA_EINVAL;
+    if ((aggs & (ISA_SUM_I64 | ISA_MIN_I64 | ISA_MAX_I64)) && !in->v_i64) return ISA_EINVAL;
+    if ((aggs & ISA_SUM_F64) && !in->v_f64) return ISA_EINVAL;
+    return ISA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batch / capacity planning for run generation.
+// ---------------------------------------------------------------------------
+
+struct Plan {
+    uint64_t batch_rows;  // Bt
+    uint64_t capacity;    // K: rows the in-memory index may hold
+};
+
+constexpr uint64_t MIN_BATCH = 4 * (uint64_t)LEAF_CAP;
+constexpr uint64_t MERGE_MARGIN = 2u << 20;
+
+uint64_t merge_scratch_bytes(uint64_t rows) {
+    const uint64_t parts = rows / MERGE_D + 2;
+    return parts * 4 + (parts + 1) * 8 + (scan_tiles(parts) + 1) * 8 + 4096;
+}
+
+// Workspace used by run generation with batch Bt and index capacity K: two
+// index buffers (the merge reads one and writes the other), one batch run, the
+// merge's scratch and the sort-reduce area of one batch.
+uint64_t rungen_bytes(uint64_t Bt, uint64_t K, const Cols& k) {
+    const uint64_t sw = (uint64_t)state_layout(k).words * 8;
+    return 2 * (K + Bt) * sw + Bt * sw + merge_scratch_bytes(K + 2 * Bt) + sort_reduce_bytes(Bt, 1, k, false) +
+           MERGE_MARGIN + 6 * 256;
+}
+
+bool plan_batches(uint64_t ws, uint64_t n, const Cols& k, Plan& p) {
+    const uint64_t sw = (uint64_t)state_layout(k).words * 8;
+    // batch area about 1/8 of the budget, the rest for the index
+    uint64_t Bt = ws / 8 / (sort_reduce_bytes(1, 0, k, false) - (4u << 20) + sw);
+    Bt = std::min<uint64_t>(Bt, n);
+    if (Bt < MIN_BATCH) Bt = MIN_BATCH;
+    for (;;) {
+        const uint64_t fixed = rungen_bytes(Bt, 0, k);
+        if (fixed < ws) {
+            // K from the remaining bytes: 2*K*sw plus merge scratch growth
+            uint64_t K = (ws - fixed) / (2 * sw + 1);
+            while (K > 0 && rungen_bytes(Bt, K, k) > ws) K -= std::max<uint64_t>(1, K / 64);
+            if (K >= Bt) {
+                p.batch_rows = Bt;
+                p.capacity = K;
+                return true;
+            }
+        }
+        if (Bt <= MIN_BATCH) return false;
+        Bt = std::max<uint64_t>(MIN_BATCH, Bt / 2);
+    }
+}
+
+struct RunInfo {
+    uint64_t row_off;  // first row in the spill buffer
+    uint64_t n;
+};
+
+// First row of [pos, n) whose key is >= x in a strided host array.
+uint64_t lower_bound_strided(const uint64_t* keys, uint64_t stride, uint64_t pos, uint64_t n, uint64_t x) {
+    uint64_t lo = pos, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (keys[mid * stride] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// The wide merge (Section 4): every run and the in-memory index are consumed
+// in one merge step, one key window at a time.  A window [start, end) is
+// chosen so that the rows of all inputs inside it fit the staging area; the
+// runs' "pages" are fence keys taken every P rows, and the next window ends at
+// the largest fence whose window still fits (the forecasting order of page
+// reads by the highest key read, Section 4 Figure 9).  Keys below the window
+// end are final once the window is reduced; they are appended to the output.
+void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::vector<RunInfo>& runs,
+                const uint64_t* host_rows, uint64_t* idx, uint64_t n_idx, isa_output* out, isa_stats* st,
+                uint64_t& n_groups) {
+    const Layout S = state_layout(k);
+    const uint64_t sw = (uint64_t)S.words;
+    const size_t R = runs.size();
+    // index keys on the host (one strided D2H copy)
+    std::vector<uint64_t> idx_keys(n_idx);
+    if (n_idx) {
+        void* p = E.pinned_buf(n_idx * 8);
+        ck(hipMemcpy2DAsync(p, 8, idx, sw * 8, 8, n_idx, hipMemcpyDeviceToHost, E.stream), "hipMemcpy2DAsync");
+        E.sync();
+        std::memcpy(idx_keys.data(), p, n_idx * 8);
+    }
+    // sources 0..R-1 are runs (host), source R is the index (device)
+    std::vector<const uint64_t*> skeys(R + 1);
+    std::vector<uint64_t> sstride(R + 1), sn(R + 1), pos(R + 1, 0);
+    for (size_t r = 0; r < R; ++r) {
+        skeys[r] = host_rows + runs[r].row_off * sw;
+        sstride[r] = sw;
+        sn[r] = runs[r].n;
+    }
+    skeys[R] = idx_keys.data();
+    sstride[R] = 1;
+    sn[R] = n_idx;
+
+    // window capacity: staging + sort-reduce of the staged state rows
+    const uint64_t per_row = sw * 8 + (sort_reduce_bytes(1, 0, k, true) - (4u << 20));
+    const uint64_t avail = A.left() > (6u << 20) ? A.left() - (6u << 20) : 0;
+    const uint64_t W = avail / per_row;
+    if (W < 2 * (R + 1)) throw Fail{ISA_ESPILL, "workspace too small for a single wide merge of all runs"};
+    const uint64_t P = std::max<uint64_t>(1, W / (4 * (R + 1)));
+    std::vector<uint64_t> fences;
+    for (size_t s = 0; s <= R; ++s)
+        for (uint64_t i = P; i < sn[s]; i += P) fences.push_back(skeys[s][i * sstride[s]]);
+    std::sort(fences.begin(), fences.end());
+    fences.erase(std::unique(fences.begin(), fences.end()), fences.end());
+
+    auto rows_below = [&](uint64_t x) {
+        uint64_t c = 0;
+        for (size_t s = 0; s <= R; ++s) c += lower_bound_strided(skeys[s], sstride[s], pos[s], sn[s], x) - pos[s];
+        return c;
+    };
+    uint64_t cursor = 0;
+    const uint64_t mark = A.off;
+    for (;;) {
+        uint64_t remaining = 0, min_key = ~0ull;
+        for (size_t s = 0; s <= R; ++s) {
+            remaining += sn[s] - pos[s];
+            if (pos[s] < sn[s]) min_key = std::min(min_key, skeys[s][pos[s] * sstride[s]]);
+        }
+        if (!remaining) break;
+        std::vector<uint64_t> end(R + 1);
+        if (remaining <= W) {
+            for (size_t s = 0; s <= R; ++s) end[s] = sn[s];
+        } else {
+            // largest fence f > min_key with rows_below(f) <= W
+            size_t lo = std::upper_bound(fences.begin(), fences.end(), min_key) - fences.begin();
+            size_t hi = fences.size();
+            size_t best = fences.size();
+            while (lo < hi) {
+                const size_t mid = (lo + hi) / 2;
+                if (rows_below(fences[mid]) <= W) {
+                    best = mid;
+                    lo = mid + 1;
+                } else {
+                    hi = mid;
+                }
+            }
+            const uint64_t x = best < fences.size() ? fences[best] : min_key + 1;
+            for (size_t s = 0; s <= R; ++s) end[s] = lower_bound_strided(skeys[s], sstride[s], pos[s], sn[s], x);
+        }
+        uint64_t wrows = 0;
+        for (size_t s = 0; s <= R; ++s) wrows += end[s] - pos[s];
+        A.off = mark;
+        uint64_t* stage = A.take_n<uint64_t>(wrows * sw);
+        uint64_t at = 0;
+        for (size_t s = 0; s <= R; ++s) {
+            const uint64_t len = end[s] - pos[s];
+            if (!len) continue;
+            if (s < R) {
+                ck(hipMemcpyAsync(stage + at * sw, host_rows + (runs[s].row_off + pos[s]) * sw, len * sw * 8,
+                                  hipMemcpyHostToDevice, E.stream),
+                   "hipMemcpyAsync(run slice)");
+            } else {
+                ck(hipMemcpyAsync(stage + at * sw, idx + pos[s] * sw, len * sw * 8, hipMemcpyDeviceToDevice,
+                                  E.stream),
+                   "hipMemcpyAsync(index slice)");
+            }
+            at += len;
+            pos[s] = end[s];
+        }
+        const uint64_t cap = out->capacity > cursor ? out->capacity - cursor : 0;
+        Dest d;
+        d.out = output_view(*out, aggs, std::min(cursor, out->capacity));
+        d.capacity = cap;
+        std::vector<Instance> inst(1);
+        inst[0].src = aos_view(stage, S);
+        inst[0].n = wrows;
+        inst[0].dest = 0;
+        const std::vector<uint64_t> g = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, true);
+        cursor += g[0];
+        if (st) st->windows++;
+    }
+    A.off = mark;
+    n_groups = cursor;
+}
+
+isa_status fail(isa_ctx* ctx, const Fail& f) {
+    if (ctx) ctx->last_error = f.what;
+    return (isa_status)f.status;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* isa_status_str(isa_status st) {
+    switch (st) {
+        case ISA_OK: return "ok";
+        case ISA_EINVAL: return "invalid argument";
+        case ISA_EBUDGET: return "workspace below the minimum";
+        case ISA_ESPILL: return "spill buffer too small or too many runs";
+        case ISA_ETRUNC: return "output capacity below the group count";
+        case ISA_EDEVICE: return "HIP device error";
+        case ISA_ENOMEM: return "out of memory";
+        case ISA_EUNIMPL: return "not implemented";
+        case ISA_EBUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+const char* isa_last_error(isa_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+isa_status isa_ctx_create(int device, isa_ctx** out) {
+    if (!out) return ISA_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return ISA_EDEVICE;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return ISA_EDEVICE;
+    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) return ISA_EDEVICE;
+    isa_ctx* c = new (std::nothrow) isa_ctx();
+    if (!c) return ISA_ENOMEM;
+    c->device = device;
+    c->eng.device = device;
+    *out = c;
+    return ISA_OK;
+}
+
+void isa_ctx_destroy(isa_ctx* ctx) {
+    if (!ctx) return;
+    ctx->eng.release();
+    delete ctx;
+}
+
+uint64_t isa_state_row_bytes(uint32_t aggs) { return (uint64_t)state_layout(cols_of(aggs)).words * 8; }
+
+uint64_t isa_min_workspace_bytes(uint32_t aggs) {
+    const Cols k = cols_of(aggs);
+    return rungen_bytes(MIN_BATCH, MIN_BATCH, k);
+}
+
+isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_workspace ws, isa_spill spill,
+                        isa_output* out, isa_stats* stats, void* stream) {
+    if (out) out->n_groups = 0;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (!ctx || !valid_aggs(aggs)) return ISA_EINVAL;
+    isa_status s = check_input(in, aggs);
+    if (s != ISA_OK) return s;
+    s = check_output(out, aggs, true);
+    if (s != ISA_OK) return s;
+    if (in->n_rows == 0) return ISA_OK;
+    if (!ws.dev || ((uintptr_t)ws.dev & 255)) return ISA_EINVAL;
+    const Cols k = cols_of(aggs);
+    if (ws.bytes < isa_min_workspace_bytes(aggs)) return ISA_EBUDGET;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    try {
+        ck(hipSetDevice(ctx->device), "hipSetDevice");
+        Engine& E = ctx->eng;
+        E.stream = (hipStream_t)stream;
+        Arena A;
+        A.base = (char*)ws.dev;
+        A.cap = ws.bytes;
+        const double t0 = now_ms();
+        const uint64_t n = in->n_rows;
+        const Layout S = state_layout(k);
+        const uint64_t sw = (uint64_t)S.words;
+        const ColView src = input_view(*in, k);
+        uint64_t n_groups = 0;
+
+        if (sort_reduce_bytes(n, 1, k, false) <= ws.bytes) {
+            // The output fits memory and the whole input is one batch: the
+            // index never fills, no run is written (Section 5: no spilling
+            // when the output fits memory).
+            Dest d;
+            d.out = output_view(*out, aggs, 0);
+            d.capacity = out->capacity;
+            std::vector<Instance> inst(1);
+            inst[0].src = src;
+            inst[0].n = n;
+            inst[0].dest = 0;
+            n_groups = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false)[0];
+            if (stats) {
+                stats->batches = 1;
+                stats->batch_rows = n;
+                stats->index_capacity = n;
+                stats->peak_ws_bytes = A.peak;
+                stats->t_rungen_ms = now_ms() - t0;
+            }
+        } else {
+            Plan p;
+            if (!plan_batches(ws.bytes, n, k, p)) return ISA_EBUDGET;
+            uint64_t* idx[2];
+            idx[0] = A.take_n<uint64_t>((p.capacity + p.batch_rows) * sw);
+            idx[1] = A.take_n<uint64_t>((p.capacity + p.batch_rows) * sw);
+            uint64_t* brun = A.take_n<uint64_t>(p.batch_rows * sw);
+            const uint64_t mscr_parts = merge_parts(p.capacity + p.batch_rows, p.batch_rows) + 1;
+            uint32_t* m_counts = A.take_n<uint32_t>(mscr_parts);
+            uint64_t* m_offs = A.take_n<uint64_t>(mscr_parts + 1);
+            uint64_t* m_tiles = A.take_n<uint64_t>(scan_tiles(mscr_parts) + 1);
+            const uint64_t mark = A.off;
+            int cur = 0;
+            uint64_t n_idx = 0;
+            std::vector<RunInfo> runs;
+            uint64_t spill_rows_cap = spill.host_pinned ? spill.bytes / (sw * 8) : 0;
+            uint64_t spill_used = 0;
+            uint64_t batches = 0, spilled = 0;
+            for (uint64_t b0 = 0; b0 < n; b0 += p.batch_rows) {
+                const uint64_t bn = std::min(p.batch_rows, n - b0);
+                ColView bsrc = src;
+                bsrc.key += b0;
+                if (bsrc.sum) bsrc.sum += b0, bsrc.mn += b0, bsrc.mx += b0;
+                if (bsrc.fs) bsrc.fs += b0;
+                std::vector<Instance> inst(1);
+                inst[0].src = bsrc;
+                inst[0].n = bn;
+                inst[0].dest = 0;
+                A.off = mark;
+                Dest d;
+                d.capacity = p.batch_rows;
+                if (n_idx == 0) {
+                    // an empty index simply becomes the batch's sorted run
+                    d.out = aos_out(idx[cur], S);
+                    n_idx = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false)[0];
+                    ++batches;
+                    continue;
+                }
+                d.out = aos_out(brun, S);
+                const uint64_t g = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false)[0];
+                ++batches;
+                // absorb the batch's distinct keys into the index if they fit
+                const ColView iv = aos_view(idx[cur], S), bv = aos_view(brun, S);
+                const uint64_t parts = merge_parts(n_idx, g);
+                launch_merge_count(iv, n_idx, bv, g, m_counts, E.stream);
+                launch_scan(m_counts, parts, m_tiles, m_offs, E.stream);
+                const uint64_t* h_m = (const uint64_t*)download_async(E, m_offs + parts, 8);
+                E.sync();
+                const uint64_t m = *h_m;
+                if (m <= p.capacity) {
+                    launch_merge_write(iv, n_idx, bv, g, m_offs, aos_out(idx[cur ^ 1], S), E.stream);
+                    cur ^= 1;
+                    n_idx = m;
+                } else {
+                    // memory is full: write the index as one sorted run
+                    // (read-sort-write) and start a new index with the batch
+                    if (spill_used + n_idx > spill_rows_cap)
+                        throw Fail{ISA_ESPILL, "spill buffer too small"};
+                    ck(hipMemcpyAsync((char*)spill.host_pinned + spill_used * sw * 8, idx[cur], n_idx * sw * 8,
+                                      hipMemcpyDeviceToHost, E.stream),
+                       "hipMemcpyAsync(spill)");
+                    RunInfo ri;
+                    ri.row_off = spill_used;
+                    ri.n = n_idx;
+                    runs.push_back(ri);
+                    spill_used += n_idx;
+                    spilled += n_idx;
+                    ck(hipMemcpyAsync(idx[cur], brun, g * sw * 8, hipMemcpyDeviceToDevice, E.stream),
+                       "hipMemcpyAsync(batch run)");
+                    n_idx = g;
+                }
+            }
+            E.sync();
+            const double t1 = now_ms();
+            if (stats) {
+                stats->batches = batches;
+                stats->batch_rows = p.batch_rows;
+                stats->index_capacity = p.capacity;
+                stats->runs = runs.size();
+                stats->spilled_rows = spilled;
+                stats->spilled_bytes = spilled * sw * 8;
+                stats->t_rungen_ms = t1 - t0;
+            }
+            if (runs.empty()) {
+                launch_copy_rows(aos_view(idx[cur], S), n_idx, output_view(*out, aggs, 0), out->capacity, E.stream);
+                E.sync();
+                n_groups = n_idx;
+            } else {
+                // keep only the live index; everything after it is merge space
+                if (cur == 1) {
+                    ck(hipMemcpyAsync(idx[0], idx[1], n_idx * sw * 8, hipMemcpyDeviceToDevice, E.stream),
+                       "hipMemcpyAsync(index)");
+                }
+                A.off = (uint64_t)((char*)idx[0] - A.base) + n_idx * sw * 8;
+                wide_merge(E, A, k, aggs, runs, (const uint64_t*)spill.host_pinned, idx[0], n_idx, out, stats,
+                           n_groups);
+            }
+            if (stats) {
+                stats->peak_ws_bytes = A.peak;
+                stats->t_merge_ms = now_ms() - t1;
+            }
+        }
+        out->n_groups = n_groups;
+        return n_groups > out->capacity ? ISA_ETRUNC : ISA_OK;
+    } catch (const Fail& f) {
+        out->n_groups = 0;
+        return fail(ctx, f);
+    } catch (const std::bad_alloc&) {
+        out->n_groups = 0;
+        return ISA_ENOMEM;
+    }
+}
+
+}  // extern "C"
+
+extern "C" {
+
+isa_status isa_group_by_segmented(isa_ctx*, const int32_t*, const int32_t*, const int64_t*, uint64_t, uint32_t,
+                                  isa_workspace, int32_t*, int32_t*, isa_output*, void*) {
+    return ISA_EUNIMPL;
+}
+isa_status isa_batch_run(isa_ctx*, uint32_t, const isa_input*, uint32_t, isa_workspace, isa_output*, void*) {
+    return ISA_EUNIMPL;
+}
+uint64_t isa_batch_workspace_bytes(uint32_t, const isa_input*, uint32_t) { return 0; }
+isa_status isa_server_create(isa_ctx*, void*, uint64_t, uint32_t, isa_server** out) {
+    if (out) *out = nullptr;
+    return ISA_EUNIMPL;
+}
+isa_status isa_server_submit(isa_server*, const isa_input*, uint32_t, isa_output*, uint64_t*) { return ISA_EUNIMPL; }
+isa_status isa_server_poll(isa_server*, uint64_t, int*, double*) { return ISA_EUNIMPL; }
+isa_status isa_server_drain(isa_server*) { return ISA_EUNIMPL; }
+void isa_server_destroy(isa_server*) {}
+
+}  // extern "C"

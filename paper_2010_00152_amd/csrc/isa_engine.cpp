@@ -1,0 +1,370 @@
+// Host engine: workspace carving and the multi-level partition driver that
+// sorts and reduces many independent instances at once.
+//
+// A "sort-reduce" call takes unsorted rows (raw input rows or state rows) of
+// one or more instances and produces, per instance, its sorted unique state
+// rows.  Each instance is split into key ranges by sampled splitters (one
+// level of an ordered index per pass, Section 3.3), ranges too large for one
+// workgroup are split again, and every final range is sorted and reduced in
+// LDS (Section 6.1: the batch is sorted within the cache and duplicates
+// collapse; Section 2.1: in-stream grouping of sorted rows).
+#include "isa_engine.h"
+
+#include <algorithm>
+#include <cstring>
+
+#include "../../include/insort.h"
+
+namespace isa {
+
+static void ck(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw Fail{ISA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+Layout raw_layout(const Cols& k) {
+    Layout L;
+    L.words = 1;
+    L.cnt = L.sum = L.mn = L.mx = L.fs = -1;
+    if (k.v) L.sum = L.mn = L.mx = L.words++;
+    if (k.f) L.fs = L.words++;
+    return L;
+}
+
+Layout state_layout(const Cols& k) {
+    Layout L;
+    L.words = 1;
+    L.cnt = L.sum = L.mn = L.mx = L.fs = -1;
+    if (k.c) L.cnt = L.words++;
+    if (k.v) {
+        L.sum = L.words++;
+        L.mn = L.words++;
+        L.mx = L.words++;
+    }
+    if (k.f) L.fs = L.words++;
+    return L;
+}
+
+ColView aos_view(const uint64_t* base, const Layout& L) {
+    ColView v;
+    v.key = base;
+    v.cnt = L.cnt >= 0 ? base + L.cnt : nullptr;
+    v.sum = L.sum >= 0 ? (const int64_t*)(base + L.sum) : nullptr;
+    v.mn = L.mn >= 0 ? (const int64_t*)(base + L.mn) : nullptr;
+    v.mx = L.mx >= 0 ? (const int64_t*)(base + L.mx) : nullptr;
+    v.fs = L.fs >= 0 ? (const double*)(base + L.fs) : nullptr;
+    v.stride = (uint64_t)L.words;
+    return v;
+}
+
+OutView aos_out(uint64_t* base, const Layout& L) {
+    OutView v;
+    v.key = base;
+    v.cnt = L.cnt >= 0 ? base + L.cnt : nullptr;
+    v.sum = L.sum >= 0 ? (int64_t*)(base + L.sum) : nullptr;
+    v.mn = L.mn >= 0 ? (int64_t*)(base + L.mn) : nullptr;
+    v.mx = L.mx >= 0 ? (int64_t*)(base + L.mx) : nullptr;
+    v.fs = L.fs >= 0 ? (double*)(base + L.fs) : nullptr;
+    v.stride = (uint64_t)L.words;
+    return v;
+}
+
+void* Arena::take(uint64_t bytes) {
+    uint64_t o = (off + 255) & ~(uint64_t)255;
+    if (o + bytes > cap)
+        throw Fail{ISA_EBUDGET, "workspace exhausted: need " + std::to_string(o + bytes) + " of " +
+                                    std::to_string(cap) + " bytes"};
+    off = o + bytes;
+    if (off > peak) peak = off;
+    return base + o;
+}
+
+// ---------------------------------------------------------------------------
+// Engine: pinned staging with a bump pointer that resets at every sync.
+// ---------------------------------------------------------------------------
+
+void* Engine::pinned_buf(uint64_t bytes) {
+    uint64_t need = ((pinned_used + 255) & ~(uint64_t)255) + bytes;
+    if (need > pinned_cap) {
+        // Older buffers may still be the target of copies in flight or hold
+        // readbacks not yet consumed: retire them, free them at destruction.
+        uint64_t cap = pinned_cap ? 2 * pinned_cap : (8u << 20);
+        while (cap < bytes + 256) cap *= 2;
+        if (pinned) retired.push_back(pinned);
+        pinned = nullptr;
+        ck(hipHostMalloc((void**)&pinned, cap, 0), "hipHostMalloc(staging)");
+        pinned_cap = cap;
+        pinned_used = 0;
+    }
+    uint64_t o = (pinned_used + 255) & ~(uint64_t)255;
+    pinned_used = o + bytes;
+    return pinned + o;
+}
+
+void Engine::release() {
+    for (char* p : retired) hipHostFree(p);
+    retired.clear();
+    if (pinned) hipHostFree(pinned);
+    pinned = nullptr;
+    pinned_cap = pinned_used = 0;
+}
+
+void Engine::upload(void* dev, const void* host, uint64_t bytes) {
+    if (!bytes) return;
+    void* p = pinned_buf(bytes);
+    std::memcpy(p, host, bytes);
+    ck(hipMemcpyAsync(dev, p, bytes, hipMemcpyHostToDevice, stream), "hipMemcpyAsync(H2D)");
+}
+
+void Engine::sync() {
+    ck(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    pinned_used = 0;
+}
+
+// Device-to-host copy into pinned staging; the data is valid after sync() and
+// until the next upload/download.
+const void* download_async(Engine& E, const void* dev, uint64_t bytes) {
+    if (!bytes) return nullptr;
+    void* p = E.pinned_buf(bytes);
+    ck(hipMemcpyAsync(p, dev, bytes, hipMemcpyDeviceToHost, E.stream), "hipMemcpyAsync(D2H)");
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// sort_reduce
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Node {
+    int kind;  // 0 sort leaf, 1 single-key leaf, 2 pending region, 3 expanded region
+    ColView src;
+    uint64_t n, pos, lo, hi;
+    uint32_t inst;
+    std::vector<int> kids;
+};
+
+uint32_t buckets_for(uint64_t n) {
+    uint64_t nb = (2 * n + LEAF_CAP - 1) / LEAF_CAP;
+    if (nb < 2) nb = 2;
+    if (nb > MAX_BUCKETS) nb = MAX_BUCKETS;
+    return (uint32_t)nb;
+}
+
+}  // namespace
+
+uint64_t sort_reduce_bytes(uint64_t rows, uint64_t n_inst, const Cols& k, bool state_rows) {
+    const Layout L = state_rows ? state_layout(k) : raw_layout(k);
+    const Layout S = state_layout(k);
+    return rows * (uint64_t)(2 * L.words + S.words) * 8 + rows * 4 + n_inst * 4608 + (4u << 20);
+}
+
+std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instance>& inst,
+                                  const std::vector<Dest>& dests, const Cols& k, bool state_rows) {
+    const Layout L = state_rows ? state_layout(k) : raw_layout(k);
+    const Layout S = state_layout(k);
+    std::vector<uint64_t> totals(dests.size(), 0);
+    std::vector<Node> pool;
+    pool.reserve(1024);
+    std::vector<int> roots(inst.size(), -1);
+    uint64_t N = 0;
+    bool need_part = false;
+    for (size_t i = 0; i < inst.size(); ++i) {
+        if (i > 0 && inst[i].dest < inst[i - 1].dest) throw Fail{ISA_EINVAL, "instances not ordered by dest"};
+        if (inst[i].n == 0) continue;
+        Node nd;
+        nd.kind = inst[i].n <= (uint64_t)LEAF_CAP ? 0 : 2;
+        nd.src = inst[i].src;
+        nd.n = inst[i].n;
+        nd.pos = N;
+        nd.lo = 0;
+        nd.hi = ~0ull;
+        nd.inst = (uint32_t)i;
+        roots[i] = (int)pool.size();
+        pool.push_back(nd);
+        N += inst[i].n;
+        if (nd.kind == 2) need_part = true;
+    }
+    if (N == 0) return totals;
+
+    uint64_t* P[2] = {nullptr, nullptr};
+    if (need_part) P[0] = A.take_n<uint64_t>(N * (uint64_t)L.words);
+    uint64_t* temp = A.take_n<uint64_t>(N * (uint64_t)S.words);
+
+    std::vector<int> pending;
+    for (int r : roots)
+        if (r >= 0 && pool[r].kind == 2) pending.push_back(r);
+
+    int level = 0;
+    while (!pending.empty()) {
+        if (level >= 48) throw Fail{ISA_EDEVICE, "key-range partitioning did not converge"};
+        if (!P[level & 1]) P[level & 1] = A.take_n<uint64_t>(N * (uint64_t)L.words);
+        uint64_t* tgt = P[level & 1];
+        std::vector<Region> regs;
+        std::vector<Chunk> chunks;
+        std::vector<uint64_t> bsb;
+        uint64_t hist_total = 0, bs_total = 0;
+        for (int id : pending) {
+            const Node& nd = pool[id];
+            Region r;
+            r.src = nd.src;
+            r.n = nd.n;
+            r.out_pos = nd.pos;
+            r.nb = buckets_for(nd.n);
+            r.n_chunks = (uint32_t)((nd.n + PART_CHUNK - 1) / PART_CHUNK);
+            r.hist_base = hist_total;
+            hist_total += (uint64_t)r.nb * r.n_chunks;
+            bsb.push_back(bs_total);
+            bs_total += r.nb + 1;
+            for (uint32_t c = 0; c < r.n_chunks; ++c) {
+                Chunk ch;
+                ch.region = (uint32_t)regs.size();
+                ch.idx = c;
+                ch.start = (uint64_t)c * PART_CHUNK;
+                const uint64_t left = nd.n - ch.start;
+                ch.n = (uint32_t)(left < (uint64_t)PART_CHUNK ? left : (uint64_t)PART_CHUNK);
+                ch.pad = 0;
+                chunks.push_back(ch);
+            }
+            regs.push_back(r);
+        }
+        const uint64_t mark = A.off;
+        Region* d_regs = A.take_n<Region>(regs.size());
+        Chunk* d_chunks = A.take_n<Chunk>(chunks.size());
+        uint64_t* d_spl = A.take_n<uint64_t>(regs.size() * (MAX_BUCKETS - 1));
+        uint32_t* d_hist = A.take_n<uint32_t>(hist_total);
+        uint64_t* d_offs = A.take_n<uint64_t>(hist_total + 1);
+        uint64_t* d_tiles = A.take_n<uint64_t>(scan_tiles(hist_total) + 1);
+        uint64_t* d_bsb = A.take_n<uint64_t>(bsb.size());
+        uint64_t* d_bstart = A.take_n<uint64_t>(bs_total);
+        E.upload(d_regs, regs.data(), regs.size() * sizeof(Region));
+        E.upload(d_chunks, chunks.data(), chunks.size() * sizeof(Chunk));
+        E.upload(d_bsb, bsb.data(), bsb.size() * sizeof(uint64_t));
+        launch_sample(d_regs, (uint32_t)regs.size(), d_spl, E.stream);
+        launch_hist(d_regs, d_chunks, (uint32_t)chunks.size(), d_spl, d_hist, E.stream);
+        launch_scan(d_hist, hist_total, d_tiles, d_offs, E.stream);
+        launch_scatter(d_regs, d_chunks, (uint32_t)chunks.size(), d_spl, d_offs, tgt, L, E.stream);
+        launch_bucket_starts(d_regs, (uint32_t)regs.size(), d_offs, d_bsb, d_bstart, E.stream);
+        ck(hipGetLastError(), "partition launch");
+        const uint64_t* h_bs = (const uint64_t*)download_async(E, d_bstart, bs_total * sizeof(uint64_t));
+        const uint64_t* h_sp =
+            (const uint64_t*)download_async(E, d_spl, regs.size() * (MAX_BUCKETS - 1) * sizeof(uint64_t));
+        E.sync();
+        std::vector<uint64_t> bstart(h_bs, h_bs + bs_total);
+        std::vector<uint64_t> spl(h_sp, h_sp + regs.size() * (MAX_BUCKETS - 1));
+        A.off = mark;
+        std::vector<int> next;
+        for (size_t ri = 0; ri < pending.size(); ++ri) {
+            const int id = pending[ri];
+            const Region& r = regs[ri];
+            const uint64_t* sp = spl.data() + ri * (MAX_BUCKETS - 1);
+            const uint64_t* bs = bstart.data() + bsb[ri];
+            if (bs[r.nb] != r.n) throw Fail{ISA_EDEVICE, "partition lost rows"};
+            std::vector<int> kids;
+            for (uint32_t b = 0; b < r.nb; ++b) {
+                const uint64_t size = bs[b + 1] - bs[b];
+                if (!size) continue;
+                uint64_t lo = b == 0 ? pool[id].lo : sp[b - 1];
+                uint64_t hi = b + 1 == r.nb ? pool[id].hi : sp[b] - 1;
+                if (lo < pool[id].lo) lo = pool[id].lo;
+                if (hi > pool[id].hi) hi = pool[id].hi;
+                Node c;
+                c.pos = pool[id].pos + bs[b];
+                c.src = aos_view(tgt + c.pos * (uint64_t)L.words, L);
+                c.n = size;
+                c.lo = lo;
+                c.hi = hi;
+                c.inst = pool[id].inst;
+                c.kind = size <= (uint64_t)LEAF_CAP ? 0 : (lo == hi ? 1 : 2);
+                kids.push_back((int)pool.size());
+                if (c.kind == 2) next.push_back((int)pool.size());
+                pool.push_back(c);
+            }
+            pool[id].kids = kids;
+            pool[id].kind = 3;
+        }
+        pending.swap(next);
+        ++level;
+    }
+
+    // Leaves in output order: instances in order, keys ascending within each.
+    std::vector<Leaf> leaves;
+    std::vector<Segment> segs;
+    std::vector<SinglePiece> pieces;
+    std::vector<uint32_t> first_seg(dests.size() + 1, 0);
+    std::vector<int> stack;
+    uint32_t cur_dest = 0;
+    for (size_t i = 0; i < inst.size(); ++i) {
+        while (cur_dest < inst[i].dest) first_seg[++cur_dest] = (uint32_t)leaves.size();
+        if (roots[i] < 0) continue;
+        stack.assign(1, roots[i]);
+        while (!stack.empty()) {
+            const int id = stack.back();
+            stack.pop_back();
+            const Node& nd = pool[id];
+            if (nd.kind == 3) {
+                for (auto it = nd.kids.rbegin(); it != nd.kids.rend(); ++it) stack.push_back(*it);
+                continue;
+            }
+            Leaf lf;
+            lf.src = nd.src;
+            lf.n = nd.n;
+            lf.out_pos = nd.pos;
+            lf.kind = (uint32_t)nd.kind;
+            lf.single_first = 0;
+            lf.single_count = 0;
+            lf.pad = 0;
+            if (nd.kind == 1) {
+                lf.single_first = (uint32_t)pieces.size();
+                for (uint64_t s = 0; s < nd.n; s += SINGLE_CHUNK) {
+                    SinglePiece p;
+                    p.leaf = (uint32_t)leaves.size();
+                    p.slot = (uint32_t)pieces.size();
+                    p.start = s;
+                    p.n = (uint32_t)std::min<uint64_t>(SINGLE_CHUNK, nd.n - s);
+                    p.pad = 0;
+                    pieces.push_back(p);
+                }
+                lf.single_count = (uint32_t)pieces.size() - lf.single_first;
+            }
+            Segment sg;
+            sg.src_pos = nd.pos;
+            sg.inst = inst[i].dest;
+            sg.pad = 0;
+            leaves.push_back(lf);
+            segs.push_back(sg);
+        }
+    }
+    while (cur_dest < dests.size()) first_seg[++cur_dest] = (uint32_t)leaves.size();
+
+    const uint64_t nl = leaves.size();
+    Leaf* d_leaves = A.take_n<Leaf>(nl);
+    Segment* d_segs = A.take_n<Segment>(nl);
+    uint32_t* d_counts = A.take_n<uint32_t>(nl);
+    uint64_t* d_offs = A.take_n<uint64_t>(nl + 1);
+    uint64_t* d_tiles = A.take_n<uint64_t>(scan_tiles(nl) + 1);
+    uint32_t* d_first = A.take_n<uint32_t>(first_seg.size());
+    Dest* d_dests = A.take_n<Dest>(dests.size());
+    uint64_t* d_totals = A.take_n<uint64_t>(dests.size());
+    SinglePiece* d_pieces = pieces.empty() ? nullptr : A.take_n<SinglePiece>(pieces.size());
+    void* d_partials = pieces.empty() ? nullptr : A.take(pieces.size() * single_partial_bytes());
+    E.upload(d_leaves, leaves.data(), nl * sizeof(Leaf));
+    E.upload(d_segs, segs.data(), nl * sizeof(Segment));
+    E.upload(d_first, first_seg.data(), first_seg.size() * sizeof(uint32_t));
+    E.upload(d_dests, dests.data(), dests.size() * sizeof(Dest));
+    if (!pieces.empty()) E.upload(d_pieces, pieces.data(), pieces.size() * sizeof(SinglePiece));
+    const OutView tout = aos_out(temp, S);
+    launch_leaf(d_leaves, (uint32_t)nl, tout, d_counts, E.stream);
+    if (!pieces.empty())
+        launch_single(d_leaves, (uint32_t)nl, d_pieces, (uint32_t)pieces.size(), d_partials, tout, d_counts,
+                      E.stream);
+    launch_scan(d_counts, nl, d_tiles, d_offs, E.stream);
+    launch_compact(d_segs, (uint32_t)nl, d_counts, d_offs, d_first, d_dests, aos_view(temp, S), E.stream);
+    launch_inst_totals(d_offs, d_first, (uint32_t)dests.size(), d_totals, E.stream);
+    ck(hipGetLastError(), "leaf launch");
+    const uint64_t* h_tot = (const uint64_t*)download_async(E, d_totals, dests.size() * sizeof(uint64_t));
+    E.sync();
+    for (size_t d = 0; d < dests.size(); ++d) totals[d] = h_tot[d];
+    return totals;
+}
+
+}  // namespace isa

@@ -1,0 +1,107 @@
+// Host engine of the grouping library: workspace carving, the multi-level
+// partition driver ("sort-reduce"), run generation and the wide merge.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "isa_internal.h"
+
+namespace isa {
+
+// ---- kernel launch wrappers (isa_kernels.hip) ----
+void launch_sample(const Region* regions, uint32_t n_regions, uint64_t* splitters, hipStream_t st);
+void launch_hist(const Region* regions, const Chunk* chunks, uint32_t n_chunks, const uint64_t* splitters,
+                 uint32_t* hist, hipStream_t st);
+void launch_scatter(const Region* regions, const Chunk* chunks, uint32_t n_chunks, const uint64_t* splitters,
+                    const uint64_t* offs, uint64_t* dst, Layout L, hipStream_t st);
+void launch_bucket_starts(const Region* regions, uint32_t n_regions, const uint64_t* offs, const uint64_t* bs_base,
+                          uint64_t* bstart, hipStream_t st);
+void launch_leaf(const Leaf* leaves, uint32_t n_leaves, OutView temp, uint32_t* counts, hipStream_t st);
+void launch_single(const Leaf* leaves, uint32_t n_leaves, const SinglePiece* pieces, uint32_t n_pieces,
+                   void* partials, OutView temp, uint32_t* counts, hipStream_t st);
+size_t single_partial_bytes();
+uint64_t merge_parts(uint64_t na, uint64_t nb);
+void launch_merge_count(ColView A, uint64_t na, ColView B, uint64_t nb, uint32_t* counts, hipStream_t st);
+void launch_merge_write(ColView A, uint64_t na, ColView B, uint64_t nb, const uint64_t* offs, OutView out,
+                        hipStream_t st);
+void launch_copy_rows(ColView src, uint64_t n, OutView dst, uint64_t cap, hipStream_t st);
+uint64_t scan_tiles(uint64_t n);
+void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* offs, hipStream_t st);
+void launch_compact(const Segment* segs, uint32_t n_segs, const uint32_t* counts, const uint64_t* offs,
+                    const uint32_t* first_seg, const Dest* dests, ColView temp, hipStream_t st);
+void launch_inst_totals(const uint64_t* offs, const uint32_t* first_seg, uint32_t n_inst, uint64_t* totals,
+                        hipStream_t st);
+void launch_pack_pairs(const int32_t* a, const int32_t* b, uint64_t n, uint64_t* keys, hipStream_t st);
+void launch_unpack_pairs(const uint64_t* keys, uint64_t n, int32_t* a, int32_t* b, hipStream_t st);
+void launch_seg_count(const int32_t* a, uint64_t n, uint32_t chunk, uint32_t* counts, uint32_t* bad,
+                      hipStream_t st);
+void launch_seg_write(const int32_t* a, uint64_t n, uint32_t chunk, const uint64_t* offs, uint64_t* starts,
+                      hipStream_t st);
+
+// Error carried out of the engine as an isa_status value.
+struct Fail {
+    int status;
+    std::string what;
+};
+
+// Which aggregate columns flow through the path.
+struct Cols {
+    bool c, v, f;  // count, int64 (sum/min/max), float64 sum
+};
+
+Layout raw_layout(const Cols& k);
+Layout state_layout(const Cols& k);
+ColView aos_view(const uint64_t* base, const Layout& L);
+OutView aos_out(uint64_t* base, const Layout& L);
+
+// Bump allocator over the caller's workspace.
+struct Arena {
+    char* base = nullptr;
+    uint64_t cap = 0;
+    uint64_t off = 0;
+    uint64_t peak = 0;
+    void* take(uint64_t bytes);  // throws Fail(ISA_EBUDGET) when exhausted
+    template <class T>
+    T* take_n(uint64_t n) { return (T*)take(n * sizeof(T)); }
+    uint64_t left() const { return cap > off ? cap - off : 0; }
+};
+
+// Per-context host state.
+struct Engine {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // pinned host staging for descriptor uploads and small readbacks
+    char* pinned = nullptr;
+    uint64_t pinned_cap = 0;
+    uint64_t pinned_used = 0;
+    std::vector<char*> retired;
+
+    void* pinned_buf(uint64_t bytes);
+    void upload(void* dev, const void* host, uint64_t bytes);
+    void sync();
+    void release();
+};
+
+// One independent grouping problem of a sort-reduce call.
+struct Instance {
+    ColView src;
+    uint64_t n;
+    uint32_t dest;  // index into the dest list
+};
+
+// Sort and reduce every instance: the sorted unique state rows of instance i
+// are appended, in instance order, to dests[instance.dest].  Returns the
+// number of groups written (or required) per dest.
+std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instance>& inst,
+                                  const std::vector<Dest>& dests, const Cols& k, bool state_rows);
+
+// Device-to-host copy into pinned staging; valid after the next sync().
+const void* download_async(Engine& E, const void* dev, uint64_t bytes);
+
+// Workspace bytes sort_reduce needs for `rows` input rows.
+uint64_t sort_reduce_bytes(uint64_t rows, uint64_t n_inst, const Cols& k, bool state_rows);
+
+}  // namespace isa

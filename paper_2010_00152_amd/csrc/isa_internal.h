@@ -1,0 +1,111 @@
+// Internal types shared by the host engine and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace isa {
+
+// Rows per leaf: the largest key range a single workgroup sorts and reduces
+// in LDS (256 threads x 16 rows).
+constexpr int LEAF_NT = 256;
+constexpr int LEAF_IPT = 16;
+constexpr int LEAF_CAP = LEAF_NT * LEAF_IPT;
+// Rows per partition chunk (one workgroup of the histogram / scatter passes).
+constexpr int PART_NT = 256;
+constexpr int PART_IPT = 16;
+constexpr int PART_TILE = PART_NT * PART_IPT;
+constexpr int PART_CHUNK = 4 * PART_TILE;
+// Buckets per partition level (8-bit digit of the splitter rank).
+constexpr int MAX_BUCKETS = 256;
+// Keys sampled per region to choose its splitters.
+constexpr int SAMPLE_N = 4096;
+// Diagonal length handled by one workgroup of the merge-path merge.
+constexpr int MERGE_D = 4096;
+// Rows reduced per workgroup for single-key buckets.
+constexpr int SINGLE_CHUNK = 4096;
+
+// Strided view of rows: element i of a column lives at col[i * stride].
+// Raw input rows have cnt == nullptr (count 1 per row) and sum == mn == mx ==
+// the int64 value column.  Absent aggregate columns are nullptr.
+struct ColView {
+    const uint64_t* key;
+    const uint64_t* cnt;
+    const int64_t* sum;
+    const int64_t* mn;
+    const int64_t* mx;
+    const double* fs;
+    uint64_t stride;
+};
+
+// Writable strided view of state rows (key + partial aggregates).
+struct OutView {
+    uint64_t* key;
+    uint64_t* cnt;
+    int64_t* sum;
+    int64_t* mn;
+    int64_t* mx;
+    double* fs;
+    uint64_t stride;
+};
+
+// Row-major layout of rows in partition buffers and of state rows in the
+// index and in runs: word offsets (8-byte words), -1 when absent.
+struct Layout {
+    int32_t words;
+    int32_t cnt, sum, mn, mx, fs;
+};
+
+// One region being partitioned at the current level.
+struct Region {
+    ColView src;        // its rows are src[0, n)
+    uint64_t n;
+    uint64_t out_pos;   // first row of the region in the target partition buffer
+    uint64_t hist_base; // offset of its nb x n_chunks histogram (bucket-major)
+    uint32_t nb;        // buckets, 2..MAX_BUCKETS
+    uint32_t n_chunks;
+};
+
+// One workgroup's share of a region in the histogram and scatter passes.
+struct Chunk {
+    uint32_t region;
+    uint32_t idx;       // chunk index within the region
+    uint64_t start;     // first row within the region
+    uint32_t n;
+    uint32_t pad;
+};
+
+// A key range small enough to sort and reduce in one workgroup (kind 0), or
+// a range holding a single key value of any size (kind 1).
+struct Leaf {
+    ColView src;
+    uint64_t n;
+    uint64_t out_pos;   // first row of its (gapped) output in the temp buffer
+    uint32_t kind;
+    uint32_t single_first;  // kind 1: first partial slot
+    uint32_t single_count;  // kind 1: number of partials
+    uint32_t pad;
+};
+
+// A piece of a single-key leaf reduced by one workgroup into one partial.
+struct SinglePiece {
+    uint32_t leaf;
+    uint32_t slot;
+    uint64_t start;
+    uint32_t n;
+    uint32_t pad;
+};
+
+// Destination of one instance's sorted unique output.
+struct Dest {
+    OutView out;
+    uint64_t capacity;
+};
+
+// A span of gapped output copied into its final place.
+struct Segment {
+    uint64_t src_pos;
+    uint32_t inst;
+    uint32_t pad;
+};
+
+}  // namespace isa

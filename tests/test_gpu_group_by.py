@@ -1,0 +1,169 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs, element by element.  Integer columns are bit-exact; the
+fp64 sum is within 1e-12 * sum(|x|) per group."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from oracle import spillsim
+import paper_2010_00152_amd as isa
+from tests.gpu_util import compare, run_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = isa.Context(0)
+    yield c
+    c.close()
+
+
+def test_plain_config_1m_rows_10k_keys(ctx):
+    # plain group-by: 1M rows, uint64 keys uniform over 10,000 distinct values,
+    # int64 values uniform in [-1e6, 1e6]; count/sum/min/max; budget above the output
+    say("case plain 1M/10k seed 1")
+    k, v, _ = datagen.plain_input(1, 1_000_000, 10_000, 0.0)
+    aggs = isa.ISA_INT_AGGS
+    got, st, status, g = run_gpu(ctx, k, v, None, aggs=aggs, budget=64 << 20)
+    assert status == isa.ISA_OK and st["runs"] == 0 and st["spilled_rows"] == 0
+    compare(got, k, v, None, aggs, "plain")
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 4095, 4096, 4097, 16383, 16384, 16385, 65537, 300001])
+def test_ragged_sizes(ctx, n):
+    say("case ragged n=%d" % n)
+    k, v, f = datagen.plain_input(100 + n % 97, n, max(1, n // 3), 0.7, with_f64=True)
+    got, st, status, g = run_gpu(ctx, k, v, f, budget=64 << 20)
+    compare(got, k, v, f, isa.ISA_ALL, "ragged %d" % n)
+
+
+def test_empty(ctx):
+    say("case empty")
+    import torch
+    e = torch.empty(0, dtype=torch.int64, device="cuda")
+    res, st, status, g = isa.group_by(ctx, e, e, torch.empty(0, dtype=torch.float64, device="cuda"),
+                                      mem_budget=32 << 20, capacity=0)
+    assert status == isa.ISA_OK and g == 0
+
+
+@pytest.mark.parametrize("n", [4097, 200_000, 1_000_003])
+def test_single_key(ctx, n):
+    say("case single key n=%d" % n)
+    k = np.full(n, 0x0123456789ABCDEF, np.uint64)
+    v = datagen.uniform_i64(7, n)
+    f = datagen.normal_f64(8, n)
+    got, st, status, g = run_gpu(ctx, k, v, f, budget=128 << 20)
+    compare(got, k, v, f, isa.ISA_ALL, "single")
+
+
+def test_all_distinct(ctx):
+    say("case all distinct")
+    n = 300_000
+    k = datagen.key_of_rank(np.arange(n, dtype=np.uint64) * np.uint64(7919))
+    v = datagen.uniform_i64(9, n)
+    f = datagen.normal_f64(10, n)
+    got, st, status, g = run_gpu(ctx, k, v, f, budget=128 << 20)
+    compare(got, k, v, f, isa.ISA_ALL, "distinct")
+
+
+def test_extreme_keys_and_values(ctx):
+    say("case extremes")
+    n = 50_000
+    rng = np.random.default_rng(3)
+    pool = np.array([0, 1, 2, (1 << 63) - 1, 1 << 63, (1 << 64) - 2, (1 << 64) - 1], np.uint64)
+    k = pool[rng.integers(0, len(pool), n)]
+    vals = np.array([np.iinfo(np.int64).min, np.iinfo(np.int64).max, 0, -1, 1], np.int64)
+    v = vals[rng.integers(0, len(vals), n)]
+    f = rng.standard_normal(n) * 1e300
+    got, st, status, g = run_gpu(ctx, k, v, f, budget=64 << 20)
+    compare(got, k, v, f, isa.ISA_ALL, "extremes")
+
+
+@pytest.mark.parametrize("s,seed", [(0.0, 2), (0.8, 3), (1.2, 4)])
+def test_zipf_all_aggs(ctx, s, seed):
+    # the spilling configuration's shape at 1/50 scale, with a budget that holds it
+    say("case zipf s=%s" % s)
+    k, v, f = datagen.plain_input(seed, 2_000_000, 200_000, s, with_f64=True)
+    got, st, status, g = run_gpu(ctx, k, v, f, budget=512 << 20)
+    assert st["runs"] == 0
+    compare(got, k, v, f, isa.ISA_ALL, "zipf %s" % s)
+
+
+@pytest.mark.parametrize("s,seed,budget_mib", [(0.0, 5, 16), (0.8, 6, 16), (1.2, 7, 12), (0.0, 8, 24)])
+def test_spilling_matches_oracle_and_simulator(ctx, s, seed, budget_mib):
+    # a budget far below the output forces runs on pinned host memory and a
+    # wide merge; the run count and spilled rows equal the read-sort-write
+    # simulation with the same batch size and index capacity
+    say("case spill s=%s budget=%dMiB" % (s, budget_mib))
+    n = 1_500_000
+    k, v, f = datagen.plain_input(seed, n, 400_000, s, with_f64=True)
+    got, st, status, g = run_gpu(ctx, k, v, f, budget=budget_mib << 20)
+    compare(got, k, v, f, isa.ISA_ALL, "spill")
+    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"])
+    assert st["runs"] == sim["runs"] and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
+    assert st["spilled_rows"] <= n
+    if s < 1.2:
+        assert st["runs"] > 0 and st["windows"] >= 1
+    assert st["peak_ws_bytes"] <= budget_mib << 20
+
+
+def test_budget_invariance(ctx):
+    # integer output is independent of the budget (and so of batches, runs and windows)
+    say("case budget invariance")
+    k, v, _ = datagen.plain_input(12, 800_000, 150_000, 0.5)
+    outs = []
+    for b in [16 << 20, 40 << 20, 512 << 20]:
+        got, st, status, g = run_gpu(ctx, k, v, None, aggs=isa.ISA_INT_AGGS, budget=b)
+        outs.append(got)
+    for o in outs[1:]:
+        for c in o:
+            assert np.array_equal(o[c], outs[0][c]), c
+
+
+@pytest.mark.parametrize("aggs", [0, isa.ISA_COUNT, isa.ISA_SUM_F64, isa.ISA_MIN_I64,
+                                  isa.ISA_MAX_I64 | isa.ISA_SUM_I64])
+def test_aggregate_subsets(ctx, aggs):
+    say("case aggs=%d" % aggs)
+    k, v, f = datagen.plain_input(13, 120_000, 20_000, 0.9, with_f64=True)
+    vv = v if aggs & (isa.ISA_SUM_I64 | isa.ISA_MIN_I64 | isa.ISA_MAX_I64) else None
+    ff = f if aggs & isa.ISA_SUM_F64 else None
+    got, st, status, g = run_gpu(ctx, k, vv, ff, aggs=aggs, budget=64 << 20)
+    compare(got, k, vv, ff, aggs, "aggs %d" % aggs)
+
+
+def test_truncation(ctx):
+    say("case truncation")
+    k, v, _ = datagen.plain_input(14, 100_000, 5_000, 0.0)
+    ref = oracle.group_by(k, v)
+    G = ref["keys"].shape[0]
+    got, st, status, g = run_gpu(ctx, k, v, None, aggs=isa.ISA_INT_AGGS, budget=64 << 20,
+                                 capacity=G - 7, check=False)
+    assert status == isa.ISA_ETRUNC and g == G
+    assert np.array_equal(got["keys"], ref["keys"][:G - 7])
+    assert np.array_equal(got["sum_i64"], ref["sum_i64"][:G - 7])
+
+
+def test_argument_errors(ctx):
+    say("case argument errors")
+    import torch
+    k, v, f = datagen.plain_input(15, 10_000, 100, 0.0, with_f64=True)
+    kd = torch.from_numpy(k.view(np.int64)).cuda()
+    # a requested aggregate without its column
+    with pytest.raises(isa.InsortError) as e:
+        isa.group_by(ctx, kd, None, None, aggs=isa.ISA_SUM_I64, mem_budget=32 << 20)
+    assert e.value.status == isa.ISA_EINVAL
+    # workspace below the minimum
+    with pytest.raises(isa.InsortError) as e:
+        isa.group_by(ctx, kd, None, None, aggs=isa.ISA_COUNT, mem_budget=1 << 20)
+    assert e.value.status == isa.ISA_EBUDGET
+    # no room to spill
+    k2, v2, _ = datagen.plain_input(16, 1_000_000, 500_000, 0.0)
+    kd2 = torch.from_numpy(k2.view(np.int64)).cuda()
+    vd2 = torch.from_numpy(v2).cuda()
+    with pytest.raises(isa.InsortError) as e:
+        isa.group_by(ctx, kd2, vd2, None, aggs=isa.ISA_INT_AGGS, mem_budget=12 << 20, spill_bytes=0)
+    assert e.value.status == isa.ISA_ESPILL
