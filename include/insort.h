@@ -203,6 +203,24 @@ void isa_server_destroy(isa_server* s);
 
 const char* isa_status_str(isa_status st);
 
+/* Per-kernel timing of launches on a context (instrumentation for
+ * measurement; not part of the grouping semantics).  isa_profile_enable(ctx,1)
+ * clears the record and brackets every later kernel launch and host-link copy
+ * of the context with HIP events on its stream; 0 stops recording.
+ * isa_profile_read aggregates the record by name into out[0..max) and returns
+ * the number of distinct names (or a negative isa_status).  `rows` are the
+ * units the launches processed, `bytes` their algorithmic bytes (each unit's
+ * row read once). */
+typedef struct {
+    char name[32];
+    uint64_t launches;
+    uint64_t rows;
+    uint64_t bytes;
+    double total_ms;
+} isa_kernel_time;
+isa_status isa_profile_enable(isa_ctx* ctx, int on);
+int isa_profile_read(isa_ctx* ctx, isa_kernel_time* out, int max);
+
 /* Message describing the last error returned on this context ("" if none).
  * The string is owned by the context and valid until its next call. */
 const char* isa_last_error(isa_ctx* ctx);

@@ -65,6 +65,11 @@ class isa_stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class isa_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", U64), ("rows", U64), ("bytes", U64),
+                ("total_ms", ctypes.c_double)]
+
+
 # Every function the header declares: name -> (restype, argtypes)
 SIGNATURES = {
     "isa_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(P)]),
@@ -87,6 +92,8 @@ SIGNATURES = {
     "isa_server_destroy": (None, [P]),
     "isa_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "isa_last_error": (ctypes.c_char_p, [P]),
+    "isa_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
+    "isa_profile_read": (ctypes.c_int, [P, ctypes.POINTER(isa_kernel_time), ctypes.c_int]),
 }
 
 _lib = None
@@ -148,6 +155,21 @@ class Context:
 
     def last_error(self) -> str:
         return lib().isa_last_error(self.handle).decode()
+
+    def profile(self, on: bool = True):
+        st = lib().isa_profile_enable(self.handle, 1 if on else 0)
+        if st != ISA_OK:
+            raise InsortError(st)
+
+    def profile_read(self):
+        """{name: {launches, rows, bytes, total_ms}} of launches since profile(True)."""
+        buf = (isa_kernel_time * 64)()
+        n = lib().isa_profile_read(self.handle, buf, 64)
+        if n < 0:
+            raise InsortError(n)
+        return {buf[i].name.decode(): {"launches": buf[i].launches, "rows": buf[i].rows,
+                                       "bytes": buf[i].bytes, "total_ms": buf[i].total_ms}
+                for i in range(min(n, 64))}
 
 
 def _alloc_outputs(torch, cap, aggs, dev, with_keys=True):

@@ -236,6 +236,7 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
         A.off = mark;
         uint64_t* stage = A.take_n<uint64_t>(wrows * sw);
         uint64_t at = 0;
+        E.pbegin("merge_h2d");
         for (size_t s = 0; s <= R; ++s) {
             const uint64_t len = end[s] - pos[s];
             if (!len) continue;
@@ -251,6 +252,7 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
             at += len;
             pos[s] = end[s];
         }
+        E.pend(wrows, wrows * sw * 8);
         const uint64_t cap = out->capacity > cursor ? out->capacity - cursor : 0;
         Dest d;
         d.out = output_view(*out, aggs, std::min(cursor, out->capacity));
@@ -313,6 +315,41 @@ void isa_ctx_destroy(isa_ctx* ctx) {
     if (!ctx) return;
     ctx->eng.release();
     delete ctx;
+}
+
+isa_status isa_profile_enable(isa_ctx* ctx, int on) {
+    if (!ctx) return ISA_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->eng.prof_on = on != 0;
+    ctx->eng.prof.clear();
+    ctx->eng.ev_used = 0;
+    return ISA_OK;
+}
+
+int isa_profile_read(isa_ctx* ctx, isa_kernel_time* out, int max) {
+    if (!ctx) return ISA_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    std::vector<isa_kernel_time> agg;
+    for (const ProfRec& r : ctx->eng.prof) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+            return ISA_EDEVICE;
+        size_t i = 0;
+        while (i < agg.size() && std::strncmp(agg[i].name, r.name, sizeof(agg[i].name)) != 0) ++i;
+        if (i == agg.size()) {
+            isa_kernel_time t;
+            std::memset(&t, 0, sizeof(t));
+            std::strncpy(t.name, r.name, sizeof(t.name) - 1);
+            agg.push_back(t);
+        }
+        agg[i].launches += 1;
+        agg[i].rows += r.rows;
+        agg[i].bytes += r.bytes;
+        agg[i].total_ms += ms;
+    }
+    const int n = (int)agg.size() < max ? (int)agg.size() : max;
+    for (int i = 0; i < n; ++i) out[i] = agg[i];
+    return (int)agg.size();
 }
 
 uint64_t isa_state_row_bytes(uint32_t aggs) { return (uint64_t)state_layout(cols_of(aggs)).words * 8; }
@@ -413,13 +450,17 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 // absorb the batch's distinct keys into the index if they fit
                 const ColView iv = aos_view(idx[cur], S), bv = aos_view(brun, S);
                 const uint64_t parts = merge_parts(n_idx, g);
+                E.pbegin("k_merge_count");
                 launch_merge_count(iv, n_idx, bv, g, m_counts, E.stream);
+                E.pend(n_idx + g, (n_idx + g) * 8);
                 launch_scan(m_counts, parts, m_tiles, m_offs, E.stream);
                 const uint64_t* h_m = (const uint64_t*)download_async(E, m_offs + parts, 8);
                 E.sync();
                 const uint64_t m = *h_m;
                 if (m <= p.capacity) {
+                    E.pbegin("k_merge_write");
                     launch_merge_write(iv, n_idx, bv, g, m_offs, aos_out(idx[cur ^ 1], S), E.stream);
+                    E.pend(n_idx + g, (n_idx + g + m) * sw * 8);
                     cur ^= 1;
                     n_idx = m;
                 } else {
@@ -427,9 +468,11 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     // (read-sort-write) and start a new index with the batch
                     if (spill_used + n_idx > spill_rows_cap)
                         throw Fail{ISA_ESPILL, "spill buffer too small"};
+                    E.pbegin("spill_d2h");
                     ck(hipMemcpyAsync((char*)spill.host_pinned + spill_used * sw * 8, idx[cur], n_idx * sw * 8,
                                       hipMemcpyDeviceToHost, E.stream),
                        "hipMemcpyAsync(spill)");
+                    E.pend(n_idx, n_idx * sw * 8);
                     RunInfo ri;
                     ri.row_off = spill_used;
                     ri.n = n_idx;
@@ -453,7 +496,9 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 stats->t_rungen_ms = t1 - t0;
             }
             if (runs.empty()) {
+                E.pbegin("k_copy_rows");
                 launch_copy_rows(aos_view(idx[cur], S), n_idx, output_view(*out, aggs, 0), out->capacity, E.stream);
+                E.pend(n_idx, 2 * n_idx * sw * 8);
                 E.sync();
                 n_groups = n_idx;
             } else {

@@ -100,7 +100,39 @@ void* Engine::pinned_buf(uint64_t bytes) {
     return pinned + o;
 }
 
+static hipEvent_t pool_event(Engine& E) {
+    if (E.ev_used == E.ev_pool.size()) {
+        hipEvent_t e;
+        ck(hipEventCreate(&e), "hipEventCreate");
+        E.ev_pool.push_back(e);
+    }
+    return E.ev_pool[E.ev_used++];
+}
+
+void Engine::pbegin(const char* name) {
+    if (!prof_on) return;
+    ProfRec r;
+    r.name = name;
+    r.a = pool_event(*this);
+    r.b = pool_event(*this);
+    r.rows = r.bytes = 0;
+    ck(hipEventRecord(r.a, stream), "hipEventRecord");
+    prof.push_back(r);
+}
+
+void Engine::pend(uint64_t rows, uint64_t bytes) {
+    if (!prof_on) return;
+    ProfRec& r = prof.back();
+    r.rows = rows;
+    r.bytes = bytes;
+    ck(hipEventRecord(r.b, stream), "hipEventRecord");
+}
+
 void Engine::release() {
+    for (hipEvent_t e : ev_pool) hipEventDestroy(e);
+    ev_pool.clear();
+    prof.clear();
+    ev_used = 0;
     for (char* p : retired) hipHostFree(p);
     retired.clear();
     if (pinned) hipHostFree(pinned);
@@ -162,6 +194,8 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
                                   const std::vector<Dest>& dests, const Cols& k, bool state_rows) {
     const Layout L = state_rows ? state_layout(k) : raw_layout(k);
     const Layout S = state_layout(k);
+    // bytes of one source row as the caller's columns hold it
+    const uint64_t src_row_bytes = (uint64_t)L.words * 8;
     std::vector<uint64_t> totals(dests.size(), 0);
     std::vector<Node> pool;
     pool.reserve(1024);
@@ -239,10 +273,21 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
         E.upload(d_regs, regs.data(), regs.size() * sizeof(Region));
         E.upload(d_chunks, chunks.data(), chunks.size() * sizeof(Chunk));
         E.upload(d_bsb, bsb.data(), bsb.size() * sizeof(uint64_t));
+        uint64_t lvl_rows = 0;
+        for (const Region& r : regs) lvl_rows += r.n;
+        const uint64_t in_bytes = (uint64_t)(level == 0 ? src_row_bytes : L.words * 8);
+        E.pbegin("k_sample");
         launch_sample(d_regs, (uint32_t)regs.size(), d_spl, E.stream);
+        E.pend(regs.size() * (uint64_t)SAMPLE_N, regs.size() * (uint64_t)SAMPLE_N * 8);
+        E.pbegin("k_hist");
         launch_hist(d_regs, d_chunks, (uint32_t)chunks.size(), d_spl, d_hist, E.stream);
+        E.pend(lvl_rows, lvl_rows * 8);
+        E.pbegin("k_scan");
         launch_scan(d_hist, hist_total, d_tiles, d_offs, E.stream);
+        E.pend(hist_total, hist_total * 12);
+        E.pbegin("k_scatter");
         launch_scatter(d_regs, d_chunks, (uint32_t)chunks.size(), d_spl, d_offs, tgt, L, E.stream);
+        E.pend(lvl_rows, lvl_rows * in_bytes);
         launch_bucket_starts(d_regs, (uint32_t)regs.size(), d_offs, d_bsb, d_bstart, E.stream);
         ck(hipGetLastError(), "partition launch");
         const uint64_t* h_bs = (const uint64_t*)download_async(E, d_bstart, bs_total * sizeof(uint64_t));
@@ -353,12 +398,22 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
     E.upload(d_dests, dests.data(), dests.size() * sizeof(Dest));
     if (!pieces.empty()) E.upload(d_pieces, pieces.data(), pieces.size() * sizeof(SinglePiece));
     const OutView tout = aos_out(temp, S);
+    uint64_t sort_rows = 0, single_rows = 0;
+    for (const Leaf& lf : leaves) (lf.kind == 0 ? sort_rows : single_rows) += lf.n;
+    const uint64_t leaf_bytes = need_part ? (uint64_t)L.words * 8 : src_row_bytes;
+    E.pbegin("k_leaf");
     launch_leaf(d_leaves, (uint32_t)nl, tout, d_counts, E.stream);
-    if (!pieces.empty())
+    E.pend(sort_rows, sort_rows * leaf_bytes);
+    if (!pieces.empty()) {
+        E.pbegin("k_single");
         launch_single(d_leaves, (uint32_t)nl, d_pieces, (uint32_t)pieces.size(), d_partials, tout, d_counts,
                       E.stream);
+        E.pend(single_rows, single_rows * leaf_bytes);
+    }
     launch_scan(d_counts, nl, d_tiles, d_offs, E.stream);
+    E.pbegin("k_compact");
     launch_compact(d_segs, (uint32_t)nl, d_counts, d_offs, d_first, d_dests, aos_view(temp, S), E.stream);
+    E.pend(0, 0);
     launch_inst_totals(d_offs, d_first, (uint32_t)dests.size(), d_totals, E.stream);
     ck(hipGetLastError(), "leaf launch");
     const uint64_t* h_tot = (const uint64_t*)download_async(E, d_totals, dests.size() * sizeof(uint64_t));

@@ -69,6 +69,14 @@ struct Arena {
     uint64_t left() const { return cap > off ? cap - off : 0; }
 };
 
+// Per-kernel launch timing (HIP events on the launch stream), off by default.
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+    uint64_t rows;   // units the launch processed
+    uint64_t bytes;  // algorithmic bytes of those units (rows read once)
+};
+
 // Per-context host state.
 struct Engine {
     int device = 0;
@@ -78,11 +86,18 @@ struct Engine {
     uint64_t pinned_cap = 0;
     uint64_t pinned_used = 0;
     std::vector<char*> retired;
+    bool prof_on = false;
+    std::vector<ProfRec> prof;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
 
     void* pinned_buf(uint64_t bytes);
     void upload(void* dev, const void* host, uint64_t bytes);
     void sync();
     void release();
+    // bracket one launch; no-ops unless profiling is on
+    void pbegin(const char* name);
+    void pend(uint64_t rows, uint64_t bytes);
 };
 
 // One independent grouping problem of a sort-reduce call.
