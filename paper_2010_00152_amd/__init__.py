@@ -226,3 +226,110 @@ def group_by(ctx: Context, keys, v_i64=None, v_f64=None, aggs: int = ISA_ALL,
     g = out.n_groups
     res = {k: v[:min(g, cap)] for k, v in o.items()}
     return res, st.as_dict(), status, g
+
+
+def group_by_segmented(ctx: Context, a, b, v=None, aggs: int = ISA_INT_AGGS, mem_budget: int = 256 << 20,
+                       capacity: int | None = None, workspace=None, stream=None, check: bool = True):
+    """Group on (a, b) for input sorted on a (int32 CUDA tensors; v int64).
+    Returns (dict with a, b and the aggregate columns, status, n_groups)."""
+    import torch
+    dev = a.device
+    n = a.numel()
+    cap = n if capacity is None else capacity
+    if workspace is None:
+        workspace = torch.empty(mem_budget, dtype=torch.uint8, device=dev)
+    o = _alloc_outputs(torch, cap, aggs, dev, with_keys=False)
+    oa = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    ob = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    out = _output_struct(o, cap)
+    ws = isa_workspace(_ptr(workspace), workspace.numel())
+    status = lib().isa_group_by_segmented(ctx.handle, _ptr(a), _ptr(b), _ptr(v), n, aggs, ws, _ptr(oa),
+                                          _ptr(ob), ctypes.byref(out), _stream_ptr(stream))
+    if check and status != ISA_OK:
+        raise InsortError(status, ctx.last_error())
+    g = out.n_groups
+    m = min(g, cap)
+    res = {k: t[:m] for k, t in o.items()}
+    res["a"] = oa[:m]
+    res["b"] = ob[:m]
+    return res, status, g
+
+
+def batch_run(ctx: Context, inputs, aggs: int = ISA_INT_AGGS, mem_budget: int = 1 << 30, workspace=None,
+              stream=None, check: bool = True):
+    """Run many independent group-bys together.  inputs: list of (keys, v_i64, v_f64)
+    CUDA tensors (v_* may be None).  Returns (list of output dicts, status)."""
+    import torch
+    k = len(inputs)
+    ins = (isa_input * max(k, 1))()
+    outs = (isa_output * max(k, 1))()
+    keep = []
+    for i, (kk, vv, ff) in enumerate(inputs):
+        n = kk.numel()
+        o = _alloc_outputs(torch, n, aggs, kk.device)
+        keep.append(o)
+        ins[i] = isa_input(_ptr(kk), _ptr(vv), _ptr(ff), n)
+        outs[i] = _output_struct(o, n)
+    if workspace is None:
+        workspace = torch.empty(mem_budget, dtype=torch.uint8, device="cuda")
+    ws = isa_workspace(_ptr(workspace), workspace.numel())
+    status = lib().isa_batch_run(ctx.handle, k, ins, aggs, ws, outs, _stream_ptr(stream))
+    if check and status != ISA_OK:
+        raise InsortError(status, ctx.last_error())
+    res = []
+    for i in range(k):
+        g = outs[i].n_groups
+        res.append({c: t[:g] for c, t in keep[i].items()})
+    return res, status
+
+
+class Server:
+    """Continuous-batching request loop of the library (isa_server_*).  Inputs
+    must be ready on the device when submitted; keep them alive until done."""
+
+    def __init__(self, ctx: Context, cap_bytes: int, slots: int = 2, workspace=None):
+        import torch
+        self.ctx = ctx
+        self.workspace = workspace if workspace is not None else torch.empty(
+            cap_bytes, dtype=torch.uint8, device="cuda")
+        h = P()
+        st = lib().isa_server_create(ctx.handle, _ptr(self.workspace), cap_bytes, slots, ctypes.byref(h))
+        if st != ISA_OK:
+            raise InsortError(st)
+        self.handle = h
+        self.live = {}
+
+    def submit(self, keys, v_i64=None, v_f64=None, aggs: int = ISA_INT_AGGS, capacity: int | None = None):
+        import torch
+        n = keys.numel()
+        cap = n if capacity is None else capacity
+        o = _alloc_outputs(torch, cap, aggs, keys.device)
+        out = _output_struct(o, cap)
+        inp = isa_input(_ptr(keys), _ptr(v_i64), _ptr(v_f64), n)
+        t = U64()
+        st = lib().isa_server_submit(self.handle, ctypes.byref(inp), aggs, ctypes.byref(out), ctypes.byref(t))
+        if st != ISA_OK:
+            raise InsortError(st)
+        self.live[t.value] = (keys, v_i64, v_f64, o, out, inp)
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int()
+        lat = ctypes.c_double()
+        st = lib().isa_server_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(lat))
+        return bool(done.value), lat.value, st
+
+    def result(self, ticket):
+        _, _, _, o, out, _ = self.live[ticket]
+        g = out.n_groups
+        return {c: t[:g] for c, t in o.items()}
+
+    def drain(self):
+        st = lib().isa_server_drain(self.handle)
+        if st != ISA_OK:
+            raise InsortError(st)
+
+    def close(self):
+        if self.handle:
+            lib().isa_server_destroy(self.handle)
+            self.handle = None

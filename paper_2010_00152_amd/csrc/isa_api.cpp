@@ -110,7 +110,7 @@ uint64_t merge_scratch_bytes(uint64_t rows) {
 uint64_t rungen_bytes(uint64_t Bt, uint64_t K, const Cols& k) {
     const uint64_t sw = (uint64_t)state_layout(k).words * 8;
     return 2 * (K + Bt) * sw + Bt * sw + merge_scratch_bytes(K + 2 * Bt) + sort_reduce_bytes(Bt, 1, k, false) +
-           MERGE_MARGIN + 6 * 256;
+           MERGE_MARGIN + 8 * 256 + (MAX_BUCKETS - 1) * 8;
 }
 
 bool plan_batches(uint64_t ws, uint64_t n, const Cols& k, Plan& p) {
@@ -417,6 +417,15 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             uint32_t* m_counts = A.take_n<uint32_t>(mscr_parts);
             uint64_t* m_offs = A.take_n<uint64_t>(mscr_parts + 1);
             uint64_t* m_tiles = A.take_n<uint64_t>(scan_tiles(mscr_parts) + 1);
+            // splitters for every batch, chosen once from a sample of the whole
+            // input (batches are slices of one input)
+            uint64_t* d_gspl = A.take_n<uint64_t>(MAX_BUCKETS - 1);
+            std::vector<uint64_t> h_gspl;
+            choose_splitters(E, A, src, n, buckets_for(p.batch_rows), d_gspl, h_gspl);
+            SplitterHint hint;
+            hint.dev = d_gspl;
+            hint.host = h_gspl.data();
+            hint.nb = buckets_for(p.batch_rows);
             const uint64_t mark = A.off;
             int cur = 0;
             uint64_t n_idx = 0;
@@ -440,12 +449,12 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 if (n_idx == 0) {
                     // an empty index simply becomes the batch's sorted run
                     d.out = aos_out(idx[cur], S);
-                    n_idx = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false)[0];
+                    n_idx = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false, &hint)[0];
                     ++batches;
                     continue;
                 }
                 d.out = aos_out(brun, S);
-                const uint64_t g = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false)[0];
+                const uint64_t g = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false, &hint)[0];
                 ++batches;
                 // absorb the batch's distinct keys into the index if they fit
                 const ColView iv = aos_view(idx[cur], S), bv = aos_view(brun, S);
@@ -531,21 +540,435 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
 
 extern "C" {
 
-isa_status isa_group_by_segmented(isa_ctx*, const int32_t*, const int32_t*, const int64_t*, uint64_t, uint32_t,
-                                  isa_workspace, int32_t*, int32_t*, isa_output*, void*) {
-    return ISA_EUNIMPL;
+isa_status isa_group_by_segmented(isa_ctx* ctx, const int32_t* a, const int32_t* b, const int64_t* v, uint64_t n,
+                                  uint32_t aggs, isa_workspace ws, int32_t* out_a, int32_t* out_b, isa_output* out,
+                                  void* stream) {
+    if (out) out->n_groups = 0;
+    if (!ctx || !valid_aggs(aggs) || (aggs & ISA_SUM_F64)) return ISA_EINVAL;
+    isa_status s = check_output(out, aggs, false);
+    if (s != ISA_OK) return s;
+    if (n == 0) return ISA_OK;
+    if (!a || !b || !out_a || !out_b) return ISA_EINVAL;
+    const Cols k = cols_of(aggs);
+    if (k.v && !v) return ISA_EINVAL;
+    if (!ws.dev || ((uintptr_t)ws.dev & 255)) return ISA_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    try {
+        ck(hipSetDevice(ctx->device), "hipSetDevice");
+        Engine& E = ctx->eng;
+        E.stream = (hipStream_t)stream;
+        Arena A;
+        A.base = (char*)ws.dev;
+        A.cap = ws.bytes;
+        // segment starts: positions where a changes (one scan of a)
+        constexpr uint32_t CH = 16384;
+        const uint64_t nch = (n + CH - 1) / CH;
+        uint32_t* d_cnt = A.take_n<uint32_t>(nch + 1);
+        uint64_t* d_offs = A.take_n<uint64_t>(nch + 2);
+        uint64_t* d_tiles = A.take_n<uint64_t>(scan_tiles(nch) + 1);
+        uint32_t* d_bad = d_cnt + nch;
+        ck(hipMemsetAsync(d_bad, 0, 4, E.stream), "hipMemsetAsync");
+        launch_seg_count(a, n, CH, d_cnt, d_bad, E.stream);
+        launch_scan(d_cnt, nch, d_tiles, d_offs, E.stream);
+        const uint64_t* h_ns = (const uint64_t*)download_async(E, d_offs + nch, 8);
+        const uint32_t* h_bad = (const uint32_t*)download_async(E, d_bad, 4);
+        E.sync();
+        const uint64_t n_seg = *h_ns;
+        if (*h_bad) throw Fail{ISA_EINVAL, "grouping prefix column is not sorted"};
+        uint64_t* d_starts = A.take_n<uint64_t>(n_seg);
+        launch_seg_write(a, n, CH, d_offs, d_starts, E.stream);
+        const uint64_t* h_st = (const uint64_t*)download_async(E, d_starts, n_seg * 8);
+        E.sync();
+        std::vector<uint64_t> starts(h_st, h_st + n_seg);
+        starts.push_back(n);
+        A.off = 0;
+        A.peak = 0;
+        // segments are independent groupings on b; several run together per wave
+        const uint64_t per_row = 16 + (sort_reduce_bytes(1, 0, k, false) - (4u << 20));
+        uint64_t cursor = 0;
+        uint64_t i0 = 0;
+        while (i0 < n_seg) {
+            uint64_t i1 = i0, rows = 0;
+            while (i1 < n_seg) {
+                const uint64_t r = starts[i1 + 1] - starts[i1];
+                const uint64_t need = (rows + r) * per_row + (i1 - i0 + 1) * 4608 + (5u << 20);
+                if (need > ws.bytes) break;
+                rows += r;
+                ++i1;
+            }
+            if (i1 == i0) throw Fail{ISA_EBUDGET, "one segment does not fit the workspace"};
+            const uint64_t r0 = starts[i0];
+            A.off = 0;
+            uint64_t* keys = A.take_n<uint64_t>(rows);
+            uint64_t* okeys = A.take_n<uint64_t>(rows);
+            launch_pack_pairs(a + r0, b + r0, rows, keys, E.stream);
+            std::vector<Instance> inst;
+            for (uint64_t i = i0; i < i1; ++i) {
+                Instance in;
+                in.src.key = keys + (starts[i] - r0);
+                in.src.cnt = nullptr;
+                in.src.sum = in.src.mn = in.src.mx = k.v ? v + starts[i] : nullptr;
+                in.src.fs = nullptr;
+                in.src.stride = 1;
+                in.n = starts[i + 1] - starts[i];
+                in.dest = 0;
+                inst.push_back(in);
+            }
+            const uint64_t cap_left = out->capacity > cursor ? out->capacity - cursor : 0;
+            Dest d;
+            d.out = output_view(*out, aggs, std::min(cursor, out->capacity));
+            d.out.key = okeys;
+            d.capacity = std::min(cap_left, rows);
+            const uint64_t g = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false)[0];
+            launch_unpack_pairs(okeys, std::min(g, d.capacity), out_a + std::min(cursor, out->capacity),
+                                out_b + std::min(cursor, out->capacity), E.stream);
+            E.sync();
+            cursor += g;
+            i0 = i1;
+        }
+        out->n_groups = cursor;
+        return cursor > out->capacity ? ISA_ETRUNC : ISA_OK;
+    } catch (const Fail& f) {
+        out->n_groups = 0;
+        return fail(ctx, f);
+    } catch (const std::bad_alloc&) {
+        out->n_groups = 0;
+        return ISA_ENOMEM;
+    }
 }
-isa_status isa_batch_run(isa_ctx*, uint32_t, const isa_input*, uint32_t, isa_workspace, isa_output*, void*) {
-    return ISA_EUNIMPL;
+
+uint64_t isa_batch_workspace_bytes(uint32_t n_inst, const isa_input* inst, uint32_t aggs) {
+    if (!inst) return 0;
+    uint64_t rows = 0;
+    for (uint32_t i = 0; i < n_inst; ++i) rows += inst[i].n_rows;
+    return sort_reduce_bytes(rows, n_inst, cols_of(aggs), false);
 }
-uint64_t isa_batch_workspace_bytes(uint32_t, const isa_input*, uint32_t) { return 0; }
-isa_status isa_server_create(isa_ctx*, void*, uint64_t, uint32_t, isa_server** out) {
-    if (out) *out = nullptr;
-    return ISA_EUNIMPL;
+
+isa_status isa_batch_run(isa_ctx* ctx, uint32_t n_inst, const isa_input* inst, uint32_t aggs, isa_workspace ws,
+                         isa_output* outs, void* stream) {
+    if (!ctx || !valid_aggs(aggs) || (n_inst && (!inst || !outs))) return ISA_EINVAL;
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        outs[i].n_groups = 0;
+        isa_status s = check_input(&inst[i], aggs);
+        if (s != ISA_OK) return s;
+        s = check_output(&outs[i], aggs, true);
+        if (s != ISA_OK) return s;
+    }
+    if (!n_inst) return ISA_OK;
+    if (!ws.dev || ((uintptr_t)ws.dev & 255)) return ISA_EINVAL;
+    const Cols k = cols_of(aggs);
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    try {
+        ck(hipSetDevice(ctx->device), "hipSetDevice");
+        Engine& E = ctx->eng;
+        E.stream = (hipStream_t)stream;
+        Arena A;
+        A.base = (char*)ws.dev;
+        A.cap = ws.bytes;
+        bool trunc = false;
+        uint32_t i0 = 0;
+        while (i0 < n_inst) {
+            // a wave: consecutive instances whose intermediate data fit together
+            uint32_t i1 = i0;
+            uint64_t rows = 0;
+            while (i1 < n_inst && sort_reduce_bytes(rows + inst[i1].n_rows, i1 - i0 + 1, k, false) <= ws.bytes) {
+                rows += inst[i1].n_rows;
+                ++i1;
+            }
+            if (i1 == i0) throw Fail{ISA_EBUDGET, "an instance does not fit the workspace"};
+            std::vector<Instance> in;
+            std::vector<Dest> ds;
+            for (uint32_t i = i0; i < i1; ++i) {
+                Instance x;
+                x.src = input_view(inst[i], k);
+                x.n = inst[i].n_rows;
+                x.dest = i - i0;
+                in.push_back(x);
+                Dest d;
+                d.out = output_view(outs[i], aggs, 0);
+                d.capacity = outs[i].capacity;
+                ds.push_back(d);
+            }
+            A.off = 0;
+            const std::vector<uint64_t> g = sort_reduce(E, A, in, ds, k, false);
+            for (uint32_t i = i0; i < i1; ++i) {
+                outs[i].n_groups = g[i - i0];
+                if (g[i - i0] > outs[i].capacity) trunc = true;
+            }
+            i0 = i1;
+        }
+        return trunc ? ISA_ETRUNC : ISA_OK;
+    } catch (const Fail& f) {
+        return fail(ctx, f);
+    } catch (const std::bad_alloc&) {
+        return ISA_ENOMEM;
+    }
 }
-isa_status isa_server_submit(isa_server*, const isa_input*, uint32_t, isa_output*, uint64_t*) { return ISA_EUNIMPL; }
-isa_status isa_server_poll(isa_server*, uint64_t, int*, double*) { return ISA_EUNIMPL; }
-isa_status isa_server_drain(isa_server*) { return ISA_EUNIMPL; }
-void isa_server_destroy(isa_server*) {}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching of group-by requests against a workspace cap.
+// ---------------------------------------------------------------------------
+
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <thread>
+#include <unordered_map>
+
+namespace {
+
+struct Req {
+    uint64_t ticket;
+    isa_input in;
+    uint32_t aggs;
+    isa_output* out;
+    uint64_t need;  // workspace bytes when run alone
+    double t_submit = 0, t_done = 0;
+    isa_status status = ISA_OK;
+    bool done = false;
+};
+
+// First-fit allocator over [0, cap) of the server's workspace.
+struct Ledger {
+    std::map<uint64_t, uint64_t> free_;  // offset -> size
+    uint64_t used = 0;
+    void init(uint64_t cap) { free_[0] = cap; }
+    bool alloc(uint64_t bytes, uint64_t& off) {
+        bytes = (bytes + 255) & ~(uint64_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                off = it->first;
+                const uint64_t rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                used += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t bytes) {
+        bytes = (bytes + 255) & ~(uint64_t)255;
+        used -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+constexpr uint32_t SERVER_MAX_BATCH = 1024;
+
+}  // namespace
+
+struct isa_server {
+    isa_ctx* ctx = nullptr;
+    char* ws = nullptr;
+    uint64_t cap = 0;
+    std::mutex mu;
+    std::condition_variable cv;       // work or memory became available
+    std::condition_variable cv_done;  // a request finished
+    std::deque<Req*> queue;
+    std::unordered_map<uint64_t, Req*> reqs;
+    uint64_t next_ticket = 1;
+    uint32_t running = 0;
+    bool stop = false;
+    Ledger ledger;
+    std::vector<std::thread> workers;
+    std::vector<Engine*> engines;
+};
+
+namespace {
+
+// Take the longest FIFO prefix of the queue with one aggregate set whose
+// combined workspace can be reserved now.
+bool take_batch(isa_server* S, std::vector<Req*>& batch, uint64_t& off, uint64_t& bytes) {
+    if (S->queue.empty()) return false;
+    const uint32_t aggs = S->queue.front()->aggs;
+    const Cols k = cols_of(aggs);
+    uint64_t rows = 0;
+    size_t cnt = 0;
+    while (cnt < S->queue.size() && cnt < SERVER_MAX_BATCH && S->queue[cnt]->aggs == aggs &&
+           sort_reduce_bytes(rows + S->queue[cnt]->in.n_rows, cnt + 1, k, false) <= S->cap) {
+        rows += S->queue[cnt]->in.n_rows;
+        ++cnt;
+    }
+    while (cnt > 0) {
+        bytes = sort_reduce_bytes(rows, cnt, k, false);
+        if (S->ledger.alloc(bytes, off)) break;
+        --cnt;
+        rows -= S->queue[cnt]->in.n_rows;
+    }
+    if (cnt == 0) return false;
+    batch.assign(S->queue.begin(), S->queue.begin() + cnt);
+    S->queue.erase(S->queue.begin(), S->queue.begin() + cnt);
+    return true;
+}
+
+void worker_loop(isa_server* S, Engine* E) {
+    hipSetDevice(S->ctx->device);
+    for (;;) {
+        std::vector<Req*> batch;
+        uint64_t off = 0, bytes = 0;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait(lk, [&] { return S->stop || take_batch(S, batch, off, bytes); });
+            if (batch.empty()) return;  // stop requested and nothing admitted
+            S->running++;
+        }
+        isa_status st = ISA_OK;
+        std::vector<uint64_t> g(batch.size(), 0);
+        try {
+            const Cols k = cols_of(batch[0]->aggs);
+            std::vector<Instance> in;
+            std::vector<Dest> ds;
+            for (size_t i = 0; i < batch.size(); ++i) {
+                Instance x;
+                x.src = input_view(batch[i]->in, k);
+                x.n = batch[i]->in.n_rows;
+                x.dest = (uint32_t)i;
+                in.push_back(x);
+                Dest d;
+                d.out = output_view(*batch[i]->out, batch[i]->aggs, 0);
+                d.capacity = batch[i]->out->capacity;
+                ds.push_back(d);
+            }
+            Arena A;
+            A.base = S->ws + off;
+            A.cap = bytes;
+            g = sort_reduce(*E, A, in, ds, k, false);
+        } catch (const Fail& f) {
+            st = (isa_status)f.status;
+        } catch (const std::bad_alloc&) {
+            st = ISA_ENOMEM;
+        }
+        const double t = now_ms();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (size_t i = 0; i < batch.size(); ++i) {
+                Req* r = batch[i];
+                r->out->n_groups = st == ISA_OK ? g[i] : 0;
+                r->status = st != ISA_OK ? st : (g[i] > r->out->capacity ? ISA_ETRUNC : ISA_OK);
+                r->t_done = t;
+                r->done = true;
+            }
+            S->ledger.release(off, bytes);
+            S->running--;
+        }
+        S->cv.notify_all();
+        S->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+isa_status isa_server_create(isa_ctx* ctx, void* workspace, uint64_t hbm_cap_bytes, uint32_t slots,
+                             isa_server** out) {
+    if (!out) return ISA_EINVAL;
+    *out = nullptr;
+    if (!ctx || !workspace || ((uintptr_t)workspace & 255) || slots == 0 || slots > 16) return ISA_EINVAL;
+    if (hbm_cap_bytes < (16u << 20)) return ISA_EBUDGET;
+    isa_server* S = new (std::nothrow) isa_server();
+    if (!S) return ISA_ENOMEM;
+    S->ctx = ctx;
+    S->ws = (char*)workspace;
+    S->cap = hbm_cap_bytes;
+    S->ledger.init(hbm_cap_bytes);
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        delete S;
+        return ISA_EDEVICE;
+    }
+    for (uint32_t i = 0; i < slots; ++i) {
+        Engine* E = new Engine();
+        E->device = ctx->device;
+        if (hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete E;
+            isa_server_destroy(S);
+            return ISA_EDEVICE;
+        }
+        S->engines.push_back(E);
+    }
+    for (Engine* E : S->engines) S->workers.emplace_back(worker_loop, S, E);
+    *out = S;
+    return ISA_OK;
+}
+
+isa_status isa_server_submit(isa_server* S, const isa_input* in, uint32_t aggs, isa_output* out, uint64_t* ticket) {
+    if (!S || !ticket || !valid_aggs(aggs)) return ISA_EINVAL;
+    isa_status s = check_input(in, aggs);
+    if (s != ISA_OK) return s;
+    s = check_output(out, aggs, true);
+    if (s != ISA_OK) return s;
+    Req* r = new (std::nothrow) Req();
+    if (!r) return ISA_ENOMEM;
+    r->in = *in;
+    r->aggs = aggs;
+    r->out = out;
+    r->need = sort_reduce_bytes(in->n_rows, 1, cols_of(aggs), false);
+    if (r->need > S->cap) {
+        delete r;
+        return ISA_ENOMEM;
+    }
+    out->n_groups = 0;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        r->ticket = S->next_ticket++;
+        r->t_submit = now_ms();
+        S->reqs[r->ticket] = r;
+        S->queue.push_back(r);
+        *ticket = r->ticket;
+    }
+    S->cv.notify_all();
+    return ISA_OK;
+}
+
+isa_status isa_server_poll(isa_server* S, uint64_t ticket, int* done, double* latency_ms) {
+    if (!S || !done) return ISA_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return ISA_EINVAL;
+    Req* r = it->second;
+    *done = r->done ? 1 : 0;
+    if (!r->done) return ISA_OK;
+    if (latency_ms) *latency_ms = r->t_done - r->t_submit;
+    return r->status;
+}
+
+isa_status isa_server_drain(isa_server* S) {
+    if (!S) return ISA_EINVAL;
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->queue.empty() && S->running == 0; });
+    return ISA_OK;
+}
+
+void isa_server_destroy(isa_server* S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    for (std::thread& t : S->workers) t.join();
+    for (Engine* E : S->engines) {
+        if (E->stream) hipStreamDestroy(E->stream);
+        E->release();
+        delete E;
+    }
+    for (auto& kv : S->reqs) delete kv.second;
+    delete S;
+}
 
 }  // extern "C"

@@ -165,6 +165,23 @@ const void* download_async(Engine& E, const void* dev, uint64_t bytes) {
 // sort_reduce
 // ---------------------------------------------------------------------------
 
+uint64_t UpPack::add(const void* src, uint64_t bytes) {
+    const uint64_t o = (total + 255) & ~(uint64_t)255;
+    parts.push_back(Part{src, bytes, o});
+    total = o + bytes;
+    return o;
+}
+
+char* UpPack::commit(Engine& E, Arena& A) {
+    char* dev = (char*)A.take(total ? total : 1);
+    if (!total) return dev;
+    char* host = (char*)E.pinned_buf(total);
+    for (const Part& p : parts)
+        if (p.bytes) std::memcpy(host + p.off, p.src, p.bytes);
+    ck(hipMemcpyAsync(dev, host, total, hipMemcpyHostToDevice, E.stream), "hipMemcpyAsync(H2D)");
+    return dev;
+}
+
 namespace {
 
 struct Node {
@@ -175,6 +192,8 @@ struct Node {
     std::vector<int> kids;
 };
 
+}  // namespace
+
 uint32_t buckets_for(uint64_t n) {
     uint64_t nb = (2 * n + LEAF_CAP - 1) / LEAF_CAP;
     if (nb < 2) nb = 2;
@@ -182,7 +201,27 @@ uint32_t buckets_for(uint64_t n) {
     return (uint32_t)nb;
 }
 
-}  // namespace
+void choose_splitters(Engine& E, Arena& A, const ColView& src, uint64_t n, uint32_t nb, uint64_t* dev_out,
+                      std::vector<uint64_t>& host_out) {
+    const uint64_t mark = A.off;
+    Region r;
+    r.src = src;
+    r.n = n;
+    r.out_pos = 0;
+    r.hist_base = 0;
+    r.nb = nb;
+    r.n_chunks = 0;
+    UpPack up;
+    up.add(&r, sizeof(r));
+    Region* d_r = (Region*)up.commit(E, A);
+    E.pbegin("k_sample");
+    launch_sample(d_r, 1, dev_out, E.stream);
+    E.pend(SAMPLE_N, SAMPLE_N * 8);
+    const uint64_t* h = (const uint64_t*)download_async(E, dev_out, (MAX_BUCKETS - 1) * sizeof(uint64_t));
+    E.sync();
+    host_out.assign(h, h + (MAX_BUCKETS - 1));
+    A.off = mark;
+}
 
 uint64_t sort_reduce_bytes(uint64_t rows, uint64_t n_inst, const Cols& k, bool state_rows) {
     const Layout L = state_rows ? state_layout(k) : raw_layout(k);
@@ -191,7 +230,8 @@ uint64_t sort_reduce_bytes(uint64_t rows, uint64_t n_inst, const Cols& k, bool s
 }
 
 std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instance>& inst,
-                                  const std::vector<Dest>& dests, const Cols& k, bool state_rows) {
+                                  const std::vector<Dest>& dests, const Cols& k, bool state_rows,
+                                  const SplitterHint* hint) {
     const Layout L = state_rows ? state_layout(k) : raw_layout(k);
     const Layout S = state_layout(k);
     // bytes of one source row as the caller's columns hold it
@@ -262,23 +302,38 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
             regs.push_back(r);
         }
         const uint64_t mark = A.off;
-        Region* d_regs = A.take_n<Region>(regs.size());
-        Chunk* d_chunks = A.take_n<Chunk>(chunks.size());
-        uint64_t* d_spl = A.take_n<uint64_t>(regs.size() * (MAX_BUCKETS - 1));
+        // one upload for the level's descriptors, one readback block for
+        // splitters and bucket starts
+        const bool fixed = hint && hint->dev && level == 0 && regs.size() == 1;
+        if (fixed) regs[0].nb = hint->nb;
+        if (fixed) {
+            // recompute the histogram layout for the hinted bucket count
+            hist_total = (uint64_t)regs[0].nb * regs[0].n_chunks;
+            bs_total = regs[0].nb + 1;
+        }
+        UpPack up;
+        const uint64_t o_regs = up.add(regs.data(), regs.size() * sizeof(Region));
+        const uint64_t o_chunks = up.add(chunks.data(), chunks.size() * sizeof(Chunk));
+        const uint64_t o_bsb = up.add(bsb.data(), bsb.size() * sizeof(uint64_t));
+        char* d_up = up.commit(E, A);
+        Region* d_regs = (Region*)(d_up + o_regs);
+        Chunk* d_chunks = (Chunk*)(d_up + o_chunks);
+        uint64_t* d_bsb = (uint64_t*)(d_up + o_bsb);
+        const uint64_t spl_words = regs.size() * (MAX_BUCKETS - 1);
+        uint64_t* d_rb = A.take_n<uint64_t>(spl_words + bs_total);
+        uint64_t* d_spl = fixed ? (uint64_t*)hint->dev : d_rb;
+        uint64_t* d_bstart = d_rb + spl_words;
         uint32_t* d_hist = A.take_n<uint32_t>(hist_total);
         uint64_t* d_offs = A.take_n<uint64_t>(hist_total + 1);
         uint64_t* d_tiles = A.take_n<uint64_t>(scan_tiles(hist_total) + 1);
-        uint64_t* d_bsb = A.take_n<uint64_t>(bsb.size());
-        uint64_t* d_bstart = A.take_n<uint64_t>(bs_total);
-        E.upload(d_regs, regs.data(), regs.size() * sizeof(Region));
-        E.upload(d_chunks, chunks.data(), chunks.size() * sizeof(Chunk));
-        E.upload(d_bsb, bsb.data(), bsb.size() * sizeof(uint64_t));
         uint64_t lvl_rows = 0;
         for (const Region& r : regs) lvl_rows += r.n;
         const uint64_t in_bytes = (uint64_t)(level == 0 ? src_row_bytes : L.words * 8);
-        E.pbegin("k_sample");
-        launch_sample(d_regs, (uint32_t)regs.size(), d_spl, E.stream);
-        E.pend(regs.size() * (uint64_t)SAMPLE_N, regs.size() * (uint64_t)SAMPLE_N * 8);
+        if (!fixed) {
+            E.pbegin("k_sample");
+            launch_sample(d_regs, (uint32_t)regs.size(), d_spl, E.stream);
+            E.pend(regs.size() * (uint64_t)SAMPLE_N, regs.size() * (uint64_t)SAMPLE_N * 8);
+        }
         E.pbegin("k_hist");
         launch_hist(d_regs, d_chunks, (uint32_t)chunks.size(), d_spl, d_hist, E.stream);
         E.pend(lvl_rows, lvl_rows * 8);
@@ -290,12 +345,13 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
         E.pend(lvl_rows, lvl_rows * in_bytes);
         launch_bucket_starts(d_regs, (uint32_t)regs.size(), d_offs, d_bsb, d_bstart, E.stream);
         ck(hipGetLastError(), "partition launch");
-        const uint64_t* h_bs = (const uint64_t*)download_async(E, d_bstart, bs_total * sizeof(uint64_t));
-        const uint64_t* h_sp =
-            (const uint64_t*)download_async(E, d_spl, regs.size() * (MAX_BUCKETS - 1) * sizeof(uint64_t));
+        const uint64_t* h_rb = (const uint64_t*)download_async(E, fixed ? d_bstart : d_rb,
+                                                               ((fixed ? 0 : spl_words) + bs_total) * sizeof(uint64_t));
         E.sync();
+        const uint64_t* h_bs = fixed ? h_rb : h_rb + spl_words;
+        const uint64_t* h_sp = fixed ? hint->host : h_rb;
         std::vector<uint64_t> bstart(h_bs, h_bs + bs_total);
-        std::vector<uint64_t> spl(h_sp, h_sp + regs.size() * (MAX_BUCKETS - 1));
+        std::vector<uint64_t> spl(h_sp, h_sp + spl_words);
         A.off = mark;
         std::vector<int> next;
         for (size_t ri = 0; ri < pending.size(); ++ri) {
@@ -382,21 +438,23 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
     while (cur_dest < dests.size()) first_seg[++cur_dest] = (uint32_t)leaves.size();
 
     const uint64_t nl = leaves.size();
-    Leaf* d_leaves = A.take_n<Leaf>(nl);
-    Segment* d_segs = A.take_n<Segment>(nl);
+    UpPack up;
+    const uint64_t o_leaves = up.add(leaves.data(), nl * sizeof(Leaf));
+    const uint64_t o_segs = up.add(segs.data(), nl * sizeof(Segment));
+    const uint64_t o_first = up.add(first_seg.data(), first_seg.size() * sizeof(uint32_t));
+    const uint64_t o_dests = up.add(dests.data(), dests.size() * sizeof(Dest));
+    const uint64_t o_pieces = up.add(pieces.data(), pieces.size() * sizeof(SinglePiece));
+    char* d_up = up.commit(E, A);
+    Leaf* d_leaves = (Leaf*)(d_up + o_leaves);
+    Segment* d_segs = (Segment*)(d_up + o_segs);
+    uint32_t* d_first = (uint32_t*)(d_up + o_first);
+    Dest* d_dests = (Dest*)(d_up + o_dests);
+    SinglePiece* d_pieces = pieces.empty() ? nullptr : (SinglePiece*)(d_up + o_pieces);
     uint32_t* d_counts = A.take_n<uint32_t>(nl);
     uint64_t* d_offs = A.take_n<uint64_t>(nl + 1);
     uint64_t* d_tiles = A.take_n<uint64_t>(scan_tiles(nl) + 1);
-    uint32_t* d_first = A.take_n<uint32_t>(first_seg.size());
-    Dest* d_dests = A.take_n<Dest>(dests.size());
     uint64_t* d_totals = A.take_n<uint64_t>(dests.size());
-    SinglePiece* d_pieces = pieces.empty() ? nullptr : A.take_n<SinglePiece>(pieces.size());
     void* d_partials = pieces.empty() ? nullptr : A.take(pieces.size() * single_partial_bytes());
-    E.upload(d_leaves, leaves.data(), nl * sizeof(Leaf));
-    E.upload(d_segs, segs.data(), nl * sizeof(Segment));
-    E.upload(d_first, first_seg.data(), first_seg.size() * sizeof(uint32_t));
-    E.upload(d_dests, dests.data(), dests.size() * sizeof(Dest));
-    if (!pieces.empty()) E.upload(d_pieces, pieces.data(), pieces.size() * sizeof(SinglePiece));
     const OutView tout = aos_out(temp, S);
     uint64_t sort_rows = 0, single_rows = 0;
     for (const Leaf& lf : leaves) (lf.kind == 0 ? sort_rows : single_rows) += lf.n;

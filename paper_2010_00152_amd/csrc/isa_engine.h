@@ -107,11 +107,38 @@ struct Instance {
     uint32_t dest;  // index into the dest list
 };
 
+// Splitters chosen once for a whole input and reused for each of its batches:
+// 255 entries (padded with UINT64_MAX), on the device and on the host.
+struct SplitterHint {
+    const uint64_t* dev = nullptr;
+    const uint64_t* host = nullptr;
+    uint32_t nb = 0;
+};
+
+// Collects several host arrays into one pinned staging block and uploads them
+// with a single copy into one workspace block.
+struct UpPack {
+    struct Part {
+        const void* src;
+        uint64_t bytes, off;
+    };
+    std::vector<Part> parts;
+    uint64_t total = 0;
+    uint64_t add(const void* src, uint64_t bytes);  // returns the part's offset
+    char* commit(Engine& E, Arena& A);              // device base of the block
+};
+
+// Choose splitters for `src` (n rows) with nb buckets from a sample of its keys.
+void choose_splitters(Engine& E, Arena& A, const ColView& src, uint64_t n, uint32_t nb, uint64_t* dev_out,
+                      std::vector<uint64_t>& host_out);
+
 // Sort and reduce every instance: the sorted unique state rows of instance i
 // are appended, in instance order, to dests[instance.dest].  Returns the
 // number of groups written (or required) per dest.
 std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instance>& inst,
-                                  const std::vector<Dest>& dests, const Cols& k, bool state_rows);
+                                  const std::vector<Dest>& dests, const Cols& k, bool state_rows,
+                                  const SplitterHint* hint = nullptr);
+uint32_t buckets_for(uint64_t n);
 
 // Device-to-host copy into pinned staging; valid after the next sync().
 const void* download_async(Engine& E, const void* dev, uint64_t bytes);

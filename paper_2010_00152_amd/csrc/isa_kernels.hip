@@ -851,6 +851,65 @@ __global__ void k_inst_totals(const uint64_t* __restrict__ offs, const uint32_t*
     if (i < n_inst) totals[i] = offs[first_seg[i + 1]] - offs[first_seg[i]];
 }
 
+
+// ---------------------------------------------------------------------------
+// Composite keys (A int32, B int32): an order-preserving normalized key
+// (Section 2.4: normalized keys compare as binary strings).  Flipping the sign
+// bit maps signed order onto unsigned order.
+// ---------------------------------------------------------------------------
+
+__global__ void k_pack_pairs(const int32_t* __restrict__ a, const int32_t* __restrict__ b, uint64_t n,
+                             uint64_t* __restrict__ keys) {
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+        keys[i] = ((uint64_t)((uint32_t)a[i] ^ 0x80000000u) << 32) | (uint64_t)((uint32_t)b[i] ^ 0x80000000u);
+}
+
+__global__ void k_unpack_pairs(const uint64_t* __restrict__ keys, uint64_t n, int32_t* __restrict__ a,
+                               int32_t* __restrict__ b) {
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        const uint64_t k = keys[i];
+        a[i] = (int32_t)((uint32_t)(k >> 32) ^ 0x80000000u);
+        b[i] = (int32_t)((uint32_t)k ^ 0x80000000u);
+    }
+}
+
+// Segment starts of a non-decreasing column: counts per chunk; *bad is set
+// when a decreasing step is seen.
+__global__ void __launch_bounds__(256) k_seg_count(const int32_t* __restrict__ a, uint64_t n, uint32_t chunk,
+                                                   uint32_t* __restrict__ counts, uint32_t* __restrict__ bad) {
+    __shared__ uint32_t s_tmp[256 / 64 + 1];
+    const uint64_t c0 = (uint64_t)blockIdx.x * chunk;
+    const uint64_t c1 = c0 + chunk < n ? c0 + chunk : n;
+    uint32_t c = 0, b = 0;
+    for (uint64_t i = c0 + threadIdx.x; i < c1; i += 256) {
+        if (i == 0 || a[i] != a[i - 1]) ++c;
+        if (i > 0 && a[i] < a[i - 1]) b = 1;
+    }
+    uint32_t tot;
+    block_exclusive_scan<256>(c, s_tmp, tot);
+    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+    if (b) atomicOr(bad, 1u);
+}
+
+__global__ void __launch_bounds__(256) k_seg_write(const int32_t* __restrict__ a, uint64_t n, uint32_t chunk,
+                                                   const uint64_t* __restrict__ offs, uint64_t* __restrict__ starts) {
+    __shared__ uint32_t s_tmp[256 / 64 + 1];
+    const uint64_t c0 = (uint64_t)blockIdx.x * chunk;
+    const uint64_t c1 = c0 + chunk < n ? c0 + chunk : n;
+    // thread t scans a contiguous sub-range so that starts come out in order
+    const uint64_t per = (chunk + 255) / 256;
+    const uint64_t t0 = c0 + threadIdx.x * per;
+    const uint64_t t1 = t0 + per < c1 ? t0 + per : c1;
+    uint32_t c = 0;
+    for (uint64_t i = t0; i < t1; ++i)
+        if (i == 0 || a[i] != a[i - 1]) ++c;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<256>(c, s_tmp, tot);
+    uint64_t o = offs[blockIdx.x] + ex;
+    for (uint64_t i = t0; i < t1; ++i)
+        if (i == 0 || a[i] != a[i - 1]) starts[o++] = i;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch wrappers
 // ---------------------------------------------------------------------------
@@ -914,6 +973,31 @@ void launch_compact(const Segment* segs, uint32_t n_segs, const uint32_t* counts
                     const uint32_t* first_seg, const Dest* dests, ColView temp, hipStream_t st) {
     if (n_segs == 0) return;
     hipLaunchKernelGGL(k_compact, dim3(n_segs), dim3(256), 0, st, segs, counts, offs, first_seg, dests, temp);
+}
+static dim3 grid_rows(uint64_t n) {
+    uint64_t g = (n + 255) / 256;
+    if (g > 16384) g = 16384;
+    return dim3((uint32_t)(g ? g : 1));
+}
+void launch_pack_pairs(const int32_t* a, const int32_t* b, uint64_t n, uint64_t* keys, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_pack_pairs, grid_rows(n), dim3(256), 0, st, a, b, n, keys);
+}
+void launch_unpack_pairs(const uint64_t* keys, uint64_t n, int32_t* a, int32_t* b, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_unpack_pairs, grid_rows(n), dim3(256), 0, st, keys, n, a, b);
+}
+void launch_seg_count(const int32_t* a, uint64_t n, uint32_t chunk, uint32_t* counts, uint32_t* bad,
+                      hipStream_t st) {
+    const uint64_t g = (n + chunk - 1) / chunk;
+    if (!g) return;
+    hipLaunchKernelGGL(k_seg_count, dim3((uint32_t)g), dim3(256), 0, st, a, n, chunk, counts, bad);
+}
+void launch_seg_write(const int32_t* a, uint64_t n, uint32_t chunk, const uint64_t* offs, uint64_t* starts,
+                      hipStream_t st) {
+    const uint64_t g = (n + chunk - 1) / chunk;
+    if (!g) return;
+    hipLaunchKernelGGL(k_seg_write, dim3((uint32_t)g), dim3(256), 0, st, a, n, chunk, offs, starts);
 }
 void launch_inst_totals(const uint64_t* offs, const uint32_t* first_seg, uint32_t n_inst, uint64_t* totals,
                         hipStream_t st) {

@@ -1,0 +1,126 @@
+"""GPU parity of the segmented, batched and served forms against the CPU
+oracle, and equality of each instance's result alone and in a batch."""
+import time
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+import paper_2010_00152_amd as isa
+from tests.gpu_util import FP64_REL, compare, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = isa.Context(0)
+    yield c
+    c.close()
+
+
+def np_out(res):
+    out = {}
+    for k, t in res.items():
+        dt = {"keys": np.uint64, "count": np.uint64, "sum_f64": np.float64, "a": np.int32,
+              "b": np.int32}.get(k, np.int64)
+        out[k] = to_np(t, dt)
+    return out
+
+
+@pytest.mark.parametrize("n,n_a,b_per_a,budget_mib", [(300_000, 40, 3_000, 64), (2_000_000, 1000, 100_000, 64),
+                                                      (3_000_000, 7, 400_000, 256)])
+def test_segmented_matches_pair_oracle(ctx, n, n_a, b_per_a, budget_mib):
+    say("case segmented n=%d n_a=%d" % (n, n_a))
+    a, b, v = datagen.segmented_input(5, n, n_a, b_per_a)
+    res, status, g = isa.group_by_segmented(ctx, to_dev(a), to_dev(b), to_dev(v), aggs=isa.ISA_INT_AGGS,
+                                            mem_budget=budget_mib << 20)
+    got = np_out(res)
+    ref = oracle.group_by_pairs(a, b, v)
+    assert g == ref["a"].shape[0]
+    for c in ["a", "b", "count", "sum_i64", "min_i64", "max_i64"]:
+        assert np.array_equal(got[c], ref[c]), c
+
+
+def test_segmented_rejects_unsorted_prefix(ctx):
+    say("case segmented unsorted")
+    a = np.array([1, 2, 1, 3] * 1000, np.int32)
+    b = np.arange(4000, dtype=np.int32)
+    v = np.zeros(4000, np.int64)
+    with pytest.raises(isa.InsortError) as e:
+        isa.group_by_segmented(ctx, to_dev(a), to_dev(b), to_dev(v), mem_budget=32 << 20)
+    assert e.value.status == isa.ISA_EINVAL
+
+
+def batch_instances(seed, count, lo, hi):
+    rng = np.random.default_rng(seed)
+    rows = np.exp(rng.uniform(np.log(lo), np.log(hi), count)).round().astype(np.int64)
+    ratio = np.exp(rng.uniform(np.log(1e-4), 0.0, count))
+    insts = []
+    for i in range(count):
+        d = max(1, int(round(rows[i] * ratio[i])))
+        k, v, f = datagen.plain_input(datagen.substream_seed(seed, i), int(rows[i]), d, 0.0, with_f64=True)
+        insts.append((k, v, f))
+    return insts
+
+
+def test_batch_matches_oracle_and_alone(ctx):
+    say("case batch 300 instances")
+    insts = batch_instances(6, 300, 1_000, 100_000)
+    dev = [(to_dev(k), to_dev(v), to_dev(f)) for k, v, f in insts]
+    res, status = isa.batch_run(ctx, dev, aggs=isa.ISA_ALL, mem_budget=512 << 20)
+    for i, (k, v, f) in enumerate(insts):
+        compare(np_out(res[i]), k, v, f, isa.ISA_ALL, "inst %d" % i)
+    # alone: the same instance through the plain entry point gives identical integers
+    for i in [0, 7, 150, 299]:
+        k, v, f = insts[i]
+        alone, st, _, _ = isa.group_by(ctx, dev[i][0], dev[i][1], dev[i][2], aggs=isa.ISA_ALL, mem_budget=64 << 20)
+        a = np_out(alone)
+        b = np_out(res[i])
+        for c in ["keys", "count", "sum_i64", "min_i64", "max_i64"]:
+            assert np.array_equal(a[c], b[c]), (i, c)
+        absum = oracle.group_by(k, None, np.abs(f))["sum_f64"]
+        assert np.all(np.abs(a["sum_f64"] - b["sum_f64"]) <= 2 * FP64_REL * absum)
+
+
+def test_batch_waves_small_workspace(ctx):
+    # a workspace that holds only a few instances at a time: processed in waves
+    say("case batch waves")
+    insts = batch_instances(16, 40, 20_000, 200_000)
+    dev = [(to_dev(k), to_dev(v), None) for k, v, f in insts]
+    res, status = isa.batch_run(ctx, dev, aggs=isa.ISA_INT_AGGS, mem_budget=48 << 20)
+    for i, (k, v, f) in enumerate(insts):
+        compare(np_out(res[i]), k, v, None, isa.ISA_INT_AGGS, "inst %d" % i)
+
+
+def test_server_results_alone_and_in_the_mix(ctx):
+    say("case server")
+    import torch
+    insts = batch_instances(7, 60, 1_000, 300_000)
+    dev = [(to_dev(k), to_dev(v), to_dev(f)) for k, v, f in insts]
+    torch.cuda.synchronize()
+    srv = isa.Server(ctx, 1 << 30, slots=3)
+    tickets = []
+    for i, (k, v, f) in enumerate(dev):
+        tickets.append(srv.submit(k, v, f, aggs=isa.ISA_ALL))
+        if i % 7 == 0:
+            time.sleep(0.002)  # requests keep arriving while others run
+    srv.drain()
+    for i, t in enumerate(tickets):
+        done, lat, st = srv.poll(t)
+        assert done and st == isa.ISA_OK and lat > 0
+        k, v, f = insts[i]
+        compare(np_out(srv.result(t)), k, v, f, isa.ISA_ALL, "req %d" % i)
+    srv.close()
+
+
+def test_server_rejects_oversized_request(ctx):
+    say("case server oversized")
+    import torch
+    srv = isa.Server(ctx, 32 << 20, slots=1)
+    k = torch.zeros(2_000_000, dtype=torch.int64, device="cuda")
+    with pytest.raises(isa.InsortError) as e:
+        srv.submit(k, k, None, aggs=isa.ISA_INT_AGGS)
+    assert e.value.status == isa.ISA_ENOMEM
+    srv.close()
