@@ -101,7 +101,7 @@ constexpr uint64_t MERGE_MARGIN = 2u << 20;
 
 uint64_t merge_scratch_bytes(uint64_t rows) {
     const uint64_t parts = rows / MERGE_D + 2;
-    return parts * 4 + (parts + 1) * 8 + (scan_tiles(parts) + 1) * 8 + 4096;
+    return (parts + 3) * 8 + 512;
 }
 
 // Workspace used by run generation with batch Bt and index capacity K: two
@@ -414,9 +414,8 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             idx[1] = A.take_n<uint64_t>((p.capacity + p.batch_rows) * sw);
             uint64_t* brun = A.take_n<uint64_t>(p.batch_rows * sw);
             const uint64_t mscr_parts = merge_parts(p.capacity + p.batch_rows, p.batch_rows) + 1;
-            uint32_t* m_counts = A.take_n<uint32_t>(mscr_parts);
-            uint64_t* m_offs = A.take_n<uint64_t>(mscr_parts + 1);
-            uint64_t* m_tiles = A.take_n<uint64_t>(scan_tiles(mscr_parts) + 1);
+            // merge control block: [ticket, error], merged row count, per-partition status
+            uint64_t* m_ctl = A.take_n<uint64_t>(mscr_parts + 2);
             // splitters for every batch, chosen once from a sample of the whole
             // input (batches are slices of one input)
             uint64_t* d_gspl = A.take_n<uint64_t>(MAX_BUCKETS - 1);
@@ -456,20 +455,21 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 d.out = aos_out(brun, S);
                 const uint64_t g = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false, &hint)[0];
                 ++batches;
-                // absorb the batch's distinct keys into the index if they fit
+                // absorb the batch's distinct keys into the index if they fit:
+                // merge into the spare index buffer, keep the result only if
+                // it holds at most K keys
                 const ColView iv = aos_view(idx[cur], S), bv = aos_view(brun, S);
                 const uint64_t parts = merge_parts(n_idx, g);
-                E.pbegin("k_merge_count");
-                launch_merge_count(iv, n_idx, bv, g, m_counts, E.stream);
-                E.pend(n_idx + g, (n_idx + g) * 8);
-                launch_scan(m_counts, parts, m_tiles, m_offs, E.stream);
-                const uint64_t* h_m = (const uint64_t*)download_async(E, m_offs + parts, 8);
+                launch_fill(m_ctl, parts + 2, 0, E.stream);
+                E.pbegin("k_merge");
+                launch_merge(iv, n_idx, bv, g, aos_out(idx[cur ^ 1], S), m_ctl + 2, (uint32_t*)m_ctl, m_ctl + 1,
+                             E.stream);
+                E.pend(n_idx + g, (n_idx + g) * sw * 8);
+                const uint64_t* h_m = (const uint64_t*)download_async(E, m_ctl, 16);
                 E.sync();
-                const uint64_t m = *h_m;
+                if (h_m[0] >> 32) throw Fail{ISA_EDEVICE, "merge placement wait timed out"};
+                const uint64_t m = h_m[1];
                 if (m <= p.capacity) {
-                    E.pbegin("k_merge_write");
-                    launch_merge_write(iv, n_idx, bv, g, m_offs, aos_out(idx[cur ^ 1], S), E.stream);
-                    E.pend(n_idx + g, (n_idx + g + m) * sw * 8);
                     cur ^= 1;
                     n_idx = m;
                 } else {

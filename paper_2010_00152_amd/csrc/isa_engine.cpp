@@ -226,7 +226,8 @@ void choose_splitters(Engine& E, Arena& A, const ColView& src, uint64_t n, uint3
 uint64_t sort_reduce_bytes(uint64_t rows, uint64_t n_inst, const Cols& k, bool state_rows) {
     const Layout L = state_rows ? state_layout(k) : raw_layout(k);
     const Layout S = state_layout(k);
-    return rows * (uint64_t)(2 * L.words + S.words) * 8 + rows * 4 + n_inst * 4608 + (4u << 20);
+    (void)S;
+    return rows * (uint64_t)(2 * L.words) * 8 + rows * 4 + n_inst * 4608 + (4u << 20);
 }
 
 std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instance>& inst,
@@ -262,7 +263,6 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
 
     uint64_t* P[2] = {nullptr, nullptr};
     if (need_part) P[0] = A.take_n<uint64_t>(N * (uint64_t)L.words);
-    uint64_t* temp = A.take_n<uint64_t>(N * (uint64_t)S.words);
 
     std::vector<int> pending;
     for (int r : roots)
@@ -284,7 +284,11 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
             r.n = nd.n;
             r.out_pos = nd.pos;
             r.nb = buckets_for(nd.n);
-            r.n_chunks = (uint32_t)((nd.n + PART_CHUNK - 1) / PART_CHUNK);
+            // chunk rows: one sub-tile for small regions (more workgroups),
+            // up to four sub-tiles for large ones
+            uint64_t crow = (nd.n / 512 + PART_TILE - 1) / PART_TILE * PART_TILE;
+            crow = std::max<uint64_t>(PART_TILE, std::min<uint64_t>(PART_CHUNK, crow));
+            r.n_chunks = (uint32_t)((nd.n + crow - 1) / crow);
             r.hist_base = hist_total;
             hist_total += (uint64_t)r.nb * r.n_chunks;
             bsb.push_back(bs_total);
@@ -293,9 +297,9 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
                 Chunk ch;
                 ch.region = (uint32_t)regs.size();
                 ch.idx = c;
-                ch.start = (uint64_t)c * PART_CHUNK;
+                ch.start = (uint64_t)c * crow;
                 const uint64_t left = nd.n - ch.start;
-                ch.n = (uint32_t)(left < (uint64_t)PART_CHUNK ? left : (uint64_t)PART_CHUNK);
+                ch.n = (uint32_t)(left < crow ? left : crow);
                 ch.pad = 0;
                 chunks.push_back(ch);
             }
@@ -389,7 +393,7 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
 
     // Leaves in output order: instances in order, keys ascending within each.
     std::vector<Leaf> leaves;
-    std::vector<Segment> segs;
+    std::vector<uint32_t> leaf_dest;
     std::vector<SinglePiece> pieces;
     std::vector<uint32_t> first_seg(dests.size() + 1, 0);
     std::vector<int> stack;
@@ -427,12 +431,8 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
                 }
                 lf.single_count = (uint32_t)pieces.size() - lf.single_first;
             }
-            Segment sg;
-            sg.src_pos = nd.pos;
-            sg.inst = inst[i].dest;
-            sg.pad = 0;
             leaves.push_back(lf);
-            segs.push_back(sg);
+            leaf_dest.push_back(inst[i].dest);
         }
     }
     while (cur_dest < dests.size()) first_seg[++cur_dest] = (uint32_t)leaves.size();
@@ -440,43 +440,39 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
     const uint64_t nl = leaves.size();
     UpPack up;
     const uint64_t o_leaves = up.add(leaves.data(), nl * sizeof(Leaf));
-    const uint64_t o_segs = up.add(segs.data(), nl * sizeof(Segment));
+    const uint64_t o_ldest = up.add(leaf_dest.data(), nl * sizeof(uint32_t));
     const uint64_t o_first = up.add(first_seg.data(), first_seg.size() * sizeof(uint32_t));
     const uint64_t o_dests = up.add(dests.data(), dests.size() * sizeof(Dest));
     const uint64_t o_pieces = up.add(pieces.data(), pieces.size() * sizeof(SinglePiece));
     char* d_up = up.commit(E, A);
     Leaf* d_leaves = (Leaf*)(d_up + o_leaves);
-    Segment* d_segs = (Segment*)(d_up + o_segs);
+    uint32_t* d_ldest = (uint32_t*)(d_up + o_ldest);
     uint32_t* d_first = (uint32_t*)(d_up + o_first);
     Dest* d_dests = (Dest*)(d_up + o_dests);
     SinglePiece* d_pieces = pieces.empty() ? nullptr : (SinglePiece*)(d_up + o_pieces);
-    uint32_t* d_counts = A.take_n<uint32_t>(nl);
-    uint64_t* d_offs = A.take_n<uint64_t>(nl + 1);
-    uint64_t* d_tiles = A.take_n<uint64_t>(scan_tiles(nl) + 1);
-    uint64_t* d_totals = A.take_n<uint64_t>(dests.size());
+    // control block: [ticket, error] word, per-dest totals, per-leaf status
+    uint64_t* d_ctl = A.take_n<uint64_t>(1 + dests.size() + nl);
+    uint64_t* d_totals = d_ctl + 1;
+    uint64_t* d_status = d_totals + dests.size();
     void* d_partials = pieces.empty() ? nullptr : A.take(pieces.size() * single_partial_bytes());
-    const OutView tout = aos_out(temp, S);
+    launch_fill(d_ctl, 1 + dests.size() + nl, 0, E.stream);
     uint64_t sort_rows = 0, single_rows = 0;
     for (const Leaf& lf : leaves) (lf.kind == 0 ? sort_rows : single_rows) += lf.n;
     const uint64_t leaf_bytes = need_part ? (uint64_t)L.words * 8 : src_row_bytes;
-    E.pbegin("k_leaf");
-    launch_leaf(d_leaves, (uint32_t)nl, tout, d_counts, E.stream);
-    E.pend(sort_rows, sort_rows * leaf_bytes);
     if (!pieces.empty()) {
         E.pbegin("k_single");
-        launch_single(d_leaves, (uint32_t)nl, d_pieces, (uint32_t)pieces.size(), d_partials, tout, d_counts,
-                      E.stream);
+        launch_single_partial(d_leaves, d_pieces, (uint32_t)pieces.size(), d_partials, E.stream);
         E.pend(single_rows, single_rows * leaf_bytes);
     }
-    launch_scan(d_counts, nl, d_tiles, d_offs, E.stream);
-    E.pbegin("k_compact");
-    launch_compact(d_segs, (uint32_t)nl, d_counts, d_offs, d_first, d_dests, aos_view(temp, S), E.stream);
-    E.pend(0, 0);
-    launch_inst_totals(d_offs, d_first, (uint32_t)dests.size(), d_totals, E.stream);
+    E.pbegin("k_leaf");
+    launch_leaf(d_leaves, (uint32_t)nl, d_ldest, d_first, d_dests, d_partials, d_status, d_totals,
+                (uint32_t*)d_ctl, E.stream);
+    E.pend(sort_rows, sort_rows * leaf_bytes);
     ck(hipGetLastError(), "leaf launch");
-    const uint64_t* h_tot = (const uint64_t*)download_async(E, d_totals, dests.size() * sizeof(uint64_t));
+    const uint64_t* h_ctl = (const uint64_t*)download_async(E, d_ctl, (1 + dests.size()) * sizeof(uint64_t));
     E.sync();
-    for (size_t d = 0; d < dests.size(); ++d) totals[d] = h_tot[d];
+    if (h_ctl[0] >> 32) throw Fail{ISA_EDEVICE, "leaf placement wait timed out"};
+    for (size_t d = 0; d < dests.size(); ++d) totals[d] = h_ctl[1 + d];
     return totals;
 }
 

@@ -19,21 +19,19 @@ void launch_scatter(const Region* regions, const Chunk* chunks, uint32_t n_chunk
                     const uint64_t* offs, uint64_t* dst, Layout L, hipStream_t st);
 void launch_bucket_starts(const Region* regions, uint32_t n_regions, const uint64_t* offs, const uint64_t* bs_base,
                           uint64_t* bstart, hipStream_t st);
-void launch_leaf(const Leaf* leaves, uint32_t n_leaves, OutView temp, uint32_t* counts, hipStream_t st);
-void launch_single(const Leaf* leaves, uint32_t n_leaves, const SinglePiece* pieces, uint32_t n_pieces,
-                   void* partials, OutView temp, uint32_t* counts, hipStream_t st);
+void launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st);
+void launch_leaf(const Leaf* leaves, uint32_t n_leaves, const uint32_t* leaf_dest, const uint32_t* first_seg,
+                 const Dest* dests, const void* partials, uint64_t* status, uint64_t* totals, uint32_t* ctl,
+                 hipStream_t st);
+void launch_single_partial(const Leaf* leaves, const SinglePiece* pieces, uint32_t n_pieces, void* partials,
+                           hipStream_t st);
 size_t single_partial_bytes();
 uint64_t merge_parts(uint64_t na, uint64_t nb);
-void launch_merge_count(ColView A, uint64_t na, ColView B, uint64_t nb, uint32_t* counts, hipStream_t st);
-void launch_merge_write(ColView A, uint64_t na, ColView B, uint64_t nb, const uint64_t* offs, OutView out,
-                        hipStream_t st);
+void launch_merge(ColView A, uint64_t na, ColView B, uint64_t nb, OutView out, uint64_t* status, uint32_t* ctl,
+                  uint64_t* total_out, hipStream_t st);
 void launch_copy_rows(ColView src, uint64_t n, OutView dst, uint64_t cap, hipStream_t st);
 uint64_t scan_tiles(uint64_t n);
 void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* offs, hipStream_t st);
-void launch_compact(const Segment* segs, uint32_t n_segs, const uint32_t* counts, const uint64_t* offs,
-                    const uint32_t* first_seg, const Dest* dests, ColView temp, hipStream_t st);
-void launch_inst_totals(const uint64_t* offs, const uint32_t* first_seg, uint32_t n_inst, uint64_t* totals,
-                        hipStream_t st);
 void launch_pack_pairs(const int32_t* a, const int32_t* b, uint64_t n, uint64_t* keys, hipStream_t st);
 void launch_unpack_pairs(const uint64_t* keys, uint64_t n, int32_t* a, int32_t* b, hipStream_t st);
 void launch_seg_count(const int32_t* a, uint64_t n, uint32_t chunk, uint32_t* counts, uint32_t* bad,

@@ -149,91 +149,120 @@ __device__ __forceinline__ uint64_t wave_match(uint32_t d, int dbits, uint64_t a
     return match;
 }
 
+__device__ __forceinline__ int pad16(int p) { return p + (p >> 4); }
+
 // ---------------------------------------------------------------------------
-// Block radix sort of NT*IPT (key, val) pairs held in registers in
-// warp-striped order (item j of lane l in wave w is logical item
-// w*64*IPT + j*64 + l).  Sorts on bits [0, nbits) of the keys, stably, eight
-// bits per pass.  Leaves the sorted pairs in s_key/s_val at position pad(p).
+// Block radix sort with per-thread digit counters.  Items are in registers,
+// thread t holding logical items t*IPT .. t*IPT+IPT-1.  Each pass ranks one
+// 5-bit digit: every thread counts its own items per digit in a private LDS
+// column (no conflicts between threads, order kept within a thread), one
+// block-wide scan over the counters in digit-major, thread-minor order gives
+// every (digit, thread) its base, and items move to base + local rank.  The
+// sort is stable, so passes go from the lowest digit up.  Sorted pairs end in
+// s.key/s.val at pad16(position).
 // ---------------------------------------------------------------------------
 
+constexpr int CNT_BITS = 5;
+constexpr int CNT_DIGITS = 1 << CNT_BITS;
+
 template <int NT, int IPT>
-struct SortSmem {
+struct CSortSmem {
     static constexpr int N = NT * IPT;
-    static constexpr int NP = N + N / 16;  // padded for conflict-light blocked reads
+    static constexpr int NP = N + N / 16;
     uint64_t key[NP];
-    uint32_t val[NP];
-    uint32_t cnt[(NT / 64) * 256];
-    uint32_t dbase[256];
+    uint16_t val[NP];
+    uint16_t cnt[CNT_DIGITS * NT];
     uint32_t tmp[NT / 64 + 1];
 };
 
-__device__ __forceinline__ int pad16(int p) { return p + (p >> 4); }
-
 template <int NT, int IPT>
-__device__ void block_radix_sort(uint64_t (&k)[IPT], uint32_t (&v)[IPT], int nbits,
-                                 SortSmem<NT, IPT>& s) {
-    static_assert(NT >= 256, "digit scan uses 256 threads");
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint64_t lt = (1ull << lane) - 1ull;
-    if (nbits <= 0) {
+__device__ void block_sort_cnt(uint64_t (&k)[IPT], uint16_t (&v)[IPT], int lo_bit, int hi_bit,
+                               CSortSmem<NT, IPT>& s) {
+    static_assert((CNT_DIGITS * NT * 2) % (16 * NT) == 0, "counter zeroing layout");
+    constexpr int ZERO4 = CNT_DIGITS * NT * 2 / 16 / NT;  // uint4 stores per thread
+    constexpr int SEG = CNT_DIGITS;                       // counters scanned per thread
+    const int tid = threadIdx.x;
+    if (lo_bit >= hi_bit) {
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            const int p = w * 64 * IPT + j * 64 + lane;
-            s.key[pad16(p)] = k[j];
-            s.val[pad16(p)] = v[j];
+            s.key[pad16(tid * IPT + j)] = k[j];
+            s.val[pad16(tid * IPT + j)] = v[j];
         }
         __syncthreads();
         return;
     }
-    for (int shift = 0; shift < nbits; shift += 8) {
-        const int dbits = (nbits - shift) < 8 ? (nbits - shift) : 8;
-        const uint32_t dmask = (1u << dbits) - 1u;
-        const bool last = shift + 8 >= nbits;
-        uint32_t* wc = s.cnt + w * 256;
-        for (int i = lane; i < 256; i += 64) wc[i] = 0;
-        uint32_t rank[IPT];
-        uint32_t dig[IPT];
+    uint4* c4 = reinterpret_cast<uint4*>(s.cnt);
+    for (int shift = lo_bit; shift < hi_bit; shift += CNT_BITS) {
+        const int dbits = hi_bit - shift < CNT_BITS ? hi_bit - shift : CNT_BITS;
+        const uint32_t mask = (1u << dbits) - 1u;
+        const bool last = shift + CNT_BITS >= hi_bit;
+#pragma unroll
+        for (int i = 0; i < ZERO4; ++i) c4[i * NT + tid] = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        uint16_t loc[IPT];
+        uint32_t dg[IPT];
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            const uint32_t d = (uint32_t)(k[j] >> shift) & dmask;
-            const uint64_t match = wave_match(d, dbits, ~0ull);
-            const uint32_t before = __popcll(match & lt);
-            const uint32_t base = wc[d];
-            if (before == 0) wc[d] = base + (uint32_t)__popcll(match);
-            rank[j] = base + before;
-            dig[j] = d;
+            const uint32_t d = (uint32_t)(k[j] >> shift) & mask;
+            dg[j] = d;
+            const uint16_t c = s.cnt[d * NT + tid];
+            loc[j] = c;
+            s.cnt[d * NT + tid] = (uint16_t)(c + 1);
         }
         __syncthreads();
-        uint32_t run = 0;
-        if (tid < 256) {
-            for (int ww = 0; ww < NT / 64; ++ww) {
-                const uint32_t c = s.cnt[ww * 256 + tid];
-                s.cnt[ww * 256 + tid] = run;
-                run += c;
-            }
+        // scan the counters in memory order (digit-major, thread-minor)
+        uint16_t seg[SEG];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < SEG; ++i) {
+            seg[i] = s.cnt[tid * SEG + i];
+            sum += seg[i];
         }
         uint32_t total;
-        const uint32_t excl = block_exclusive_scan<NT>(tid < 256 ? run : 0u, s.tmp, total);
-        if (tid < 256) s.dbase[tid] = excl;
+        uint32_t run = block_exclusive_scan<NT>(sum, s.tmp, total);
+#pragma unroll
+        for (int i = 0; i < SEG; ++i) {
+            s.cnt[tid * SEG + i] = (uint16_t)run;
+            run += seg[i];
+        }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            const int pos = (int)(s.dbase[dig[j]] + s.cnt[w * 256 + dig[j]] + rank[j]);
-            const int q = last ? pad16(pos) : pos;
-            s.key[q] = k[j];
-            s.val[q] = v[j];
+            const int pos = (int)s.cnt[dg[j] * NT + tid] + (int)loc[j];
+            s.key[pad16(pos)] = k[j];
+            s.val[pad16(pos)] = v[j];
         }
         __syncthreads();
         if (!last) {
 #pragma unroll
             for (int j = 0; j < IPT; ++j) {
-                const int p = w * 64 * IPT + j * 64 + lane;
-                k[j] = s.key[p];
-                v[j] = s.val[p];
+                k[j] = s.key[pad16(tid * IPT + j)];
+                v[j] = s.val[pad16(tid * IPT + j)];
             }
-            __syncthreads();
         }
     }
+}
+
+// Move items loaded warp-striped (coalesced: item j of lane l in wave w is row
+// w*64*IPT + j*64 + l) into blocked order (thread t holds rows t*IPT ..
+// t*IPT+IPT-1) through LDS, so the first sort pass sees rows in row order and
+// padding rows (beyond n) stay after every real row.
+template <int NT, int IPT>
+__device__ void striped_to_blocked(uint64_t (&k)[IPT], uint16_t (&v)[IPT], CSortSmem<NT, IPT>& s) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int q = w * 64 * IPT + j * 64 + lane;
+        s.key[pad16(q)] = k[j];
+        s.val[pad16(q)] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        k[j] = s.key[pad16(tid * IPT + j)];
+        v[j] = s.val[pad16(tid * IPT + j)];
+    }
+    __syncthreads();
 }
 
 // Block-wide min and max of uint64 values.
@@ -273,18 +302,18 @@ __device__ void block_minmax(uint64_t& mn, uint64_t& mx, uint64_t* s_tmp /* 2*NT
 __global__ void __launch_bounds__(LEAF_NT) k_sample(const Region* __restrict__ regions,
                                                     uint64_t* __restrict__ splitters) {
     constexpr int NT = LEAF_NT, IPT = LEAF_IPT;
-    __shared__ SortSmem<NT, IPT> s;
+    __shared__ CSortSmem<NT, IPT> s;
     __shared__ uint64_t s_mm[2 * NT / 64];
     const Region R = regions[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t S = R.n < (uint64_t)SAMPLE_N ? R.n : (uint64_t)SAMPLE_N;
     uint64_t k[IPT];
-    uint32_t v[IPT];
+    uint16_t v[IPT];
     uint64_t mn = ~0ull, mx = 0ull;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const uint64_t q = (uint64_t)(w * 64 * IPT + j * 64 + lane);
-        v[j] = (uint32_t)q;
+        v[j] = (uint16_t)q;
         if (q < S) {
             const uint64_t pos = (uint64_t)(((unsigned __int128)(2 * q + 1) * R.n) / (2 * S));
             k[j] = R.src.key[pos * R.src.stride];
@@ -301,7 +330,8 @@ __global__ void __launch_bounds__(LEAF_NT) k_sample(const Region* __restrict__ r
         const uint64_t q = (uint64_t)(w * 64 * IPT + j * 64 + lane);
         k[j] = q < S ? k[j] - mn : range;  // padding sorts last
     }
-    block_radix_sort<NT, IPT>(k, v, bit_length(range), s);
+    striped_to_blocked<NT, IPT>(k, v, s);
+    block_sort_cnt<NT, IPT>(k, v, 0, bit_length(range), s);
     __shared__ uint64_t s_spl[MAX_BUCKETS];
     const uint32_t nb = R.nb;
     if (tid < (int)nb - 1) {
@@ -450,128 +480,79 @@ __global__ void k_bucket_starts(const Region* __restrict__ regions, const uint64
 // temp buffer; counts[leaf] = number of groups.
 // ---------------------------------------------------------------------------
 
-struct LeafSmem {
-    SortSmem<LEAF_NT, LEAF_IPT> sort;
-    uint64_t mm[2 * LEAF_NT / 64];
-    uint64_t pre_cnt[LEAF_NT];
-    uint64_t pre_sum[LEAF_NT];
-    int64_t pre_mn[LEAF_NT];
-    int64_t pre_mx[LEAF_NT];
-    double pre_fs[LEAF_NT];
-    uint32_t pre_flags[LEAF_NT];  // bit0: thread has a head, bit1: thread has rows
-    uint32_t scan_tmp[LEAF_NT / 64 + 1];
-};
+// ---------------------------------------------------------------------------
+// Chained prefix over workgroups in ticket order (decoupled look-back): a
+// workgroup publishes its own count as soon as it is known, then sums its
+// predecessors' counts back to the nearest published inclusive prefix.
+// Tickets are taken at workgroup start, so every predecessor has already
+// started.  status[i] = 0 (not published), ST_AGG|count, or ST_PRE|inclusive.
+// A wait that exceeds LOOKBACK_SPINS sets *err and gives up, so every wait
+// ends; the host then reports the call as failed.
+// ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(LEAF_NT) k_leaf(const Leaf* __restrict__ leaves, OutView temp,
-                                                  uint32_t* __restrict__ counts) {
-    constexpr int NT = LEAF_NT, IPT = LEAF_IPT;
-    __shared__ LeafSmem s;
-    const Leaf Lf = leaves[blockIdx.x];
-    if (Lf.kind != 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t n = (uint32_t)Lf.n;
-    const ColView V = Lf.src;
-    uint64_t k[IPT];
-    uint32_t v[IPT];
-    uint64_t mn = ~0ull, mx = 0ull;
+constexpr uint64_t ST_AGG = 1ull << 62;
+constexpr uint64_t ST_PRE = 2ull << 62;
+constexpr uint64_t ST_VAL = (1ull << 62) - 1;
+constexpr uint32_t LOOKBACK_SPINS = 1u << 22;
+
+// Status words are the only data one workgroup reads from another here, so
+// relaxed device-scope atomics suffice (coherent across the chip without the
+// cache writeback/invalidate that release/acquire ordering would add).
+__device__ __forceinline__ void st_publish(uint64_t* p, uint64_t w) {
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t st_read(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
 #pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const uint32_t q = (uint32_t)(w * 64 * IPT + j * 64 + lane);
-        v[j] = q;
-        if (q < n) {
-            k[j] = V.key[(uint64_t)q * V.stride];
-            mn = k[j] < mn ? k[j] : mn;
-            mx = k[j] > mx ? k[j] : mx;
-        } else {
-            k[j] = 0;
-        }
-    }
-    block_minmax<NT>(mn, mx, s.mm);
-    const uint64_t range = mx - mn;
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const uint32_t q = (uint32_t)(w * 64 * IPT + j * 64 + lane);
-        k[j] = q < n ? k[j] - mn : range;
-    }
-    block_radix_sort<NT, IPT>(k, v, bit_length(range), s.sort);
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
 
-    // Blocked arrangement: thread t owns sorted positions [t*IPT, t*IPT+IPT).
-    const int p0 = tid * IPT;
-    uint32_t nheads = 0;
-    {
-        uint64_t prev = p0 > 0 ? s.sort.key[pad16(p0 - 1)] : 0;
-        for (int j = 0; j < IPT; ++j) {
-            const int p = p0 + j;
-            if (p >= (int)n) break;
-            const uint64_t kk = s.sort.key[pad16(p)];
-            if (p == 0 || kk != prev) ++nheads;
-            prev = kk;
-        }
+// Called by all 64 lanes of one wave (i and first uniform).  Returns the
+// exclusive prefix of item i over items first..i-1 and publishes the
+// inclusive prefix of item i.  The wave reads 64 predecessors' status words
+// at a time and sums back to the nearest published inclusive prefix.
+__device__ uint64_t chained_prefix(uint64_t* status, uint32_t i, uint32_t first, uint64_t count, uint32_t* err) {
+    const int lane = threadIdx.x & 63;
+    if (i == first) {
+        if (lane == 0) st_publish(&status[i], ST_PRE | count);
+        return 0;
     }
-    uint32_t total;
-    const uint32_t obase = block_exclusive_scan<NT>(nheads, s.scan_tmp, total);
-
-    Agg acc;
-    empty_agg(acc);
-    bool have_head = false;
-    uint32_t h = 0;
-    uint64_t prev = p0 > 0 ? s.sort.key[pad16(p0 - 1)] : 0;
-    int nrows = 0;
-    for (int j = 0; j < IPT; ++j) {
-        const int p = p0 + j;
-        if (p >= (int)n) break;
-        ++nrows;
-        const uint64_t kk = s.sort.key[pad16(p)];
-        const uint32_t row = s.sort.val[pad16(p)];
-        Agg r;
-        r.key = kk + mn;
-        load_payload(V, row, r);
-        const bool head = (p == 0) || (kk != prev);
-        prev = kk;
-        if (head) {
-            if (!have_head) {
-                s.pre_cnt[tid] = acc.cnt;
-                s.pre_sum[tid] = acc.sum;
-                s.pre_mn[tid] = acc.mn;
-                s.pre_mx[tid] = acc.mx;
-                s.pre_fs[tid] = acc.fs;
-                have_head = true;
-            } else {
-                store_agg(temp, Lf.out_pos + obase + h - 1, acc);
+    if (lane == 0) st_publish(&status[i], ST_AGG | count);
+    uint64_t sum = 0;
+    int64_t top = (int64_t)i - 1;
+    uint32_t spins = 0;
+    for (;;) {
+        const int64_t j = top - lane;
+        // items before `first` read as an inclusive prefix of zero
+        const uint64_t w = j >= (int64_t)first ? st_read(&status[j]) : ST_PRE;
+        const uint32_t flag = (uint32_t)(w >> 62);
+        const uint64_t pre_mask = __ballot(flag == 2);
+        const uint64_t zero_mask = __ballot(flag == 0);
+        const int nearest = pre_mask ? __ffsll((long long)pre_mask) - 1 : 64;
+        const uint64_t needed = nearest >= 63 ? ~0ull : ((1ull << (nearest + 1)) - 1ull);
+        if (zero_mask & needed) {
+            if (++spins >= LOOKBACK_SPINS) {
+                if (lane == 0) atomicOr(err, 1u);
+                break;
             }
-            acc = r;
-            ++h;
-        } else {
-            combine(acc, r);
+            __builtin_amdgcn_s_sleep(1);
+            continue;
         }
+        sum += wave_sum_u64(lane <= nearest ? (w & ST_VAL) : 0);
+        if (nearest < 64) break;
+        top -= 64;
     }
-    if (!have_head) {
-        s.pre_cnt[tid] = acc.cnt;
-        s.pre_sum[tid] = acc.sum;
-        s.pre_mn[tid] = acc.mn;
-        s.pre_mx[tid] = acc.mx;
-        s.pre_fs[tid] = acc.fs;
-    }
-    s.pre_flags[tid] = (have_head ? 1u : 0u) | (nrows > 0 ? 2u : 0u);
-    __syncthreads();
-    if (have_head) {
-        // the last group of this thread continues into following threads up
-        // to the next thread that starts a group
-        for (int u = tid + 1; u < NT; ++u) {
-            const uint32_t f = s.pre_flags[u];
-            if (!(f & 2u)) break;
-            Agg b;
-            b.cnt = s.pre_cnt[u];
-            b.sum = s.pre_sum[u];
-            b.mn = s.pre_mn[u];
-            b.mx = s.pre_mx[u];
-            b.fs = s.pre_fs[u];
-            combine(acc, b);
-            if (f & 1u) break;
-        }
-        store_agg(temp, Lf.out_pos + obase + h - 1, acc);
-    }
-    if (tid == 0) counts[blockIdx.x] = total;
+    if (lane == 0) st_publish(&status[i], ST_PRE | (sum + count));
+    return sum;
+}
+
+__global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t value) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
 }
 
 // ---------------------------------------------------------------------------
@@ -612,21 +593,212 @@ __global__ void __launch_bounds__(256) k_single_partial(const Leaf* __restrict__
     }
 }
 
-__global__ void __launch_bounds__(256) k_single_final(const Leaf* __restrict__ leaves,
-                                                      const Agg* __restrict__ partials, OutView temp,
-                                                      uint32_t* __restrict__ counts) {
-    __shared__ Agg s_agg[256];
-    const Leaf Lf = leaves[blockIdx.x];
-    if (Lf.kind != 1) return;
-    Agg a;
-    empty_agg(a);
-    for (uint32_t i = threadIdx.x; i < Lf.single_count; i += 256) combine(a, partials[Lf.single_first + i]);
-    block_reduce_agg<256>(a, s_agg);
-    if (threadIdx.x == 0) {
-        a.key = partials[Lf.single_first].key;
-        store_agg(temp, Lf.out_pos, a);
-        counts[blockIdx.x] = 1;
+// ---------------------------------------------------------------------------
+// Leaf sort-reduce with direct placement: one workgroup per key range.  Leaves
+// are taken in ticket order, which is their key order within each
+// destination; a leaf's groups go straight to its destination at the chained
+// prefix of the group counts of the destination's earlier leaves.
+// Kind 0: at most LEAF_CAP rows, loaded, sorted in LDS (ordered on their top
+// LEAF_TRUNC bits relative to the leaf minimum, re-sorted on all bits if two
+// distinct keys share those bits) and reduced.  Kind 1: a single key, whose
+// pieces were reduced by k_single_partial; combined here with a fixed tree.
+// ---------------------------------------------------------------------------
+
+struct LeafSmem {
+    CSortSmem<LEAF_NT, LEAF_IPT> sort;
+    uint64_t mm[2 * LEAF_NT / 64];
+    uint64_t pre_cnt[LEAF_NT];
+    uint64_t pre_sum[LEAF_NT];
+    int64_t pre_mn[LEAF_NT];
+    int64_t pre_mx[LEAF_NT];
+    double pre_fs[LEAF_NT];
+    uint32_t pre_flags[LEAF_NT];  // bit0: thread has a head, bit1: thread has rows
+    uint32_t scan_tmp[LEAF_NT / 64 + 1];
+};
+
+constexpr int LEAF_TRUNC = 30;
+constexpr int LEAF_ROUND = 8;  // payload loads issued together
+
+__global__ void __launch_bounds__(LEAF_NT) k_leaf(const Leaf* __restrict__ leaves,
+                                                  const uint32_t* __restrict__ leaf_dest,
+                                                  const uint32_t* __restrict__ first_seg,
+                                                  const Dest* __restrict__ dests, const Agg* __restrict__ partials,
+                                                  uint64_t* __restrict__ status, uint64_t* __restrict__ totals,
+                                                  uint32_t* __restrict__ ctl) {
+    constexpr int NT = LEAF_NT, IPT = LEAF_IPT;
+    __shared__ LeafSmem s;
+    __shared__ uint32_t s_li;
+    __shared__ uint64_t s_pre;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_li = atomicAdd(&ctl[0], 1u);
+    __syncthreads();
+    const uint32_t li = s_li;
+    const Leaf Lf = leaves[li];
+    const uint32_t d = leaf_dest[li];
+    const Dest D = dests[d];
+    const uint32_t first = first_seg[d], last = first_seg[d + 1] - 1;
+
+    if (Lf.kind == 1) {
+        if (w == 0) {
+            const uint64_t pre = chained_prefix(status, li, first, 1, &ctl[1]);
+            if (lane == 0) s_pre = pre;
+        }
+        Agg a;
+        empty_agg(a);
+        for (uint32_t i = tid; i < Lf.single_count; i += NT) combine(a, partials[Lf.single_first + i]);
+        Agg* red = reinterpret_cast<Agg*>(s.sort.key);  // NT*48 bytes fit the key array
+        block_reduce_agg<NT>(a, red);
+        if (tid == 0) {
+            a.key = partials[Lf.single_first].key;
+            const uint64_t pos = s_pre;
+            if (pos < D.capacity) store_agg(D.out, pos, a);
+            if (li == last) totals[d] = pos + 1;
+        }
+        return;
     }
+
+    const uint32_t n = (uint32_t)Lf.n;
+    const ColView V = Lf.src;
+    uint64_t k[IPT];
+    uint16_t v[IPT];
+    uint64_t mn = ~0ull, mx = 0ull;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        // coalesced loads, moved to blocked order before sorting
+        const uint32_t q = (uint32_t)(w * 64 * IPT + j * 64 + lane);
+        v[j] = (uint16_t)q;
+        if (q < n) {
+            k[j] = V.key[(uint64_t)q * V.stride];
+            mn = k[j] < mn ? k[j] : mn;
+            mx = k[j] > mx ? k[j] : mx;
+        } else {
+            k[j] = 0;
+        }
+    }
+    block_minmax<NT>(mn, mx, s.mm);
+    const uint64_t range = mx - mn;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t q = (uint32_t)(w * 64 * IPT + j * 64 + lane);
+        k[j] = q < n ? k[j] - mn : range;  // padding sorts last
+    }
+    const int nbits = bit_length(range);
+    const int lo_bit = nbits > LEAF_TRUNC ? nbits - LEAF_TRUNC : 0;
+    striped_to_blocked<NT, IPT>(k, v, s.sort);
+    block_sort_cnt<NT, IPT>(k, v, lo_bit, nbits, s.sort);
+    if (lo_bit > 0) {
+        bool clash = false;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const int p = tid * IPT + j;
+            if (p > 0 && p < (int)n) {
+                const uint64_t a = s.sort.key[pad16(p - 1)], b = s.sort.key[pad16(p)];
+                clash |= (a != b) && ((a >> lo_bit) == (b >> lo_bit));
+            }
+        }
+        if (__syncthreads_or(clash)) {
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+                k[j] = s.sort.key[pad16(tid * IPT + j)];
+                v[j] = s.sort.val[pad16(tid * IPT + j)];
+            }
+            __syncthreads();
+            block_sort_cnt<NT, IPT>(k, v, 0, nbits, s.sort);
+        }
+    }
+
+    // Blocked arrangement: thread t owns sorted positions [t*IPT, t*IPT+IPT).
+    const int p0 = tid * IPT;
+    uint64_t kk[IPT];
+    uint16_t rw[IPT];
+    uint32_t heads = 0;  // bit j: position p0+j starts a group
+    int nrows = 0;
+    {
+        uint64_t prev = p0 > 0 ? s.sort.key[pad16(p0 - 1)] : 0;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            const int p = p0 + j;
+            kk[j] = s.sort.key[pad16(p)];
+            rw[j] = s.sort.val[pad16(p)];
+            if (p < (int)n) {
+                ++nrows;
+                if (p == 0 || kk[j] != prev) heads |= 1u << j;
+            }
+            prev = kk[j];
+        }
+    }
+    const uint32_t nheads = __popc(heads);
+    uint32_t total;
+    const uint32_t obase = block_exclusive_scan<NT>(nheads, s.scan_tmp, total);
+    if (w == 0) {
+        const uint64_t pre = chained_prefix(status, li, first, total, &ctl[1]);
+        if (lane == 0) s_pre = pre;
+    }
+    __syncthreads();
+    const uint64_t base = s_pre + obase;
+
+    Agg acc;
+    empty_agg(acc);
+    bool have_head = false;
+    uint32_t h = 0;
+#pragma unroll
+    for (int r0 = 0; r0 < IPT; r0 += LEAF_ROUND) {
+        Agg pay[LEAF_ROUND];
+#pragma unroll
+        for (int j = 0; j < LEAF_ROUND; ++j)
+            if (r0 + j < nrows) load_payload(V, rw[r0 + j], pay[j]);
+#pragma unroll
+        for (int j = 0; j < LEAF_ROUND; ++j) {
+            if (r0 + j >= nrows) break;
+            Agg& r = pay[j];
+            r.key = kk[r0 + j] + mn;
+            if (heads & (1u << (r0 + j))) {
+                if (!have_head) {
+                    s.pre_cnt[tid] = acc.cnt;
+                    s.pre_sum[tid] = acc.sum;
+                    s.pre_mn[tid] = acc.mn;
+                    s.pre_mx[tid] = acc.mx;
+                    s.pre_fs[tid] = acc.fs;
+                    have_head = true;
+                } else {
+                    const uint64_t pos = base + h - 1;
+                    if (pos < D.capacity) store_agg(D.out, pos, acc);
+                }
+                acc = r;
+                ++h;
+            } else {
+                combine(acc, r);
+            }
+        }
+    }
+    if (!have_head) {
+        s.pre_cnt[tid] = acc.cnt;
+        s.pre_sum[tid] = acc.sum;
+        s.pre_mn[tid] = acc.mn;
+        s.pre_mx[tid] = acc.mx;
+        s.pre_fs[tid] = acc.fs;
+    }
+    s.pre_flags[tid] = (have_head ? 1u : 0u) | (nrows > 0 ? 2u : 0u);
+    __syncthreads();
+    if (have_head) {
+        // the last group of this thread continues into following threads up
+        // to the next thread that starts a group
+        for (int u = tid + 1; u < NT; ++u) {
+            const uint32_t f = s.pre_flags[u];
+            if (!(f & 2u)) break;
+            Agg b;
+            b.cnt = s.pre_cnt[u];
+            b.sum = s.pre_sum[u];
+            b.mn = s.pre_mn[u];
+            b.mx = s.pre_mx[u];
+            b.fs = s.pre_fs[u];
+            combine(acc, b);
+            if (f & 1u) break;
+        }
+        const uint64_t pos = base + h - 1;
+        if (pos < D.capacity) store_agg(D.out, pos, acc);
+    }
+    if (tid == 0 && li == last) totals[d] = s_pre + total;
 }
 
 // ---------------------------------------------------------------------------
@@ -657,11 +829,11 @@ struct MergeRange {
 };
 
 __device__ __forceinline__ MergeRange merge_thread_range(const ColView& A, uint64_t na, const ColView& B,
-                                                         uint64_t nb, uint64_t* s_i, uint64_t* s_j) {
+                                                         uint64_t nb, uint64_t part, uint64_t* s_i, uint64_t* s_j) {
     constexpr int NT = 256, PER = MERGE_D / NT;
     const int tid = threadIdx.x;
     const uint64_t total = na + nb;
-    const uint64_t d0 = (uint64_t)blockIdx.x * MERGE_D;
+    const uint64_t d0 = part * MERGE_D;
     uint64_t d = d0 + (uint64_t)tid * PER;
     if (d > total) d = total;
     merge_split(A, na, B, nb, d, s_i[tid], s_j[tid]);
@@ -696,28 +868,32 @@ __device__ __forceinline__ uint32_t merge_count_range(const ColView& A, const Co
     return c;
 }
 
-// Pass 1: groups produced by each partition.
-__global__ void __launch_bounds__(256) k_merge_count(ColView A, uint64_t na, ColView B, uint64_t nb,
-                                                     uint32_t* __restrict__ counts) {
+// One pass: each partition (taken in ticket order) counts its groups, takes
+// its output offset from the chained prefix and writes; the last partition
+// stores the merged row count in *total_out.
+__global__ void __launch_bounds__(256) k_merge(ColView A, uint64_t na, ColView B, uint64_t nb, OutView out,
+                                               uint64_t* __restrict__ status, uint32_t* __restrict__ ctl,
+                                               uint64_t* __restrict__ total_out) {
     __shared__ uint64_t s_i[257], s_j[257];
     __shared__ uint32_t s_tmp[256 / 64 + 1];
-    const MergeRange m = merge_thread_range(A, na, B, nb, s_i, s_j);
+    __shared__ uint32_t s_part;
+    __shared__ uint64_t s_pre;
+    if (threadIdx.x == 0) s_part = atomicAdd(&ctl[0], 1u);
+    __syncthreads();
+    const uint32_t part = s_part;
+    const MergeRange m = merge_thread_range(A, na, B, nb, part, s_i, s_j);
     const uint32_t c = merge_count_range(A, B, m);
     uint32_t tot;
-    block_exclusive_scan<256>(c, s_tmp, tot);
-    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
-}
-
-// Pass 2: write each partition's groups at its scanned offset.
-__global__ void __launch_bounds__(256) k_merge_write(ColView A, uint64_t na, ColView B, uint64_t nb,
-                                                     const uint64_t* __restrict__ offs, OutView out) {
-    __shared__ uint64_t s_i[257], s_j[257];
-    __shared__ uint32_t s_tmp[256 / 64 + 1];
-    const MergeRange m = merge_thread_range(A, na, B, nb, s_i, s_j);
-    const uint32_t c = merge_count_range(A, B, m);
-    uint32_t tot;
-    const uint32_t base = block_exclusive_scan<256>(c, s_tmp, tot);
-    uint64_t o = offs[blockIdx.x] + base;
+    const uint32_t off = block_exclusive_scan<256>(c, s_tmp, tot);
+    if (threadIdx.x < 64) {
+        const uint64_t pre = chained_prefix(status, part, 0, tot, &ctl[1]);
+        if (threadIdx.x == 0) {
+            s_pre = pre;
+            if (part == gridDim.x - 1) *total_out = pre + tot;
+        }
+    }
+    __syncthreads();
+    uint64_t o = s_pre + off;
     uint64_t i = m.ia, j = m.ja;
     while (i < m.ib || j < m.jb) {
         Agg r;
@@ -824,35 +1000,6 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_final(const uint32_t* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Placement of gapped outputs: segment s (counts[s] rows at temp[src_pos])
-// goes to dests[inst] at offs[s] - offs[first_seg[inst]].
-// ---------------------------------------------------------------------------
-
-__global__ void __launch_bounds__(256) k_compact(const Segment* __restrict__ segs, const uint32_t* __restrict__ counts,
-                                                 const uint64_t* __restrict__ offs,
-                                                 const uint32_t* __restrict__ first_seg,
-                                                 const Dest* __restrict__ dests, ColView temp) {
-    const Segment S = segs[blockIdx.x];
-    const uint32_t c = counts[blockIdx.x];
-    const Dest D = dests[S.inst];
-    const uint64_t dst0 = offs[blockIdx.x] - offs[first_seg[S.inst]];
-    for (uint32_t r = threadIdx.x; r < c; r += 256) {
-        const uint64_t d = dst0 + r;
-        if (d >= D.capacity) break;
-        const Agg a = load_agg(temp, S.src_pos + r);
-        store_agg(D.out, d, a);
-    }
-}
-
-// n_groups per instance: offs[end] - offs[first].
-__global__ void k_inst_totals(const uint64_t* __restrict__ offs, const uint32_t* __restrict__ first_seg,
-                              uint32_t n_inst, uint64_t* __restrict__ totals) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_inst) totals[i] = offs[first_seg[i + 1]] - offs[first_seg[i]];
-}
-
-
-// ---------------------------------------------------------------------------
 // Composite keys (A int32, B int32): an order-preserving normalized key
 // (Section 2.4: normalized keys compare as binary strings).  Flipping the sign
 // bit maps signed order onto unsigned order.
@@ -929,26 +1076,32 @@ void launch_bucket_starts(const Region* regions, uint32_t n_regions, const uint6
                           uint64_t* bstart, hipStream_t st) {
     hipLaunchKernelGGL(k_bucket_starts, dim3(n_regions), dim3(256), 0, st, regions, offs, bs_base, bstart);
 }
-void launch_leaf(const Leaf* leaves, uint32_t n_leaves, OutView temp, uint32_t* counts, hipStream_t st) {
-    hipLaunchKernelGGL(k_leaf, dim3(n_leaves), dim3(LEAF_NT), 0, st, leaves, temp, counts);
+void launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st) {
+    if (!n) return;
+    uint64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)g), dim3(256), 0, st, p, n, value);
 }
-void launch_single(const Leaf* leaves, uint32_t n_leaves, const SinglePiece* pieces, uint32_t n_pieces,
-                   void* partials, OutView temp, uint32_t* counts, hipStream_t st) {
+void launch_leaf(const Leaf* leaves, uint32_t n_leaves, const uint32_t* leaf_dest, const uint32_t* first_seg,
+                 const Dest* dests, const void* partials, uint64_t* status, uint64_t* totals, uint32_t* ctl,
+                 hipStream_t st) {
+    if (!n_leaves) return;
+    hipLaunchKernelGGL(k_leaf, dim3(n_leaves), dim3(LEAF_NT), 0, st, leaves, leaf_dest, first_seg, dests,
+                       (const Agg*)partials, status, totals, ctl);
+}
+void launch_single_partial(const Leaf* leaves, const SinglePiece* pieces, uint32_t n_pieces, void* partials,
+                           hipStream_t st) {
+    if (!n_pieces) return;
     hipLaunchKernelGGL(k_single_partial, dim3(n_pieces), dim3(256), 0, st, leaves, pieces, (Agg*)partials);
-    hipLaunchKernelGGL(k_single_final, dim3(n_leaves), dim3(256), 0, st, leaves, (const Agg*)partials, temp, counts);
 }
 size_t single_partial_bytes() { return sizeof(Agg); }
 uint64_t merge_parts(uint64_t na, uint64_t nb) { return (na + nb + MERGE_D - 1) / MERGE_D; }
-void launch_merge_count(ColView A, uint64_t na, ColView B, uint64_t nb, uint32_t* counts, hipStream_t st) {
+// status: merge_parts entries, zeroed; ctl: 2 words, zeroed.
+void launch_merge(ColView A, uint64_t na, ColView B, uint64_t nb, OutView out, uint64_t* status, uint32_t* ctl,
+                  uint64_t* total_out, hipStream_t st) {
     const uint64_t parts = merge_parts(na, nb);
     if (parts == 0) return;
-    hipLaunchKernelGGL(k_merge_count, dim3((uint32_t)parts), dim3(256), 0, st, A, na, B, nb, counts);
-}
-void launch_merge_write(ColView A, uint64_t na, ColView B, uint64_t nb, const uint64_t* offs, OutView out,
-                        hipStream_t st) {
-    const uint64_t parts = merge_parts(na, nb);
-    if (parts == 0) return;
-    hipLaunchKernelGGL(k_merge_write, dim3((uint32_t)parts), dim3(256), 0, st, A, na, B, nb, offs, out);
+    hipLaunchKernelGGL(k_merge, dim3((uint32_t)parts), dim3(256), 0, st, A, na, B, nb, out, status, ctl, total_out);
 }
 void launch_copy_rows(ColView src, uint64_t n, OutView dst, uint64_t cap, hipStream_t st) {
     const uint64_t lim = n < cap ? n : cap;
@@ -968,11 +1121,6 @@ void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* 
     hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)t), dim3(SCAN_NT), 0, st, in, n, tile_sums);
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_sums, t);
     hipLaunchKernelGGL(k_scan_final, dim3((uint32_t)t), dim3(SCAN_NT), 0, st, in, n, tile_sums, offs);
-}
-void launch_compact(const Segment* segs, uint32_t n_segs, const uint32_t* counts, const uint64_t* offs,
-                    const uint32_t* first_seg, const Dest* dests, ColView temp, hipStream_t st) {
-    if (n_segs == 0) return;
-    hipLaunchKernelGGL(k_compact, dim3(n_segs), dim3(256), 0, st, segs, counts, offs, first_seg, dests, temp);
 }
 static dim3 grid_rows(uint64_t n) {
     uint64_t g = (n + 255) / 256;
@@ -998,11 +1146,6 @@ void launch_seg_write(const int32_t* a, uint64_t n, uint32_t chunk, const uint64
     const uint64_t g = (n + chunk - 1) / chunk;
     if (!g) return;
     hipLaunchKernelGGL(k_seg_write, dim3((uint32_t)g), dim3(256), 0, st, a, n, chunk, offs, starts);
-}
-void launch_inst_totals(const uint64_t* offs, const uint32_t* first_seg, uint32_t n_inst, uint64_t* totals,
-                        hipStream_t st) {
-    if (n_inst == 0) return;
-    hipLaunchKernelGGL(k_inst_totals, dim3((n_inst + 255) / 256), dim3(256), 0, st, offs, first_seg, n_inst, totals);
 }
 
 }  // namespace isa

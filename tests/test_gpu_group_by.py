@@ -167,3 +167,16 @@ def test_argument_errors(ctx):
     with pytest.raises(isa.InsortError) as e:
         isa.group_by(ctx, kd2, vd2, None, aggs=isa.ISA_INT_AGGS, mem_budget=12 << 20, spill_bytes=0)
     assert e.value.status == isa.ISA_ESPILL
+
+
+@pytest.mark.parametrize("n", [100, 3000, 4095])
+def test_leaf_max_key_ties_with_padding(ctx, n):
+    # a leaf smaller than the workgroup tile: rows holding the leaf's largest
+    # key must sort before the padding rows that share that key value
+    say("case max-key ties n=%d" % n)
+    rng = np.random.default_rng(n)
+    k = rng.integers(0, 50, n).astype(np.uint64)
+    k[rng.random(n) < 0.4] = np.uint64(49)
+    v = rng.integers(-1000, 1000, n).astype(np.int64)
+    got, st, status, g = run_gpu(ctx, k, v, None, aggs=isa.ISA_INT_AGGS, budget=32 << 20)
+    compare(got, k, v, None, isa.ISA_INT_AGGS, "ties %d" % n)
