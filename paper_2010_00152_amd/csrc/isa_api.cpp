@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -100,8 +101,8 @@ constexpr uint64_t MIN_BATCH = 4 * (uint64_t)LEAF_CAP;
 constexpr uint64_t MERGE_MARGIN = 2u << 20;
 
 uint64_t merge_scratch_bytes(uint64_t rows) {
-    const uint64_t parts = rows / MERGE_D + 2;
-    return (parts + 3) * 8 + 512;
+    const uint64_t parts = merge_parts(rows, 0) + 2;
+    return (3 * parts + 5) * 8 + 1024;
 }
 
 // Workspace used by run generation with batch Bt and index capacity K: two
@@ -109,14 +110,22 @@ uint64_t merge_scratch_bytes(uint64_t rows) {
 // merge's scratch and the sort-reduce area of one batch.
 uint64_t rungen_bytes(uint64_t Bt, uint64_t K, const Cols& k) {
     const uint64_t sw = (uint64_t)state_layout(k).words * 8;
+    const uint64_t split_scratch = ((K + Bt) / 4096 + 4) * 24 + 1024;
     return 2 * (K + Bt) * sw + Bt * sw + merge_scratch_bytes(K + 2 * Bt) + sort_reduce_bytes(Bt, 1, k, false) +
-           MERGE_MARGIN + 8 * 256 + (MAX_BUCKETS - 1) * 8;
+           split_scratch + MERGE_MARGIN + 12 * 256 + (MAX_BUCKETS - 1) * 8;
+}
+
+// Share of the budget given to the batch area (1/share); the rest holds the
+// index.  ISA_BATCH_SHARE overrides the default for tuning.
+uint64_t batch_share() {
+    const char* e = std::getenv("ISA_BATCH_SHARE");
+    const long v = e ? std::atol(e) : 0;
+    return v >= 2 && v <= 64 ? (uint64_t)v : 6;
 }
 
 bool plan_batches(uint64_t ws, uint64_t n, const Cols& k, Plan& p) {
     const uint64_t sw = (uint64_t)state_layout(k).words * 8;
-    // batch area about 1/8 of the budget, the rest for the index
-    uint64_t Bt = ws / 8 / (sort_reduce_bytes(1, 0, k, false) - (4u << 20) + sw);
+    uint64_t Bt = ws / batch_share() / (sort_reduce_bytes(1, 0, k, false) - (4u << 20) + sw);
     Bt = std::min<uint64_t>(Bt, n);
     if (Bt < MIN_BATCH) Bt = MIN_BATCH;
     for (;;) {
@@ -136,9 +145,13 @@ bool plan_batches(uint64_t ws, uint64_t n, const Cols& k, Plan& p) {
     }
 }
 
+// A run in the spill buffer: n_single rows in raw layout (count 1) followed
+// by n_multi rows in state layout, both sorted on the key.  Runs written
+// without count information hold only state rows (n_single = 0).
 struct RunInfo {
-    uint64_t row_off;  // first row in the spill buffer
-    uint64_t n;
+    uint64_t byte_off;
+    uint64_t n_single;
+    uint64_t n_multi;
 };
 
 // First row of [pos, n) whose key is >= x in a strided host array.
@@ -160,11 +173,11 @@ uint64_t lower_bound_strided(const uint64_t* keys, uint64_t stride, uint64_t pos
 // reads by the highest key read, Section 4 Figure 9).  Keys below the window
 // end are final once the window is reduced; they are appended to the output.
 void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::vector<RunInfo>& runs,
-                const uint64_t* host_rows, uint64_t* idx, uint64_t n_idx, isa_output* out, isa_stats* st,
+                const char* host, uint64_t* idx, uint64_t n_idx, isa_output* out, isa_stats* st,
                 uint64_t& n_groups) {
     const Layout S = state_layout(k);
-    const uint64_t sw = (uint64_t)S.words;
-    const size_t R = runs.size();
+    const Layout Rl = raw_layout(k);
+    const uint64_t sw = (uint64_t)S.words, rw = (uint64_t)Rl.words;
     // index keys on the host (one strided D2H copy)
     std::vector<uint64_t> idx_keys(n_idx);
     if (n_idx) {
@@ -173,47 +186,62 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
         E.sync();
         std::memcpy(idx_keys.data(), p, n_idx * 8);
     }
-    // sources 0..R-1 are runs (host), source R is the index (device)
-    std::vector<const uint64_t*> skeys(R + 1);
-    std::vector<uint64_t> sstride(R + 1), sn(R + 1), pos(R + 1, 0);
-    for (size_t r = 0; r < R; ++r) {
-        skeys[r] = host_rows + runs[r].row_off * sw;
-        sstride[r] = sw;
-        sn[r] = runs[r].n;
+    // Sources: every run contributes its count-1 sub-run (raw rows, host) and
+    // its other rows (state rows, host); the last source is the index
+    // (state rows, device).
+    struct Src {
+        const uint64_t* keys;   // host view of the keys, strided
+        uint64_t stride, n;
+        const uint64_t* rows;   // rows to copy (host or device)
+        bool raw, device;
+    };
+    std::vector<Src> src;
+    for (const RunInfo& r : runs) {
+        const uint64_t* base = (const uint64_t*)(host + r.byte_off);
+        if (r.n_single) src.push_back(Src{base, rw, r.n_single, base, true, false});
+        const uint64_t* mb = base + r.n_single * rw;
+        if (r.n_multi) src.push_back(Src{mb, sw, r.n_multi, mb, false, false});
     }
-    skeys[R] = idx_keys.data();
-    sstride[R] = 1;
-    sn[R] = n_idx;
+    if (n_idx) src.push_back(Src{idx_keys.data(), 1, n_idx, idx, false, true});
+    const size_t ns = src.size();
+    std::vector<uint64_t> pos(ns, 0);
 
-    // window capacity: staging + sort-reduce of the staged state rows
-    const uint64_t per_row = sw * 8 + (sort_reduce_bytes(1, 0, k, true) - (4u << 20));
+    // window capacity: two state staging buffers (the next window is copied
+    // while the current one is reduced), one raw area (expanded before the
+    // next window's copies start on the same stream) and the sort-reduce of
+    // the state rows
+    const uint64_t per_row = (2 * sw + rw) * 8 + (sort_reduce_bytes(1, 0, k, true) - (4u << 20));
     const uint64_t avail = A.left() > (6u << 20) ? A.left() - (6u << 20) : 0;
     const uint64_t W = avail / per_row;
-    if (W < 2 * (R + 1)) throw Fail{ISA_ESPILL, "workspace too small for a single wide merge of all runs"};
-    const uint64_t P = std::max<uint64_t>(1, W / (4 * (R + 1)));
+    if (W < 2 * (ns + 1)) throw Fail{ISA_ESPILL, "workspace too small for a single wide merge of all runs"};
+    const uint64_t P = std::max<uint64_t>(1, W / (4 * (ns + 1)));
     std::vector<uint64_t> fences;
-    for (size_t s = 0; s <= R; ++s)
-        for (uint64_t i = P; i < sn[s]; i += P) fences.push_back(skeys[s][i * sstride[s]]);
+    for (size_t s = 0; s < ns; ++s)
+        for (uint64_t i = P; i < src[s].n; i += P) fences.push_back(src[s].keys[i * src[s].stride]);
     std::sort(fences.begin(), fences.end());
     fences.erase(std::unique(fences.begin(), fences.end()), fences.end());
 
+    auto lb = [&](size_t s, uint64_t x) {
+        return lower_bound_strided(src[s].keys, src[s].stride, pos[s], src[s].n, x);
+    };
     auto rows_below = [&](uint64_t x) {
         uint64_t c = 0;
-        for (size_t s = 0; s <= R; ++s) c += lower_bound_strided(skeys[s], sstride[s], pos[s], sn[s], x) - pos[s];
+        for (size_t s = 0; s < ns; ++s) c += lb(s, x) - pos[s];
         return c;
     };
-    uint64_t cursor = 0;
-    const uint64_t mark = A.off;
+    // plan every window: per source, the slice [lo, hi)
+    std::vector<std::vector<uint64_t>> win_lo, win_hi;
+    std::vector<uint64_t> win_rows, win_raw;
     for (;;) {
         uint64_t remaining = 0, min_key = ~0ull;
-        for (size_t s = 0; s <= R; ++s) {
-            remaining += sn[s] - pos[s];
-            if (pos[s] < sn[s]) min_key = std::min(min_key, skeys[s][pos[s] * sstride[s]]);
+        for (size_t s = 0; s < ns; ++s) {
+            remaining += src[s].n - pos[s];
+            if (pos[s] < src[s].n) min_key = std::min(min_key, src[s].keys[pos[s] * src[s].stride]);
         }
         if (!remaining) break;
-        std::vector<uint64_t> end(R + 1);
+        std::vector<uint64_t> end(ns);
         if (remaining <= W) {
-            for (size_t s = 0; s <= R; ++s) end[s] = sn[s];
+            for (size_t s = 0; s < ns; ++s) end[s] = src[s].n;
         } else {
             // largest fence f > min_key with rows_below(f) <= W
             size_t lo = std::upper_bound(fences.begin(), fences.end(), min_key) - fences.begin();
@@ -229,37 +257,80 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
                 }
             }
             const uint64_t x = best < fences.size() ? fences[best] : min_key + 1;
-            for (size_t s = 0; s <= R; ++s) end[s] = lower_bound_strided(skeys[s], sstride[s], pos[s], sn[s], x);
+            for (size_t s = 0; s < ns; ++s) end[s] = lb(s, x);
         }
-        uint64_t wrows = 0;
-        for (size_t s = 0; s <= R; ++s) wrows += end[s] - pos[s];
-        A.off = mark;
-        uint64_t* stage = A.take_n<uint64_t>(wrows * sw);
-        uint64_t at = 0;
-        E.pbegin("merge_h2d");
-        for (size_t s = 0; s <= R; ++s) {
-            const uint64_t len = end[s] - pos[s];
+        uint64_t wrows = 0, wraw = 0;
+        for (size_t s = 0; s < ns; ++s) {
+            wrows += end[s] - pos[s];
+            if (src[s].raw) wraw += end[s] - pos[s];
+        }
+        win_lo.push_back(pos);
+        win_hi.push_back(end);
+        win_rows.push_back(wrows);
+        win_raw.push_back(wraw);
+        pos = end;
+    }
+    const size_t nw = win_rows.size();
+    uint64_t* stage[2];
+    stage[0] = A.take_n<uint64_t>(W * sw);
+    stage[1] = A.take_n<uint64_t>(W * sw);
+    uint64_t* stage_raw = A.take_n<uint64_t>(W * rw);
+    const uint64_t mark = A.off;
+    hipStream_t cs = E.copier();
+    constexpr int NQ = 4;  // copy queues: the copy stream and three side streams
+    hipStream_t q[NQ] = {cs, E.side(0), E.side(1), E.side(2)};
+    // Window w into stage[w % 2]: state slices directly, count-1 slices into
+    // the raw area; slices spread over the copy queues, which join on the
+    // copy stream; the raw rows are then expanded behind the state rows.
+    auto issue = [&](size_t w) {
+        uint64_t* dst = stage[w & 1];
+        uint64_t at = 0, at_raw = 0;
+        E.pbegin("merge_h2d", cs);
+        ck(hipEventRecord(E.sync_event(4), cs), "hipEventRecord");
+        for (int i = 1; i < NQ; ++i) ck(hipStreamWaitEvent(q[i], E.sync_event(4), 0), "hipStreamWaitEvent");
+        uint64_t bytes = 0;
+        int qi = 0;
+        for (size_t s = 0; s < ns; ++s) {
+            const uint64_t lo = win_lo[w][s], len = win_hi[w][s] - lo;
             if (!len) continue;
-            if (s < R) {
-                ck(hipMemcpyAsync(stage + at * sw, host_rows + (runs[s].row_off + pos[s]) * sw, len * sw * 8,
-                                  hipMemcpyHostToDevice, E.stream),
+            hipStream_t qs = q[qi];
+            qi = (qi + 1) % NQ;
+            if (src[s].raw) {
+                ck(hipMemcpyAsync(stage_raw + at_raw * rw, src[s].rows + lo * rw, len * rw * 8, hipMemcpyHostToDevice,
+                                  qs),
                    "hipMemcpyAsync(run slice)");
+                at_raw += len;
+                bytes += len * rw * 8;
             } else {
-                ck(hipMemcpyAsync(stage + at * sw, idx + pos[s] * sw, len * sw * 8, hipMemcpyDeviceToDevice,
-                                  E.stream),
-                   "hipMemcpyAsync(index slice)");
+                ck(hipMemcpyAsync(dst + at * sw, src[s].rows + lo * sw, len * sw * 8,
+                                  src[s].device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, qs),
+                   "hipMemcpyAsync(run slice)");
+                at += len;
+                if (!src[s].device) bytes += len * sw * 8;
             }
-            at += len;
-            pos[s] = end[s];
         }
-        E.pend(wrows, wrows * sw * 8);
+        for (int i = 1; i < NQ; ++i) {
+            ck(hipEventRecord(E.sync_event(4 + i), q[i]), "hipEventRecord");
+            ck(hipStreamWaitEvent(cs, E.sync_event(4 + i), 0), "hipStreamWaitEvent");
+        }
+        E.pend(win_rows[w], bytes, cs);
+        launch_expand(stage_raw, at_raw, Rl, S, dst + at * sw, cs);
+        ck(hipEventRecord(E.sync_event(2 + (w & 1)), cs), "hipEventRecord");
+    };
+    if (nw) issue(0);
+    uint64_t cursor = 0;
+    for (size_t w = 0; w < nw; ++w) {
+        // stage[(w+1) % 2] was last read by window w-1, which has completed
+        if (w + 1 < nw) issue(w + 1);
+        ck(hipStreamWaitEvent(E.stream, E.sync_event(2 + (w & 1)), 0), "hipStreamWaitEvent");
+        A.off = mark;
         const uint64_t cap = out->capacity > cursor ? out->capacity - cursor : 0;
         Dest d;
         d.out = output_view(*out, aggs, std::min(cursor, out->capacity));
         d.capacity = cap;
         std::vector<Instance> inst(1);
-        inst[0].src = aos_view(stage, S);
-        inst[0].n = wrows;
+        inst[0].src = aos_view(stage[w & 1], S);
+        inst[0].n = win_rows[w];
         inst[0].dest = 0;
         const std::vector<uint64_t> g = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, true);
         cursor += g[0];
@@ -414,8 +485,17 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             idx[1] = A.take_n<uint64_t>((p.capacity + p.batch_rows) * sw);
             uint64_t* brun = A.take_n<uint64_t>(p.batch_rows * sw);
             const uint64_t mscr_parts = merge_parts(p.capacity + p.batch_rows, p.batch_rows) + 1;
-            // merge control block: [ticket, error], merged row count, per-partition status
+            // merge control block: [ticket, error], merged row count, per-partition
+            // status; then the partition splits
             uint64_t* m_ctl = A.take_n<uint64_t>(mscr_parts + 2);
+            uint64_t* m_splits = A.take_n<uint64_t>(2 * (mscr_parts + 1));
+            // compact runs need a count column and a raw row narrower than a state row
+            const Layout Rl = raw_layout(k);
+            const bool compact = S.cnt >= 0 && Rl.words < S.words;
+            const uint64_t sp_blocks = split_blocks(p.capacity + p.batch_rows) + 1;
+            uint32_t* sp_counts = A.take_n<uint32_t>(sp_blocks);
+            uint64_t* sp_offs = A.take_n<uint64_t>(sp_blocks + 1);
+            uint64_t* sp_tiles = A.take_n<uint64_t>(scan_tiles(sp_blocks) + 1);
             // splitters for every batch, chosen once from a sample of the whole
             // input (batches are slices of one input)
             uint64_t* d_gspl = A.take_n<uint64_t>(MAX_BUCKETS - 1);
@@ -429,9 +509,9 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             int cur = 0;
             uint64_t n_idx = 0;
             std::vector<RunInfo> runs;
-            uint64_t spill_rows_cap = spill.host_pinned ? spill.bytes / (sw * 8) : 0;
-            uint64_t spill_used = 0;
+            uint64_t spill_used = 0, spilled_bytes = 0;  // bytes of the spill buffer in use
             uint64_t batches = 0, spilled = 0;
+            bool spill_pending = false;
             for (uint64_t b0 = 0; b0 < n; b0 += p.batch_rows) {
                 const uint64_t bn = std::min(p.batch_rows, n - b0);
                 ColView bsrc = src;
@@ -458,12 +538,16 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 // absorb the batch's distinct keys into the index if they fit:
                 // merge into the spare index buffer, keep the result only if
                 // it holds at most K keys
-                const ColView iv = aos_view(idx[cur], S), bv = aos_view(brun, S);
                 const uint64_t parts = merge_parts(n_idx, g);
+                if (spill_pending) {
+                    // the spare buffer is the source of a spill still in flight
+                    ck(hipStreamWaitEvent(E.stream, E.sync_event(1), 0), "hipStreamWaitEvent");
+                    spill_pending = false;
+                }
                 launch_fill(m_ctl, parts + 2, 0, E.stream);
                 E.pbegin("k_merge");
-                launch_merge(iv, n_idx, bv, g, aos_out(idx[cur ^ 1], S), m_ctl + 2, (uint32_t*)m_ctl, m_ctl + 1,
-                             E.stream);
+                launch_merge(idx[cur], n_idx, brun, g, idx[cur ^ 1], S, m_splits, m_ctl + 2, (uint32_t*)m_ctl,
+                             m_ctl + 1, E.stream);
                 E.pend(n_idx + g, (n_idx + g) * sw * 8);
                 const uint64_t* h_m = (const uint64_t*)download_async(E, m_ctl, 16);
                 E.sync();
@@ -474,25 +558,49 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     n_idx = m;
                 } else {
                     // memory is full: write the index as one sorted run
-                    // (read-sort-write) and start a new index with the batch
-                    if (spill_used + n_idx > spill_rows_cap)
+                    // (read-sort-write) and start a new index with the batch.
+                    // The run is split into its count-1 rows (raw layout) and
+                    // the others in the spare buffer, copied to host memory
+                    // on the copy stream while run generation continues.
+                    uint64_t n_single = 0;
+                    const uint64_t* src_run = idx[cur];
+                    if (compact) {
+                        launch_split(idx[cur], n_idx, S, Rl, sp_counts, sp_tiles, sp_offs, idx[cur ^ 1], E.stream);
+                        const uint64_t* h_s =
+                            (const uint64_t*)download_async(E, sp_offs + split_blocks(n_idx), 8);
+                        E.sync();
+                        n_single = *h_s;
+                        src_run = idx[cur ^ 1];
+                    }
+                    const uint64_t bytes = n_single * Rl.words * 8 + (n_idx - n_single) * sw * 8;
+                    if (!spill.host_pinned || spill_used + bytes > spill.bytes)
                         throw Fail{ISA_ESPILL, "spill buffer too small"};
-                    E.pbegin("spill_d2h");
-                    ck(hipMemcpyAsync((char*)spill.host_pinned + spill_used * sw * 8, idx[cur], n_idx * sw * 8,
-                                      hipMemcpyDeviceToHost, E.stream),
+                    hipStream_t cs = E.copier();
+                    ck(hipEventRecord(E.sync_event(0), E.stream), "hipEventRecord");
+                    ck(hipStreamWaitEvent(cs, E.sync_event(0), 0), "hipStreamWaitEvent");
+                    E.pbegin("spill_d2h", cs);
+                    ck(hipMemcpyAsync((char*)spill.host_pinned + spill_used, src_run, bytes, hipMemcpyDeviceToHost, cs),
                        "hipMemcpyAsync(spill)");
-                    E.pend(n_idx, n_idx * sw * 8);
+                    E.pend(n_idx, bytes, cs);
+                    ck(hipEventRecord(E.sync_event(1), cs), "hipEventRecord");
                     RunInfo ri;
-                    ri.row_off = spill_used;
-                    ri.n = n_idx;
+                    ri.byte_off = spill_used;
+                    ri.n_single = n_single;
+                    ri.n_multi = n_idx - n_single;
                     runs.push_back(ri);
-                    spill_used += n_idx;
+                    spill_used += bytes;
                     spilled += n_idx;
-                    ck(hipMemcpyAsync(idx[cur], brun, g * sw * 8, hipMemcpyDeviceToDevice, E.stream),
+                    spilled_bytes += bytes;
+                    // the batch run becomes the index in the buffer not being copied
+                    uint64_t* dst = compact ? idx[cur] : idx[cur ^ 1];
+                    ck(hipMemcpyAsync(dst, brun, g * sw * 8, hipMemcpyDeviceToDevice, E.stream),
                        "hipMemcpyAsync(batch run)");
+                    if (!compact) cur ^= 1;
                     n_idx = g;
+                    spill_pending = true;
                 }
             }
+            if (spill_pending) ck(hipStreamSynchronize(E.copier()), "hipStreamSynchronize(copy)");
             E.sync();
             const double t1 = now_ms();
             if (stats) {
@@ -501,7 +609,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 stats->index_capacity = p.capacity;
                 stats->runs = runs.size();
                 stats->spilled_rows = spilled;
-                stats->spilled_bytes = spilled * sw * 8;
+                stats->spilled_bytes = spilled_bytes;
                 stats->t_rungen_ms = t1 - t0;
             }
             if (runs.empty()) {
@@ -517,7 +625,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                        "hipMemcpyAsync(index)");
                 }
                 A.off = (uint64_t)((char*)idx[0] - A.base) + n_idx * sw * 8;
-                wide_merge(E, A, k, aggs, runs, (const uint64_t*)spill.host_pinned, idx[0], n_idx, out, stats,
+                wide_merge(E, A, k, aggs, runs, (const char*)spill.host_pinned, idx[0], n_idx, out, stats,
                            n_groups);
             }
             if (stats) {

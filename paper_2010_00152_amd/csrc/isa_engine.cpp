@@ -109,26 +109,53 @@ static hipEvent_t pool_event(Engine& E) {
     return E.ev_pool[E.ev_used++];
 }
 
-void Engine::pbegin(const char* name) {
+void Engine::pbegin(const char* name, hipStream_t st) {
     if (!prof_on) return;
     ProfRec r;
     r.name = name;
     r.a = pool_event(*this);
     r.b = pool_event(*this);
     r.rows = r.bytes = 0;
-    ck(hipEventRecord(r.a, stream), "hipEventRecord");
+    ck(hipEventRecord(r.a, st ? st : stream), "hipEventRecord");
     prof.push_back(r);
 }
 
-void Engine::pend(uint64_t rows, uint64_t bytes) {
+void Engine::pend(uint64_t rows, uint64_t bytes, hipStream_t st) {
     if (!prof_on) return;
     ProfRec& r = prof.back();
     r.rows = rows;
     r.bytes = bytes;
-    ck(hipEventRecord(r.b, stream), "hipEventRecord");
+    ck(hipEventRecord(r.b, st ? st : stream), "hipEventRecord");
+}
+
+hipStream_t Engine::copier() {
+    if (!copy_stream) ck(hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking), "hipStreamCreate");
+    return copy_stream;
+}
+
+hipStream_t Engine::side(int i) {
+    if (!side_streams[i]) ck(hipStreamCreateWithFlags(&side_streams[i], hipStreamNonBlocking), "hipStreamCreate");
+    return side_streams[i];
+}
+
+hipEvent_t Engine::sync_event(size_t i) {
+    while (sync_events.size() <= i) {
+        hipEvent_t e;
+        ck(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+        sync_events.push_back(e);
+    }
+    return sync_events[i];
 }
 
 void Engine::release() {
+    if (copy_stream) hipStreamDestroy(copy_stream);
+    copy_stream = nullptr;
+    for (hipStream_t& st : side_streams) {
+        if (st) hipStreamDestroy(st);
+        st = nullptr;
+    }
+    for (hipEvent_t e : sync_events) hipEventDestroy(e);
+    sync_events.clear();
     for (hipEvent_t e : ev_pool) hipEventDestroy(e);
     ev_pool.clear();
     prof.clear();

@@ -27,8 +27,12 @@ void launch_single_partial(const Leaf* leaves, const SinglePiece* pieces, uint32
                            hipStream_t st);
 size_t single_partial_bytes();
 uint64_t merge_parts(uint64_t na, uint64_t nb);
-void launch_merge(ColView A, uint64_t na, ColView B, uint64_t nb, OutView out, uint64_t* status, uint32_t* ctl,
-                  uint64_t* total_out, hipStream_t st);
+void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb, uint64_t* out, Layout L,
+                  uint64_t* splits, uint64_t* status, uint32_t* ctl, uint64_t* total_out, hipStream_t st);
+uint64_t split_blocks(uint64_t n);
+void launch_split(const uint64_t* rows, uint64_t n, Layout S, Layout R, uint32_t* counts, uint64_t* tiles,
+                  uint64_t* offs, uint64_t* out, hipStream_t st);
+void launch_expand(const uint64_t* raw, uint64_t n, Layout R, Layout S, uint64_t* out, hipStream_t st);
 void launch_copy_rows(ColView src, uint64_t n, OutView dst, uint64_t cap, hipStream_t st);
 uint64_t scan_tiles(uint64_t n);
 void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* offs, hipStream_t st);
@@ -89,13 +93,22 @@ struct Engine {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
 
+    // second stream for host-link copies that overlap compute, and events
+    hipStream_t copy_stream = nullptr;
+    hipStream_t side_streams[3] = {nullptr, nullptr, nullptr};  // extra copy queues
+    std::vector<hipEvent_t> sync_events;
+
     void* pinned_buf(uint64_t bytes);
     void upload(void* dev, const void* host, uint64_t bytes);
     void sync();
     void release();
-    // bracket one launch; no-ops unless profiling is on
-    void pbegin(const char* name);
-    void pend(uint64_t rows, uint64_t bytes);
+    hipStream_t copier();             // created on first use
+    hipStream_t side(int i);          // extra copy streams 0..2, created on first use
+    hipEvent_t sync_event(size_t i);  // i-th reusable synchronisation event
+    // bracket one launch or copy on `st` (default: stream); no-ops unless
+    // profiling is on
+    void pbegin(const char* name, hipStream_t st = nullptr);
+    void pend(uint64_t rows, uint64_t bytes, hipStream_t st = nullptr);
 };
 
 // One independent grouping problem of a sort-reduce call.

@@ -177,7 +177,8 @@ struct CSortSmem {
 
 template <int NT, int IPT>
 __device__ void block_sort_cnt(uint64_t (&k)[IPT], uint16_t (&v)[IPT], int lo_bit, int hi_bit,
-                               CSortSmem<NT, IPT>& s) {
+                               CSortSmem<NT, IPT>& s, int ipt = IPT) {
+    // ipt <= IPT items per thread take part (thread t: items t*ipt .. t*ipt+ipt-1)
     static_assert((CNT_DIGITS * NT * 2) % (16 * NT) == 0, "counter zeroing layout");
     constexpr int ZERO4 = CNT_DIGITS * NT * 2 / 16 / NT;  // uint4 stores per thread
     constexpr int SEG = CNT_DIGITS;                       // counters scanned per thread
@@ -185,8 +186,10 @@ __device__ void block_sort_cnt(uint64_t (&k)[IPT], uint16_t (&v)[IPT], int lo_bi
     if (lo_bit >= hi_bit) {
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            s.key[pad16(tid * IPT + j)] = k[j];
-            s.val[pad16(tid * IPT + j)] = v[j];
+            if (j < ipt) {
+                s.key[pad16(tid * ipt + j)] = k[j];
+                s.val[pad16(tid * ipt + j)] = v[j];
+            }
         }
         __syncthreads();
         return;
@@ -203,11 +206,13 @@ __device__ void block_sort_cnt(uint64_t (&k)[IPT], uint16_t (&v)[IPT], int lo_bi
         uint32_t dg[IPT];
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            const uint32_t d = (uint32_t)(k[j] >> shift) & mask;
-            dg[j] = d;
-            const uint16_t c = s.cnt[d * NT + tid];
-            loc[j] = c;
-            s.cnt[d * NT + tid] = (uint16_t)(c + 1);
+            if (j < ipt) {
+                const uint32_t d = (uint32_t)(k[j] >> shift) & mask;
+                dg[j] = d;
+                const uint16_t c = s.cnt[d * NT + tid];
+                loc[j] = c;
+                s.cnt[d * NT + tid] = (uint16_t)(c + 1);
+            }
         }
         __syncthreads();
         // scan the counters in memory order (digit-major, thread-minor)
@@ -228,16 +233,20 @@ __device__ void block_sort_cnt(uint64_t (&k)[IPT], uint16_t (&v)[IPT], int lo_bi
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            const int pos = (int)s.cnt[dg[j] * NT + tid] + (int)loc[j];
-            s.key[pad16(pos)] = k[j];
-            s.val[pad16(pos)] = v[j];
+            if (j < ipt) {
+                const int pos = (int)s.cnt[dg[j] * NT + tid] + (int)loc[j];
+                s.key[pad16(pos)] = k[j];
+                s.val[pad16(pos)] = v[j];
+            }
         }
         __syncthreads();
         if (!last) {
 #pragma unroll
             for (int j = 0; j < IPT; ++j) {
-                k[j] = s.key[pad16(tid * IPT + j)];
-                v[j] = s.val[pad16(tid * IPT + j)];
+                if (j < ipt) {
+                    k[j] = s.key[pad16(tid * ipt + j)];
+                    v[j] = s.val[pad16(tid * ipt + j)];
+                }
             }
         }
     }
@@ -248,7 +257,7 @@ __device__ void block_sort_cnt(uint64_t (&k)[IPT], uint16_t (&v)[IPT], int lo_bi
 // t*IPT+IPT-1) through LDS, so the first sort pass sees rows in row order and
 // padding rows (beyond n) stay after every real row.
 template <int NT, int IPT>
-__device__ void striped_to_blocked(uint64_t (&k)[IPT], uint16_t (&v)[IPT], CSortSmem<NT, IPT>& s) {
+__device__ void striped_to_blocked(uint64_t (&k)[IPT], uint16_t (&v)[IPT], CSortSmem<NT, IPT>& s, int ipt = IPT) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
@@ -259,8 +268,10 @@ __device__ void striped_to_blocked(uint64_t (&k)[IPT], uint16_t (&v)[IPT], CSort
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-        k[j] = s.key[pad16(tid * IPT + j)];
-        v[j] = s.val[pad16(tid * IPT + j)];
+        if (j < ipt) {
+            k[j] = s.key[pad16(tid * ipt + j)];
+            v[j] = s.val[pad16(tid * ipt + j)];
+        }
     }
     __syncthreads();
 }
@@ -684,14 +695,16 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf(const Leaf* __restrict__ leave
     }
     const int nbits = bit_length(range);
     const int lo_bit = nbits > LEAF_TRUNC ? nbits - LEAF_TRUNC : 0;
-    striped_to_blocked<NT, IPT>(k, v, s.sort);
-    block_sort_cnt<NT, IPT>(k, v, lo_bit, nbits, s.sort);
+    // only the slots the leaf fills take part in the sort
+    const int ipt = (int)((n + NT - 1) / NT);
+    striped_to_blocked<NT, IPT>(k, v, s.sort, ipt);
+    block_sort_cnt<NT, IPT>(k, v, lo_bit, nbits, s.sort, ipt);
     if (lo_bit > 0) {
         bool clash = false;
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            const int p = tid * IPT + j;
-            if (p > 0 && p < (int)n) {
+            const int p = tid * ipt + j;
+            if (j < ipt && p > 0 && p < (int)n) {
                 const uint64_t a = s.sort.key[pad16(p - 1)], b = s.sort.key[pad16(p)];
                 clash |= (a != b) && ((a >> lo_bit) == (b >> lo_bit));
             }
@@ -699,16 +712,18 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf(const Leaf* __restrict__ leave
         if (__syncthreads_or(clash)) {
 #pragma unroll
             for (int j = 0; j < IPT; ++j) {
-                k[j] = s.sort.key[pad16(tid * IPT + j)];
-                v[j] = s.sort.val[pad16(tid * IPT + j)];
+                if (j < ipt) {
+                    k[j] = s.sort.key[pad16(tid * ipt + j)];
+                    v[j] = s.sort.val[pad16(tid * ipt + j)];
+                }
             }
             __syncthreads();
-            block_sort_cnt<NT, IPT>(k, v, 0, nbits, s.sort);
+            block_sort_cnt<NT, IPT>(k, v, 0, nbits, s.sort, ipt);
         }
     }
 
-    // Blocked arrangement: thread t owns sorted positions [t*IPT, t*IPT+IPT).
-    const int p0 = tid * IPT;
+    // Blocked arrangement: thread t owns sorted positions [t*ipt, t*ipt+ipt).
+    const int p0 = tid * ipt;
     uint64_t kk[IPT];
     uint16_t rw[IPT];
     uint32_t heads = 0;  // bit j: position p0+j starts a group
@@ -718,6 +733,7 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf(const Leaf* __restrict__ leave
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
             const int p = p0 + j;
+            if (j >= ipt) break;
             kk[j] = s.sort.key[pad16(p)];
             rw[j] = s.sort.val[pad16(p)];
             if (p < (int)n) {
@@ -802,117 +818,149 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf(const Leaf* __restrict__ leave
 }
 
 // ---------------------------------------------------------------------------
-// Merge of two sorted runs of unique keys with aggregation of equal keys
-// (merge path; a split never separates an equal pair).  Partition p covers
-// diagonals [p*MERGE_D, ...) and writes its groups at temp[p*MERGE_D ...].
+// LDS-staged merge of two sorted runs of unique keys, both row-major with
+// the same layout, combining equal keys (A's row first).  Partition p covers
+// merge diagonals [p*MG_D, (p+1)*MG_D); its A and B rows are copied to LDS
+// with coalesced loads, merged there by merge path per thread, staged again
+// in LDS and written out with coalesced stores at the chained prefix of the
+// partitions' group counts.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void merge_split(const ColView& A, uint64_t na, const ColView& B, uint64_t nb,
-                                            uint64_t d, uint64_t& i_out, uint64_t& j_out) {
+constexpr int MG_NT = 128;
+constexpr int MG_PER = 4;
+constexpr int MG_D = MG_NT * MG_PER;
+constexpr int MG_MAXW = 6;
+
+// Split of diagonal d over row-major key columns (stride w words); an equal
+// pair is never separated (its B row goes with the A row before the split).
+__device__ __forceinline__ void merge_split_rows(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb,
+                                                 uint32_t w, uint64_t d, uint64_t& i_out, uint64_t& j_out) {
     uint64_t lo = d > nb ? d - nb : 0;
     uint64_t hi = d < na ? d : na;
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
-        if (A.key[mid * A.stride] <= B.key[(d - 1 - mid) * B.stride]) lo = mid + 1;
+        if (A[mid * w] <= B[(d - 1 - mid) * w]) lo = mid + 1;
         else hi = mid;
     }
     uint64_t i = lo, j = d - lo;
-    if (i > 0 && j < nb && A.key[(i - 1) * A.stride] == B.key[j * B.stride]) ++j;
+    if (i > 0 && j < nb && A[(i - 1) * w] == B[j * w]) ++j;
     i_out = i;
     j_out = j;
 }
 
-// Per-thread sub-range of a merge partition: thread t of partition p covers
-// diagonals [p*MERGE_D + t*PER, ...).
-struct MergeRange {
-    uint64_t ia, ib, ja, jb;
-};
-
-__device__ __forceinline__ MergeRange merge_thread_range(const ColView& A, uint64_t na, const ColView& B,
-                                                         uint64_t nb, uint64_t part, uint64_t* s_i, uint64_t* s_j) {
-    constexpr int NT = 256, PER = MERGE_D / NT;
-    const int tid = threadIdx.x;
-    const uint64_t total = na + nb;
-    const uint64_t d0 = part * MERGE_D;
-    uint64_t d = d0 + (uint64_t)tid * PER;
-    if (d > total) d = total;
-    merge_split(A, na, B, nb, d, s_i[tid], s_j[tid]);
-    if (tid == 0) {
-        uint64_t de = d0 + MERGE_D;
-        if (de > total) de = total;
-        merge_split(A, na, B, nb, de, s_i[NT], s_j[NT]);
-    }
-    __syncthreads();
-    MergeRange r;
-    r.ia = s_i[tid];
-    r.ib = s_i[tid + 1] > r.ia ? s_i[tid + 1] : r.ia;
-    r.ja = s_j[tid];
-    r.jb = s_j[tid + 1] > r.ja ? s_j[tid + 1] : r.ja;
-    return r;
+// One thread per partition boundary: splits[2*p], splits[2*p+1].
+__global__ void k_merge_splits(const uint64_t* __restrict__ A, uint64_t na, const uint64_t* __restrict__ B,
+                               uint64_t nb, uint32_t w, uint64_t parts, uint64_t* __restrict__ splits) {
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > parts) return;
+    uint64_t d = p * MG_D;
+    if (d > na + nb) d = na + nb;
+    uint64_t i, j;
+    merge_split_rows(A, na, B, nb, w, d, i, j);
+    splits[2 * p] = i;
+    splits[2 * p + 1] = j;
 }
 
-__device__ __forceinline__ uint32_t merge_count_range(const ColView& A, const ColView& B, const MergeRange& m) {
-    uint32_t c = 0;
-    uint64_t i = m.ia, j = m.ja;
-    while (i < m.ib || j < m.jb) {
-        if (j >= m.jb) ++i;
-        else if (i >= m.ib) ++j;
-        else {
-            const uint64_t ka = A.key[i * A.stride], kb = B.key[j * B.stride];
-            if (ka < kb) ++i;
-            else if (kb < ka) ++j;
-            else { ++i; ++j; }
-        }
-        ++c;
-    }
-    return c;
+__device__ __forceinline__ void combine_rows(uint64_t* o, const uint64_t* a, const uint64_t* b, const Layout& L) {
+    o[0] = a[0];
+    if (L.cnt >= 0) o[L.cnt] = a[L.cnt] + b[L.cnt];
+    if (L.sum >= 0) o[L.sum] = a[L.sum] + b[L.sum];
+    if (L.mn >= 0) o[L.mn] = (uint64_t)((int64_t)a[L.mn] < (int64_t)b[L.mn] ? (int64_t)a[L.mn] : (int64_t)b[L.mn]);
+    if (L.mx >= 0) o[L.mx] = (uint64_t)((int64_t)a[L.mx] > (int64_t)b[L.mx] ? (int64_t)a[L.mx] : (int64_t)b[L.mx]);
+    if (L.fs >= 0) o[L.fs] = __double_as_longlong(__longlong_as_double(a[L.fs]) + __longlong_as_double(b[L.fs]));
 }
 
-// One pass: each partition (taken in ticket order) counts its groups, takes
-// its output offset from the chained prefix and writes; the last partition
-// stores the merged row count in *total_out.
-__global__ void __launch_bounds__(256) k_merge(ColView A, uint64_t na, ColView B, uint64_t nb, OutView out,
-                                               uint64_t* __restrict__ status, uint32_t* __restrict__ ctl,
-                                               uint64_t* __restrict__ total_out) {
-    __shared__ uint64_t s_i[257], s_j[257];
-    __shared__ uint32_t s_tmp[256 / 64 + 1];
+__global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A, uint64_t na,
+                                                 const uint64_t* __restrict__ B, uint64_t nb,
+                                                 const uint64_t* __restrict__ splits, uint64_t* __restrict__ out,
+                                                 Layout L, uint64_t* __restrict__ status, uint32_t* __restrict__ ctl,
+                                                 uint64_t* __restrict__ total_out) {
+    __shared__ uint64_t s_in[(MG_D + 2) * MG_MAXW];
+    __shared__ uint64_t s_out[(MG_D + 2) * MG_MAXW];
+    __shared__ uint32_t s_li[MG_NT + 1], s_lj[MG_NT + 1];
+    __shared__ uint32_t s_tmp[MG_NT / 64 + 1];
     __shared__ uint32_t s_part;
     __shared__ uint64_t s_pre;
-    if (threadIdx.x == 0) s_part = atomicAdd(&ctl[0], 1u);
+    const int tid = threadIdx.x;
+    const uint32_t W = (uint32_t)L.words;
+    if (tid == 0) s_part = atomicAdd(&ctl[0], 1u);
     __syncthreads();
     const uint32_t part = s_part;
-    const MergeRange m = merge_thread_range(A, na, B, nb, part, s_i, s_j);
-    const uint32_t c = merge_count_range(A, B, m);
+    const uint64_t ia0 = splits[2 * part], ja0 = splits[2 * part + 1];
+    const uint64_t ia1 = splits[2 * part + 2], ja1 = splits[2 * part + 3];
+    const uint32_t la = (uint32_t)(ia1 - ia0), lb = (uint32_t)(ja1 - ja0);
+    for (uint32_t x = tid; x < la * W; x += MG_NT) s_in[x] = A[ia0 * W + x];
+    for (uint32_t x = tid; x < lb * W; x += MG_NT) s_in[la * W + x] = B[ja0 * W + x];
+    __syncthreads();
+    const uint64_t* a = s_in;
+    const uint64_t* b = s_in + la * W;
+    {
+        // local split of this thread's diagonal
+        uint32_t d = (uint32_t)tid * MG_PER;
+        if (d > la + lb) d = la + lb;
+        uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a[mid * W] <= b[(d - 1 - mid) * W]) lo = mid + 1;
+            else hi = mid;
+        }
+        uint32_t i = lo, j = d - lo;
+        if (i > 0 && j < lb && a[(i - 1) * W] == b[j * W]) ++j;
+        s_li[tid] = i;
+        s_lj[tid] = j;
+        if (tid == 0) {
+            s_li[MG_NT] = la;
+            s_lj[MG_NT] = lb;
+        }
+    }
+    __syncthreads();
+    const uint32_t i0 = s_li[tid], i1 = s_li[tid + 1] > i0 ? s_li[tid + 1] : i0;
+    const uint32_t j0 = s_lj[tid], j1 = s_lj[tid + 1] > j0 ? s_lj[tid + 1] : j0;
+    uint32_t c = 0;
+    {
+        uint32_t i = i0, j = j0;
+        while (i < i1 || j < j1) {
+            if (j >= j1) ++i;
+            else if (i >= i1) ++j;
+            else {
+                const uint64_t ka = a[i * W], kb = b[j * W];
+                if (ka < kb) ++i;
+                else if (kb < ka) ++j;
+                else { ++i; ++j; }
+            }
+            ++c;
+        }
+    }
     uint32_t tot;
-    const uint32_t off = block_exclusive_scan<256>(c, s_tmp, tot);
-    if (threadIdx.x < 64) {
+    const uint32_t off = block_exclusive_scan<MG_NT>(c, s_tmp, tot);
+    if (tid < 64) {
         const uint64_t pre = chained_prefix(status, part, 0, tot, &ctl[1]);
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             s_pre = pre;
             if (part == gridDim.x - 1) *total_out = pre + tot;
         }
     }
-    __syncthreads();
-    uint64_t o = s_pre + off;
-    uint64_t i = m.ia, j = m.ja;
-    while (i < m.ib || j < m.jb) {
-        Agg r;
-        if (j >= m.jb) { r = load_agg(A, i); ++i; }
-        else if (i >= m.ib) { r = load_agg(B, j); ++j; }
-        else {
-            const uint64_t ka = A.key[i * A.stride], kb = B.key[j * B.stride];
-            if (ka < kb) { r = load_agg(A, i); ++i; }
-            else if (kb < ka) { r = load_agg(B, j); ++j; }
-            else {
-                r = load_agg(A, i);
-                const Agg rb = load_agg(B, j);
-                combine(r, rb);
+    {
+        uint32_t o = off, i = i0, j = j0;
+        while (i < i1 || j < j1) {
+            uint64_t* dst = s_out + o * W;
+            if (j >= j1 || (i < i1 && a[i * W] < b[j * W])) {
+                for (uint32_t x = 0; x < W; ++x) dst[x] = a[i * W + x];
+                ++i;
+            } else if (i >= i1 || b[j * W] < a[i * W]) {
+                for (uint32_t x = 0; x < W; ++x) dst[x] = b[j * W + x];
+                ++j;
+            } else {
+                combine_rows(dst, a + i * W, b + j * W, L);
                 ++i;
                 ++j;
             }
+            ++o;
         }
-        store_agg(out, o++, r);
     }
+    __syncthreads();
+    const uint64_t base = s_pre * W;
+    for (uint32_t x = tid; x < tot * W; x += MG_NT) out[base + x] = s_out[x];
 }
 
 // Copy n rows between strided views, writing only below `cap`.
@@ -1057,6 +1105,85 @@ __global__ void __launch_bounds__(256) k_seg_write(const int32_t* __restrict__ a
         if (i == 0 || a[i] != a[i - 1]) starts[o++] = i;
 }
 
+
+// ---------------------------------------------------------------------------
+// Compact run format.  A state row whose count is 1 holds a single input row,
+// so key plus raw value columns describe it; a run is written as the sorted
+// sub-run of such rows in raw layout followed by the sorted sub-run of the
+// other rows in state layout (stable split, two passes).
+// ---------------------------------------------------------------------------
+
+constexpr int SPLIT_T = 4096;  // rows per workgroup
+
+__global__ void __launch_bounds__(256) k_split_count(const uint64_t* __restrict__ rows, uint64_t n, Layout S,
+                                                     uint32_t* __restrict__ counts) {
+    __shared__ uint32_t s_tmp[256 / 64 + 1];
+    const uint64_t r0 = (uint64_t)blockIdx.x * SPLIT_T;
+    uint32_t c = 0;
+    for (uint32_t i = threadIdx.x; i < SPLIT_T; i += 256) {
+        const uint64_t r = r0 + i;
+        if (r < n && rows[r * S.words + S.cnt] == 1) ++c;
+    }
+    uint32_t tot;
+    block_exclusive_scan<256>(c, s_tmp, tot);
+    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+// offs: exclusive scan of the counts (offs[nblocks] = all singles).  Singles
+// go to out[0 ..) in raw layout R, the rest after them in state layout S.
+__global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict__ rows, uint64_t n, Layout S,
+                                                     Layout R, const uint64_t* __restrict__ offs, uint64_t nblocks,
+                                                     uint64_t* __restrict__ out) {
+    __shared__ uint32_t s_tmp[256 / 64 + 1];
+    constexpr int PER = SPLIT_T / 256;
+    const uint64_t r0 = (uint64_t)blockIdx.x * SPLIT_T + (uint64_t)threadIdx.x * PER;
+    uint32_t c = 0;
+    for (int i = 0; i < PER; ++i) {
+        const uint64_t r = r0 + i;
+        if (r < n && rows[r * S.words + S.cnt] == 1) ++c;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<256>(c, s_tmp, tot);
+    const uint64_t n_single = offs[nblocks];
+    uint64_t so = offs[blockIdx.x] + ex;                       // singles before this thread
+    uint64_t mo = r0 - so;                                     // others before this thread
+    uint64_t* multi = out + n_single * R.words;
+    for (int i = 0; i < PER; ++i) {
+        const uint64_t r = r0 + i;
+        if (r >= n) break;
+        const uint64_t* src = rows + r * S.words;
+        if (src[S.cnt] == 1) {
+            uint64_t* d = out + so * R.words;
+            d[0] = src[0];
+            if (R.sum >= 0) d[R.sum] = src[S.sum];
+            if (R.fs >= 0) d[R.fs] = src[S.fs];
+            ++so;
+        } else {
+            uint64_t* d = multi + mo * S.words;
+            for (int x = 0; x < S.words; ++x) d[x] = src[x];
+            ++mo;
+        }
+    }
+}
+
+// Raw rows (layout R) to state rows (layout S) with count 1.
+__global__ void k_expand(const uint64_t* __restrict__ raw, uint64_t n, Layout R, Layout S,
+                         uint64_t* __restrict__ out) {
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t* src = raw + r * R.words;
+        uint64_t* d = out + r * S.words;
+        d[0] = src[0];
+        if (S.cnt >= 0) d[S.cnt] = 1;
+        if (S.sum >= 0) {
+            const uint64_t v = src[R.sum];
+            d[S.sum] = v;
+            d[S.mn] = v;
+            d[S.mx] = v;
+        }
+        if (S.fs >= 0) d[S.fs] = src[R.fs];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch wrappers
 // ---------------------------------------------------------------------------
@@ -1095,13 +1222,34 @@ void launch_single_partial(const Leaf* leaves, const SinglePiece* pieces, uint32
     hipLaunchKernelGGL(k_single_partial, dim3(n_pieces), dim3(256), 0, st, leaves, pieces, (Agg*)partials);
 }
 size_t single_partial_bytes() { return sizeof(Agg); }
-uint64_t merge_parts(uint64_t na, uint64_t nb) { return (na + nb + MERGE_D - 1) / MERGE_D; }
-// status: merge_parts entries, zeroed; ctl: 2 words, zeroed.
-void launch_merge(ColView A, uint64_t na, ColView B, uint64_t nb, OutView out, uint64_t* status, uint32_t* ctl,
-                  uint64_t* total_out, hipStream_t st) {
+uint64_t merge_parts(uint64_t na, uint64_t nb) { return (na + nb + MG_D - 1) / MG_D; }
+// A, B, out: row-major state rows of layout L.  splits: 2*(parts+1) words;
+// status: parts words and ctl: 2 words, both zeroed.
+void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb, uint64_t* out, Layout L,
+                  uint64_t* splits, uint64_t* status, uint32_t* ctl, uint64_t* total_out, hipStream_t st) {
     const uint64_t parts = merge_parts(na, nb);
     if (parts == 0) return;
-    hipLaunchKernelGGL(k_merge, dim3((uint32_t)parts), dim3(256), 0, st, A, na, B, nb, out, status, ctl, total_out);
+    hipLaunchKernelGGL(k_merge_splits, dim3((uint32_t)((parts + 1 + 255) / 256)), dim3(256), 0, st, A, na, B, nb,
+                       (uint32_t)L.words, parts, splits);
+    hipLaunchKernelGGL(k_merge, dim3((uint32_t)parts), dim3(MG_NT), 0, st, A, na, B, nb, splits, out, L, status, ctl,
+                       total_out);
+}
+void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* offs, hipStream_t st);
+uint64_t split_blocks(uint64_t n) { return (n + SPLIT_T - 1) / SPLIT_T; }
+// counts: split_blocks(n) words; offs/tiles as for launch_scan.
+void launch_split(const uint64_t* rows, uint64_t n, Layout S, Layout R, uint32_t* counts, uint64_t* tiles,
+                  uint64_t* offs, uint64_t* out, hipStream_t st) {
+    const uint64_t nb = split_blocks(n);
+    if (!nb) return;
+    hipLaunchKernelGGL(k_split_count, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, counts);
+    launch_scan(counts, nb, tiles, offs, st);
+    hipLaunchKernelGGL(k_split_write, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, R, offs, nb, out);
+}
+void launch_expand(const uint64_t* raw, uint64_t n, Layout R, Layout S, uint64_t* out, hipStream_t st) {
+    if (!n) return;
+    uint64_t g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_expand, dim3((uint32_t)g), dim3(256), 0, st, raw, n, R, S, out);
 }
 void launch_copy_rows(ColView src, uint64_t n, OutView dst, uint64_t cap, hipStream_t st) {
     const uint64_t lim = n < cap ? n : cap;
