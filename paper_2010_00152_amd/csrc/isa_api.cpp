@@ -44,6 +44,29 @@ Cols cols_of(uint32_t aggs) {
     return k;
 }
 
+// Sort-reduce dispatch by size class: instances of at most FLAT_MAX rows take
+// the flat plan (one partition level, no host round trip; optionally one
+// graph launch); larger instances, or a flat attempt that met an oversized
+// bucket, take the general multi-level plan.
+std::vector<uint64_t> run_instances(Engine& E, Arena& A, const std::vector<Instance>& inst,
+                                    const std::vector<Dest>& dests, const Cols& k, bool state_rows,
+                                    const SplitterHint* hint, bool graph) {
+    bool small = true;
+    for (const Instance& x : inst) small &= x.n <= FLAT_MAX;
+    if (small) {
+        const uint64_t mark = A.off;
+        std::vector<uint64_t> t;
+        if (sort_reduce_flat(E, A, inst, dests, k, state_rows, hint, graph, t)) return t;
+        A.off = mark;
+    }
+    return sort_reduce(E, A, inst, dests, k, state_rows, hint);
+}
+
+bool graph_batches() {
+    const char* e = std::getenv("ISA_BATCH_GRAPH");
+    return !(e && e[0] == '0');
+}
+
 // Raw input rows viewed column-wise.
 ColView input_view(const isa_input& in, const Cols& k) {
     ColView v;
@@ -469,7 +492,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             inst[0].src = src;
             inst[0].n = n;
             inst[0].dest = 0;
-            n_groups = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false)[0];
+            n_groups = run_instances(E, A, inst, std::vector<Dest>(1, d), k, false, nullptr, false)[0];
             if (stats) {
                 stats->batches = 1;
                 stats->batch_rows = n;
@@ -528,12 +551,12 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 if (n_idx == 0) {
                     // an empty index simply becomes the batch's sorted run
                     d.out = aos_out(idx[cur], S);
-                    n_idx = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false, &hint)[0];
+                    n_idx = run_instances(E, A, inst, std::vector<Dest>(1, d), k, false, &hint, false)[0];
                     ++batches;
                     continue;
                 }
                 d.out = aos_out(brun, S);
-                const uint64_t g = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false, &hint)[0];
+                const uint64_t g = run_instances(E, A, inst, std::vector<Dest>(1, d), k, false, &hint, false)[0];
                 ++batches;
                 // absorb the batch's distinct keys into the index if they fit:
                 // merge into the spare index buffer, keep the result only if
@@ -727,7 +750,7 @@ isa_status isa_group_by_segmented(isa_ctx* ctx, const int32_t* a, const int32_t*
             d.out = output_view(*out, aggs, std::min(cursor, out->capacity));
             d.out.key = okeys;
             d.capacity = std::min(cap_left, rows);
-            const uint64_t g = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, false)[0];
+            const uint64_t g = run_instances(E, A, inst, std::vector<Dest>(1, d), k, false, nullptr, false)[0];
             launch_unpack_pairs(okeys, std::min(g, d.capacity), out_a + std::min(cursor, out->capacity),
                                 out_b + std::min(cursor, out->capacity), E.stream);
             E.sync();
@@ -774,34 +797,47 @@ isa_status isa_batch_run(isa_ctx* ctx, uint32_t n_inst, const isa_input* inst, u
         A.base = (char*)ws.dev;
         A.cap = ws.bytes;
         bool trunc = false;
-        uint32_t i0 = 0;
-        while (i0 < n_inst) {
-            // a wave: consecutive instances whose intermediate data fit together
-            uint32_t i1 = i0;
+        // size classes: small instances first (flat plan, one graph launch per
+        // wave), then large ones (general plan)
+        std::vector<uint32_t> order;
+        for (uint32_t i = 0; i < n_inst; ++i)
+            if (inst[i].n_rows <= FLAT_MAX) order.push_back(i);
+        const size_t n_small = order.size();
+        for (uint32_t i = 0; i < n_inst; ++i)
+            if (inst[i].n_rows > FLAT_MAX) order.push_back(i);
+        size_t i0 = 0;
+        while (i0 < order.size()) {
+            // a wave: instances of one class whose intermediate data fit together
+            const bool small = i0 < n_small;
+            const size_t lim = small ? n_small : order.size();
+            size_t i1 = i0;
             uint64_t rows = 0;
-            while (i1 < n_inst && sort_reduce_bytes(rows + inst[i1].n_rows, i1 - i0 + 1, k, false) <= ws.bytes) {
-                rows += inst[i1].n_rows;
+            while (i1 < lim && i1 - i0 < 65536 &&
+                   sort_reduce_bytes(rows + inst[order[i1]].n_rows, i1 - i0 + 1, k, false) <= ws.bytes) {
+                rows += inst[order[i1]].n_rows;
                 ++i1;
             }
             if (i1 == i0) throw Fail{ISA_EBUDGET, "an instance does not fit the workspace"};
             std::vector<Instance> in;
             std::vector<Dest> ds;
-            for (uint32_t i = i0; i < i1; ++i) {
-                Instance x;
-                x.src = input_view(inst[i], k);
-                x.n = inst[i].n_rows;
-                x.dest = i - i0;
-                in.push_back(x);
+            for (size_t x = i0; x < i1; ++x) {
+                const uint32_t i = order[x];
+                Instance y;
+                y.src = input_view(inst[i], k);
+                y.n = inst[i].n_rows;
+                y.dest = (uint32_t)(x - i0);
+                in.push_back(y);
                 Dest d;
                 d.out = output_view(outs[i], aggs, 0);
                 d.capacity = outs[i].capacity;
                 ds.push_back(d);
             }
             A.off = 0;
-            const std::vector<uint64_t> g = sort_reduce(E, A, in, ds, k, false);
-            for (uint32_t i = i0; i < i1; ++i) {
-                outs[i].n_groups = g[i - i0];
-                if (g[i - i0] > outs[i].capacity) trunc = true;
+            const std::vector<uint64_t> g = run_instances(E, A, in, ds, k, false, nullptr, small && graph_batches());
+            for (size_t x = i0; x < i1; ++x) {
+                const uint32_t i = order[x];
+                outs[i].n_groups = g[x - i0];
+                if (g[x - i0] > outs[i].capacity) trunc = true;
             }
             i0 = i1;
         }
@@ -955,7 +991,7 @@ void worker_loop(isa_server* S, Engine* E) {
             Arena A;
             A.base = S->ws + off;
             A.cap = bytes;
-            g = sort_reduce(*E, A, in, ds, k, false);
+            g = run_instances(*E, A, in, ds, k, false, nullptr, false);
         } catch (const Fail& f) {
             st = (isa_status)f.status;
         } catch (const std::bad_alloc&) {

@@ -138,6 +138,11 @@ hipStream_t Engine::side(int i) {
     return side_streams[i];
 }
 
+hipStream_t Engine::capturer() {
+    if (!capture_stream) ck(hipStreamCreateWithFlags(&capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+    return capture_stream;
+}
+
 hipEvent_t Engine::sync_event(size_t i) {
     while (sync_events.size() <= i) {
         hipEvent_t e;
@@ -154,6 +159,8 @@ void Engine::release() {
         if (st) hipStreamDestroy(st);
         st = nullptr;
     }
+    if (capture_stream) hipStreamDestroy(capture_stream);
+    capture_stream = nullptr;
     for (hipEvent_t e : sync_events) hipEventDestroy(e);
     sync_events.clear();
     for (hipEvent_t e : ev_pool) hipEventDestroy(e);
@@ -504,3 +511,159 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
 }
 
 }  // namespace isa
+
+namespace isa {
+
+// Error word of a flat launch: bit 0 a timed-out wait (fatal), bit 1 an
+// oversized bucket (the caller falls back to the general plan).
+static bool finish_flat(const uint64_t* h_ctl, size_t n_dests, std::vector<uint64_t>& totals) {
+    const uint64_t err = h_ctl[0] >> 32;
+    if (err & 1) throw Fail{ISA_EDEVICE, "leaf placement wait timed out"};
+    if (err & 2) return false;
+    for (size_t d = 0; d < n_dests; ++d) totals[d] = h_ctl[1 + d];
+    return true;
+}
+
+bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, const std::vector<Dest>& dests,
+                      const Cols& k, bool state_rows, const SplitterHint* hint, bool graph,
+                      std::vector<uint64_t>& totals) {
+    const Layout L = state_rows ? state_layout(k) : raw_layout(k);
+    totals.assign(dests.size(), 0);
+    std::vector<Region> regs;
+    std::vector<Chunk> chunks;
+    std::vector<FlatInst> finst;
+    std::vector<FlatSlot> slots;
+    std::vector<uint32_t> first_slot(dests.size() + 1, 0);
+    uint64_t N = 0, hist_total = 0;
+    uint32_t cur_dest = 0;
+    for (size_t i = 0; i < inst.size(); ++i) {
+        const Instance& in = inst[i];
+        if (i > 0 && in.dest < inst[i - 1].dest) throw Fail{ISA_EINVAL, "instances not ordered by dest"};
+        if (in.n > FLAT_MAX) throw Fail{ISA_EINVAL, "instance too large for the flat plan"};
+        while (cur_dest < in.dest) first_slot[++cur_dest] = (uint32_t)slots.size();
+        if (in.n == 0) continue;
+        if (in.n <= (uint64_t)LEAF_CAP) {
+            FlatInst fi;
+            fi.src = in.src;
+            fi.n = in.n;
+            slots.push_back(FlatSlot{0, (uint32_t)finst.size(), 0, in.dest});
+            finst.push_back(fi);
+            continue;
+        }
+        Region r;
+        r.src = in.src;
+        r.n = in.n;
+        r.out_pos = N;
+        r.nb = (hint && hint->dev && inst.size() == 1) ? hint->nb : buckets_for(in.n);
+        uint64_t crow = (in.n / 512 + PART_TILE - 1) / PART_TILE * PART_TILE;
+        crow = std::max<uint64_t>(PART_TILE, std::min<uint64_t>(PART_CHUNK, crow));
+        r.n_chunks = (uint32_t)((in.n + crow - 1) / crow);
+        r.hist_base = hist_total;
+        hist_total += (uint64_t)r.nb * r.n_chunks;
+        for (uint32_t c = 0; c < r.n_chunks; ++c) {
+            Chunk ch;
+            ch.region = (uint32_t)regs.size();
+            ch.idx = c;
+            ch.start = (uint64_t)c * crow;
+            const uint64_t left = in.n - ch.start;
+            ch.n = (uint32_t)(left < crow ? left : crow);
+            ch.pad = 0;
+            chunks.push_back(ch);
+        }
+        for (uint32_t b = 0; b < r.nb; ++b) slots.push_back(FlatSlot{1, (uint32_t)regs.size(), b, in.dest});
+        regs.push_back(r);
+        N += in.n;
+    }
+    while (cur_dest < dests.size()) first_slot[++cur_dest] = (uint32_t)slots.size();
+    if (slots.empty()) return true;
+    const bool fixed = hint && hint->dev && regs.size() == 1;
+
+    uint64_t* part = N ? A.take_n<uint64_t>(N * (uint64_t)L.words) : nullptr;
+    uint64_t* d_spl = fixed ? (uint64_t*)hint->dev : A.take_n<uint64_t>(std::max<size_t>(1, regs.size()) * (MAX_BUCKETS - 1));
+    uint32_t* d_hist = A.take_n<uint32_t>(hist_total + 1);
+    uint64_t* d_offs = A.take_n<uint64_t>(hist_total + 1);
+    uint64_t* d_tiles = A.take_n<uint64_t>(scan_tiles(hist_total) + 1);
+    uint64_t* d_ctl = A.take_n<uint64_t>(1 + dests.size() + slots.size());
+    uint64_t* d_totals = d_ctl + 1;
+    uint64_t* d_status = d_totals + dests.size();
+
+    // descriptors are uploaded on the caller's stream before any capture
+    UpPack up;
+    const uint64_t o_regs = up.add(regs.data(), regs.size() * sizeof(Region));
+    const uint64_t o_chunks = up.add(chunks.data(), chunks.size() * sizeof(Chunk));
+    const uint64_t o_slots = up.add(slots.data(), slots.size() * sizeof(FlatSlot));
+    const uint64_t o_inst = up.add(finst.data(), finst.size() * sizeof(FlatInst));
+    const uint64_t o_first = up.add(first_slot.data(), first_slot.size() * sizeof(uint32_t));
+    const uint64_t o_dests = up.add(dests.data(), dests.size() * sizeof(Dest));
+    char* d_up = up.commit(E, A);
+    Region* d_regs = (Region*)(d_up + o_regs);
+    Chunk* d_chunks = (Chunk*)(d_up + o_chunks);
+    uint64_t rows = 0;
+    for (const Region& r : regs) rows += r.n;
+    uint64_t leaf_rows = N;
+    for (const FlatInst& fi : finst) leaf_rows += fi.n;
+    // the kernels: launched directly on the caller's stream, or captured on a
+    // private stream and launched as one graph on the caller's stream
+    auto launches = [&](hipStream_t st) {
+        launch_fill(d_ctl, 1 + dests.size() + slots.size(), 0, st);
+        if (!regs.empty()) {
+            if (!fixed) {
+                E.pbegin("k_sample", st);
+                launch_sample(d_regs, (uint32_t)regs.size(), d_spl, st);
+                E.pend(regs.size() * (uint64_t)SAMPLE_N, regs.size() * (uint64_t)SAMPLE_N * 8, st);
+            }
+            E.pbegin("k_hist", st);
+            launch_hist(d_regs, d_chunks, (uint32_t)chunks.size(), d_spl, d_hist, st);
+            E.pend(rows, rows * 8, st);
+            launch_scan(d_hist, hist_total, d_tiles, d_offs, st);
+            E.pbegin("k_scatter", st);
+            launch_scatter(d_regs, d_chunks, (uint32_t)chunks.size(), d_spl, d_offs, part, L, st);
+            E.pend(rows, rows * (uint64_t)L.words * 8, st);
+        }
+        E.pbegin("k_leaf", st);
+        launch_leaf_flat((FlatSlot*)(d_up + o_slots), (uint32_t)slots.size(), (FlatInst*)(d_up + o_inst), d_regs,
+                         d_spl, d_offs, part, L, (uint32_t*)(d_up + o_first), (Dest*)(d_up + o_dests), d_status,
+                         d_totals, (uint32_t*)d_ctl, st);
+        E.pend(leaf_rows, leaf_rows * (uint64_t)L.words * 8, st);
+    };
+    if (graph) {
+        hipStream_t cs = E.capturer();
+        const bool prof = E.prof_on;
+        E.prof_on = false;
+        // the capture stream must see the upload: order it after the caller's stream
+        ck(hipEventRecord(E.sync_event(8), E.stream), "hipEventRecord");
+        ck(hipStreamWaitEvent(cs, E.sync_event(8), 0), "hipStreamWaitEvent");
+        ck(hipStreamSynchronize(cs), "hipStreamSynchronize");
+        hipGraph_t gr = nullptr;
+        ck(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        launches(cs);
+        const hipError_t ec = hipStreamEndCapture(cs, &gr);
+        E.prof_on = prof;
+        ck(ec, "hipStreamEndCapture");
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            hipGraphDestroy(gr);
+            ck(ei, "hipGraphInstantiate");
+        }
+        E.pbegin("graph_launch");
+        const hipError_t el = hipGraphLaunch(ex, E.stream);
+        E.pend(leaf_rows, 0);
+        const uint64_t* h = (const uint64_t*)download_async(E, d_ctl, (1 + dests.size()) * sizeof(uint64_t));
+        const hipError_t es = hipStreamSynchronize(E.stream);
+        hipGraphExecDestroy(ex);
+        hipGraphDestroy(gr);
+        ck(el, "hipGraphLaunch");
+        ck(es, "hipStreamSynchronize");
+        E.sync();
+        return finish_flat(h, dests.size(), totals);
+    }
+    launches(E.stream);
+    ck(hipGetLastError(), "flat launch");
+    const uint64_t* h_ctl = (const uint64_t*)download_async(E, d_ctl, (1 + dests.size()) * sizeof(uint64_t));
+    E.sync();
+    return finish_flat(h_ctl, dests.size(), totals);
+}
+
+}  // namespace isa
+

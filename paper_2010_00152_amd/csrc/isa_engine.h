@@ -23,6 +23,10 @@ void launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st);
 void launch_leaf(const Leaf* leaves, uint32_t n_leaves, const uint32_t* leaf_dest, const uint32_t* first_seg,
                  const Dest* dests, const void* partials, uint64_t* status, uint64_t* totals, uint32_t* ctl,
                  hipStream_t st);
+void launch_leaf_flat(const FlatSlot* slots, uint32_t n_slots, const FlatInst* insts, const Region* regions,
+                      const uint64_t* splitters, const uint64_t* offs, const uint64_t* part, Layout L,
+                      const uint32_t* first_slot, const Dest* dests, uint64_t* status, uint64_t* totals,
+                      uint32_t* ctl, hipStream_t st);
 void launch_single_partial(const Leaf* leaves, const SinglePiece* pieces, uint32_t n_pieces, void* partials,
                            hipStream_t st);
 size_t single_partial_bytes();
@@ -96,6 +100,7 @@ struct Engine {
     // second stream for host-link copies that overlap compute, and events
     hipStream_t copy_stream = nullptr;
     hipStream_t side_streams[3] = {nullptr, nullptr, nullptr};  // extra copy queues
+    hipStream_t capture_stream = nullptr;                       // graph capture only
     std::vector<hipEvent_t> sync_events;
 
     void* pinned_buf(uint64_t bytes);
@@ -104,6 +109,7 @@ struct Engine {
     void release();
     hipStream_t copier();             // created on first use
     hipStream_t side(int i);          // extra copy streams 0..2, created on first use
+    hipStream_t capturer();           // private stream for graph capture
     hipEvent_t sync_event(size_t i);  // i-th reusable synchronisation event
     // bracket one launch or copy on `st` (default: stream); no-ops unless
     // profiling is on
@@ -153,6 +159,15 @@ uint32_t buckets_for(uint64_t n);
 
 // Device-to-host copy into pinned staging; valid after the next sync().
 const void* download_async(Engine& E, const void* dev, uint64_t bytes);
+
+// The flat plan (one partition level, buckets are leaves, no host round trip
+// until the end): every instance must have at most FLAT_MAX rows.  With
+// `graph` the launch sequence is captured and launched as one HIP graph.
+// Returns false, having written nothing reliable, when a bucket turned out too
+// large for a leaf; the caller then uses sort_reduce.
+bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, const std::vector<Dest>& dests,
+                      const Cols& k, bool state_rows, const SplitterHint* hint, bool graph,
+                      std::vector<uint64_t>& totals);
 
 // Workspace bytes sort_reduce needs for `rows` input rows.
 uint64_t sort_reduce_bytes(uint64_t rows, uint64_t n_inst, const Cols& k, bool state_rows);

@@ -95,6 +95,24 @@ struct SinglePiece {
     uint32_t pad;
 };
 
+// Largest instance the single-level flat plan takes: every bucket of a full
+// 256-way split then averages half a leaf.
+constexpr uint64_t FLAT_MAX = (uint64_t)LEAF_CAP * MAX_BUCKETS / 2;
+
+// One leaf slot of the flat plan: a whole small instance (kind 0) or one
+// bucket of a partitioned instance (kind 1).
+struct FlatSlot {
+    uint32_t kind;
+    uint32_t idx;     // instance index (kind 0) or region index (kind 1)
+    uint32_t bucket;
+    uint32_t dest;
+};
+
+struct FlatInst {
+    ColView src;
+    uint64_t n;
+};
+
 // Destination of one instance's sorted unique output.
 struct Dest {
     OutView out;

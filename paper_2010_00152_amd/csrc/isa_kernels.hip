@@ -630,46 +630,14 @@ struct LeafSmem {
 constexpr int LEAF_TRUNC = 30;
 constexpr int LEAF_ROUND = 8;  // payload loads issued together
 
-__global__ void __launch_bounds__(LEAF_NT) k_leaf(const Leaf* __restrict__ leaves,
-                                                  const uint32_t* __restrict__ leaf_dest,
-                                                  const uint32_t* __restrict__ first_seg,
-                                                  const Dest* __restrict__ dests, const Agg* __restrict__ partials,
-                                                  uint64_t* __restrict__ status, uint64_t* __restrict__ totals,
-                                                  uint32_t* __restrict__ ctl) {
+// Sort, reduce and place one leaf of at most LEAF_CAP rows (workgroup-wide).
+// li is the leaf's ticket, [first, last] the tickets of its destination d.
+__device__ __forceinline__ void leaf_sort_reduce(const ColView& V, const uint32_t n, const Dest& D, const uint32_t li,
+                                                 const uint32_t first, const uint32_t last, const uint32_t d,
+                                                 uint64_t* __restrict__ status, uint64_t* __restrict__ totals,
+                                                 uint32_t* __restrict__ ctl, LeafSmem& s, uint64_t& s_pre) {
     constexpr int NT = LEAF_NT, IPT = LEAF_IPT;
-    __shared__ LeafSmem s;
-    __shared__ uint32_t s_li;
-    __shared__ uint64_t s_pre;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) s_li = atomicAdd(&ctl[0], 1u);
-    __syncthreads();
-    const uint32_t li = s_li;
-    const Leaf Lf = leaves[li];
-    const uint32_t d = leaf_dest[li];
-    const Dest D = dests[d];
-    const uint32_t first = first_seg[d], last = first_seg[d + 1] - 1;
-
-    if (Lf.kind == 1) {
-        if (w == 0) {
-            const uint64_t pre = chained_prefix(status, li, first, 1, &ctl[1]);
-            if (lane == 0) s_pre = pre;
-        }
-        Agg a;
-        empty_agg(a);
-        for (uint32_t i = tid; i < Lf.single_count; i += NT) combine(a, partials[Lf.single_first + i]);
-        Agg* red = reinterpret_cast<Agg*>(s.sort.key);  // NT*48 bytes fit the key array
-        block_reduce_agg<NT>(a, red);
-        if (tid == 0) {
-            a.key = partials[Lf.single_first].key;
-            const uint64_t pos = s_pre;
-            if (pos < D.capacity) store_agg(D.out, pos, a);
-            if (li == last) totals[d] = pos + 1;
-        }
-        return;
-    }
-
-    const uint32_t n = (uint32_t)Lf.n;
-    const ColView V = Lf.src;
     uint64_t k[IPT];
     uint16_t v[IPT];
     uint64_t mn = ~0ull, mx = 0ull;
@@ -815,6 +783,148 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf(const Leaf* __restrict__ leave
         if (pos < D.capacity) store_agg(D.out, pos, acc);
     }
     if (tid == 0 && li == last) totals[d] = s_pre + total;
+}
+
+// Reduce all rows of a single-key range of any size in one workgroup
+// (fixed per-thread order, then a fixed tree) and place its one group.
+__device__ __forceinline__ void leaf_single_stream(const ColView& V, const uint64_t n, const Dest& D,
+                                                   const uint32_t li, const uint32_t first, const uint32_t last,
+                                                   const uint32_t d, uint64_t* __restrict__ status,
+                                                   uint64_t* __restrict__ totals, uint32_t* __restrict__ ctl,
+                                                   LeafSmem& s, uint64_t& s_pre) {
+    constexpr int NT = LEAF_NT;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (w == 0) {
+        const uint64_t pre = chained_prefix(status, li, first, 1, &ctl[1]);
+        if (lane == 0) s_pre = pre;
+    }
+    Agg a;
+    empty_agg(a);
+    for (uint64_t i = tid; i < n; i += NT) {
+        Agg r;
+        load_payload(V, i, r);
+        combine(a, r);
+    }
+    Agg* red = reinterpret_cast<Agg*>(s.sort.key);
+    block_reduce_agg<NT>(a, red);
+    if (tid == 0) {
+        a.key = V.key[0];
+        const uint64_t pos = s_pre;
+        if (pos < D.capacity) store_agg(D.out, pos, a);
+        if (li == last) totals[d] = pos + 1;
+    }
+}
+
+__global__ void __launch_bounds__(LEAF_NT) k_leaf(const Leaf* __restrict__ leaves,
+                                                  const uint32_t* __restrict__ leaf_dest,
+                                                  const uint32_t* __restrict__ first_seg,
+                                                  const Dest* __restrict__ dests, const Agg* __restrict__ partials,
+                                                  uint64_t* __restrict__ status, uint64_t* __restrict__ totals,
+                                                  uint32_t* __restrict__ ctl) {
+    constexpr int NT = LEAF_NT, IPT = LEAF_IPT;
+    __shared__ LeafSmem s;
+    __shared__ uint32_t s_li;
+    __shared__ uint64_t s_pre;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_li = atomicAdd(&ctl[0], 1u);
+    __syncthreads();
+    const uint32_t li = s_li;
+    const Leaf Lf = leaves[li];
+    const uint32_t d = leaf_dest[li];
+    const Dest D = dests[d];
+    const uint32_t first = first_seg[d], last = first_seg[d + 1] - 1;
+
+    if (Lf.kind == 1) {
+        if (w == 0) {
+            const uint64_t pre = chained_prefix(status, li, first, 1, &ctl[1]);
+            if (lane == 0) s_pre = pre;
+        }
+        Agg a;
+        empty_agg(a);
+        for (uint32_t i = tid; i < Lf.single_count; i += NT) combine(a, partials[Lf.single_first + i]);
+        Agg* red = reinterpret_cast<Agg*>(s.sort.key);  // NT*48 bytes fit the key array
+        block_reduce_agg<NT>(a, red);
+        if (tid == 0) {
+            a.key = partials[Lf.single_first].key;
+            const uint64_t pos = s_pre;
+            if (pos < D.capacity) store_agg(D.out, pos, a);
+            if (li == last) totals[d] = pos + 1;
+        }
+        return;
+    }
+
+    leaf_sort_reduce(Lf.src, (uint32_t)Lf.n, D, li, first, last, d, status, totals, ctl, s, s_pre);
+}
+
+// ---------------------------------------------------------------------------
+// Flat plan: one partition level whose buckets are the leaves.  Every slot
+// finds its rows from the scanned histogram on the device, so the whole plan
+// runs without the host (and can be captured as one graph).  A bucket larger
+// than a leaf that holds more than one key cannot be taken here: it raises
+// bit 1 of the error word and the host redoes the call on the general path.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ ColView aos_view_d(const uint64_t* base, const Layout& L) {
+    ColView v;
+    v.key = base;
+    v.cnt = L.cnt >= 0 ? base + L.cnt : nullptr;
+    v.sum = L.sum >= 0 ? (const int64_t*)(base + L.sum) : nullptr;
+    v.mn = L.mn >= 0 ? (const int64_t*)(base + L.mn) : nullptr;
+    v.mx = L.mx >= 0 ? (const int64_t*)(base + L.mx) : nullptr;
+    v.fs = L.fs >= 0 ? (const double*)(base + L.fs) : nullptr;
+    v.stride = (uint64_t)L.words;
+    return v;
+}
+
+__global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restrict__ slots,
+                                                       const FlatInst* __restrict__ insts,
+                                                       const Region* __restrict__ regions,
+                                                       const uint64_t* __restrict__ splitters,
+                                                       const uint64_t* __restrict__ offs,
+                                                       const uint64_t* __restrict__ part, Layout L,
+                                                       const uint32_t* __restrict__ first_slot,
+                                                       const Dest* __restrict__ dests, uint64_t* __restrict__ status,
+                                                       uint64_t* __restrict__ totals, uint32_t* __restrict__ ctl) {
+    __shared__ LeafSmem s;
+    __shared__ uint32_t s_li;
+    __shared__ uint64_t s_pre;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_li = atomicAdd(&ctl[0], 1u);
+    __syncthreads();
+    const uint32_t li = s_li;
+    const FlatSlot sl = slots[li];
+    const uint32_t d = sl.dest;
+    const Dest D = dests[d];
+    const uint32_t first = first_slot[d], last = first_slot[d + 1] - 1;
+    ColView V;
+    uint64_t n;
+    bool single = false;
+    if (sl.kind == 0) {
+        V = insts[sl.idx].src;
+        n = insts[sl.idx].n;
+    } else {
+        const Region R = regions[sl.idx];
+        const uint32_t b = sl.bucket;
+        const uint64_t rb = offs[R.hist_base];
+        const uint64_t start = offs[R.hist_base + (uint64_t)b * R.n_chunks] - rb;
+        const uint64_t end = b + 1 < R.nb ? offs[R.hist_base + (uint64_t)(b + 1) * R.n_chunks] - rb : R.n;
+        n = end - start;
+        V = aos_view_d(part + (R.out_pos + start) * (uint64_t)L.words, L);
+        const uint64_t* spl = splitters + (uint64_t)sl.idx * (MAX_BUCKETS - 1);
+        const uint64_t lo = b ? spl[b - 1] : 0ull;
+        const uint64_t hi = b + 1 < R.nb ? spl[b] - 1 : ~0ull;
+        single = n > 0 && lo == hi;
+    }
+    if (n == 0 || (n > (uint64_t)LEAF_CAP && !single)) {
+        if (n > 0 && tid == 0) atomicOr(&ctl[1], 2u);
+        if (w == 0) {
+            const uint64_t pre = chained_prefix(status, li, first, 0, &ctl[1]);
+            if (lane == 0 && li == last) totals[d] = pre;
+        }
+        return;
+    }
+    if (single) leaf_single_stream(V, n, D, li, first, last, d, status, totals, ctl, s, s_pre);
+    else leaf_sort_reduce(V, (uint32_t)n, D, li, first, last, d, status, totals, ctl, s, s_pre);
 }
 
 // ---------------------------------------------------------------------------
@@ -1215,6 +1325,14 @@ void launch_leaf(const Leaf* leaves, uint32_t n_leaves, const uint32_t* leaf_des
     if (!n_leaves) return;
     hipLaunchKernelGGL(k_leaf, dim3(n_leaves), dim3(LEAF_NT), 0, st, leaves, leaf_dest, first_seg, dests,
                        (const Agg*)partials, status, totals, ctl);
+}
+void launch_leaf_flat(const FlatSlot* slots, uint32_t n_slots, const FlatInst* insts, const Region* regions,
+                      const uint64_t* splitters, const uint64_t* offs, const uint64_t* part, Layout L,
+                      const uint32_t* first_slot, const Dest* dests, uint64_t* status, uint64_t* totals,
+                      uint32_t* ctl, hipStream_t st) {
+    if (!n_slots) return;
+    hipLaunchKernelGGL(k_leaf_flat, dim3(n_slots), dim3(LEAF_NT), 0, st, slots, insts, regions, splitters, offs, part,
+                       L, first_slot, dests, status, totals, ctl);
 }
 void launch_single_partial(const Leaf* leaves, const SinglePiece* pieces, uint32_t n_pieces, void* partials,
                            hipStream_t st) {

@@ -180,3 +180,18 @@ def test_leaf_max_key_ties_with_padding(ctx, n):
     v = rng.integers(-1000, 1000, n).astype(np.int64)
     got, st, status, g = run_gpu(ctx, k, v, None, aggs=isa.ISA_INT_AGGS, budget=32 << 20)
     compare(got, k, v, None, isa.ISA_INT_AGGS, "ties %d" % n)
+
+
+def test_flat_plan_falls_back_on_oversized_bucket(ctx):
+    # every row the splitter sample reads holds the same key, all other rows
+    # are distinct: the sampled splitters isolate that key and leave two huge
+    # multi-key buckets, which the single-level plan cannot take; the call must
+    # still give the exact result (through the multi-level plan)
+    say("case flat fallback")
+    n, S = 300_000, 4096
+    k = datagen.key_of_rank(np.arange(n, dtype=np.uint64) + np.uint64(10))
+    pos = ((2 * np.arange(S, dtype=np.int64) + 1) * n) // (2 * S)
+    k[pos] = np.uint64(1 << 62)
+    v = datagen.uniform_i64(17, n)
+    got, st, status, g = run_gpu(ctx, k, v, None, aggs=isa.ISA_INT_AGGS, budget=128 << 20)
+    compare(got, k, v, None, isa.ISA_INT_AGGS, "fallback")
