@@ -33,6 +33,250 @@ WORKLOADS = {
     "nospill_100M_zipf1.2": (100_000_000, 10_000_000, 1.2, 4, 12 * 1024, True, "all"),
     "plain_1M_10k": (1_000_000, 10_000, 0.0, 1, 64, False, "int"),
 }
+# Forms beyond the plain operator (each prints its own JSON line):
+#   batch_c3:    instances with rows log-uniform 1e3..1e7 and distinct/rows
+#                log-uniform 1e-4..1, uint64 key, int64 value (count of
+#                instances from --instances); batched launch vs per-instance calls
+#   batch_small: the same with rows log-uniform 1e3..1e5 (launch-bound regime)
+#   serve_c4:    Poisson stream of requests, rows log-uniform 1e4..1e8, distinct
+#                ratio log-uniform 1e-4..1, Zipf s uniform in [0, 1.2]; server
+#                (continuous batching, 64 GiB workspace cap) vs FIFO plain calls
+FORMS = ("batch_c3", "batch_small", "serve_c4")
+
+
+def _instances(seed, count, lo, hi):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    rows = np.exp(rng.uniform(np.log(lo), np.log(hi), count)).round().astype(np.int64)
+    ratio = np.exp(rng.uniform(np.log(1e-4), 0.0, count))
+    d = np.maximum(1, np.round(rows * ratio)).astype(np.int64)
+    return rows, d, rng
+
+
+def bench_batch(args, lo, hi):
+    import ctypes
+    import numpy as np
+    import torch
+
+    import datagen
+    import datagen.device as dgd
+    import paper_2010_00152_amd as isa
+
+    count = args.instances
+    rows, d, _ = _instances(6, count, lo, hi)
+    ctx = isa.Context(0)
+    L = isa.lib()
+    aggs = isa.ISA_INT_AGGS
+    wave_rows = 200_000_000
+    ws = torch.empty(24 << 30, dtype=torch.uint8, device="cuda")
+    wss = isa.isa_workspace(isa._ptr(ws), ws.numel())
+    sp = isa._stream_ptr()
+    t_batch = t_graphless = t_plain = 0.0
+    total_rows = int(rows.sum())
+    i0 = 0
+    waves = 0
+    while i0 < count:
+        i1, acc = i0, 0
+        while i1 < count and (acc + rows[i1] <= wave_rows or i1 == i0):
+            acc += int(rows[i1])
+            i1 += 1
+        n_w = i1 - i0
+        keys = torch.empty(acc, dtype=torch.int64, device="cuda")
+        vals = torch.empty(acc, dtype=torch.int64, device="cuda")
+        outs_mem = [torch.empty(acc, dtype=torch.int64, device="cuda") for _ in range(5)]
+        ins = (isa.isa_input * n_w)()
+        outs = (isa.isa_output * n_w)()
+        off = 0
+        for j, i in enumerate(range(i0, i1)):
+            n = int(rows[i])
+            seed = datagen.substream_seed(6, i)
+            dgd.keys(datagen.substream_seed(seed, 1), n, int(d[i]), 0.0, out=keys[off:off + n])
+            dgd.uniform_i64(datagen.substream_seed(seed, 2), n, out=vals[off:off + n])
+            ins[j] = isa.isa_input(keys[off:].data_ptr(), vals[off:].data_ptr(), None, n)
+            outs[j] = isa.isa_output(outs_mem[0][off:].data_ptr(), outs_mem[1][off:].data_ptr(),
+                                     outs_mem[2][off:].data_ptr(), None, outs_mem[3][off:].data_ptr(),
+                                     outs_mem[4][off:].data_ptr(), n, 0)
+            off += n
+        torch.cuda.synchronize()
+
+        def batched():
+            rc = L.isa_batch_run(ctx.handle, n_w, ins, aggs, wss, outs, sp)
+            if rc != isa.ISA_OK:
+                raise isa.InsortError(rc, ctx.last_error())
+
+        batched()  # warm
+        os.environ["ISA_BATCH_GRAPH"] = "1"
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batched()
+        torch.cuda.synchronize()
+        t_batch += time.perf_counter() - t0
+        os.environ["ISA_BATCH_GRAPH"] = "0"
+        t0 = time.perf_counter()
+        batched()
+        torch.cuda.synchronize()
+        t_graphless += time.perf_counter() - t0
+        os.environ["ISA_BATCH_GRAPH"] = "1"
+        sps = isa.isa_spill(None, 0)
+        t0 = time.perf_counter()
+        for j in range(n_w):
+            rc = L.isa_group_by(ctx.handle, ctypes.byref(ins[j]), aggs, wss, sps, ctypes.byref(outs[j]), None, sp)
+            if rc != isa.ISA_OK:
+                raise isa.InsortError(rc, ctx.last_error())
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        waves += 1
+        print("bench: wave %d (%d instances, %d rows) done" % (waves, n_w, acc), file=sys.stderr, flush=True)
+        del keys, vals, outs_mem
+        i0 = i1
+    res = {
+        "metric": "input rows/s aggregated, batched launch vs per-instance plain calls",
+        "value": round(total_rows / t_batch, 1),
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "data": "synthetic",
+        "dtype": "u64+i64",
+        "config": {"workload": args.workload, "instances": count, "rows_lo": lo, "rows_hi": hi,
+                   "total_rows": total_rows, "waves": waves},
+        "batched_graph_rows_per_s": round(total_rows / t_batch, 1),
+        "batched_direct_rows_per_s": round(total_rows / t_graphless, 1),
+        "plain_per_instance_rows_per_s": round(total_rows / t_plain, 1),
+        "speedup_vs_plain": round(t_plain / t_batch, 3),
+        "ms": {"batched_graph": round(1e3 * t_batch, 2), "batched_direct": round(1e3 * t_graphless, 2),
+               "plain": round(1e3 * t_plain, 2)},
+    }
+    print(json.dumps(res))
+    ctx.close()
+
+
+def bench_serve(args):
+    import ctypes
+    import numpy as np
+    import torch
+
+    import datagen
+    import datagen.device as dgd
+    import paper_2010_00152_amd as isa
+
+    n_req = args.requests
+    rows, d, rng = _instances(7, n_req, 1e4, 1e8)
+    s_zipf = rng.uniform(0.0, 1.2, n_req)
+    ctx = isa.Context(0)
+    L = isa.lib()
+    aggs = isa.ISA_INT_AGGS
+    cap = 64 << 30
+    ws_srv = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    gen_stream = torch.cuda.Stream()
+
+    def make(i):
+        n = int(rows[i])
+        seed = datagen.substream_seed(7, i)
+        with torch.cuda.stream(gen_stream):
+            k = dgd.zipf_approx_keys(datagen.substream_seed(seed, 1), n, int(d[i]), float(s_zipf[i]))
+            v = dgd.uniform_i64(datagen.substream_seed(seed, 2), n)
+        gen_stream.synchronize()
+        return k, v
+
+    # the plain rate of this GPU sets the arrival rate (rho * R_plain / E[rows])
+    sp = isa._stream_ptr()
+    wsp = isa.isa_workspace(isa._ptr(ws_srv), cap)
+    nosp = isa.isa_spill(None, 0)
+
+    def plain(k, v):
+        n = k.numel()
+        o = isa._alloc_outputs(torch, n, aggs, "cuda")
+        out = isa._output_struct(o, n)
+        inp = isa.isa_input(k.data_ptr(), v.data_ptr(), None, n)
+        rc = L.isa_group_by(ctx.handle, ctypes.byref(inp), aggs, wsp, nosp, ctypes.byref(out), None, sp)
+        if rc != isa.ISA_OK:
+            raise isa.InsortError(rc, ctx.last_error())
+        torch.cuda.synchronize()
+        return out.n_groups
+
+    k, v = make(0)
+    plain(k, v)
+    # R_plain: plain-path rate on the first requests of the trace (group-by time only)
+    tt, cal_rows = 0.0, 0
+    for i in range(min(8, n_req)):
+        k, v = make(i)
+        t1 = time.perf_counter()
+        plain(k, v)
+        tt += time.perf_counter() - t1
+        cal_rows += int(rows[i])
+    del k, v
+    r_plain = cal_rows / tt
+    lam = args.rho * r_plain / float(rows.mean())
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
+    print("bench: plain %.3g rows/s, arrival rate %.1f req/s over %.1f s" % (r_plain, lam, arrivals[-1]),
+          file=sys.stderr, flush=True)
+
+    def run(mode):
+        # latency = scheduled arrival -> output ready; a request the client
+        # reaches late (the previous plain call still running) waits from its
+        # scheduled arrival, as in a FIFO queue
+        lat = np.zeros(n_req)
+        srv = isa.Server(ctx, cap, slots=args.slots, workspace=ws_srv) if mode == "server" else None
+        pending = {}
+        start = time.perf_counter()
+        for i in range(n_req):
+            now = time.perf_counter() - start
+            if arrivals[i] > now:
+                time.sleep(arrivals[i] - now)
+            k, v = make(i)
+            if mode == "server":
+                late_ms = 1e3 * (time.perf_counter() - start - arrivals[i])
+                t = srv.submit(k, v, None, aggs=aggs)
+                pending[t] = (i, late_ms)
+                for tk in list(pending):
+                    done, lat_ms, st = srv.poll(tk)
+                    if done:
+                        if st != isa.ISA_OK:
+                            raise isa.InsortError(st, "request %d" % pending[tk][0])
+                        j, late = pending.pop(tk)
+                        lat[j] = lat_ms + late
+                        srv.live.pop(tk, None)
+            else:
+                plain(k, v)
+                lat[i] = 1e3 * (time.perf_counter() - start - arrivals[i])
+            del k, v
+            if i % 200 == 0:
+                print("bench: %s request %d" % (mode, i), file=sys.stderr, flush=True)
+        if srv is not None:
+            srv.drain()
+            for tk in list(pending):
+                done, lat_ms, st = srv.poll(tk)
+                if st != isa.ISA_OK:
+                    raise isa.InsortError(st, "request %d" % pending[tk][0])
+                j, late = pending.pop(tk)
+                lat[j] = lat_ms + late
+            srv.close()
+        wall = time.perf_counter() - start
+        return lat, wall
+
+    lat_s, wall_s = run("server")
+    lat_f, wall_f = run("fifo")
+    tot = int(rows.sum())
+    res = {
+        "metric": "p50/p99 latency batched vs plain; input rows/s aggregated",
+        "value": round(float(np.percentile(lat_s, 99)), 3),
+        "unit": "ms (p99, server)",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "data": "synthetic",
+        "dtype": "u64+i64",
+        "config": {"workload": "serve_c4", "requests": n_req, "rho": args.rho, "slots": args.slots,
+                   "hbm_cap_bytes": cap, "total_rows": tot},
+        "server": {"p50_ms": round(float(np.percentile(lat_s, 50)), 3),
+                   "p99_ms": round(float(np.percentile(lat_s, 99)), 3),
+                   "rows_per_s": round(tot / wall_s, 1), "wall_s": round(wall_s, 3)},
+        "fifo_plain": {"p50_ms": round(float(np.percentile(lat_f, 50)), 3),
+                       "p99_ms": round(float(np.percentile(lat_f, 99)), 3),
+                       "rows_per_s": round(tot / wall_f, 1), "wall_s": round(wall_f, 3)},
+        "plain_rate_rows_per_s": round(r_plain, 1),
+    }
+    print(json.dumps(res))
+    ctx.close()
 
 
 def main():
@@ -40,7 +284,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="spill_100M_zipf0.8", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="spill_100M_zipf0.8", choices=sorted(WORKLOADS) + list(FORMS))
+    ap.add_argument("--instances", type=int, default=10000, help="batch_*: number of instances")
+    ap.add_argument("--requests", type=int, default=2000, help="serve_c4: number of requests")
+    ap.add_argument("--rho", type=float, default=0.8, help="serve_c4: offered load vs the plain rate")
+    ap.add_argument("--slots", type=int, default=3, help="serve_c4: concurrent server batches")
     ap.add_argument("--cpu-sample", type=int, default=10_000_000,
                     help="rows of the input the CPU oracle is timed on (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
@@ -65,6 +313,13 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": nbytes, "calibrate_copy_bytes_written": nbytes,
                           "launches": 3}))
         return
+
+    if args.workload == "batch_c3":
+        return bench_batch(args, 1e3, 1e7)
+    if args.workload == "batch_small":
+        return bench_batch(args, 1e3, 1e5)
+    if args.workload == "serve_c4":
+        return bench_serve(args)
 
     import datagen
     import datagen.device as dgd

@@ -38,6 +38,7 @@ def _load():
         L.dg_zipf_keys.argtypes = [U, U, U, P, U, U, P, P]
         L.dg_uniform_i64.argtypes = [U, U, U, ctypes.c_int64, U, P, P]
         L.dg_normal_f64.argtypes = [U, U, U, P, P]
+        L.dg_zipf_approx_keys.argtypes = [U, U, U, U, ctypes.c_double, U, P, P]
         _lib = L
     return _lib
 
@@ -63,6 +64,15 @@ def keys(seed: int, n: int, d: int, s: float = 0.0, table_dev=None, start: int =
         if table_dev is None:
             table_dev = torch.from_numpy(zipf_cdf_table(d, s).view(np.int64)).cuda()
         _ck(L.dg_zipf_keys(seed, start, n, table_dev.data_ptr(), d, int(KEY_SALT), out.data_ptr(), _st()))
+    return out
+
+
+def zipf_approx_keys(seed: int, n: int, d: int, s: float, start: int = 0, out=None):
+    """Keys over a d-value domain with approximately Zipf(s) ranks (continuous
+    inversion; no table), for domains too large for an exact CDF table."""
+    import torch
+    out = torch.empty(n, dtype=torch.int64, device="cuda") if out is None else out
+    _ck(_load().dg_zipf_approx_keys(seed, start, n, d, float(s), int(KEY_SALT), out.data_ptr(), _st()))
     return out
 
 

@@ -48,6 +48,28 @@ __global__ void k_uniform_i64(uint64_t seed, uint64_t start, uint64_t n, int64_t
         out[i] = (int64_t)mulhi64(stream_at(seed, start + i), span) + lo;
 }
 
+// Approximate Zipf ranks over [0, d) by inverting the continuous density
+// proportional to x^-s on [1, d+1) (s != 1; s == 1 inverts the log).  Used
+// where an exact CDF table of the domain would be too large.
+__global__ void k_zipf_approx_keys(uint64_t seed, uint64_t start, uint64_t n, uint64_t d, double s, uint64_t salt,
+                                   uint64_t* out) {
+    const double dd = (double)d + 1.0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const double u = (double)(stream_at(seed, start + i) >> 11) * (1.0 / 9007199254740992.0);
+        double x;
+        if (fabs(s - 1.0) < 1e-9) {
+            x = exp(u * log(dd));
+        } else {
+            const double a = 1.0 - s;
+            x = pow(u * (pow(dd, a) - 1.0) + 1.0, 1.0 / a);
+        }
+        uint64_t r = (uint64_t)x;
+        r = r >= 1 ? r - 1 : 0;
+        if (r >= d) r = d - 1;
+        out[i] = mix64(r ^ salt);
+    }
+}
+
 // Standard normal by the Box-Muller transform of two stream values.
 __global__ void k_normal_f64(uint64_t seed, uint64_t start, uint64_t n, double* out) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -78,6 +100,12 @@ int dg_zipf_keys(uint64_t seed, uint64_t start, uint64_t n, const uint64_t* tabl
                  uint64_t* out, void* st) {
     if (!n) return 0;
     hipLaunchKernelGGL(k_zipf_keys, grid_for(n), dim3(256), 0, (hipStream_t)st, seed, start, n, table, d, salt, out);
+    return (int)hipGetLastError();
+}
+int dg_zipf_approx_keys(uint64_t seed, uint64_t start, uint64_t n, uint64_t d, double s, uint64_t salt, uint64_t* out,
+                        void* st) {
+    if (!n) return 0;
+    hipLaunchKernelGGL(k_zipf_approx_keys, grid_for(n), dim3(256), 0, (hipStream_t)st, seed, start, n, d, s, salt, out);
     return (int)hipGetLastError();
 }
 int dg_uniform_i64(uint64_t seed, uint64_t start, uint64_t n, int64_t lo, uint64_t span, int64_t* out, void* st) {
