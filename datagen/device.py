@@ -11,7 +11,7 @@ import subprocess
 
 import numpy as np
 
-from . import KEY_SALT, substream_seed, zipf_cdf_table
+from . import KEY_SALT, stream, substream_seed, zipf_cdf_table
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdatagen.so")
@@ -39,6 +39,8 @@ def _load():
         L.dg_uniform_i64.argtypes = [U, U, U, ctypes.c_int64, U, P, P]
         L.dg_normal_f64.argtypes = [U, U, U, P, P]
         L.dg_zipf_approx_keys.argtypes = [U, U, U, U, ctypes.c_double, U, P, P]
+        L.dg_uniform_ranks.argtypes = [U, U, U, U, P, P]
+        L.dg_segment_b.argtypes = [U, U, U, U, P, P, P]
         _lib = L
     return _lib
 
@@ -96,3 +98,24 @@ def plain_input(seed: int, n: int, d: int, s: float = 0.0, with_f64: bool = Fals
     v = uniform_i64(substream_seed(seed, 2), n)
     f = normal_f64(substream_seed(seed, 3), n) if with_f64 else None
     return k, v, f
+
+
+def segmented_input(seed: int, n: int, n_a: int = 1000, b_per_a: int = 100_000):
+    """Device twin of datagen.segmented_input (all three columns bit-identical).
+    The segment of each row is drawn on the device and sorted there."""
+    import torch
+    L = _load()
+    cand = (stream(substream_seed(seed, 10), 0, 4 * n_a) >> np.uint64(32)).astype(np.uint32).view(np.int32)
+    _, first = np.unique(cand, return_index=True)
+    a_vals = np.sort(cand[np.sort(first)[:n_a]])
+    n_a = a_vals.shape[0]
+    seg = torch.empty(n, dtype=torch.int64, device="cuda")
+    _ck(L.dg_uniform_ranks(substream_seed(seed, 11), 0, n, n_a, seg.data_ptr(), _st()))
+    seg = torch.sort(seg).values
+    a = torch.from_numpy(a_vals).cuda()[seg]
+    b = torch.empty(n, dtype=torch.int32, device="cuda")
+    _ck(L.dg_segment_b(substream_seed(seed, 12), n, b_per_a, substream_seed(seed, 13), seg.data_ptr(),
+                       b.data_ptr(), _st()))
+    del seg
+    v = uniform_i64(substream_seed(seed, 14), n)
+    return a, b, v

@@ -48,6 +48,23 @@ __global__ void k_uniform_i64(uint64_t seed, uint64_t start, uint64_t n, int64_t
         out[i] = (int64_t)mulhi64(stream_at(seed, start + i), span) + lo;
 }
 
+// Ranks uniform over [0, d) (no key mixing).
+__global__ void k_uniform_ranks(uint64_t seed, uint64_t start, uint64_t n, uint64_t d, int64_t* out) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = (int64_t)mulhi64(stream_at(seed, start + i), d);
+}
+
+// B column of the segmented input: per-A domain value j of segment g is the
+// top 32 bits of mix(g * b_per_a + j) ^ salt.
+__global__ void k_segment_b(uint64_t seed, uint64_t n, uint64_t b_per_a, uint64_t salt, const int64_t* seg,
+                            int32_t* b) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t j = mulhi64(stream_at(seed, i), b_per_a);
+        const uint64_t code = (uint64_t)seg[i] * b_per_a + j;
+        b[i] = (int32_t)(uint32_t)(mix64(code ^ salt) >> 32);
+    }
+}
+
 // Approximate Zipf ranks over [0, d) by inverting the continuous density
 // proportional to x^-s on [1, d+1) (s != 1; s == 1 inverts the log).  Used
 // where an exact CDF table of the domain would be too large.
@@ -111,6 +128,17 @@ int dg_zipf_approx_keys(uint64_t seed, uint64_t start, uint64_t n, uint64_t d, d
 int dg_uniform_i64(uint64_t seed, uint64_t start, uint64_t n, int64_t lo, uint64_t span, int64_t* out, void* st) {
     if (!n) return 0;
     hipLaunchKernelGGL(k_uniform_i64, grid_for(n), dim3(256), 0, (hipStream_t)st, seed, start, n, lo, span, out);
+    return (int)hipGetLastError();
+}
+int dg_uniform_ranks(uint64_t seed, uint64_t start, uint64_t n, uint64_t d, int64_t* out, void* st) {
+    if (!n) return 0;
+    hipLaunchKernelGGL(k_uniform_ranks, grid_for(n), dim3(256), 0, (hipStream_t)st, seed, start, n, d, out);
+    return (int)hipGetLastError();
+}
+int dg_segment_b(uint64_t seed, uint64_t n, uint64_t b_per_a, uint64_t salt, const int64_t* seg, int32_t* b,
+                 void* st) {
+    if (!n) return 0;
+    hipLaunchKernelGGL(k_segment_b, grid_for(n), dim3(256), 0, (hipStream_t)st, seed, n, b_per_a, salt, seg, b);
     return (int)hipGetLastError();
 }
 int dg_normal_f64(uint64_t seed, uint64_t start, uint64_t n, double* out, void* st) {
