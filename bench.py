@@ -292,6 +292,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=10_000_000,
                     help="rows of the input the CPU oracle is timed on (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--profile-steps", type=int, default=2,
+                    help="extra untimed steps with per-kernel HIP-event timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -356,8 +358,6 @@ def main():
     for i in range(args.warmup):
         step()
         print("bench: warmup %d done" % i, file=sys.stderr, flush=True)
-    if not args.no_profile:
-        ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -365,9 +365,19 @@ def main():
         print("bench: step %d done" % i, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = ctx.profile_read() if not args.no_profile else {}
-    ctx.profile(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    # per-kernel HIP-event timing in separate steps, so that the event records
+    # do not enter the timed steps above
+    prof = {}
+    prof_steps = 0 if args.no_profile else args.profile_steps
+    if prof_steps:
+        ctx.profile(True)
+        for i in range(prof_steps):
+            step()
+        torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        print("bench: %d profiled step(s) done" % prof_steps, file=sys.stderr, flush=True)
     groups = out.n_groups
     stats = st.as_dict()
 
@@ -380,7 +390,7 @@ def main():
     if prof:
         for name, r in prof.items():
             kernels[name] = {"launches": r["launches"], "avg_us": 1e3 * r["total_ms"] / max(1, r["launches"]),
-                             "ms_per_step": r["total_ms"] / args.steps,
+                             "ms_per_step": r["total_ms"] / prof_steps,
                              "rows_per_launch": r["rows"] / max(1, r["launches"]),
                              "algo_GBps": (r["bytes"] / (r["total_ms"] * 1e-3) / 1e9) if r["total_ms"] else None}
         dev_kernels = {k: v for k, v in prof.items() if k.startswith("k_")}
@@ -395,7 +405,7 @@ def main():
     host_link = None
     if stats["spilled_rows"]:
         hb = 2 * stats["spilled_bytes"]
-        hl_ms = sum(prof[k]["total_ms"] for k in ("spill_d2h", "merge_h2d") if k in prof) / args.steps
+        hl_ms = sum(prof[k]["total_ms"] for k in ("spill_d2h", "merge_h2d") if k in prof) / max(1, prof_steps)
         host_link = {"bytes_per_step": hb, "copy_ms_per_step": round(hl_ms, 2),
                      "GBps": round(hb / (hl_ms * 1e-3) / 1e9, 1) if hl_ms else None}
 

@@ -129,13 +129,15 @@ uint64_t merge_scratch_bytes(uint64_t rows) {
 }
 
 // Workspace used by run generation with batch Bt and index capacity K: two
-// index buffers (the merge reads one and writes the other), one batch run, the
-// merge's scratch and the sort-reduce area of one batch.
+// index buffers of K + Bt rows (the merge reads one and writes the other),
+// three batch runs (one being sorted, one being absorbed, one kept until the
+// previous absorb is decided), the merge's scratch, the batch program and the
+// compact-run split's scratch.
 uint64_t rungen_bytes(uint64_t Bt, uint64_t K, const Cols& k) {
     const uint64_t sw = (uint64_t)state_layout(k).words * 8;
     const uint64_t split_scratch = ((K + Bt) / 4096 + 4) * 24 + 1024;
-    return 2 * (K + Bt) * sw + Bt * sw + merge_scratch_bytes(K + 2 * Bt) + sort_reduce_bytes(Bt, 1, k, false) +
-           split_scratch + MERGE_MARGIN + 12 * 256 + (MAX_BUCKETS - 1) * 8;
+    return 2 * (K + Bt) * sw + 3 * Bt * sw + merge_scratch_bytes(K + 2 * Bt) + batch_program_bytes(Bt, k) +
+           split_scratch + MERGE_MARGIN + 16 * 256 + (MAX_BUCKETS - 1) * 8;
 }
 
 // Share of the budget given to the batch area (1/share); the rest holds the
@@ -195,170 +197,239 @@ uint64_t lower_bound_strided(const uint64_t* keys, uint64_t stride, uint64_t pos
 // the largest fence whose window still fits (the forecasting order of page
 // reads by the highest key read, Section 4 Figure 9).  Keys below the window
 // end are final once the window is reduced; they are appended to the output.
+//
+// Runs are read in place from pinned host memory through its device mapping:
+// one gather launch per window copies every slice into a staging buffer (and
+// expands count-1 rows to state rows), on a side stream, two windows ahead of
+// the window being reduced.  A window is cut at fence keys into pieces of at
+// most PIECE_CAP rows; its pieces are reduced together by one flat launch
+// sequence as key-ordered instances sharing the window's destination.
+constexpr uint64_t PIECE_CAP = FLAT_MAX * 3 / 4;
+
 void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::vector<RunInfo>& runs,
                 const char* host, uint64_t* idx, uint64_t n_idx, isa_output* out, isa_stats* st,
                 uint64_t& n_groups) {
     const Layout S = state_layout(k);
     const Layout Rl = raw_layout(k);
     const uint64_t sw = (uint64_t)S.words, rw = (uint64_t)Rl.words;
+    void* hdev = nullptr;
+    if (hipHostGetDevicePointer(&hdev, (void*)host, 0) != hipSuccess || !hdev)
+        throw Fail{ISA_EINVAL, "spill buffer is not device-mapped pinned memory"};
+    const char* host_dev = (const char*)hdev;
     // index keys on the host (one strided D2H copy)
     std::vector<uint64_t> idx_keys(n_idx);
     if (n_idx) {
+        const uint64_t mark0 = A.off;
+        uint64_t* d_keys = A.take_n<uint64_t>(n_idx);
+        launch_extract_keys(idx, n_idx, (uint32_t)sw, d_keys, E.stream);
         void* p = E.pinned_buf(n_idx * 8);
-        ck(hipMemcpy2DAsync(p, 8, idx, sw * 8, 8, n_idx, hipMemcpyDeviceToHost, E.stream), "hipMemcpy2DAsync");
+        ck(hipMemcpyAsync(p, d_keys, n_idx * 8, hipMemcpyDeviceToHost, E.stream), "hipMemcpyAsync(index keys)");
         E.sync();
         std::memcpy(idx_keys.data(), p, n_idx * 8);
+        A.off = mark0;
     }
-    // Sources: every run contributes its count-1 sub-run (raw rows, host) and
-    // its other rows (state rows, host); the last source is the index
-    // (state rows, device).
+    // Sources: every run contributes its count-1 sub-run (raw rows) and its
+    // other rows (state rows); the last source is the index (state rows,
+    // device).  keys: host view of the keys, strided; rows: device-visible
+    // address of the rows.
     struct Src {
-        const uint64_t* keys;   // host view of the keys, strided
+        const uint64_t* keys;
         uint64_t stride, n;
-        const uint64_t* rows;   // rows to copy (host or device)
-        bool raw, device;
+        const uint64_t* rows;
+        bool raw;
     };
     std::vector<Src> src;
+    auto on_dev = [&](const uint64_t* hp) { return (const uint64_t*)(host_dev + ((const char*)hp - host)); };
+    uint64_t total = 0;
     for (const RunInfo& r : runs) {
         const uint64_t* base = (const uint64_t*)(host + r.byte_off);
-        if (r.n_single) src.push_back(Src{base, rw, r.n_single, base, true, false});
+        if (r.n_single) src.push_back(Src{base, rw, r.n_single, on_dev(base), true});
         const uint64_t* mb = base + r.n_single * rw;
-        if (r.n_multi) src.push_back(Src{mb, sw, r.n_multi, mb, false, false});
+        if (r.n_multi) src.push_back(Src{mb, sw, r.n_multi, on_dev(mb), false});
+        total += r.n_single + r.n_multi;
     }
-    if (n_idx) src.push_back(Src{idx_keys.data(), 1, n_idx, idx, false, true});
+    if (n_idx) src.push_back(Src{idx_keys.data(), 1, n_idx, idx, false});
+    total += n_idx;
     const size_t ns = src.size();
     std::vector<uint64_t> pos(ns, 0);
 
-    // window capacity: two state staging buffers (the next window is copied
-    // while the current one is reduced), one raw area (expanded before the
-    // next window's copies start on the same stream) and the sort-reduce of
-    // the state rows
-    const uint64_t per_row = (2 * sw + rw) * 8 + (sort_reduce_bytes(1, 0, k, true) - (4u << 20));
-    const uint64_t avail = A.left() > (6u << 20) ? A.left() - (6u << 20) : 0;
-    const uint64_t W = avail / per_row;
+    // window capacity W: three staging buffers (two windows gathered ahead of
+    // the one being reduced), the gather task table and the flat plan of a
+    // window; a piece that falls back to the general plan is reduced alone
+    const uint64_t avail0 = A.left() > (8u << 20) ? A.left() - (8u << 20) : 0;
+    const uint64_t piece_fallback = sort_reduce_bytes(PIECE_CAP, 1, k, true);
+    auto need = [&](uint64_t w, uint64_t tasks) {
+        const uint64_t pieces = w / (PIECE_CAP / 2) + 2;
+        return 3 * w * sw * 8 + tasks * sizeof(GatherTask) +
+               std::max(flat_bytes(w, pieces, k, true), std::min(piece_fallback, sort_reduce_bytes(w, 1, k, true)));
+    };
+    // every window but the last holds at least 3/4 W rows (fences every P rows)
+    auto task_bound = [&](uint64_t w) {
+        return total / GATHER_ROWS + (total / (w - w / 4) + 2) * (ns + 1) * (w / (PIECE_CAP / 2) + 2) + 16;
+    };
+    uint64_t W = avail0 / (3 * sw * 8);
+    while (W > 2 * (ns + 1) && need(W, task_bound(W)) > avail0) W -= W / 32 + 1;
     if (W < 2 * (ns + 1)) throw Fail{ISA_ESPILL, "workspace too small for a single wide merge of all runs"};
-    const uint64_t P = std::max<uint64_t>(1, W / (4 * (ns + 1)));
-    std::vector<uint64_t> fences;
+    // Fences: the key of every P-th row of each source, merged in key order.
+    // A cut at key x ends source s at lb_s(x) = its first row >= x; with c_s
+    // of its fences below x, lb_s(x) lies in [c_s P, (c_s + 1) P], so the
+    // fences bound the rows below x from above without touching the runs,
+    // and one short search per source makes the chosen cut exact.
+    const uint64_t P = std::max<uint64_t>(1, std::min(W, PIECE_CAP) / (4 * (ns + 1)));
+    struct Fence {
+        uint64_t key;
+        uint32_t src;
+    };
+    std::vector<Fence> fl;
     for (size_t s = 0; s < ns; ++s)
-        for (uint64_t i = P; i < src[s].n; i += P) fences.push_back(src[s].keys[i * src[s].stride]);
-    std::sort(fences.begin(), fences.end());
-    fences.erase(std::unique(fences.begin(), fences.end()), fences.end());
-
-    auto lb = [&](size_t s, uint64_t x) {
-        return lower_bound_strided(src[s].keys, src[s].stride, pos[s], src[s].n, x);
+        for (uint64_t i = P; i < src[s].n; i += P) fl.push_back(Fence{src[s].keys[i * src[s].stride], (uint32_t)s});
+    std::sort(fl.begin(), fl.end(), [](const Fence& x, const Fence& y) { return x.key < y.key; });
+    std::vector<uint64_t> cnt(ns, 0);  // fences of each source below the last cut key
+    size_t fi = 0;                     // first fence not below the last cut key
+    auto hi_of = [&](size_t s, uint64_t c) { return std::min<uint64_t>(src[s].n, (c + 1) * P); };
+    auto lb_in = [&](size_t s, uint64_t x) {
+        const uint64_t lo = std::max<uint64_t>(pos[s], cnt[s] * P);
+        return lower_bound_strided(src[s].keys, src[s].stride, lo, hi_of(s, cnt[s]), x);
     };
-    auto rows_below = [&](uint64_t x) {
-        uint64_t c = 0;
-        for (size_t s = 0; s < ns; ++s) c += lb(s, x) - pos[s];
-        return c;
-    };
-    // plan every window: per source, the slice [lo, hi)
-    std::vector<std::vector<uint64_t>> win_lo, win_hi;
-    std::vector<uint64_t> win_rows, win_raw;
-    for (;;) {
+    // the next cut: all remaining rows if at most `cap`, else every row below
+    // the largest fence key x whose bound on the rows below it is <= cap;
+    // with no such key, the rows of the smallest key (at most one per source)
+    // when `must`, else nothing
+    auto next_cut = [&](uint64_t cap, bool must, std::vector<uint64_t>& end) -> uint64_t {
         uint64_t remaining = 0, min_key = ~0ull;
         for (size_t s = 0; s < ns; ++s) {
             remaining += src[s].n - pos[s];
             if (pos[s] < src[s].n) min_key = std::min(min_key, src[s].keys[pos[s] * src[s].stride]);
         }
-        if (!remaining) break;
-        std::vector<uint64_t> end(ns);
-        if (remaining <= W) {
+        // (all remaining keys equal to the largest key value: at most one row per source)
+        if (remaining <= cap || (must && min_key == ~0ull)) {
             for (size_t s = 0; s < ns; ++s) end[s] = src[s].n;
+            while (fi < fl.size()) ++cnt[fl[fi++].src];
+            return remaining;
+        }
+        if (min_key == ~0ull) return 0;
+        uint64_t U = 0;
+        for (size_t s = 0; s < ns; ++s) U += hi_of(s, cnt[s]) - pos[s];
+        size_t j = fi, best_j = fl.size();
+        uint64_t x = 0;
+        while (j < fl.size() && U <= cap) {
+            const uint64_t key = fl[j].key;
+            if (key > min_key) {
+                x = key;
+                best_j = j;
+            }
+            for (; j < fl.size() && fl[j].key == key; ++j) {
+                const uint32_t s = fl[j].src;
+                U += hi_of(s, cnt[s] + 1) - hi_of(s, cnt[s]);
+                ++cnt[s];
+            }
+        }
+        if (best_j == fl.size()) {
+            for (size_t t = fi; t < j; ++t) --cnt[fl[t].src];
+            if (!must) return 0;
+            x = min_key + 1;
+            for (j = fi; j < fl.size() && fl[j].key <= min_key; ++j) ++cnt[fl[j].src];
+            best_j = j;
+            // every fence at or below min_key is counted: each source's cut lies
+            // in its bounded range
         } else {
-            // largest fence f > min_key with rows_below(f) <= W
-            size_t lo = std::upper_bound(fences.begin(), fences.end(), min_key) - fences.begin();
-            size_t hi = fences.size();
-            size_t best = fences.size();
-            while (lo < hi) {
-                const size_t mid = (lo + hi) / 2;
-                if (rows_below(fences[mid]) <= W) {
-                    best = mid;
-                    lo = mid + 1;
-                } else {
-                    hi = mid;
+            for (size_t t = best_j; t < j; ++t) --cnt[fl[t].src];
+        }
+        fi = best_j;
+        uint64_t c = 0;
+        for (size_t s = 0; s < ns; ++s) {
+            end[s] = lb_in(s, x);
+            c += end[s] - pos[s];
+        }
+        return c;
+    };
+    // plan every window: its pieces and the gather tasks that lay the pieces
+    // out one after the other in the staging buffer
+    std::vector<GatherTask> tasks;
+    std::vector<uint32_t> task_first;
+    std::vector<uint64_t> win_rows, win_host_bytes;
+    std::vector<std::vector<uint64_t>> win_pieces;
+    std::vector<uint64_t> end(ns);
+    uint64_t left = total;
+    while (left) {
+        task_first.push_back((uint32_t)tasks.size());
+        uint64_t at = 0, hb = 0;
+        std::vector<uint64_t> pieces;
+        while (left && at < W) {
+            const uint64_t c = next_cut(std::min(PIECE_CAP, W - at), at == 0, end);
+            if (c == 0) break;  // the next piece would not fit this window
+            for (size_t s = 0; s < ns; ++s) {
+                const uint64_t w = src[s].raw ? rw : sw;
+                for (uint64_t r = pos[s]; r < end[s]; r += GATHER_ROWS) {
+                    const uint64_t len = std::min<uint64_t>(GATHER_ROWS, end[s] - r);
+                    tasks.push_back(GatherTask{src[s].rows + r * w, at, (uint32_t)len, src[s].raw ? 1u : 0u});
+                    at += len;
+                    if (s + 1 < ns || !n_idx) hb += len * w * 8;
                 }
             }
-            const uint64_t x = best < fences.size() ? fences[best] : min_key + 1;
-            for (size_t s = 0; s < ns; ++s) end[s] = lb(s, x);
+            pieces.push_back(c);
+            left -= c;
+            pos = end;
         }
-        uint64_t wrows = 0, wraw = 0;
-        for (size_t s = 0; s < ns; ++s) {
-            wrows += end[s] - pos[s];
-            if (src[s].raw) wraw += end[s] - pos[s];
-        }
-        win_lo.push_back(pos);
-        win_hi.push_back(end);
-        win_rows.push_back(wrows);
-        win_raw.push_back(wraw);
-        pos = end;
+        win_rows.push_back(at);
+        win_host_bytes.push_back(hb);
+        win_pieces.push_back(pieces);
     }
+    task_first.push_back((uint32_t)tasks.size());
     const size_t nw = win_rows.size();
-    uint64_t* stage[2];
-    stage[0] = A.take_n<uint64_t>(W * sw);
-    stage[1] = A.take_n<uint64_t>(W * sw);
-    uint64_t* stage_raw = A.take_n<uint64_t>(W * rw);
+    GatherTask* d_tasks = A.take_n<GatherTask>(tasks.size() + 1);
+    E.upload(d_tasks, tasks.data(), tasks.size() * sizeof(GatherTask));
+    uint64_t* stage[3];
+    for (int j = 0; j < 3; ++j) stage[j] = A.take_n<uint64_t>(W * sw);
     const uint64_t mark = A.off;
-    hipStream_t cs = E.copier();
-    constexpr int NQ = 4;  // copy queues: the copy stream and three side streams
-    hipStream_t q[NQ] = {cs, E.side(0), E.side(1), E.side(2)};
-    // Window w into stage[w % 2]: state slices directly, count-1 slices into
-    // the raw area; slices spread over the copy queues, which join on the
-    // copy stream; the raw rows are then expanded behind the state rows.
+    hipStream_t gs = E.side(0);
+    // the gathers read the task table uploaded on the caller's stream
+    ck(hipEventRecord(E.sync_event(4), E.stream), "hipEventRecord");
+    ck(hipStreamWaitEvent(gs, E.sync_event(4), 0), "hipStreamWaitEvent");
     auto issue = [&](size_t w) {
-        uint64_t* dst = stage[w & 1];
-        uint64_t at = 0, at_raw = 0;
-        E.pbegin("merge_h2d", cs);
-        ck(hipEventRecord(E.sync_event(4), cs), "hipEventRecord");
-        for (int i = 1; i < NQ; ++i) ck(hipStreamWaitEvent(q[i], E.sync_event(4), 0), "hipStreamWaitEvent");
-        uint64_t bytes = 0;
-        int qi = 0;
-        for (size_t s = 0; s < ns; ++s) {
-            const uint64_t lo = win_lo[w][s], len = win_hi[w][s] - lo;
-            if (!len) continue;
-            hipStream_t qs = q[qi];
-            qi = (qi + 1) % NQ;
-            if (src[s].raw) {
-                ck(hipMemcpyAsync(stage_raw + at_raw * rw, src[s].rows + lo * rw, len * rw * 8, hipMemcpyHostToDevice,
-                                  qs),
-                   "hipMemcpyAsync(run slice)");
-                at_raw += len;
-                bytes += len * rw * 8;
-            } else {
-                ck(hipMemcpyAsync(dst + at * sw, src[s].rows + lo * sw, len * sw * 8,
-                                  src[s].device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, qs),
-                   "hipMemcpyAsync(run slice)");
-                at += len;
-                if (!src[s].device) bytes += len * sw * 8;
-            }
-        }
-        for (int i = 1; i < NQ; ++i) {
-            ck(hipEventRecord(E.sync_event(4 + i), q[i]), "hipEventRecord");
-            ck(hipStreamWaitEvent(cs, E.sync_event(4 + i), 0), "hipStreamWaitEvent");
-        }
-        E.pend(win_rows[w], bytes, cs);
-        launch_expand(stage_raw, at_raw, Rl, S, dst + at * sw, cs);
-        ck(hipEventRecord(E.sync_event(2 + (w & 1)), cs), "hipEventRecord");
+        // stage[w % 3] was last read by window w-3, whose reduction has completed
+        E.pbegin("merge_h2d", gs);
+        launch_gather(d_tasks + task_first[w], task_first[w + 1] - task_first[w], Rl, S, stage[w % 3], gs);
+        E.pend(win_rows[w], win_host_bytes[w], gs);
+        ck(hipEventRecord(E.sync_event(5 + (w % 3)), gs), "hipEventRecord");
     };
-    if (nw) issue(0);
+    for (size_t w = 0; w < std::min<size_t>(2, nw); ++w) issue(w);
     uint64_t cursor = 0;
     for (size_t w = 0; w < nw; ++w) {
-        // stage[(w+1) % 2] was last read by window w-1, which has completed
-        if (w + 1 < nw) issue(w + 1);
-        ck(hipStreamWaitEvent(E.stream, E.sync_event(2 + (w & 1)), 0), "hipStreamWaitEvent");
+        if (w + 2 < nw) issue(w + 2);
+        ck(hipStreamWaitEvent(E.stream, E.sync_event(5 + (w % 3)), 0), "hipStreamWaitEvent");
         A.off = mark;
-        const uint64_t cap = out->capacity > cursor ? out->capacity - cursor : 0;
-        Dest d;
-        d.out = output_view(*out, aggs, std::min(cursor, out->capacity));
-        d.capacity = cap;
-        std::vector<Instance> inst(1);
-        inst[0].src = aos_view(stage[w & 1], S);
-        inst[0].n = win_rows[w];
-        inst[0].dest = 0;
-        const std::vector<uint64_t> g = sort_reduce(E, A, inst, std::vector<Dest>(1, d), k, true);
-        cursor += g[0];
+        auto dest_at = [&](uint64_t c) {
+            Dest d;
+            d.out = output_view(*out, aggs, std::min(c, out->capacity));
+            d.capacity = out->capacity > c ? out->capacity - c : 0;
+            return d;
+        };
+        std::vector<Instance> inst;
+        uint64_t row = 0;
+        for (uint64_t pc : win_pieces[w]) {
+            Instance x;
+            x.src = aos_view(stage[w % 3] + row * sw, S);
+            x.n = pc;
+            x.dest = 0;
+            inst.push_back(x);
+            row += pc;
+        }
+        std::vector<uint64_t> g;
+        if (sort_reduce_flat(E, A, inst, std::vector<Dest>(1, dest_at(cursor)), k, true, nullptr, false, g)) {
+            cursor += g[0];
+        } else {
+            // a bucket too large for a leaf: reduce the pieces one at a time
+            // with the general plan
+            for (const Instance& x : inst) {
+                A.off = mark;
+                cursor += sort_reduce(E, A, std::vector<Instance>(1, x), std::vector<Dest>(1, dest_at(cursor)), k,
+                                      true)[0];
+            }
+        }
         if (st) st->windows++;
     }
+    ck(hipStreamSynchronize(gs), "hipStreamSynchronize(gather)");
     A.off = mark;
     n_groups = cursor;
 }
@@ -503,11 +574,14 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
         } else {
             Plan p;
             if (!plan_batches(ws.bytes, n, k, p)) return ISA_EBUDGET;
+            const uint64_t buf_rows = p.capacity + p.batch_rows;
+            const uint64_t buf_bytes = buf_rows * sw * 8;
             uint64_t* idx[2];
-            idx[0] = A.take_n<uint64_t>((p.capacity + p.batch_rows) * sw);
-            idx[1] = A.take_n<uint64_t>((p.capacity + p.batch_rows) * sw);
-            uint64_t* brun = A.take_n<uint64_t>(p.batch_rows * sw);
-            const uint64_t mscr_parts = merge_parts(p.capacity + p.batch_rows, p.batch_rows) + 1;
+            idx[0] = A.take_n<uint64_t>(buf_rows * sw);
+            idx[1] = A.take_n<uint64_t>(buf_rows * sw);
+            uint64_t* brun[3];
+            for (int j = 0; j < 3; ++j) brun[j] = A.take_n<uint64_t>(p.batch_rows * sw);
+            const uint64_t mscr_parts = merge_parts(buf_rows, p.batch_rows) + 1;
             // merge control block: [ticket, error], merged row count, per-partition
             // status; then the partition splits
             uint64_t* m_ctl = A.take_n<uint64_t>(mscr_parts + 2);
@@ -515,7 +589,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             // compact runs need a count column and a raw row narrower than a state row
             const Layout Rl = raw_layout(k);
             const bool compact = S.cnt >= 0 && Rl.words < S.words;
-            const uint64_t sp_blocks = split_blocks(p.capacity + p.batch_rows) + 1;
+            const uint64_t sp_blocks = split_blocks(buf_rows) + 1;
             uint32_t* sp_counts = A.take_n<uint32_t>(sp_blocks);
             uint64_t* sp_offs = A.take_n<uint64_t>(sp_blocks + 1);
             uint64_t* sp_tiles = A.take_n<uint64_t>(scan_tiles(sp_blocks) + 1);
@@ -528,102 +602,169 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             hint.dev = d_gspl;
             hint.host = h_gspl.data();
             hint.nb = buckets_for(p.batch_rows);
-            const uint64_t mark = A.off;
+            std::vector<Dest> bdest(3);
+            for (int j = 0; j < 3; ++j) {
+                bdest[j].out = aos_out(brun[j], S);
+                bdest[j].capacity = p.batch_rows;
+            }
+            BatchProgram bp;
+            bp.setup(E, A, src, n, p.batch_rows, k, hint, bdest);
+            const uint64_t top = A.off;
+
+            // The batches form a software pipeline on the stream: batch i+1 is
+            // sorted while the host decides on the absorb of batch i-1, so the
+            // device never waits for a host round trip.  Batch runs rotate over
+            // three buffers.
             int cur = 0;
             uint64_t n_idx = 0;
+            bool have_index = false;
             std::vector<RunInfo> runs;
             uint64_t spill_used = 0, spilled_bytes = 0;  // bytes of the spill buffer in use
             uint64_t batches = 0, spilled = 0;
-            bool spill_pending = false;
-            for (uint64_t b0 = 0; b0 < n; b0 += p.batch_rows) {
-                const uint64_t bn = std::min(p.batch_rows, n - b0);
-                ColView bsrc = src;
-                bsrc.key += b0;
-                if (bsrc.sum) bsrc.sum += b0, bsrc.mn += b0, bsrc.mx += b0;
-                if (bsrc.fs) bsrc.fs += b0;
-                std::vector<Instance> inst(1);
-                inst[0].src = bsrc;
-                inst[0].n = bn;
-                inst[0].dest = 0;
-                A.off = mark;
-                Dest d;
-                d.capacity = p.batch_rows;
-                if (n_idx == 0) {
-                    // an empty index simply becomes the batch's sorted run
-                    d.out = aos_out(idx[cur], S);
-                    n_idx = run_instances(E, A, inst, std::vector<Dest>(1, d), k, false, &hint, false)[0];
-                    ++batches;
-                    continue;
-                }
-                d.out = aos_out(brun, S);
-                const uint64_t g = run_instances(E, A, inst, std::vector<Dest>(1, d), k, false, &hint, false)[0];
-                ++batches;
-                // absorb the batch's distinct keys into the index if they fit:
-                // merge into the spare index buffer, keep the result only if
-                // it holds at most K keys
-                const uint64_t parts = merge_parts(n_idx, g);
-                if (spill_pending) {
-                    // the spare buffer is the source of a spill still in flight
+            // a run still being copied to host memory occupies idx[pend_buf]
+            // from byte pend_lo to its end
+            int pend_buf = -1;
+            uint64_t pend_lo = 0;
+            hipStream_t cs = E.copier();
+            auto ev_sort = [&](uint64_t i) { return E.sync_event(16 + (i % 4)); };
+            auto ev_merge = [&](uint64_t i) { return E.sync_event(20 + (i % 4)); };
+            auto rb_sort = [&](uint64_t i) { return E.ring_slot(i % 8); };
+            auto rb_merge = [&](uint64_t i) { return E.ring_slot(8 + (i % 8)); };
+            // order the stream after the pending run's copy when [0, end) of
+            // idx[buf] is about to be written over it
+            auto guard = [&](int buf, uint64_t end) {
+                if (pend_buf == buf && end > pend_lo) {
                     ck(hipStreamWaitEvent(E.stream, E.sync_event(1), 0), "hipStreamWaitEvent");
-                    spill_pending = false;
+                    pend_buf = -1;
                 }
-                launch_fill(m_ctl, parts + 2, 0, E.stream);
-                E.pbegin("k_merge");
-                launch_merge(idx[cur], n_idx, brun, g, idx[cur ^ 1], S, m_splits, m_ctl + 2, (uint32_t*)m_ctl,
-                             m_ctl + 1, E.stream);
-                E.pend(n_idx + g, (n_idx + g) * sw * 8);
-                const uint64_t* h_m = (const uint64_t*)download_async(E, m_ctl, 16);
-                E.sync();
-                if (h_m[0] >> 32) throw Fail{ISA_EDEVICE, "merge placement wait timed out"};
-                const uint64_t m = h_m[1];
+            };
+            // the batch's sorted run becomes the index
+            auto index_from_batch = [&](uint32_t slot, uint64_t g) {
+                guard(cur, g * sw * 8);
+                launch_copy_words(brun[slot], idx[cur], g * sw, E.stream);
+                n_idx = g;
+            };
+            // memory is full: write the index as one sorted run (read-sort-write).
+            // The run is split into its count-1 rows (raw layout) and the others,
+            // placed at the end of the spare buffer, and copied to host memory on
+            // the copy stream while run generation continues in the spare
+            // buffer's front.
+            auto spill_index = [&]() {
+                const int spare = cur ^ 1;
+                if (pend_buf >= 0) {
+                    ck(hipStreamWaitEvent(E.stream, E.sync_event(1), 0), "hipStreamWaitEvent");
+                    pend_buf = -1;
+                }
+                uint64_t n_single = 0, bytes = n_idx * sw * 8;
+                const uint64_t* run_src = idx[cur];
+                if (compact) {
+                    launch_split(idx[cur], n_idx, S, Rl, sp_counts, sp_tiles, sp_offs, idx[spare], buf_rows * sw,
+                                 E.stream);
+                    char* rb = E.ring_slot(16);
+                    ck(hipMemcpyAsync(rb, sp_offs + split_blocks(n_idx), 8, hipMemcpyDeviceToHost, E.stream),
+                       "hipMemcpyAsync(split count)");
+                    ck(hipStreamSynchronize(E.stream), "hipStreamSynchronize");
+                    n_single = *(const uint64_t*)rb;
+                    bytes = n_single * Rl.words * 8 + (n_idx - n_single) * sw * 8;
+                    run_src = (const uint64_t*)((const char*)idx[spare] + buf_bytes - bytes);
+                }
+                if (!spill.host_pinned || spill_used + bytes > spill.bytes)
+                    throw Fail{ISA_ESPILL, "spill buffer too small"};
+                ck(hipEventRecord(E.sync_event(0), E.stream), "hipEventRecord");
+                ck(hipStreamWaitEvent(cs, E.sync_event(0), 0), "hipStreamWaitEvent");
+                E.pbegin("spill_d2h", cs);
+                ck(hipMemcpyAsync((char*)spill.host_pinned + spill_used, run_src, bytes, hipMemcpyDeviceToHost, cs),
+                   "hipMemcpyAsync(spill)");
+                E.pend(n_idx, bytes, cs);
+                ck(hipEventRecord(E.sync_event(1), cs), "hipEventRecord");
+                RunInfo ri;
+                ri.byte_off = spill_used;
+                ri.n_single = n_single;
+                ri.n_multi = n_idx - n_single;
+                runs.push_back(ri);
+                spill_used += bytes;
+                spilled += n_idx;
+                spilled_bytes += bytes;
+                if (compact) {
+                    pend_buf = spare;
+                    pend_lo = buf_bytes - bytes;
+                } else {
+                    // the run is the index buffer itself; the next index lives in the spare
+                    pend_buf = cur;
+                    pend_lo = 0;
+                    cur = spare;
+                }
+                n_idx = 0;
+            };
+            // absorb decision for the merge of batch j (g_j rows): keep the
+            // merged index if it holds at most K keys, else spill the old index
+            // and start a new one with the batch
+            auto decide = [&](uint64_t j, uint64_t gj) {
+                const uint64_t* h = (const uint64_t*)rb_merge(j);
+                if (h[0] >> 32) throw Fail{ISA_EDEVICE, "merge placement wait timed out"};
+                const uint64_t m = h[1];
                 if (m <= p.capacity) {
                     cur ^= 1;
                     n_idx = m;
                 } else {
-                    // memory is full: write the index as one sorted run
-                    // (read-sort-write) and start a new index with the batch.
-                    // The run is split into its count-1 rows (raw layout) and
-                    // the others in the spare buffer, copied to host memory
-                    // on the copy stream while run generation continues.
-                    uint64_t n_single = 0;
-                    const uint64_t* src_run = idx[cur];
-                    if (compact) {
-                        launch_split(idx[cur], n_idx, S, Rl, sp_counts, sp_tiles, sp_offs, idx[cur ^ 1], E.stream);
-                        const uint64_t* h_s =
-                            (const uint64_t*)download_async(E, sp_offs + split_blocks(n_idx), 8);
-                        E.sync();
-                        n_single = *h_s;
-                        src_run = idx[cur ^ 1];
-                    }
-                    const uint64_t bytes = n_single * Rl.words * 8 + (n_idx - n_single) * sw * 8;
-                    if (!spill.host_pinned || spill_used + bytes > spill.bytes)
-                        throw Fail{ISA_ESPILL, "spill buffer too small"};
-                    hipStream_t cs = E.copier();
-                    ck(hipEventRecord(E.sync_event(0), E.stream), "hipEventRecord");
-                    ck(hipStreamWaitEvent(cs, E.sync_event(0), 0), "hipStreamWaitEvent");
-                    E.pbegin("spill_d2h", cs);
-                    ck(hipMemcpyAsync((char*)spill.host_pinned + spill_used, src_run, bytes, hipMemcpyDeviceToHost, cs),
-                       "hipMemcpyAsync(spill)");
-                    E.pend(n_idx, bytes, cs);
-                    ck(hipEventRecord(E.sync_event(1), cs), "hipEventRecord");
-                    RunInfo ri;
-                    ri.byte_off = spill_used;
-                    ri.n_single = n_single;
-                    ri.n_multi = n_idx - n_single;
-                    runs.push_back(ri);
-                    spill_used += bytes;
-                    spilled += n_idx;
-                    spilled_bytes += bytes;
-                    // the batch run becomes the index in the buffer not being copied
-                    uint64_t* dst = compact ? idx[cur] : idx[cur ^ 1];
-                    ck(hipMemcpyAsync(dst, brun, g * sw * 8, hipMemcpyDeviceToDevice, E.stream),
-                       "hipMemcpyAsync(batch run)");
-                    if (!compact) cur ^= 1;
-                    n_idx = g;
-                    spill_pending = true;
+                    spill_index();
+                    index_from_batch((uint32_t)(j % 3), gj);
                 }
+            };
+            bp.enqueue(E, 0, 0, rb_sort(0));
+            ck(hipEventRecord(ev_sort(0), E.stream), "hipEventRecord");
+            bool merge_out = false;  // a merge whose absorb is not decided yet
+            uint64_t merge_batch = 0, merge_g = 0;
+            for (uint64_t i = 0; i < bp.batches; ++i) {
+                const uint32_t slot = (uint32_t)(i % 3);
+                if (i + 1 < bp.batches) {
+                    bp.enqueue(E, i + 1, (uint32_t)((i + 1) % 3), rb_sort(i + 1));
+                    ck(hipEventRecord(ev_sort(i + 1), E.stream), "hipEventRecord");
+                }
+                ck(hipEventSynchronize(ev_sort(i)), "hipEventSynchronize");
+                if (merge_out) ck(hipEventSynchronize(ev_merge(merge_batch)), "hipEventSynchronize");
+                uint64_t g = 0;
+                if (!bp.result(rb_sort(i), g)) {
+                    // a bucket was too large for a leaf: redo the batch with the
+                    // general plan in the batch program's scratch (every queued
+                    // launch that uses it precedes this one on the stream)
+                    A.off = bp.scratch_off;
+                    std::vector<Instance> inst(1);
+                    inst[0].src = bp.batch_src(i);
+                    inst[0].n = bp.batch_n(i);
+                    inst[0].dest = 0;
+                    g = sort_reduce(E, A, inst, std::vector<Dest>(1, bdest[slot]), k, false, &hint)[0];
+                    A.off = top;
+                }
+                ++batches;
+                if (merge_out) {
+                    decide(merge_batch, merge_g);
+                    merge_out = false;
+                }
+                if (!have_index || n_idx == 0) {
+                    // an empty index simply becomes the batch's sorted run
+                    index_from_batch(slot, g);
+                    have_index = true;
+                    continue;
+                }
+                guard(cur ^ 1, (n_idx + g) * sw * 8);
+                const uint64_t parts = merge_parts(n_idx, g);
+                launch_fill(m_ctl, parts + 2, 0, E.stream);
+                E.pbegin("k_merge");
+                launch_merge(idx[cur], n_idx, brun[slot], g, idx[cur ^ 1], S, m_splits, m_ctl + 2, (uint32_t*)m_ctl,
+                             m_ctl + 1, E.stream);
+                E.pend(n_idx + g, (n_idx + g) * sw * 8);
+                ck(hipMemcpyAsync(rb_merge(i), m_ctl, 16, hipMemcpyDeviceToHost, E.stream), "hipMemcpyAsync(merge ctl)");
+                ck(hipEventRecord(ev_merge(i), E.stream), "hipEventRecord");
+                merge_out = true;
+                merge_batch = i;
+                merge_g = g;
             }
-            if (spill_pending) ck(hipStreamSynchronize(E.copier()), "hipStreamSynchronize(copy)");
+            if (merge_out) {
+                ck(hipEventSynchronize(ev_merge(merge_batch)), "hipEventSynchronize");
+                decide(merge_batch, merge_g);
+            }
+            if (!runs.empty()) ck(hipStreamSynchronize(cs), "hipStreamSynchronize(copy)");
             E.sync();
             const double t1 = now_ms();
             if (stats) {
@@ -643,10 +784,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 n_groups = n_idx;
             } else {
                 // keep only the live index; everything after it is merge space
-                if (cur == 1) {
-                    ck(hipMemcpyAsync(idx[0], idx[1], n_idx * sw * 8, hipMemcpyDeviceToDevice, E.stream),
-                       "hipMemcpyAsync(index)");
-                }
+                if (cur == 1) launch_copy_words(idx[1], idx[0], n_idx * sw, E.stream);
                 A.off = (uint64_t)((char*)idx[0] - A.base) + n_idx * sw * 8;
                 wide_merge(E, A, k, aggs, runs, (const char*)spill.host_pinned, idx[0], n_idx, out, stats,
                            n_groups);

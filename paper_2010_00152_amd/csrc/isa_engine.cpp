@@ -152,7 +152,15 @@ hipEvent_t Engine::sync_event(size_t i) {
     return sync_events[i];
 }
 
+char* Engine::ring_slot(size_t i) {
+    constexpr size_t SLOTS = 64;
+    if (!ring) ck(hipHostMalloc((void**)&ring, SLOTS * 64, 0), "hipHostMalloc(ring)");
+    return ring + (i % SLOTS) * 64;
+}
+
 void Engine::release() {
+    if (ring) hipHostFree(ring);
+    ring = nullptr;
     if (copy_stream) hipStreamDestroy(copy_stream);
     copy_stream = nullptr;
     for (hipStream_t& st : side_streams) {
@@ -262,6 +270,18 @@ uint64_t sort_reduce_bytes(uint64_t rows, uint64_t n_inst, const Cols& k, bool s
     const Layout S = state_layout(k);
     (void)S;
     return rows * (uint64_t)(2 * L.words) * 8 + rows * 4 + n_inst * 4608 + (4u << 20);
+}
+
+uint64_t flat_bytes(uint64_t rows, uint64_t n_inst, const Cols& k, bool state_rows) {
+    const Layout L = state_rows ? state_layout(k) : raw_layout(k);
+    // partition rows; per PART_TILE rows one histogram column of MAX_BUCKETS
+    // counters and offsets and one chunk; per instance its splitters, slots,
+    // status words and descriptors; 256-byte alignment of every block
+    const uint64_t cols = rows / PART_TILE + n_inst;
+    return rows * (uint64_t)L.words * 8 + cols * ((uint64_t)MAX_BUCKETS * 12 + sizeof(Chunk)) +
+           n_inst * ((MAX_BUCKETS - 1) * 8 + (uint64_t)MAX_BUCKETS * (sizeof(FlatSlot) + 8) + sizeof(Region) +
+                     sizeof(FlatInst) + sizeof(Dest) + 16) +
+           (64u << 10);
 }
 
 std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instance>& inst,
@@ -665,5 +685,129 @@ bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, co
     return finish_flat(h_ctl, dests.size(), totals);
 }
 
-}  // namespace isa
+// ---------------------------------------------------------------------------
+// BatchProgram: run generation's per-batch sort-reduce with every descriptor
+// uploaded once, so that a batch is a fixed sequence of launches.
+// ---------------------------------------------------------------------------
 
+namespace {
+constexpr uint32_t BP_CTL_RING = 8;  // control blocks reused round-robin
+
+uint64_t bp_chunk_rows(uint64_t Bt) {
+    uint64_t crow = (Bt / 512 + PART_TILE - 1) / PART_TILE * PART_TILE;
+    return std::max<uint64_t>(PART_TILE, std::min<uint64_t>(PART_CHUNK, crow));
+}
+}  // namespace
+
+uint64_t batch_program_bytes(uint64_t Bt, const Cols& k) {
+    const uint64_t ch = (Bt + bp_chunk_rows(Bt) - 1) / bp_chunk_rows(Bt);
+    const uint64_t hist = (uint64_t)MAX_BUCKETS * ch;
+    const uint64_t desc = BP_CTL_RING * sizeof(Region) + 2 * ch * sizeof(Chunk) + MAX_BUCKETS * sizeof(FlatSlot) +
+                          16 + 3 * sizeof(Dest) + BP_CTL_RING * (2 + MAX_BUCKETS) * 8;
+    const uint64_t scratch = Bt * (uint64_t)raw_layout(k).words * 8 + hist * 4 + (hist + 1) * 8 +
+                             (scan_tiles(hist) + 1) * 8 + 8 * 256;
+    // the scratch area also serves the general plan when a batch falls back
+    return desc + 8 * 256 + std::max(scratch, sort_reduce_bytes(Bt, 1, k, false));
+}
+
+void BatchProgram::setup(Engine& E, Arena& A, const ColView& src_rows, uint64_t n_rows, uint64_t batch_rows,
+                         const Cols& k, const SplitterHint& hint, const std::vector<Dest>& dests) {
+    n = n_rows;
+    Bt = batch_rows;
+    batches = (n + Bt - 1) / Bt;
+    nb = hint.nb;
+    L = raw_layout(k);
+    src = src_rows;
+    splitters = hint.dev;
+    const uint64_t crow = bp_chunk_rows(Bt);
+    chunks_full = (uint32_t)((Bt + crow - 1) / crow);
+    const uint64_t last_n = n - (batches - 1) * Bt;
+    chunks_last = (uint32_t)((last_n + crow - 1) / crow);
+    auto chunk_list = [&](uint64_t bn, uint32_t cnt) {
+        std::vector<Chunk> v(cnt);
+        for (uint32_t c = 0; c < cnt; ++c) {
+            v[c].region = 0;
+            v[c].idx = c;
+            v[c].start = (uint64_t)c * crow;
+            const uint64_t left = bn - v[c].start;
+            v[c].n = (uint32_t)(left < crow ? left : crow);
+            v[c].pad = 0;
+        }
+        return v;
+    };
+    const std::vector<Chunk> cf = chunk_list(Bt < n ? Bt : n, chunks_full);
+    const std::vector<Chunk> cl = chunk_list(last_n, chunks_last);
+    std::vector<FlatSlot> slots(nb);
+    for (uint32_t b = 0; b < nb; ++b) slots[b] = FlatSlot{1, 0, b, 0};
+    const uint32_t first[2] = {0, nb};
+    UpPack up;
+    const uint64_t o_cf = up.add(cf.data(), cf.size() * sizeof(Chunk));
+    const uint64_t o_cl = up.add(cl.data(), cl.size() * sizeof(Chunk));
+    const uint64_t o_slots = up.add(slots.data(), slots.size() * sizeof(FlatSlot));
+    const uint64_t o_first = up.add(first, sizeof(first));
+    const uint64_t o_dests = up.add(dests.data(), dests.size() * sizeof(Dest));
+    char* d = up.commit(E, A);
+    d_chunks_full = (Chunk*)(d + o_cf);
+    d_chunks_last = (Chunk*)(d + o_cl);
+    d_slots = (FlatSlot*)(d + o_slots);
+    d_first = (uint32_t*)(d + o_first);
+    d_dests = (Dest*)(d + o_dests);
+    d_regs = A.take_n<Region>(BP_CTL_RING);
+    d_ctl = A.take_n<uint64_t>(BP_CTL_RING * ctl_words());
+    scratch_off = A.off;
+    const uint64_t hist = (uint64_t)nb * chunks_full;
+    part = A.take_n<uint64_t>((Bt < n ? Bt : n) * (uint64_t)L.words);
+    d_hist = A.take_n<uint32_t>(hist + 1);
+    d_offs = A.take_n<uint64_t>(hist + 1);
+    d_tiles = A.take_n<uint64_t>(scan_tiles(hist) + 1);
+}
+
+ColView BatchProgram::batch_src(uint64_t i) const {
+    const uint64_t b0 = i * Bt;
+    ColView v = src;
+    v.key += b0;
+    if (v.sum) v.sum += b0, v.mn += b0, v.mx += b0;
+    if (v.fs) v.fs += b0;
+    return v;
+}
+
+void BatchProgram::enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback) {
+    const uint64_t bn = batch_n(i);
+    const bool last = i + 1 == batches;
+    const Chunk* ch = last ? d_chunks_last : d_chunks_full;
+    const uint32_t nch = last ? chunks_last : chunks_full;
+    Region r;
+    r.src = batch_src(i);
+    r.n = bn;
+    r.out_pos = 0;
+    r.hist_base = 0;
+    r.nb = nb;
+    r.n_chunks = nch;
+    Region* reg = d_regs + (i % BP_CTL_RING);
+    uint64_t* ctl = d_ctl + (i % BP_CTL_RING) * ctl_words();
+    hipStream_t st = E.stream;
+    launch_batch_prep(r, reg, ctl, (uint32_t)ctl_words(), st);
+    E.pbegin("k_hist", st);
+    launch_hist(reg, ch, nch, splitters, d_hist, st);
+    E.pend(bn, bn * 8, st);
+    launch_scan(d_hist, (uint64_t)nb * nch, d_tiles, d_offs, st);
+    E.pbegin("k_scatter", st);
+    launch_scatter(reg, ch, nch, splitters, d_offs, part, L, st);
+    E.pend(bn, bn * (uint64_t)L.words * 8, st);
+    E.pbegin("k_leaf", st);
+    launch_leaf_flat(d_slots, nb, nullptr, reg, splitters, d_offs, part, L, d_first, d_dests + slot, ctl + 2, ctl + 1,
+                     (uint32_t*)ctl, st);
+    E.pend(bn, bn * (uint64_t)L.words * 8, st);
+    ck(hipMemcpyAsync(readback, ctl, 16, hipMemcpyDeviceToHost, st), "hipMemcpyAsync(batch ctl)");
+}
+
+bool BatchProgram::result(const char* readback, uint64_t& groups) const {
+    const uint64_t* h = (const uint64_t*)readback;
+    const uint64_t err = h[0] >> 32;
+    if (err & 1) throw Fail{ISA_EDEVICE, "leaf placement wait timed out"};
+    if (err & 2) return false;
+    groups = h[1];
+    return true;
+}
+
+}  // namespace isa

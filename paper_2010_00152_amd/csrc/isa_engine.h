@@ -20,6 +20,9 @@ void launch_scatter(const Region* regions, const Chunk* chunks, uint32_t n_chunk
 void launch_bucket_starts(const Region* regions, uint32_t n_regions, const uint64_t* offs, const uint64_t* bs_base,
                           uint64_t* bstart, hipStream_t st);
 void launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st);
+void launch_copy_words(const uint64_t* src, uint64_t* dst, uint64_t n, hipStream_t st);
+void launch_extract_keys(const uint64_t* rows, uint64_t n, uint32_t stride, uint64_t* keys, hipStream_t st);
+void launch_batch_prep(const Region& r, Region* reg, uint64_t* ctl, uint32_t ctl_words, hipStream_t st);
 void launch_leaf(const Leaf* leaves, uint32_t n_leaves, const uint32_t* leaf_dest, const uint32_t* first_seg,
                  const Dest* dests, const void* partials, uint64_t* status, uint64_t* totals, uint32_t* ctl,
                  hipStream_t st);
@@ -35,8 +38,8 @@ void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb
                   uint64_t* splits, uint64_t* status, uint32_t* ctl, uint64_t* total_out, hipStream_t st);
 uint64_t split_blocks(uint64_t n);
 void launch_split(const uint64_t* rows, uint64_t n, Layout S, Layout R, uint32_t* counts, uint64_t* tiles,
-                  uint64_t* offs, uint64_t* out, hipStream_t st);
-void launch_expand(const uint64_t* raw, uint64_t n, Layout R, Layout S, uint64_t* out, hipStream_t st);
+                  uint64_t* offs, uint64_t* out, uint64_t end_words, hipStream_t st);
+void launch_gather(const GatherTask* tasks, uint32_t n_tasks, Layout R, Layout S, uint64_t* dst, hipStream_t st);
 void launch_copy_rows(ColView src, uint64_t n, OutView dst, uint64_t cap, hipStream_t st);
 uint64_t scan_tiles(uint64_t n);
 void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* offs, hipStream_t st);
@@ -103,6 +106,11 @@ struct Engine {
     hipStream_t capture_stream = nullptr;                       // graph capture only
     std::vector<hipEvent_t> sync_events;
 
+    // small pinned ring for readbacks that stay in flight across host waits
+    // (slots of 64 bytes, allocated once)
+    char* ring = nullptr;
+    char* ring_slot(size_t i);
+
     void* pinned_buf(uint64_t bytes);
     void upload(void* dev, const void* host, uint64_t bytes);
     void sync();
@@ -168,6 +176,45 @@ const void* download_async(Engine& E, const void* dev, uint64_t bytes);
 bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, const std::vector<Dest>& dests,
                       const Cols& k, bool state_rows, const SplitterHint* hint, bool graph,
                       std::vector<uint64_t>& totals);
+
+// The batches of one input sorted and reduced with the flat plan and fixed
+// splitters, every launch parameter prepared up front: batch i covers input
+// rows [i*Bt, min(n, (i+1)*Bt)) and its sorted unique state rows go to
+// dest[slot].  enqueue() launches one batch without any host round trip and
+// queues the readback of its control words into a ring slot; result() reads
+// them once that copy has completed.
+struct BatchProgram {
+    uint64_t n = 0, Bt = 0, batches = 0;
+    uint32_t nb = 0, chunks_full = 0, chunks_last = 0;
+    Layout L{};
+    ColView src{};
+    const uint64_t* splitters = nullptr;
+    Region* d_regs = nullptr;  // region ring (one per batch in flight)
+    Chunk* d_chunks_full = nullptr;
+    Chunk* d_chunks_last = nullptr;
+    FlatSlot* d_slots = nullptr;
+    uint32_t* d_first = nullptr;
+    Dest* d_dests = nullptr;
+    uint64_t* d_ctl = nullptr;  // ring of per-batch [ticket|error, total, status x nb]
+    uint64_t scratch_off = 0;   // arena offset of the per-batch scratch (reusable by a fallback)
+    uint64_t* part = nullptr;
+    uint32_t* d_hist = nullptr;
+    uint64_t* d_offs = nullptr;
+    uint64_t* d_tiles = nullptr;
+    uint64_t ctl_words() const { return 2 + (uint64_t)nb; }
+    void setup(Engine& E, Arena& A, const ColView& src, uint64_t n_rows, uint64_t batch_rows, const Cols& k,
+               const SplitterHint& hint, const std::vector<Dest>& dests);
+    void enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback);
+    // false when a bucket was too large for a leaf (the batch must be redone)
+    bool result(const char* readback, uint64_t& groups) const;
+    uint64_t batch_n(uint64_t i) const { return i + 1 < batches ? Bt : n - i * Bt; }
+    ColView batch_src(uint64_t i) const;
+};
+// Workspace of a BatchProgram, including room for the general plan of one batch.
+uint64_t batch_program_bytes(uint64_t Bt, const Cols& k);
+
+// Workspace bytes sort_reduce_flat needs for `rows` rows in n_inst instances.
+uint64_t flat_bytes(uint64_t rows, uint64_t n_inst, const Cols& k, bool state_rows);
 
 // Workspace bytes sort_reduce needs for `rows` input rows.
 uint64_t sort_reduce_bytes(uint64_t rows, uint64_t n_inst, const Cols& k, bool state_rows);

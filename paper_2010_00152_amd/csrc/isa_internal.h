@@ -119,6 +119,17 @@ struct Dest {
     uint64_t capacity;
 };
 
+// Rows per gather task of the wide merge (a raw slice is staged in LDS).
+constexpr uint32_t GATHER_ROWS = 1024;
+
+// One slice of a wide-merge window copied into the window's staging buffer.
+struct GatherTask {
+    const uint64_t* src;  // first row: host-mapped pinned memory or device memory
+    uint64_t dst_row;     // first state row written in the staging buffer
+    uint32_t n;           // rows, at most GATHER_ROWS
+    uint32_t raw;         // 1: raw-layout rows with count 1, expanded to state rows
+};
+
 // A span of gapped output copied into its final place.
 struct Segment {
     uint64_t src_pos;

@@ -561,6 +561,24 @@ __device__ uint64_t chained_prefix(uint64_t* status, uint32_t i, uint32_t first,
     return sum;
 }
 
+// Per-batch set-up of run generation: store the batch's region descriptor
+// (passed by value) and clear its control block.
+__global__ void k_batch_prep(Region r, Region* __restrict__ reg, uint64_t* __restrict__ ctl, uint32_t ctl_words) {
+    for (uint32_t i = threadIdx.x; i < ctl_words; i += blockDim.x) ctl[i] = 0;
+    if (threadIdx.x == 0) *reg = r;
+}
+
+// Plain word copy (device to device) and strided key extraction.
+__global__ void k_copy_words(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+__global__ void k_extract_keys(const uint64_t* __restrict__ rows, uint64_t n, uint32_t stride,
+                               uint64_t* __restrict__ keys) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        keys[i] = rows[i * stride];
+}
+
 __global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t value) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = value;
@@ -1240,10 +1258,11 @@ __global__ void __launch_bounds__(256) k_split_count(const uint64_t* __restrict_
 }
 
 // offs: exclusive scan of the counts (offs[nblocks] = all singles).  Singles
-// go to out[0 ..) in raw layout R, the rest after them in state layout S.
+// go first in raw layout R, the rest after them in state layout S; the block
+// starts at out[0], or ends at out[end_words] when end_words is nonzero.
 __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict__ rows, uint64_t n, Layout S,
                                                      Layout R, const uint64_t* __restrict__ offs, uint64_t nblocks,
-                                                     uint64_t* __restrict__ out) {
+                                                     uint64_t* __restrict__ out, uint64_t end_words) {
     __shared__ uint32_t s_tmp[256 / 64 + 1];
     constexpr int PER = SPLIT_T / 256;
     const uint64_t r0 = (uint64_t)blockIdx.x * SPLIT_T + (uint64_t)threadIdx.x * PER;
@@ -1255,6 +1274,7 @@ __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict_
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan<256>(c, s_tmp, tot);
     const uint64_t n_single = offs[nblocks];
+    if (end_words) out += end_words - (n_single * R.words + (n - n_single) * S.words);
     uint64_t so = offs[blockIdx.x] + ex;                       // singles before this thread
     uint64_t mo = r0 - so;                                     // others before this thread
     uint64_t* multi = out + n_single * R.words;
@@ -1276,21 +1296,59 @@ __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict_
     }
 }
 
-// Raw rows (layout R) to state rows (layout S) with count 1.
-__global__ void k_expand(const uint64_t* __restrict__ raw, uint64_t n, Layout R, Layout S,
-                         uint64_t* __restrict__ out) {
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t* src = raw + r * R.words;
-        uint64_t* d = out + r * S.words;
-        d[0] = src[0];
-        if (S.cnt >= 0) d[S.cnt] = 1;
-        if (S.sum >= 0) {
-            const uint64_t v = src[R.sum];
-            d[S.sum] = v;
-            d[S.mn] = v;
-            d[S.mx] = v;
+// Gather of a wide-merge window into one staging buffer of state rows.  A
+// small persistent grid walks the window's tasks (run slices of at most
+// GATHER_ROWS rows), reading pinned host memory through its device mapping
+// (or device memory) with contiguous word loads, four in flight per thread.
+// The grid is kept small on purpose: the loads wait on the host link, and
+// the window being reduced meanwhile needs the compute units.  Raw slices
+// (count-1 rows) are staged in LDS and expanded to state rows on the way out.
+constexpr int GATHER_NT = 256;
+constexpr uint32_t GATHER_GRID = 96;
+__global__ void __launch_bounds__(GATHER_NT) k_gather(const GatherTask* __restrict__ tasks, uint32_t n_tasks,
+                                                      Layout R, Layout S, uint64_t* __restrict__ dst) {
+    __shared__ uint64_t s_raw[GATHER_ROWS * 3];
+    const uint32_t sw = (uint32_t)S.words, rw = (uint32_t)R.words;
+    for (uint32_t ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
+        const GatherTask t = tasks[ti];
+        uint64_t* __restrict__ out = dst + t.dst_row * sw;
+        const uint64_t* __restrict__ in = t.src;
+        if (!t.raw) {
+            const uint32_t words = t.n * sw;
+            uint32_t i = threadIdx.x;
+            for (; i + 3 * GATHER_NT < words; i += 4 * GATHER_NT) {
+                const uint64_t a = in[i], b = in[i + GATHER_NT], c = in[i + 2 * GATHER_NT], d = in[i + 3 * GATHER_NT];
+                out[i] = a;
+                out[i + GATHER_NT] = b;
+                out[i + 2 * GATHER_NT] = c;
+                out[i + 3 * GATHER_NT] = d;
+            }
+            for (; i < words; i += GATHER_NT) out[i] = in[i];
+            continue;
         }
-        if (S.fs >= 0) d[S.fs] = src[R.fs];
+        const uint32_t words = t.n * rw;
+        uint32_t i = threadIdx.x;
+        for (; i + 3 * GATHER_NT < words; i += 4 * GATHER_NT) {
+            const uint64_t a = in[i], b = in[i + GATHER_NT], c = in[i + 2 * GATHER_NT], d = in[i + 3 * GATHER_NT];
+            s_raw[i] = a;
+            s_raw[i + GATHER_NT] = b;
+            s_raw[i + 2 * GATHER_NT] = c;
+            s_raw[i + 3 * GATHER_NT] = d;
+        }
+        for (; i < words; i += GATHER_NT) s_raw[i] = in[i];
+        __syncthreads();
+        const uint32_t owords = t.n * sw;
+        for (uint32_t o = threadIdx.x; o < owords; o += GATHER_NT) {
+            const uint32_t r = o / sw, c = o - r * sw;
+            const uint64_t* x = s_raw + r * rw;
+            uint64_t v;
+            if (c == 0) v = x[0];
+            else if ((int)c == S.cnt) v = 1;
+            else if ((int)c == S.fs) v = x[R.fs];
+            else v = x[R.sum];  // sum, min and max of one row are its value
+            out[o] = v;
+        }
+        __syncthreads();  // s_raw is refilled by the next task
     }
 }
 
@@ -1312,6 +1370,21 @@ void launch_scatter(const Region* regions, const Chunk* chunks, uint32_t n_chunk
 void launch_bucket_starts(const Region* regions, uint32_t n_regions, const uint64_t* offs, const uint64_t* bs_base,
                           uint64_t* bstart, hipStream_t st) {
     hipLaunchKernelGGL(k_bucket_starts, dim3(n_regions), dim3(256), 0, st, regions, offs, bs_base, bstart);
+}
+void launch_batch_prep(const Region& r, Region* reg, uint64_t* ctl, uint32_t ctl_words, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_prep, dim3(1), dim3(256), 0, st, r, reg, ctl, ctl_words);
+}
+void launch_copy_words(const uint64_t* src, uint64_t* dst, uint64_t n, hipStream_t st) {
+    if (!n) return;
+    uint64_t g = (n + 1023) / 1024;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_copy_words, dim3((uint32_t)g), dim3(256), 0, st, src, dst, n);
+}
+void launch_extract_keys(const uint64_t* rows, uint64_t n, uint32_t stride, uint64_t* keys, hipStream_t st) {
+    if (!n) return;
+    uint64_t g = (n + 1023) / 1024;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_extract_keys, dim3((uint32_t)g), dim3(256), 0, st, rows, n, stride, keys);
 }
 void launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st) {
     if (!n) return;
@@ -1356,18 +1429,17 @@ void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* 
 uint64_t split_blocks(uint64_t n) { return (n + SPLIT_T - 1) / SPLIT_T; }
 // counts: split_blocks(n) words; offs/tiles as for launch_scan.
 void launch_split(const uint64_t* rows, uint64_t n, Layout S, Layout R, uint32_t* counts, uint64_t* tiles,
-                  uint64_t* offs, uint64_t* out, hipStream_t st) {
+                  uint64_t* offs, uint64_t* out, uint64_t end_words, hipStream_t st) {
     const uint64_t nb = split_blocks(n);
     if (!nb) return;
     hipLaunchKernelGGL(k_split_count, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, counts);
     launch_scan(counts, nb, tiles, offs, st);
-    hipLaunchKernelGGL(k_split_write, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, R, offs, nb, out);
+    hipLaunchKernelGGL(k_split_write, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, R, offs, nb, out, end_words);
 }
-void launch_expand(const uint64_t* raw, uint64_t n, Layout R, Layout S, uint64_t* out, hipStream_t st) {
-    if (!n) return;
-    uint64_t g = (n + 255) / 256;
-    if (g > 8192) g = 8192;
-    hipLaunchKernelGGL(k_expand, dim3((uint32_t)g), dim3(256), 0, st, raw, n, R, S, out);
+void launch_gather(const GatherTask* tasks, uint32_t n_tasks, Layout R, Layout S, uint64_t* dst, hipStream_t st) {
+    if (!n_tasks) return;
+    const uint32_t g = n_tasks < GATHER_GRID ? n_tasks : GATHER_GRID;
+    hipLaunchKernelGGL(k_gather, dim3(g), dim3(GATHER_NT), 0, st, tasks, n_tasks, R, S, dst);
 }
 void launch_copy_rows(ColView src, uint64_t n, OutView dst, uint64_t cap, hipStream_t st) {
     const uint64_t lim = n < cap ? n : cap;
@@ -1381,7 +1453,7 @@ uint64_t scan_tiles(uint64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE; }
 void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* offs, hipStream_t st) {
     const uint64_t t = scan_tiles(n);
     if (t == 0) {
-        hipMemsetAsync(offs, 0, sizeof(uint64_t), st);
+        launch_fill(offs, 1, 0, st);
         return;
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)t), dim3(SCAN_NT), 0, st, in, n, tile_sums);

@@ -93,7 +93,7 @@ def test_zipf_all_aggs(ctx, s, seed):
     compare(got, k, v, f, isa.ISA_ALL, "zipf %s" % s)
 
 
-@pytest.mark.parametrize("s,seed,budget_mib", [(0.0, 5, 16), (0.8, 6, 16), (1.2, 7, 12), (0.0, 8, 24)])
+@pytest.mark.parametrize("s,seed,budget_mib", [(0.0, 5, 16), (0.8, 6, 16), (1.2, 7, 14), (0.0, 8, 24)])
 def test_spilling_matches_oracle_and_simulator(ctx, s, seed, budget_mib):
     # a budget far below the output forces runs on pinned host memory and a
     # wide merge; the run count and spilled rows equal the read-sort-write
@@ -195,3 +195,21 @@ def test_flat_plan_falls_back_on_oversized_bucket(ctx):
     v = datagen.uniform_i64(17, n)
     got, st, status, g = run_gpu(ctx, k, v, None, aggs=isa.ISA_INT_AGGS, budget=128 << 20)
     compare(got, k, v, None, isa.ISA_INT_AGGS, "fallback")
+
+
+def test_spilling_with_extreme_keys(ctx):
+    # runs whose first and last keys are 0 and 2^64-1: the wide merge's key
+    # windows must end exactly at the largest key value
+    say("case spill extreme keys")
+    n = 900_000
+    rng = np.random.default_rng(21)
+    k, v, f = datagen.plain_input(22, n, 300_000, 0.0, with_f64=True)
+    pool = np.array([0, 1, 1 << 63, (1 << 64) - 2, (1 << 64) - 1], np.uint64)
+    pick = rng.random(n) < 0.3
+    k = k.copy()
+    k[pick] = pool[rng.integers(0, len(pool), int(pick.sum()))]
+    got, st, status, g = run_gpu(ctx, k, v, f, budget=16 << 20)
+    compare(got, k, v, f, isa.ISA_ALL, "spill extremes")
+    assert st["runs"] > 0
+    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"])
+    assert st["runs"] == sim["runs"] and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
