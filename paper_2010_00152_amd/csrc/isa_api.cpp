@@ -159,7 +159,8 @@ bool plan_batches(uint64_t ws, uint64_t n, const Cols& k, Plan& p) {
             // K from the remaining bytes: 2*K*sw plus merge scratch growth
             uint64_t K = (ws - fixed) / (2 * sw + 1);
             while (K > 0 && rungen_bytes(Bt, K, k) > ws) K -= std::max<uint64_t>(1, K / 64);
-            if (K >= Bt) {
+            // K >= 2 Bt: an index made of one batch always absorbs the next batch
+            if (K >= 2 * Bt) {
                 p.batch_rows = Bt;
                 p.capacity = K;
                 return true;
@@ -521,7 +522,7 @@ uint64_t isa_state_row_bytes(uint32_t aggs) { return (uint64_t)state_layout(cols
 
 uint64_t isa_min_workspace_bytes(uint32_t aggs) {
     const Cols k = cols_of(aggs);
-    return rungen_bytes(MIN_BATCH, MIN_BATCH, k);
+    return rungen_bytes(MIN_BATCH, 2 * MIN_BATCH, k);
 }
 
 isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_workspace ws, isa_spill spill,
@@ -615,9 +616,12 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             // sorted while the host decides on the absorb of batch i-1, so the
             // device never waits for a host round trip.  Batch runs rotate over
             // three buffers.
-            int cur = 0;
+            // The index is `ip` (n_idx rows): one of the two index buffers, or,
+            // right after a spill or at the first batch, the batch run that
+            // starts it (K >= 2 Bt guarantees that the next merge absorbs it,
+            // before its buffer is reused).
+            const uint64_t* ip = nullptr;
             uint64_t n_idx = 0;
-            bool have_index = false;
             std::vector<RunInfo> runs;
             uint64_t spill_used = 0, spilled_bytes = 0;  // bytes of the spill buffer in use
             uint64_t batches = 0, spilled = 0;
@@ -626,10 +630,25 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             int pend_buf = -1;
             uint64_t pend_lo = 0;
             hipStream_t cs = E.copier();
+            // runs are written to the pinned spill buffer through its device mapping
+            char* spill_dev = nullptr;
+            if (spill.host_pinned) {
+                void* p_dev = nullptr;
+                if (hipHostGetDevicePointer(&p_dev, spill.host_pinned, 0) != hipSuccess || !p_dev)
+                    throw Fail{ISA_EINVAL, "spill buffer is not device-mapped pinned memory"};
+                spill_dev = (char*)p_dev;
+            }
             auto ev_sort = [&](uint64_t i) { return E.sync_event(16 + (i % 4)); };
             auto ev_merge = [&](uint64_t i) { return E.sync_event(20 + (i % 4)); };
             auto rb_sort = [&](uint64_t i) { return E.ring_slot(i % 8); };
             auto rb_merge = [&](uint64_t i) { return E.ring_slot(8 + (i % 8)); };
+            // the index buffer the next merge writes: not the index itself, and
+            // preferably not the one whose tail holds a run being copied out
+            auto merge_target = [&]() -> int {
+                if (ip == idx[0]) return 1;
+                if (ip == idx[1]) return 0;
+                return pend_buf == 0 ? 1 : 0;
+            };
             // order the stream after the pending run's copy when [0, end) of
             // idx[buf] is about to be written over it
             auto guard = [&](int buf, uint64_t end) {
@@ -638,28 +657,24 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     pend_buf = -1;
                 }
             };
-            // the batch's sorted run becomes the index
-            auto index_from_batch = [&](uint32_t slot, uint64_t g) {
-                guard(cur, g * sw * 8);
-                launch_copy_words(brun[slot], idx[cur], g * sw, E.stream);
-                n_idx = g;
-            };
             // memory is full: write the index as one sorted run (read-sort-write).
             // The run is split into its count-1 rows (raw layout) and the others,
-            // placed at the end of the spare buffer, and copied to host memory on
-            // the copy stream while run generation continues in the spare
-            // buffer's front.
+            // placed at the end of the other index buffer, and copied to host
+            // memory on the copy stream while run generation continues.
             auto spill_index = [&]() {
-                const int spare = cur ^ 1;
+                // an index that fails to absorb a batch holds more than one
+                // batch, so it lives in an index buffer
+                if (ip != idx[0] && ip != idx[1]) throw Fail{ISA_EDEVICE, "internal: spilling a batch run"};
+                const int own = ip == idx[0] ? 0 : 1;
+                const int spare = own ^ 1;
                 if (pend_buf >= 0) {
                     ck(hipStreamWaitEvent(E.stream, E.sync_event(1), 0), "hipStreamWaitEvent");
                     pend_buf = -1;
                 }
                 uint64_t n_single = 0, bytes = n_idx * sw * 8;
-                const uint64_t* run_src = idx[cur];
+                const uint64_t* run_src = ip;
                 if (compact) {
-                    launch_split(idx[cur], n_idx, S, Rl, sp_counts, sp_tiles, sp_offs, idx[spare], buf_rows * sw,
-                                 E.stream);
+                    launch_split(ip, n_idx, S, Rl, sp_counts, sp_tiles, sp_offs, idx[spare], buf_rows * sw, E.stream);
                     char* rb = E.ring_slot(16);
                     ck(hipMemcpyAsync(rb, sp_offs + split_blocks(n_idx), 8, hipMemcpyDeviceToHost, E.stream),
                        "hipMemcpyAsync(split count)");
@@ -673,7 +688,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 ck(hipEventRecord(E.sync_event(0), E.stream), "hipEventRecord");
                 ck(hipStreamWaitEvent(cs, E.sync_event(0), 0), "hipStreamWaitEvent");
                 E.pbegin("spill_d2h", cs);
-                ck(hipMemcpyAsync((char*)spill.host_pinned + spill_used, run_src, bytes, hipMemcpyDeviceToHost, cs),
+                ck(hipMemcpyAsync(spill_dev + spill_used, run_src, bytes, hipMemcpyDeviceToDeviceNoCU, cs),
                    "hipMemcpyAsync(spill)");
                 E.pend(n_idx, bytes, cs);
                 ck(hipEventRecord(E.sync_event(1), cs), "hipEventRecord");
@@ -685,36 +700,31 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 spill_used += bytes;
                 spilled += n_idx;
                 spilled_bytes += bytes;
-                if (compact) {
-                    pend_buf = spare;
-                    pend_lo = buf_bytes - bytes;
-                } else {
-                    // the run is the index buffer itself; the next index lives in the spare
-                    pend_buf = cur;
-                    pend_lo = 0;
-                    cur = spare;
-                }
+                pend_buf = compact ? spare : own;
+                pend_lo = compact ? buf_bytes - bytes : 0;
                 n_idx = 0;
             };
-            // absorb decision for the merge of batch j (g_j rows): keep the
-            // merged index if it holds at most K keys, else spill the old index
-            // and start a new one with the batch
-            auto decide = [&](uint64_t j, uint64_t gj) {
+            // absorb decision for the merge of batch j (g_j rows) into
+            // idx[target]: keep the merged index if it holds at most K keys,
+            // else spill the old index and start a new one with the batch run
+            auto decide = [&](uint64_t j, uint64_t gj, int target) {
                 const uint64_t* h = (const uint64_t*)rb_merge(j);
                 if (h[0] >> 32) throw Fail{ISA_EDEVICE, "merge placement wait timed out"};
                 const uint64_t m = h[1];
                 if (m <= p.capacity) {
-                    cur ^= 1;
+                    ip = idx[target];
                     n_idx = m;
                 } else {
                     spill_index();
-                    index_from_batch((uint32_t)(j % 3), gj);
+                    ip = brun[j % 3];
+                    n_idx = gj;
                 }
             };
             bp.enqueue(E, 0, 0, rb_sort(0));
             ck(hipEventRecord(ev_sort(0), E.stream), "hipEventRecord");
             bool merge_out = false;  // a merge whose absorb is not decided yet
             uint64_t merge_batch = 0, merge_g = 0;
+            int merge_tgt = 0;
             for (uint64_t i = 0; i < bp.batches; ++i) {
                 const uint32_t slot = (uint32_t)(i % 3);
                 if (i + 1 < bp.batches) {
@@ -738,31 +748,33 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 }
                 ++batches;
                 if (merge_out) {
-                    decide(merge_batch, merge_g);
+                    decide(merge_batch, merge_g, merge_tgt);
                     merge_out = false;
                 }
-                if (!have_index || n_idx == 0) {
-                    // an empty index simply becomes the batch's sorted run
-                    index_from_batch(slot, g);
-                    have_index = true;
+                if (!ip) {
+                    // the first batch run is the index
+                    ip = brun[slot];
+                    n_idx = g;
                     continue;
                 }
-                guard(cur ^ 1, (n_idx + g) * sw * 8);
+                const int tgt = merge_target();
+                guard(tgt, (n_idx + g) * sw * 8);
                 const uint64_t parts = merge_parts(n_idx, g);
                 launch_fill(m_ctl, parts + 2, 0, E.stream);
                 E.pbegin("k_merge");
-                launch_merge(idx[cur], n_idx, brun[slot], g, idx[cur ^ 1], S, m_splits, m_ctl + 2, (uint32_t*)m_ctl,
-                             m_ctl + 1, E.stream);
+                launch_merge(ip, n_idx, brun[slot], g, idx[tgt], S, m_splits, m_ctl + 2, (uint32_t*)m_ctl, m_ctl + 1,
+                             E.stream);
                 E.pend(n_idx + g, (n_idx + g) * sw * 8);
                 ck(hipMemcpyAsync(rb_merge(i), m_ctl, 16, hipMemcpyDeviceToHost, E.stream), "hipMemcpyAsync(merge ctl)");
                 ck(hipEventRecord(ev_merge(i), E.stream), "hipEventRecord");
                 merge_out = true;
                 merge_batch = i;
                 merge_g = g;
+                merge_tgt = tgt;
             }
             if (merge_out) {
                 ck(hipEventSynchronize(ev_merge(merge_batch)), "hipEventSynchronize");
-                decide(merge_batch, merge_g);
+                decide(merge_batch, merge_g, merge_tgt);
             }
             if (!runs.empty()) ck(hipStreamSynchronize(cs), "hipStreamSynchronize(copy)");
             E.sync();
@@ -778,13 +790,14 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             }
             if (runs.empty()) {
                 E.pbegin("k_copy_rows");
-                launch_copy_rows(aos_view(idx[cur], S), n_idx, output_view(*out, aggs, 0), out->capacity, E.stream);
+                launch_copy_rows(aos_view(ip, S), n_idx, output_view(*out, aggs, 0), out->capacity, E.stream);
                 E.pend(n_idx, 2 * n_idx * sw * 8);
                 E.sync();
                 n_groups = n_idx;
             } else {
-                // keep only the live index; everything after it is merge space
-                if (cur == 1) launch_copy_words(idx[1], idx[0], n_idx * sw, E.stream);
+                // keep only the live index, at the front; everything after it
+                // is merge space
+                if (ip != idx[0]) launch_copy_words(ip, idx[0], n_idx * sw, E.stream);
                 A.off = (uint64_t)((char*)idx[0] - A.base) + n_idx * sw * 8;
                 wide_merge(E, A, k, aggs, runs, (const char*)spill.host_pinned, idx[0], n_idx, out, stats,
                            n_groups);

@@ -165,7 +165,7 @@ def test_argument_errors(ctx):
     kd2 = torch.from_numpy(k2.view(np.int64)).cuda()
     vd2 = torch.from_numpy(v2).cuda()
     with pytest.raises(isa.InsortError) as e:
-        isa.group_by(ctx, kd2, vd2, None, aggs=isa.ISA_INT_AGGS, mem_budget=12 << 20, spill_bytes=0)
+        isa.group_by(ctx, kd2, vd2, None, aggs=isa.ISA_INT_AGGS, mem_budget=16 << 20, spill_bytes=0)
     assert e.value.status == isa.ISA_ESPILL
 
 
