@@ -687,6 +687,8 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     throw Fail{ISA_ESPILL, "spill buffer too small"};
                 ck(hipEventRecord(E.sync_event(0), E.stream), "hipEventRecord");
                 ck(hipStreamWaitEvent(cs, E.sync_event(0), 0), "hipStreamWaitEvent");
+                // one runtime copy on the copy stream: a kernel of our own
+                // writing host memory slows the concurrent kernels far more
                 E.pbegin("spill_d2h", cs);
                 ck(hipMemcpyAsync(spill_dev + spill_used, run_src, bytes, hipMemcpyDeviceToDeviceNoCU, cs),
                    "hipMemcpyAsync(spill)");
