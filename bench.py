@@ -75,6 +75,15 @@ def bench_batch(args, lo, hi):
     total_rows = int(rows.sum())
     i0 = 0
     waves = 0
+    # launch configuration: from the tuning table if it holds this workload's
+    # signature, else autotuned on the first wave (untimed) and recorded
+    from paper_2010_00152_amd.tuning import TuningTable, signature
+    table = TuningTable(args.tuning_file)
+    sig = signature(rows, aggs)
+    tuned = table.lookup(sig)
+    tune_info = {"source": "table" if tuned else "autotuned on the first wave"}
+    if tuned:
+        ctx.set_tuning(**tuned)
     while i0 < count:
         i1, acc = i0, 0
         while i1 < count and (acc + rows[i1] <= wave_rows or i1 == i0):
@@ -104,19 +113,34 @@ def bench_batch(args, lo, hi):
             if rc != isa.ISA_OK:
                 raise isa.InsortError(rc, ctx.last_error())
 
+        if tuned is None:
+            nc = L.isa_tune_candidates(None, 0)
+            times = (isa.ctypes.c_double * nc)()
+            best = isa.isa_tuning()
+            rc = L.isa_tune_batch(ctx.handle, n_w, ins, aggs, wss, outs, sp, isa.ctypes.byref(best), times, nc)
+            if rc != isa.ISA_OK:
+                raise isa.InsortError(rc, ctx.last_error())
+            tuned = best.as_dict()
+            cands = isa.tune_candidates()
+            dflt = cands.index({"leaf_rows": 2048, "chunk_split": 512, "graph": 1})
+            tune_info.update({"first_wave_ms_default": round(times[dflt], 3),
+                              "first_wave_ms_tuned": round(min(times[i] for i in range(nc)), 3),
+                              "candidates": nc})
+            table.record(sig, tuned, min(times[i] for i in range(nc)))
+            print("bench: tuned %s" % tuned, file=sys.stderr, flush=True)
         batched()  # warm
-        os.environ["ISA_BATCH_GRAPH"] = "1"
+        ctx.set_tuning(**tuned)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         batched()
         torch.cuda.synchronize()
         t_batch += time.perf_counter() - t0
-        os.environ["ISA_BATCH_GRAPH"] = "0"
+        ctx.set_tuning()  # the library's default configuration
         t0 = time.perf_counter()
         batched()
         torch.cuda.synchronize()
         t_graphless += time.perf_counter() - t0
-        os.environ["ISA_BATCH_GRAPH"] = "1"
+        ctx.set_tuning(**tuned)
         sps = isa.isa_spill(None, 0)
         t0 = time.perf_counter()
         for j in range(n_w):
@@ -139,11 +163,12 @@ def bench_batch(args, lo, hi):
         "dtype": "u64+i64",
         "config": {"workload": args.workload, "instances": count, "rows_lo": lo, "rows_hi": hi,
                    "total_rows": total_rows, "waves": waves},
-        "batched_graph_rows_per_s": round(total_rows / t_batch, 1),
-        "batched_direct_rows_per_s": round(total_rows / t_graphless, 1),
+        "batched_tuned_rows_per_s": round(total_rows / t_batch, 1),
+        "batched_default_config_rows_per_s": round(total_rows / t_graphless, 1),
         "plain_per_instance_rows_per_s": round(total_rows / t_plain, 1),
         "speedup_vs_plain": round(t_plain / t_batch, 3),
-        "ms": {"batched_graph": round(1e3 * t_batch, 2), "batched_direct": round(1e3 * t_graphless, 2),
+        "tuning": dict(tuned, **tune_info),
+        "ms": {"batched_tuned": round(1e3 * t_batch, 2), "batched_default_config": round(1e3 * t_graphless, 2),
                "plain": round(1e3 * t_plain, 2)},
     }
     print(json.dumps(res))
@@ -289,6 +314,8 @@ def main():
     ap.add_argument("--requests", type=int, default=2000, help="serve_c4: number of requests")
     ap.add_argument("--rho", type=float, default=0.8, help="serve_c4: offered load vs the plain rate")
     ap.add_argument("--slots", type=int, default=3, help="serve_c4: concurrent server batches")
+    ap.add_argument("--tuning-file", default=None,
+                    help="batch_*: JSON table of autotuned launch configurations (read, and written when tuning)")
     ap.add_argument("--cpu-sample", type=int, default=10_000_000,
                     help="rows of the input the CPU oracle is timed on (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")

@@ -32,6 +32,10 @@ def _load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libdatagen.so is not built")
+        # torch's HIP runtime must be the one the library binds to: loaded
+        # first, it satisfies the library's libamdhip64 dependency; loaded
+        # after, a second runtime would come up without the GPU
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         U, P = ctypes.c_uint64, ctypes.c_void_p
         L.dg_uniform_keys.argtypes = [U, U, U, U, U, P, P]

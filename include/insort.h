@@ -180,6 +180,42 @@ isa_status isa_batch_run(isa_ctx* ctx, uint32_t n_inst, const isa_input* inst,
 uint64_t isa_batch_workspace_bytes(uint32_t n_inst, const isa_input* inst, uint32_t aggs);
 
 /*
+ * Launch configuration of the device plans, held per context: the search
+ * space of the autotuner below.  It changes speed only, never results.
+ * Defaults: leaf_rows 2048, chunk_split 512, graph 1.
+ */
+typedef struct {
+    uint32_t leaf_rows;    /* target rows per sort leaf (buckets per partition = rows / leaf_rows,
+                              2..256); 256..2048 */
+    uint32_t chunk_split;  /* partition chunks per region: chunk rows = rows / chunk_split, clamped
+                              to 4096..16384; 64..4096 */
+    uint32_t graph;        /* 1: a wave of small batched instances launches as one captured HIP
+                              graph; 0: direct launches */
+    uint32_t reserved;     /* must be 0 */
+} isa_tuning;
+isa_status isa_get_tuning(isa_ctx* ctx, isa_tuning* out);
+/* ISA_EINVAL when a field is outside its range. */
+isa_status isa_set_tuning(isa_ctx* ctx, const isa_tuning* t);
+
+/*
+ * Autotuner for batched runs.  Writes the candidate grid (leaf_rows x
+ * chunk_split x graph) to out[0..max) and returns its size.
+ */
+uint32_t isa_tune_candidates(isa_tuning* out, uint32_t max);
+/*
+ * Runs isa_batch_run on the given instances under every candidate
+ * configuration (twice each, keeping the shorter wall time), leaves the
+ * fastest configuration set on the context and stores it in *best.  The
+ * outputs hold the results of the last run (identical under every
+ * configuration).  times_ms (may be NULL) receives each candidate's time in
+ * the order of isa_tune_candidates, up to n_times entries.  Errors as for
+ * isa_batch_run; on error the context keeps its previous configuration.
+ */
+isa_status isa_tune_batch(isa_ctx* ctx, uint32_t n_inst, const isa_input* inst, uint32_t aggs,
+                          isa_workspace ws, isa_output* outs, void* stream, isa_tuning* best,
+                          double* times_ms, uint32_t n_times);
+
+/*
  * Serving: a request loop that admits group-by requests against a device
  * workspace cap and runs admitted requests together (continuous batching):
  * requests that arrive while others run are admitted as soon as workspace and

@@ -70,6 +70,13 @@ class isa_kernel_time(ctypes.Structure):
                 ("total_ms", ctypes.c_double)]
 
 
+class isa_tuning(ctypes.Structure):
+    _fields_ = [("leaf_rows", U32), ("chunk_split", U32), ("graph", U32), ("reserved", U32)]
+
+    def as_dict(self):
+        return {"leaf_rows": self.leaf_rows, "chunk_split": self.chunk_split, "graph": self.graph}
+
+
 # Every function the header declares: name -> (restype, argtypes)
 SIGNATURES = {
     "isa_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(P)]),
@@ -94,6 +101,12 @@ SIGNATURES = {
     "isa_last_error": (ctypes.c_char_p, [P]),
     "isa_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
     "isa_profile_read": (ctypes.c_int, [P, ctypes.POINTER(isa_kernel_time), ctypes.c_int]),
+    "isa_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(isa_tuning)]),
+    "isa_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(isa_tuning)]),
+    "isa_tune_candidates": (U32, [ctypes.POINTER(isa_tuning), U32]),
+    "isa_tune_batch": (ctypes.c_int, [P, U32, ctypes.POINTER(isa_input), U32, isa_workspace,
+                                      ctypes.POINTER(isa_output), P, ctypes.POINTER(isa_tuning),
+                                      ctypes.POINTER(ctypes.c_double), U32]),
 }
 
 _lib = None
@@ -105,6 +118,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libinsort.so is not built; run paper_2010_00152_amd/build.py")
+        # torch's HIP runtime must be the one the library binds to: loaded
+        # first, it satisfies the library's libamdhip64 dependency; loaded
+        # after, a second runtime would come up without the GPU
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -160,6 +177,19 @@ class Context:
         st = lib().isa_profile_enable(self.handle, 1 if on else 0)
         if st != ISA_OK:
             raise InsortError(st)
+
+    def get_tuning(self) -> dict:
+        t = isa_tuning()
+        st = lib().isa_get_tuning(self.handle, ctypes.byref(t))
+        if st != ISA_OK:
+            raise InsortError(st)
+        return t.as_dict()
+
+    def set_tuning(self, leaf_rows: int = 2048, chunk_split: int = 512, graph: int = 1):
+        t = isa_tuning(leaf_rows, chunk_split, graph, 0)
+        st = lib().isa_set_tuning(self.handle, ctypes.byref(t))
+        if st != ISA_OK:
+            raise InsortError(st, "tuning %r" % (t.as_dict(),))
 
     def profile_read(self):
         """{name: {launches, rows, bytes, total_ms}} of launches since profile(True)."""
@@ -281,6 +311,41 @@ def batch_run(ctx: Context, inputs, aggs: int = ISA_INT_AGGS, mem_budget: int = 
         g = outs[i].n_groups
         res.append({c: t[:g] for c, t in keep[i].items()})
     return res, status
+
+
+def tune_candidates():
+    n = lib().isa_tune_candidates(None, 0)
+    buf = (isa_tuning * n)()
+    lib().isa_tune_candidates(buf, n)
+    return [buf[i].as_dict() for i in range(n)]
+
+
+def tune_batch(ctx: Context, inputs, aggs: int = ISA_INT_AGGS, mem_budget: int = 1 << 30, workspace=None,
+               stream=None):
+    """Autotune the launch configuration on a batch of instances (list of
+    (keys, v_i64, v_f64) CUDA tensors); the fastest configuration stays set on
+    the context.  Returns (best config dict, {candidate index: ms})."""
+    import torch
+    k = len(inputs)
+    ins = (isa_input * max(k, 1))()
+    outs = (isa_output * max(k, 1))()
+    keep = []
+    for i, (kk, vv, ff) in enumerate(inputs):
+        n = kk.numel()
+        o = _alloc_outputs(torch, n, aggs, kk.device)
+        keep.append(o)
+        ins[i] = isa_input(_ptr(kk), _ptr(vv), _ptr(ff), n)
+        outs[i] = _output_struct(o, n)
+    if workspace is None:
+        workspace = torch.empty(mem_budget, dtype=torch.uint8, device="cuda")
+    ws = isa_workspace(_ptr(workspace), workspace.numel())
+    nc = lib().isa_tune_candidates(None, 0)
+    times = (ctypes.c_double * nc)()
+    best = isa_tuning()
+    st = lib().isa_tune_batch(ctx.handle, k, ins, aggs, ws, outs, _stream_ptr(stream), ctypes.byref(best), times, nc)
+    if st != ISA_OK:
+        raise InsortError(st, ctx.last_error())
+    return best.as_dict(), {i: times[i] for i in range(nc)}
 
 
 class Server:

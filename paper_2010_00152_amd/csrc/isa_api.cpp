@@ -62,11 +62,6 @@ std::vector<uint64_t> run_instances(Engine& E, Arena& A, const std::vector<Insta
     return sort_reduce(E, A, inst, dests, k, state_rows, hint);
 }
 
-bool graph_batches() {
-    const char* e = std::getenv("ISA_BATCH_GRAPH");
-    return !(e && e[0] == '0');
-}
-
 // Raw input rows viewed column-wise.
 ColView input_view(const isa_input& in, const Cols& k) {
     ColView v;
@@ -151,7 +146,8 @@ uint64_t batch_share() {
 bool plan_batches(uint64_t ws, uint64_t n, const Cols& k, Plan& p) {
     const uint64_t sw = (uint64_t)state_layout(k).words * 8;
     uint64_t Bt = ws / batch_share() / (sort_reduce_bytes(1, 0, k, false) - (4u << 20) + sw);
-    Bt = std::min<uint64_t>(Bt, n);
+    // a batch is sorted by the flat plan
+    Bt = std::min<uint64_t>(std::min<uint64_t>(Bt, n), FLAT_MAX);
     if (Bt < MIN_BATCH) Bt = MIN_BATCH;
     for (;;) {
         const uint64_t fixed = rungen_bytes(Bt, 0, k);
@@ -598,11 +594,11 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             // input (batches are slices of one input)
             uint64_t* d_gspl = A.take_n<uint64_t>(MAX_BUCKETS - 1);
             std::vector<uint64_t> h_gspl;
-            choose_splitters(E, A, src, n, buckets_for(p.batch_rows), d_gspl, h_gspl);
+            choose_splitters(E, A, src, n, buckets_for(E, p.batch_rows), d_gspl, h_gspl);
             SplitterHint hint;
             hint.dev = d_gspl;
             hint.host = h_gspl.data();
-            hint.nb = buckets_for(p.batch_rows);
+            hint.nb = buckets_for(E, p.batch_rows);
             std::vector<Dest> bdest(3);
             for (int j = 0; j < 3; ++j) {
                 bdest[j].out = aos_out(brun[j], S);
@@ -986,7 +982,7 @@ isa_status isa_batch_run(isa_ctx* ctx, uint32_t n_inst, const isa_input* inst, u
                 ds.push_back(d);
             }
             A.off = 0;
-            const std::vector<uint64_t> g = run_instances(E, A, in, ds, k, false, nullptr, small && graph_batches());
+            const std::vector<uint64_t> g = run_instances(E, A, in, ds, k, false, nullptr, small && E.tune.graph);
             for (size_t x = i0; x < i1; ++x) {
                 const uint32_t i = order[x];
                 outs[i].n_groups = g[x - i0];
@@ -1000,6 +996,80 @@ isa_status isa_batch_run(isa_ctx* ctx, uint32_t n_inst, const isa_input* inst, u
     } catch (const std::bad_alloc&) {
         return ISA_ENOMEM;
     }
+}
+
+namespace {
+bool valid_tuning(const isa_tuning& t) {
+    // leaves up to half the leaf capacity on average keep sampled buckets within it
+    return t.leaf_rows >= 256 && t.leaf_rows <= (uint32_t)LEAF_CAP / 2 && t.chunk_split >= 64 &&
+           t.chunk_split <= 4096 && t.graph <= 1 && t.reserved == 0;
+}
+}  // namespace
+
+isa_status isa_get_tuning(isa_ctx* ctx, isa_tuning* out) {
+    if (!ctx || !out) return ISA_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    out->leaf_rows = ctx->eng.tune.leaf_rows;
+    out->chunk_split = ctx->eng.tune.chunk_split;
+    out->graph = ctx->eng.tune.graph;
+    out->reserved = 0;
+    return ISA_OK;
+}
+
+isa_status isa_set_tuning(isa_ctx* ctx, const isa_tuning* t) {
+    if (!ctx || !t || !valid_tuning(*t)) return ISA_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->eng.tune.leaf_rows = t->leaf_rows;
+    ctx->eng.tune.chunk_split = t->chunk_split;
+    ctx->eng.tune.graph = t->graph;
+    return ISA_OK;
+}
+
+uint32_t isa_tune_candidates(isa_tuning* out, uint32_t max) {
+    static const uint32_t leaf[] = {1024, 1536, 2048};
+    static const uint32_t split[] = {256, 512, 1024};
+    uint32_t c = 0;
+    for (uint32_t g = 0; g < 2; ++g)
+        for (uint32_t l : leaf)
+            for (uint32_t sp : split) {
+                if (out && c < max) out[c] = isa_tuning{l, sp, 1 - g, 0};
+                ++c;
+            }
+    return c;
+}
+
+isa_status isa_tune_batch(isa_ctx* ctx, uint32_t n_inst, const isa_input* inst, uint32_t aggs, isa_workspace ws,
+                          isa_output* outs, void* stream, isa_tuning* best, double* times_ms, uint32_t n_times) {
+    if (!ctx) return ISA_EINVAL;
+    isa_tuning prev;
+    isa_get_tuning(ctx, &prev);
+    const uint32_t nc = isa_tune_candidates(nullptr, 0);
+    std::vector<isa_tuning> cand(nc);
+    isa_tune_candidates(cand.data(), nc);
+    double best_ms = 0;
+    uint32_t best_i = 0;
+    for (uint32_t c = 0; c < nc; ++c) {
+        isa_set_tuning(ctx, &cand[c]);
+        double ms = 0;
+        for (int rep = 0; rep < 2; ++rep) {
+            const double t0 = now_ms();
+            const isa_status st = isa_batch_run(ctx, n_inst, inst, aggs, ws, outs, stream);
+            const double t = now_ms() - t0;
+            if (st != ISA_OK) {
+                isa_set_tuning(ctx, &prev);
+                return st;
+            }
+            ms = rep == 0 ? t : std::min(ms, t);
+        }
+        if (times_ms && c < n_times) times_ms[c] = ms;
+        if (c == 0 || ms < best_ms) {
+            best_ms = ms;
+            best_i = c;
+        }
+    }
+    isa_set_tuning(ctx, &cand[best_i]);
+    if (best) *best = cand[best_i];
+    return ISA_OK;
 }
 
 }  // extern "C"

@@ -236,11 +236,19 @@ struct Node {
 
 }  // namespace
 
-uint32_t buckets_for(uint64_t n) {
-    uint64_t nb = (2 * n + LEAF_CAP - 1) / LEAF_CAP;
+uint32_t buckets_for(const Engine& E, uint64_t n) {
+    const uint64_t t = E.tune.leaf_rows;
+    uint64_t nb = (n + t - 1) / t;
     if (nb < 2) nb = 2;
     if (nb > MAX_BUCKETS) nb = MAX_BUCKETS;
     return (uint32_t)nb;
+}
+
+// Rows per partition chunk: one sub-tile for small regions (more
+// workgroups), up to four sub-tiles for large ones.
+uint64_t chunk_rows(const Engine& E, uint64_t n) {
+    const uint64_t crow = (n / E.tune.chunk_split + PART_TILE - 1) / PART_TILE * PART_TILE;
+    return std::max<uint64_t>(PART_TILE, std::min<uint64_t>(PART_CHUNK, crow));
 }
 
 void choose_splitters(Engine& E, Arena& A, const ColView& src, uint64_t n, uint32_t nb, uint64_t* dev_out,
@@ -337,11 +345,8 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
             r.src = nd.src;
             r.n = nd.n;
             r.out_pos = nd.pos;
-            r.nb = buckets_for(nd.n);
-            // chunk rows: one sub-tile for small regions (more workgroups),
-            // up to four sub-tiles for large ones
-            uint64_t crow = (nd.n / 512 + PART_TILE - 1) / PART_TILE * PART_TILE;
-            crow = std::max<uint64_t>(PART_TILE, std::min<uint64_t>(PART_CHUNK, crow));
+            r.nb = buckets_for(E, nd.n);
+            const uint64_t crow = chunk_rows(E, nd.n);
             r.n_chunks = (uint32_t)((nd.n + crow - 1) / crow);
             r.hist_base = hist_total;
             hist_total += (uint64_t)r.nb * r.n_chunks;
@@ -574,9 +579,8 @@ bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, co
         r.src = in.src;
         r.n = in.n;
         r.out_pos = N;
-        r.nb = (hint && hint->dev && inst.size() == 1) ? hint->nb : buckets_for(in.n);
-        uint64_t crow = (in.n / 512 + PART_TILE - 1) / PART_TILE * PART_TILE;
-        crow = std::max<uint64_t>(PART_TILE, std::min<uint64_t>(PART_CHUNK, crow));
+        r.nb = (hint && hint->dev && inst.size() == 1) ? hint->nb : buckets_for(E, in.n);
+        const uint64_t crow = chunk_rows(E, in.n);
         r.n_chunks = (uint32_t)((in.n + crow - 1) / crow);
         r.hist_base = hist_total;
         hist_total += (uint64_t)r.nb * r.n_chunks;
@@ -693,14 +697,10 @@ bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, co
 namespace {
 constexpr uint32_t BP_CTL_RING = 8;  // control blocks reused round-robin
 
-uint64_t bp_chunk_rows(uint64_t Bt) {
-    uint64_t crow = (Bt / 512 + PART_TILE - 1) / PART_TILE * PART_TILE;
-    return std::max<uint64_t>(PART_TILE, std::min<uint64_t>(PART_CHUNK, crow));
-}
 }  // namespace
 
 uint64_t batch_program_bytes(uint64_t Bt, const Cols& k) {
-    const uint64_t ch = (Bt + bp_chunk_rows(Bt) - 1) / bp_chunk_rows(Bt);
+    const uint64_t ch = (Bt + PART_TILE - 1) / PART_TILE;  // the most chunks any tuning gives
     const uint64_t hist = (uint64_t)MAX_BUCKETS * ch;
     const uint64_t desc = BP_CTL_RING * sizeof(Region) + 2 * ch * sizeof(Chunk) + MAX_BUCKETS * sizeof(FlatSlot) +
                           16 + 3 * sizeof(Dest) + BP_CTL_RING * (2 + MAX_BUCKETS) * 8;
@@ -719,7 +719,7 @@ void BatchProgram::setup(Engine& E, Arena& A, const ColView& src_rows, uint64_t 
     L = raw_layout(k);
     src = src_rows;
     splitters = hint.dev;
-    const uint64_t crow = bp_chunk_rows(Bt);
+    const uint64_t crow = chunk_rows(E, Bt);
     chunks_full = (uint32_t)((Bt + crow - 1) / crow);
     const uint64_t last_n = n - (batches - 1) * Bt;
     chunks_last = (uint32_t)((last_n + crow - 1) / crow);

@@ -87,8 +87,16 @@ struct ProfRec {
 };
 
 // Per-context host state.
+// Launch configuration of the sort-reduce plans (the autotuner's search space).
+struct Tuning {
+    uint32_t leaf_rows = 2048;  // target rows per leaf bucket (buckets = rows / leaf_rows, 2..MAX_BUCKETS)
+    uint32_t chunk_split = 512; // partition chunks per region: chunk rows = rows / chunk_split, in [PART_TILE, PART_CHUNK]
+    uint32_t graph = 1;         // batched waves of small instances launch as one captured graph
+};
+
 struct Engine {
     int device = 0;
+    Tuning tune;
     hipStream_t stream = nullptr;
     // pinned host staging for descriptor uploads and small readbacks
     char* pinned = nullptr;
@@ -163,7 +171,8 @@ void choose_splitters(Engine& E, Arena& A, const ColView& src, uint64_t n, uint3
 std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instance>& inst,
                                   const std::vector<Dest>& dests, const Cols& k, bool state_rows,
                                   const SplitterHint* hint = nullptr);
-uint32_t buckets_for(uint64_t n);
+uint32_t buckets_for(const Engine& E, uint64_t n);
+uint64_t chunk_rows(const Engine& E, uint64_t n);
 
 // Device-to-host copy into pinned staging; valid after the next sync().
 const void* download_async(Engine& E, const void* dev, uint64_t bytes);

@@ -8,7 +8,7 @@ import pytest
 import datagen
 import oracle
 import paper_2010_00152_amd as isa
-from tests.gpu_util import FP64_REL, compare, say, to_dev, to_np
+from tests.gpu_util import run_gpu, FP64_REL, compare, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -92,6 +92,53 @@ def test_batch_waves_small_workspace(ctx):
     res, status = isa.batch_run(ctx, dev, aggs=isa.ISA_INT_AGGS, mem_budget=48 << 20)
     for i, (k, v, f) in enumerate(insts):
         compare(np_out(res[i]), k, v, None, isa.ISA_INT_AGGS, "inst %d" % i)
+
+
+@pytest.mark.parametrize("cfg", [dict(leaf_rows=1024, chunk_split=256, graph=1),
+                                 dict(leaf_rows=1536, chunk_split=1024, graph=0),
+                                 dict(leaf_rows=256, chunk_split=64, graph=1),
+                                 dict(leaf_rows=2048, chunk_split=4096, graph=0)])
+def test_tuning_changes_speed_not_results(ctx, cfg):
+    # every launch configuration gives the oracle's result (I9), on the
+    # batched path (flat plan, both size classes) and on the spilling path
+    say("case tuning %r" % (cfg,))
+    insts = batch_instances(26, 30, 1_000, 700_000)
+    dev = [(to_dev(k), to_dev(v), None) for k, v, f in insts]
+    ctx.set_tuning(**cfg)
+    try:
+        assert ctx.get_tuning() == cfg
+        res, status = isa.batch_run(ctx, dev, aggs=isa.ISA_INT_AGGS, mem_budget=512 << 20)
+        for i, (k, v, f) in enumerate(insts):
+            compare(np_out(res[i]), k, v, None, isa.ISA_INT_AGGS, "inst %d" % i)
+        k, v, f = datagen.plain_input(27, 1_200_000, 300_000, 0.8, with_f64=True)
+        got, st, _, _ = run_gpu(ctx, k, v, f, budget=24 << 20)
+        assert st["runs"] > 0
+        compare(got, k, v, f, isa.ISA_ALL, "spill under tuning")
+    finally:
+        ctx.set_tuning()
+
+
+def test_tuning_rejects_out_of_range(ctx):
+    for bad in [dict(leaf_rows=100), dict(leaf_rows=4096), dict(chunk_split=8), dict(graph=2)]:
+        with pytest.raises(isa.InsortError) as e:
+            ctx.set_tuning(**bad)
+        assert e.value.status == isa.ISA_EINVAL
+    assert ctx.get_tuning() == dict(leaf_rows=2048, chunk_split=512, graph=1)
+
+
+def test_autotuner_picks_a_candidate_and_keeps_results(ctx):
+    say("case autotuner")
+    insts = batch_instances(28, 40, 1_000, 200_000)
+    dev = [(to_dev(k), to_dev(v), None) for k, v, f in insts]
+    best, times = isa.tune_batch(ctx, dev, aggs=isa.ISA_INT_AGGS, mem_budget=512 << 20)
+    cands = isa.tune_candidates()
+    assert best in cands and len(times) == len(cands) and all(t > 0 for t in times.values())
+    assert ctx.get_tuning() == best
+    assert times[cands.index(best)] == min(times.values())
+    res, status = isa.batch_run(ctx, dev, aggs=isa.ISA_INT_AGGS, mem_budget=512 << 20)
+    for i, (k, v, f) in enumerate(insts):
+        compare(np_out(res[i]), k, v, None, isa.ISA_INT_AGGS, "inst %d" % i)
+    ctx.set_tuning()
 
 
 def test_server_results_alone_and_in_the_mix(ctx):
