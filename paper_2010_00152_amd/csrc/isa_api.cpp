@@ -594,11 +594,13 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             // input (batches are slices of one input)
             uint64_t* d_gspl = A.take_n<uint64_t>(MAX_BUCKETS - 1);
             std::vector<uint64_t> h_gspl;
-            choose_splitters(E, A, src, n, buckets_for(E, p.batch_rows), d_gspl, h_gspl);
+            std::vector<double> share;
+            choose_splitters(E, A, src, n, buckets_for(E, p.batch_rows), d_gspl, h_gspl, &share);
             SplitterHint hint;
             hint.dev = d_gspl;
             hint.host = h_gspl.data();
             hint.nb = buckets_for(E, p.batch_rows);
+            hint.share = share.data();
             std::vector<Dest> bdest(3);
             for (int j = 0; j < 3; ++j) {
                 bdest[j].out = aos_out(brun[j], S);

@@ -11,6 +11,7 @@
 #include "isa_engine.h"
 
 #include <algorithm>
+#include <functional>
 #include <cstring>
 
 #include "../../include/insort.h"
@@ -251,25 +252,81 @@ uint64_t chunk_rows(const Engine& E, uint64_t n) {
     return std::max<uint64_t>(PART_TILE, std::min<uint64_t>(PART_CHUNK, crow));
 }
 
+// Splitters for every batch of one input, from a stratified sample of
+// WIDE_SAMPLE keys sorted on the host.  A heavy key (at least one bucket's
+// share of the sample) gets a bucket of its own, [key, key+1); the light keys
+// share the remaining buckets evenly by sample count.  A bucket boundary never
+// falls inside a run of equal keys.
 void choose_splitters(Engine& E, Arena& A, const ColView& src, uint64_t n, uint32_t nb, uint64_t* dev_out,
-                      std::vector<uint64_t>& host_out) {
+                      std::vector<uint64_t>& host_out, std::vector<double>* share) {
+    constexpr uint64_t WIDE_SAMPLE = 32768;
     const uint64_t mark = A.off;
-    Region r;
-    r.src = src;
-    r.n = n;
-    r.out_pos = 0;
-    r.hist_base = 0;
-    r.nb = nb;
-    r.n_chunks = 0;
-    UpPack up;
-    up.add(&r, sizeof(r));
-    Region* d_r = (Region*)up.commit(E, A);
+    const uint64_t S = std::min<uint64_t>(n, WIDE_SAMPLE);
+    uint64_t* d_s = A.take_n<uint64_t>(S + 1);
     E.pbegin("k_sample");
-    launch_sample(d_r, 1, dev_out, E.stream);
-    E.pend(SAMPLE_N, SAMPLE_N * 8);
-    const uint64_t* h = (const uint64_t*)download_async(E, dev_out, (MAX_BUCKETS - 1) * sizeof(uint64_t));
+    launch_sample_keys(src, n, S, d_s, E.stream);
+    E.pend(S, S * 8);
+    const uint64_t* h = (const uint64_t*)download_async(E, d_s, S * sizeof(uint64_t));
     E.sync();
-    host_out.assign(h, h + (MAX_BUCKETS - 1));
+    std::vector<uint64_t> x(h, h + S);
+    std::sort(x.begin(), x.end());
+    // runs of equal keys in the sample
+    std::vector<std::pair<uint64_t, uint64_t>> runs;  // (key, count)
+    for (uint64_t i = 0; i < S;) {
+        uint64_t j = i;
+        while (j < S && x[j] == x[i]) ++j;
+        runs.push_back({x[i], j - i});
+        i = j;
+    }
+    // heavy: at least a bucket's share, and among the nb/4 largest runs (so
+    // that light keys keep at least half of the buckets)
+    uint64_t heavy_at = std::max<uint64_t>(1, S / nb);
+    {
+        std::vector<uint64_t> cnt;
+        for (const auto& r : runs) cnt.push_back(r.second);
+        const size_t top = nb / 4;
+        if (cnt.size() > top && top > 0) {
+            std::nth_element(cnt.begin(), cnt.begin() + (top - 1), cnt.end(), std::greater<uint64_t>());
+            heavy_at = std::max(heavy_at, cnt[top - 1] + 1);
+        }
+    }
+    uint64_t n_heavy = 0, light = 0;
+    for (const auto& r : runs) {
+        if (r.second >= heavy_at) ++n_heavy;
+        else light += r.second;
+    }
+    // buckets: two boundaries per heavy key at most, the rest for light keys
+    const uint64_t light_buckets = nb > 2 * n_heavy + 1 ? nb - 2 * n_heavy : 1;
+    const uint64_t target = std::max<uint64_t>(1, (light + light_buckets - 1) / light_buckets);
+    std::vector<uint64_t> spl;
+    uint64_t acc = 0;
+    auto cut = [&](uint64_t key) {  // a boundary below `key`
+        if (spl.size() + 1 < nb && key > 0 && (spl.empty() || spl.back() < key)) spl.push_back(key);
+    };
+    for (const auto& r : runs) {
+        if (r.second >= heavy_at) {
+            cut(r.first);
+            if (r.first != ~0ull) cut(r.first + 1);
+            acc = 0;
+            continue;
+        }
+        if (acc > 0 && acc + r.second > target) {
+            cut(r.first);
+            acc = 0;
+        }
+        acc += r.second;
+    }
+    host_out.assign(MAX_BUCKETS - 1, ~0ull);
+    for (size_t i = 0; i < spl.size() && i < (size_t)(nb - 1); ++i) host_out[i] = spl[i];
+    if (share) {
+        share->assign(nb, 0.0);
+        for (const auto& r : runs) {
+            const size_t b = std::upper_bound(spl.begin(), spl.end(), r.first) - spl.begin();
+            (*share)[std::min<size_t>(b, nb - 1)] += (double)r.second / (double)S;
+        }
+    }
+    E.upload(dev_out, host_out.data(), (MAX_BUCKETS - 1) * sizeof(uint64_t));
+    E.sync();
     A.off = mark;
 }
 
@@ -702,8 +759,10 @@ constexpr uint32_t BP_CTL_RING = 8;  // control blocks reused round-robin
 uint64_t batch_program_bytes(uint64_t Bt, const Cols& k) {
     const uint64_t ch = (Bt + PART_TILE - 1) / PART_TILE;  // the most chunks any tuning gives
     const uint64_t hist = (uint64_t)MAX_BUCKETS * ch;
+    const uint64_t pieces = (Bt + SINGLE_CHUNK - 1) / SINGLE_CHUNK;
     const uint64_t desc = BP_CTL_RING * sizeof(Region) + 2 * ch * sizeof(Chunk) + MAX_BUCKETS * sizeof(FlatSlot) +
-                          16 + 3 * sizeof(Dest) + BP_CTL_RING * (2 + MAX_BUCKETS) * 8;
+                          16 + 3 * sizeof(Dest) + BP_CTL_RING * (2 + MAX_BUCKETS) * 8 + 2 * MAX_BUCKETS * 4 +
+                          (uint64_t)MAX_BUCKETS * pieces * single_partial_bytes() + 4 * 256;
     const uint64_t scratch = Bt * (uint64_t)raw_layout(k).words * 8 + hist * 4 + (hist + 1) * 8 +
                              (scan_tiles(hist) + 1) * 8 + 8 * 256;
     // the scratch area also serves the general plan when a batch falls back
@@ -740,13 +799,32 @@ void BatchProgram::setup(Engine& E, Arena& A, const ColView& src_rows, uint64_t 
     std::vector<FlatSlot> slots(nb);
     for (uint32_t b = 0; b < nb; ++b) slots[b] = FlatSlot{1, 0, b, 0};
     const uint32_t first[2] = {0, nb};
+    // single-key buckets: a splitter range [lo, hi] with lo == hi
+    std::vector<uint32_t> single_list, single_of(nb, ~0u);
+    for (uint32_t b = 0; b < nb; ++b) {
+        const uint64_t lo = b ? hint.host[b - 1] : 0ull;
+        const uint64_t hi = b + 1 < nb ? hint.host[b] - 1 : ~0ull;
+        // worth pieces of its own when one workgroup would stream many chunks
+        const bool big = !hint.share || hint.share[b] * (double)Bt > 4.0 * SINGLE_CHUNK;
+        if (lo == hi && big) {
+            single_of[b] = (uint32_t)single_list.size();
+            single_list.push_back(b);
+        }
+    }
+    n_single = (uint32_t)single_list.size();
+    max_pieces = (uint32_t)((std::min(Bt, n) + SINGLE_CHUNK - 1) / SINGLE_CHUNK);
     UpPack up;
     const uint64_t o_cf = up.add(cf.data(), cf.size() * sizeof(Chunk));
     const uint64_t o_cl = up.add(cl.data(), cl.size() * sizeof(Chunk));
     const uint64_t o_slots = up.add(slots.data(), slots.size() * sizeof(FlatSlot));
     const uint64_t o_first = up.add(first, sizeof(first));
     const uint64_t o_dests = up.add(dests.data(), dests.size() * sizeof(Dest));
+    const uint64_t o_sl = up.add(single_list.data(), single_list.size() * sizeof(uint32_t));
+    const uint64_t o_so = up.add(single_of.data(), single_of.size() * sizeof(uint32_t));
     char* d = up.commit(E, A);
+    d_single_list = n_single ? (uint32_t*)(d + o_sl) : nullptr;
+    d_single_of = n_single ? (uint32_t*)(d + o_so) : nullptr;
+    d_partials = n_single ? A.take((uint64_t)n_single * max_pieces * single_partial_bytes()) : nullptr;
     d_chunks_full = (Chunk*)(d + o_cf);
     d_chunks_last = (Chunk*)(d + o_cl);
     d_slots = (FlatSlot*)(d + o_slots);
@@ -794,9 +872,14 @@ void BatchProgram::enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback)
     E.pbegin("k_scatter", st);
     launch_scatter(reg, ch, nch, splitters, d_offs, part, L, st);
     E.pend(bn, bn * (uint64_t)L.words * 8, st);
+    if (n_single) {
+        E.pbegin("k_single_partial", st);
+        launch_flat_single_partial(reg, d_offs, part, L, d_single_list, n_single, max_pieces, d_partials, st);
+        E.pend(bn, 0, st);
+    }
     E.pbegin("k_leaf", st);
     launch_leaf_flat(d_slots, nb, nullptr, reg, splitters, d_offs, part, L, d_first, d_dests + slot, ctl + 2, ctl + 1,
-                     (uint32_t*)ctl, st);
+                     (uint32_t*)ctl, st, d_single_of, d_partials, max_pieces);
     E.pend(bn, bn * (uint64_t)L.words * 8, st);
     ck(hipMemcpyAsync(readback, ctl, 16, hipMemcpyDeviceToHost, st), "hipMemcpyAsync(batch ctl)");
 }

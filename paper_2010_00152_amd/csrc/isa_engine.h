@@ -20,6 +20,7 @@ void launch_scatter(const Region* regions, const Chunk* chunks, uint32_t n_chunk
 void launch_bucket_starts(const Region* regions, uint32_t n_regions, const uint64_t* offs, const uint64_t* bs_base,
                           uint64_t* bstart, hipStream_t st);
 void launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st);
+void launch_sample_keys(ColView src, uint64_t n, uint64_t S, uint64_t* out, hipStream_t st);
 void launch_copy_words(const uint64_t* src, uint64_t* dst, uint64_t n, hipStream_t st);
 void launch_extract_keys(const uint64_t* rows, uint64_t n, uint32_t stride, uint64_t* keys, hipStream_t st);
 void launch_batch_prep(const Region& r, Region* reg, uint64_t* ctl, uint32_t ctl_words, hipStream_t st);
@@ -29,7 +30,11 @@ void launch_leaf(const Leaf* leaves, uint32_t n_leaves, const uint32_t* leaf_des
 void launch_leaf_flat(const FlatSlot* slots, uint32_t n_slots, const FlatInst* insts, const Region* regions,
                       const uint64_t* splitters, const uint64_t* offs, const uint64_t* part, Layout L,
                       const uint32_t* first_slot, const Dest* dests, uint64_t* status, uint64_t* totals,
-                      uint32_t* ctl, hipStream_t st);
+                      uint32_t* ctl, hipStream_t st, const uint32_t* single_of = nullptr,
+                      const void* partials = nullptr, uint32_t max_pieces = 0);
+void launch_flat_single_partial(const Region* regions, const uint64_t* offs, const uint64_t* part, Layout L,
+                                const uint32_t* single_buckets, uint32_t n_single, uint32_t max_pieces, void* partials,
+                                hipStream_t st);
 void launch_single_partial(const Leaf* leaves, const SinglePiece* pieces, uint32_t n_pieces, void* partials,
                            hipStream_t st);
 size_t single_partial_bytes();
@@ -146,6 +151,7 @@ struct SplitterHint {
     const uint64_t* dev = nullptr;
     const uint64_t* host = nullptr;
     uint32_t nb = 0;
+    const double* share = nullptr;  // optional: each bucket's share of the sample
 };
 
 // Collects several host arrays into one pinned staging block and uploads them
@@ -163,7 +169,7 @@ struct UpPack {
 
 // Choose splitters for `src` (n rows) with nb buckets from a sample of its keys.
 void choose_splitters(Engine& E, Arena& A, const ColView& src, uint64_t n, uint32_t nb, uint64_t* dev_out,
-                      std::vector<uint64_t>& host_out);
+                      std::vector<uint64_t>& host_out, std::vector<double>* share = nullptr);
 
 // Sort and reduce every instance: the sorted unique state rows of instance i
 // are appended, in instance order, to dests[instance.dest].  Returns the
@@ -210,6 +216,12 @@ struct BatchProgram {
     uint32_t* d_hist = nullptr;
     uint64_t* d_offs = nullptr;
     uint64_t* d_tiles = nullptr;
+    // single-key buckets (known from the splitters): their pieces are reduced
+    // in parallel before the leaves combine them
+    uint32_t n_single = 0, max_pieces = 0;
+    uint32_t* d_single_list = nullptr;  // bucket of each single-key bucket
+    uint32_t* d_single_of = nullptr;    // per bucket: its index in the list, or ~0
+    void* d_partials = nullptr;
     uint64_t ctl_words() const { return 2 + (uint64_t)nb; }
     void setup(Engine& E, Arena& A, const ColView& src, uint64_t n_rows, uint64_t batch_rows, const Cols& k,
                const SplitterHint& hint, const std::vector<Dest>& dests);

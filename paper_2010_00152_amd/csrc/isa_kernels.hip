@@ -579,6 +579,14 @@ __global__ void k_extract_keys(const uint64_t* __restrict__ rows, uint64_t n, ui
         keys[i] = rows[i * stride];
 }
 
+// Stratified key sample: key of row floor((2q+1) n / 2S) for q < S.
+__global__ void k_sample_keys(ColView src, uint64_t n, uint64_t S, uint64_t* __restrict__ out) {
+    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < S; q += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t pos = (uint64_t)(((unsigned __int128)(2 * q + 1) * n) / (2 * S));
+        out[q] = src.key[pos * src.stride];
+    }
+}
+
 __global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t value) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = value;
@@ -894,6 +902,40 @@ __device__ __forceinline__ ColView aos_view_d(const uint64_t* base, const Layout
     return v;
 }
 
+// Pieces of the single-key buckets of one flat region whose single-key
+// buckets are known in advance (their splitter ranges hold one key): block
+// (s, p) reduces rows [p*SINGLE_CHUNK, (p+1)*SINGLE_CHUNK) of the s-th such
+// bucket into partials[s*max_pieces + p]; pieces past the bucket's end exit.
+__global__ void __launch_bounds__(256) k_flat_single_partial(const Region* __restrict__ regions,
+                                                             const uint64_t* __restrict__ offs,
+                                                             const uint64_t* __restrict__ part, Layout L,
+                                                             const uint32_t* __restrict__ single_buckets,
+                                                             uint32_t max_pieces, Agg* __restrict__ partials) {
+    __shared__ Agg s_agg[256];
+    const uint32_t si = blockIdx.x / max_pieces, p = blockIdx.x - si * max_pieces;
+    const Region R = regions[0];
+    const uint32_t b = single_buckets[si];
+    const uint64_t rb = offs[R.hist_base];
+    const uint64_t start = offs[R.hist_base + (uint64_t)b * R.n_chunks] - rb;
+    const uint64_t end = b + 1 < R.nb ? offs[R.hist_base + (uint64_t)(b + 1) * R.n_chunks] - rb : R.n;
+    const uint64_t p0 = (uint64_t)p * SINGLE_CHUNK;
+    if (start + p0 >= end) return;
+    const uint32_t n = (uint32_t)(end - start - p0 < SINGLE_CHUNK ? end - start - p0 : SINGLE_CHUNK);
+    const ColView V = aos_view_d(part + (R.out_pos + start + p0) * (uint64_t)L.words, L);
+    Agg a;
+    empty_agg(a);
+    for (uint32_t i = threadIdx.x; i < n; i += 256) {
+        Agg r;
+        load_payload(V, i, r);
+        combine(a, r);
+    }
+    block_reduce_agg<256>(a, s_agg);
+    if (threadIdx.x == 0) {
+        a.key = V.key[0];
+        partials[(uint64_t)si * max_pieces + p] = a;
+    }
+}
+
 __global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restrict__ slots,
                                                        const FlatInst* __restrict__ insts,
                                                        const Region* __restrict__ regions,
@@ -902,7 +944,9 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restric
                                                        const uint64_t* __restrict__ part, Layout L,
                                                        const uint32_t* __restrict__ first_slot,
                                                        const Dest* __restrict__ dests, uint64_t* __restrict__ status,
-                                                       uint64_t* __restrict__ totals, uint32_t* __restrict__ ctl) {
+                                                       uint64_t* __restrict__ totals, uint32_t* __restrict__ ctl,
+                                                       const uint32_t* __restrict__ single_of,
+                                                       const Agg* __restrict__ partials, uint32_t max_pieces) {
     __shared__ LeafSmem s;
     __shared__ uint32_t s_li;
     __shared__ uint64_t s_pre;
@@ -938,6 +982,27 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restric
         if (w == 0) {
             const uint64_t pre = chained_prefix(status, li, first, 0, &ctl[1]);
             if (lane == 0 && li == last) totals[d] = pre;
+        }
+        return;
+    }
+    if (single && single_of && single_of[sl.bucket] != ~0u) {
+        // a single-key bucket whose pieces k_flat_single_partial reduced:
+        // combine them with a fixed tree
+        if (w == 0) {
+            const uint64_t pre = chained_prefix(status, li, first, 1, &ctl[1]);
+            if (lane == 0) s_pre = pre;
+        }
+        const Agg* pa = partials + (uint64_t)single_of[sl.bucket] * max_pieces;
+        const uint32_t np = (uint32_t)((n + SINGLE_CHUNK - 1) / SINGLE_CHUNK);
+        Agg a;
+        empty_agg(a);
+        for (uint32_t i = tid; i < np; i += LEAF_NT) combine(a, pa[i]);
+        Agg* red = reinterpret_cast<Agg*>(s.sort.key);  // LEAF_NT*48 bytes fit the key array
+        block_reduce_agg<LEAF_NT>(a, red);
+        if (tid == 0) {
+            a.key = pa[0].key;
+            if (s_pre < D.capacity) store_agg(D.out, s_pre, a);
+            if (li == last) totals[d] = s_pre + 1;
         }
         return;
     }
@@ -1386,6 +1451,10 @@ void launch_extract_keys(const uint64_t* rows, uint64_t n, uint32_t stride, uint
     if (g > 8192) g = 8192;
     hipLaunchKernelGGL(k_extract_keys, dim3((uint32_t)g), dim3(256), 0, st, rows, n, stride, keys);
 }
+void launch_sample_keys(ColView src, uint64_t n, uint64_t S, uint64_t* out, hipStream_t st) {
+    if (!S) return;
+    hipLaunchKernelGGL(k_sample_keys, dim3((uint32_t)((S + 255) / 256)), dim3(256), 0, st, src, n, S, out);
+}
 void launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st) {
     if (!n) return;
     uint64_t g = (n + 255) / 256;
@@ -1402,10 +1471,18 @@ void launch_leaf(const Leaf* leaves, uint32_t n_leaves, const uint32_t* leaf_des
 void launch_leaf_flat(const FlatSlot* slots, uint32_t n_slots, const FlatInst* insts, const Region* regions,
                       const uint64_t* splitters, const uint64_t* offs, const uint64_t* part, Layout L,
                       const uint32_t* first_slot, const Dest* dests, uint64_t* status, uint64_t* totals,
-                      uint32_t* ctl, hipStream_t st) {
+                      uint32_t* ctl, hipStream_t st, const uint32_t* single_of, const void* partials,
+                      uint32_t max_pieces) {
     if (!n_slots) return;
     hipLaunchKernelGGL(k_leaf_flat, dim3(n_slots), dim3(LEAF_NT), 0, st, slots, insts, regions, splitters, offs, part,
-                       L, first_slot, dests, status, totals, ctl);
+                       L, first_slot, dests, status, totals, ctl, single_of, (const Agg*)partials, max_pieces);
+}
+void launch_flat_single_partial(const Region* regions, const uint64_t* offs, const uint64_t* part, Layout L,
+                                const uint32_t* single_buckets, uint32_t n_single, uint32_t max_pieces, void* partials,
+                                hipStream_t st) {
+    if (!n_single) return;
+    hipLaunchKernelGGL(k_flat_single_partial, dim3(n_single * max_pieces), dim3(256), 0, st, regions, offs, part, L,
+                       single_buckets, max_pieces, (Agg*)partials);
 }
 void launch_single_partial(const Leaf* leaves, const SinglePiece* pieces, uint32_t n_pieces, void* partials,
                            hipStream_t st) {
