@@ -304,6 +304,36 @@ def bench_serve(args):
     ctx.close()
 
 
+# Profile labels of the library's launches -> kernel names in rocprofv3 output
+KERNELS_OF_LABEL = {"k_leaf": ["k_leaf_flat", "k_leaf"], "k_merge": ["k_merge"], "k_scatter": ["k_scatter"],
+                    "k_hist": ["k_hist"], "k_sample": ["k_sample", "k_sample_keys"]}
+
+
+def hbm_traffic(workload, label):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) of the kernels
+    behind a profile label, from profiles/hbm_traffic.json; None when the
+    workload was not profiled or the kernels changed since (source hash)."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(here, "profiles", "hbm_traffic.json")) as f:
+            t = json.load(f)
+        src = open(os.path.join(here, "paper_2010_00152_amd", "csrc", "isa_kernels.hip"), "rb").read()
+    except OSError:
+        return None, None
+    if hashlib.sha256(src).hexdigest()[:16] != t.get("kernel_source_sha256_16"):
+        return None, None
+    wl = t.get("workloads", {}).get(workload)
+    if not wl:
+        return None, None
+    n = b = 0.0
+    for k in KERNELS_OF_LABEL.get(label, [label]):
+        if k in wl:
+            n += wl[k]["launches"]
+            b += wl[k]["launches"] * (wl[k]["fetch_bytes_per_launch"] + wl[k]["write_bytes_per_launch"])
+    return (b / n, None) if n else (None, None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -424,10 +454,14 @@ def main():
         dom = max(dev_kernels, key=lambda k: dev_kernels[k]["total_ms"])
         r = dev_kernels[dom]
         achieved = r["bytes"] / (r["total_ms"] * 1e-3) / 1e9
+        algo_pl = r["bytes"] / r["launches"]
+        traffic, ratio = hbm_traffic(args.workload, dom)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": int(traffic) if traffic else None,
+                    "traffic_over_algo": round(traffic / algo_pl, 3) if traffic else None,
                     "avg_launch_us": round(1e3 * r["total_ms"] / r["launches"], 2),
-                    "algo_bytes_per_launch": int(r["bytes"] / r["launches"])}
+                    "algo_bytes_per_launch": int(algo_pl)}
 
     host_link = None
     if stats["spilled_rows"]:
