@@ -165,6 +165,10 @@ __device__ __forceinline__ int pad16(int p) { return p + (p >> 4); }
 constexpr int CNT_BITS = 5;
 constexpr int CNT_DIGITS = 1 << CNT_BITS;
 
+// Key bits (below the range's top) that leaf sorts and splitter samples order
+// first; a leaf re-sorts at full width when two distinct keys share them.
+constexpr int LEAF_TRUNC = 30;
+
 template <int NT, int IPT>
 struct CSortSmem {
     static constexpr int N = NT * IPT;
@@ -342,7 +346,11 @@ __global__ void __launch_bounds__(LEAF_NT) k_sample(const Region* __restrict__ r
         k[j] = q < S ? k[j] - mn : range;  // padding sorts last
     }
     striped_to_blocked<NT, IPT>(k, v, s);
-    block_sort_cnt<NT, IPT>(k, v, 0, bit_length(range), s);
+    // quantiles need only the order of the top LEAF_TRUNC bits: keys that
+    // agree on them may stay unordered among themselves (any increasing
+    // splitters are valid; the fix-up below makes them strictly increasing)
+    const int nbits = bit_length(range);
+    block_sort_cnt<NT, IPT>(k, v, nbits > LEAF_TRUNC ? nbits - LEAF_TRUNC : 0, nbits, s);
     __shared__ uint64_t s_spl[MAX_BUCKETS];
     const uint32_t nb = R.nb;
     if (tid < (int)nb - 1) {
@@ -653,7 +661,6 @@ struct LeafSmem {
     uint32_t scan_tmp[LEAF_NT / 64 + 1];
 };
 
-constexpr int LEAF_TRUNC = 30;
 constexpr int LEAF_ROUND = 8;  // payload loads issued together
 
 // Sort, reduce and place one leaf of at most LEAF_CAP rows (workgroup-wide).
@@ -1014,9 +1021,9 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restric
 // LDS-staged merge of two sorted runs of unique keys, both row-major with
 // the same layout, combining equal keys (A's row first).  Partition p covers
 // merge diagonals [p*MG_D, (p+1)*MG_D); its A and B rows are copied to LDS
-// with coalesced loads, merged there by merge path per thread, staged again
-// in LDS and written out with coalesced stores at the chained prefix of the
-// partitions' group counts.
+// with coalesced loads, merged there by merge path per thread, and each
+// thread writes its merged rows at the chained prefix of the partitions'
+// group counts.
 // ---------------------------------------------------------------------------
 
 constexpr int MG_NT = 128;
@@ -1069,7 +1076,6 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
                                                  Layout L, uint64_t* __restrict__ status, uint32_t* __restrict__ ctl,
                                                  uint64_t* __restrict__ total_out) {
     __shared__ uint64_t s_in[(MG_D + 2) * MG_MAXW];
-    __shared__ uint64_t s_out[(MG_D + 2) * MG_MAXW];
     __shared__ uint32_t s_li[MG_NT + 1], s_lj[MG_NT + 1];
     __shared__ uint32_t s_tmp[MG_NT / 64 + 1];
     __shared__ uint32_t s_part;
@@ -1133,10 +1139,15 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
             if (part == gridDim.x - 1) *total_out = pre + tot;
         }
     }
+    __syncthreads();
     {
+        // each thread writes its merged rows straight to their place: the
+        // rows of consecutive threads are adjacent, so a wave's stores fill
+        // whole cache lines between them
+        uint64_t* const ob = out + s_pre * W;
         uint32_t o = off, i = i0, j = j0;
         while (i < i1 || j < j1) {
-            uint64_t* dst = s_out + o * W;
+            uint64_t* dst = ob + (uint64_t)o * W;
             if (j >= j1 || (i < i1 && a[i * W] < b[j * W])) {
                 for (uint32_t x = 0; x < W; ++x) dst[x] = a[i * W + x];
                 ++i;
@@ -1151,9 +1162,6 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
             ++o;
         }
     }
-    __syncthreads();
-    const uint64_t base = s_pre * W;
-    for (uint32_t x = tid; x < tot * W; x += MG_NT) out[base + x] = s_out[x];
 }
 
 // Copy n rows between strided views, writing only below `cap`.
@@ -1364,12 +1372,12 @@ __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict_
 // Gather of a wide-merge window into one staging buffer of state rows.  A
 // small persistent grid walks the window's tasks (run slices of at most
 // GATHER_ROWS rows), reading pinned host memory through its device mapping
-// (or device memory) with contiguous word loads, four in flight per thread.
+// (or device memory) with contiguous word loads, eight in flight per thread.
 // The grid is kept small on purpose: the loads wait on the host link, and
 // the window being reduced meanwhile needs the compute units.  Raw slices
 // (count-1 rows) are staged in LDS and expanded to state rows on the way out.
 constexpr int GATHER_NT = 256;
-constexpr uint32_t GATHER_GRID = 96;
+constexpr uint32_t GATHER_GRID = 48;
 __global__ void __launch_bounds__(GATHER_NT) k_gather(const GatherTask* __restrict__ tasks, uint32_t n_tasks,
                                                       Layout R, Layout S, uint64_t* __restrict__ dst) {
     __shared__ uint64_t s_raw[GATHER_ROWS * 3];
@@ -1381,24 +1389,24 @@ __global__ void __launch_bounds__(GATHER_NT) k_gather(const GatherTask* __restri
         if (!t.raw) {
             const uint32_t words = t.n * sw;
             uint32_t i = threadIdx.x;
-            for (; i + 3 * GATHER_NT < words; i += 4 * GATHER_NT) {
-                const uint64_t a = in[i], b = in[i + GATHER_NT], c = in[i + 2 * GATHER_NT], d = in[i + 3 * GATHER_NT];
-                out[i] = a;
-                out[i + GATHER_NT] = b;
-                out[i + 2 * GATHER_NT] = c;
-                out[i + 3 * GATHER_NT] = d;
+            for (; i + 7 * GATHER_NT < words; i += 8 * GATHER_NT) {
+                uint64_t r[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) r[q] = in[i + q * GATHER_NT];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) out[i + q * GATHER_NT] = r[q];
             }
             for (; i < words; i += GATHER_NT) out[i] = in[i];
             continue;
         }
         const uint32_t words = t.n * rw;
         uint32_t i = threadIdx.x;
-        for (; i + 3 * GATHER_NT < words; i += 4 * GATHER_NT) {
-            const uint64_t a = in[i], b = in[i + GATHER_NT], c = in[i + 2 * GATHER_NT], d = in[i + 3 * GATHER_NT];
-            s_raw[i] = a;
-            s_raw[i + GATHER_NT] = b;
-            s_raw[i + 2 * GATHER_NT] = c;
-            s_raw[i + 3 * GATHER_NT] = d;
+        for (; i + 7 * GATHER_NT < words; i += 8 * GATHER_NT) {
+            uint64_t r[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r[q] = in[i + q * GATHER_NT];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s_raw[i + q * GATHER_NT] = r[q];
         }
         for (; i < words; i += GATHER_NT) s_raw[i] = in[i];
         __syncthreads();
