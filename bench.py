@@ -32,6 +32,9 @@ WORKLOADS = {
     "nospill_100M_zipf0": (100_000_000, 10_000_000, 0.0, 2, 12 * 1024, True, "all"),
     "nospill_100M_zipf1.2": (100_000_000, 10_000_000, 1.2, 4, 12 * 1024, True, "all"),
     "plain_1M_10k": (1_000_000, 10_000, 0.0, 1, 64, False, "int"),
+    # input already sorted on the key (in-stream aggregation, no sort): keys are
+    # 1e8 ranks uniform over 1e7 values, sorted on the device
+    "sorted_100M_1e7": (100_000_000, 10_000_000, 0.0, 8, 16, True, "all"),
 }
 # Forms beyond the plain operator (each prints its own JSON line):
 #   batch_c3:    instances with rows log-uniform 1e3..1e7 and distinct/rows
@@ -388,7 +391,12 @@ def main():
     aggs = isa.ISA_ALL if aggs_name == "all" else isa.ISA_INT_AGGS
     print("bench: workload %s, generating %d rows on the device" % (args.workload, n), file=sys.stderr,
           flush=True)
-    kd, vd, fd = dgd.plain_input(seed, n, d, s, with_f64=with_f)
+    if args.workload.startswith("sorted_"):
+        kd = torch.sort(dgd.uniform_ranks(datagen.substream_seed(seed, 1), n, d)).values
+        vd = dgd.uniform_i64(datagen.substream_seed(seed, 2), n)
+        fd = dgd.normal_f64(datagen.substream_seed(seed, 3), n) if with_f else None
+    else:
+        kd, vd, fd = dgd.plain_input(seed, n, d, s, with_f64=with_f)
     torch.cuda.synchronize()
     ctx = isa.Context(0)
     L = isa.lib()
@@ -407,8 +415,11 @@ def main():
     sp = isa._stream_ptr(stream)
 
     def step():
-        rc = L.isa_group_by(ctx.handle, isa.ctypes.byref(inp), aggs, wss, sps, isa.ctypes.byref(out),
-                            isa.ctypes.byref(st), sp)
+        if args.workload.startswith("sorted_"):
+            rc = L.isa_group_by_sorted(ctx.handle, isa.ctypes.byref(inp), aggs, wss, isa.ctypes.byref(out), sp)
+        else:
+            rc = L.isa_group_by(ctx.handle, isa.ctypes.byref(inp), aggs, wss, sps, isa.ctypes.byref(out),
+                                isa.ctypes.byref(st), sp)
         if rc != isa.ISA_OK:
             raise isa.InsortError(rc, ctx.last_error())
 

@@ -82,6 +82,14 @@ def zipf_approx_keys(seed: int, n: int, d: int, s: float, start: int = 0, out=No
     return out
 
 
+def uniform_ranks(seed: int, n: int, d: int, start: int = 0, out=None):
+    """int64 ranks uniform over [0, d) (datagen.uniform_ranks on the device)."""
+    import torch
+    out = torch.empty(n, dtype=torch.int64, device="cuda") if out is None else out
+    _ck(_load().dg_uniform_ranks(seed, start, n, d, out.data_ptr(), _st()))
+    return out
+
+
 def uniform_i64(seed: int, n: int, lo: int = -1_000_000, hi: int = 1_000_000, start: int = 0, out=None):
     import torch
     out = torch.empty(n, dtype=torch.int64, device="cuda") if out is None else out

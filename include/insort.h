@@ -149,6 +149,19 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs,
                         isa_stats* stats, void* stream);
 
 /*
+ * Group input that is already sorted on its key (ascending, unsigned): the
+ * in-stream aggregation of the paper's decision table for sorted input (§1,
+ * and §2.1 on in-stream grouping) with no sort and no run.  One pass finds the
+ * groups, a second reduces them; groups longer than 4096 rows are reduced in
+ * parallel pieces.  The workspace holds only per-4096-row bookkeeping (about
+ * 48 bytes per 4096 input rows).  Errors: ISA_EINVAL if a key is below its
+ * predecessor (nothing is written), ISA_ETRUNC (n_groups = required), as for
+ * isa_group_by otherwise.
+ */
+isa_status isa_group_by_sorted(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_workspace ws,
+                               isa_output* out, void* stream);
+
+/*
  * Group on the pair (a, b) of int32 columns for input sorted on a only
  * (Section 1: with input sorted on a prefix of the grouping key, grouping
  * proceeds one segment at a time).  Each a-segment is grouped on b

@@ -87,6 +87,8 @@ SIGNATURES = {
                                     ctypes.POINTER(isa_output), ctypes.POINTER(isa_stats), P]),
     "isa_group_by_segmented": (ctypes.c_int, [P, P, P, P, U64, U32, isa_workspace, P, P,
                                               ctypes.POINTER(isa_output), P]),
+    "isa_group_by_sorted": (ctypes.c_int, [P, ctypes.POINTER(isa_input), U32, isa_workspace,
+                                           ctypes.POINTER(isa_output), P]),
     "isa_batch_run": (ctypes.c_int, [P, U32, ctypes.POINTER(isa_input), U32, isa_workspace,
                                      ctypes.POINTER(isa_output), P]),
     "isa_batch_workspace_bytes": (U64, [U32, ctypes.POINTER(isa_input), U32]),
@@ -256,6 +258,28 @@ def group_by(ctx: Context, keys, v_i64=None, v_f64=None, aggs: int = ISA_ALL,
     g = out.n_groups
     res = {k: v[:min(g, cap)] for k, v in o.items()}
     return res, st.as_dict(), status, g
+
+
+def group_by_sorted(ctx: Context, keys, v_i64=None, v_f64=None, aggs: int = ISA_ALL, mem_budget: int = 16 << 20,
+                    capacity: int | None = None, workspace=None, stream=None, check: bool = True):
+    """Group input already sorted on its key (isa_group_by_sorted).
+    Returns (dict of output tensors trimmed to n_groups, status, n_groups)."""
+    import torch
+    dev = keys.device
+    n = keys.numel()
+    cap = n if capacity is None else capacity
+    if workspace is None:
+        workspace = torch.empty(mem_budget, dtype=torch.uint8, device=dev)
+    o = _alloc_outputs(torch, cap, aggs, dev)
+    out = _output_struct(o, cap)
+    inp = isa_input(_ptr(keys), _ptr(v_i64), _ptr(v_f64), n)
+    ws = isa_workspace(_ptr(workspace), workspace.numel())
+    status = lib().isa_group_by_sorted(ctx.handle, ctypes.byref(inp), aggs, ws, ctypes.byref(out),
+                                       _stream_ptr(stream))
+    if check and status != ISA_OK:
+        raise InsortError(status, ctx.last_error())
+    g = out.n_groups
+    return {k: v[:min(g, cap)] for k, v in o.items()}, status, g
 
 
 def group_by_segmented(ctx: Context, a, b, v=None, aggs: int = ISA_INT_AGGS, mem_budget: int = 256 << 20,

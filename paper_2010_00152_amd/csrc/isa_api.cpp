@@ -822,6 +822,118 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
 
 extern "C" {
 
+}  // extern "C"
+
+namespace {
+
+// In-stream grouping of rows already sorted on key >> shift into `ov`
+// (capacity cap); returns the number of groups (> cap: nothing written).
+// Rows are in raw layout: count 1 or a count column, and one value column for
+// sum, min and max.
+uint64_t sorted_group(Engine& E, Arena& A, const ColView& V, uint64_t n, int shift, const OutView& ov, uint64_t cap) {
+    if (V.mn != V.sum || V.mx != V.sum) throw Fail{ISA_EINVAL, "internal: sorted grouping takes raw rows"};
+    const uint64_t m = sorted_tiles(n);
+    uint32_t* heads = A.take_n<uint32_t>(m + 1);
+    uint64_t* offs = A.take_n<uint64_t>(m + 1);
+    uint64_t* tiles = A.take_n<uint64_t>(scan_tiles(m) + 1);
+    uint64_t* bounds = A.take_n<uint64_t>(m + 1);
+    uint64_t* bigs = A.take_n<uint64_t>(3 * m + 3);
+    uint64_t* ctl = A.take_n<uint64_t>(1);  // [bad, n_bigs] as two u32
+    launch_fill(ctl, 1, 0, E.stream);
+    E.pbegin("k_sorted_tiles");
+    launch_sorted_tiles(V, n, shift, heads, (uint32_t*)ctl, E.stream);
+    E.pend(n, n * 8);
+    launch_scan(heads, m, tiles, offs, E.stream);
+    const uint64_t* h = (const uint64_t*)download_async(E, ctl, 8);
+    const uint64_t* hg = (const uint64_t*)download_async(E, offs + m, 8);
+    E.sync();
+    if ((uint32_t)h[0]) throw Fail{ISA_EINVAL, "input is not sorted on the key"};
+    const uint64_t groups = *hg;
+    if (groups > cap) return groups;
+    launch_sorted_align(V, n, shift, bounds, E.stream);
+    E.pbegin("k_sorted_ranges");
+    launch_sorted_ranges(V, n, shift, bounds, offs, ov, cap, bigs, (uint32_t*)ctl + 1, E.stream);
+    E.pend(n, n * 24);
+    const uint64_t* hb = (const uint64_t*)download_async(E, ctl, 8);
+    E.sync();
+    const uint32_t n_bigs = (uint32_t)(hb[0] >> 32);
+    if (n_bigs) {
+        std::vector<uint64_t> hbig(3 * (size_t)n_bigs);
+        const uint64_t* p = (const uint64_t*)download_async(E, bigs, hbig.size() * 8);
+        E.sync();
+        std::memcpy(hbig.data(), p, hbig.size() * 8);
+        Leaf lf;
+        std::memset(&lf, 0, sizeof(lf));
+        lf.src = V;
+        std::vector<SinglePiece> pieces;
+        std::vector<uint32_t> first(n_bigs + 1, 0);
+        for (uint32_t b = 0; b < n_bigs; ++b) {
+            first[b] = (uint32_t)pieces.size();
+            for (uint64_t r = hbig[3 * b]; r < hbig[3 * b + 1]; r += SINGLE_CHUNK) {
+                SinglePiece sp;
+                sp.leaf = 0;
+                sp.slot = (uint32_t)pieces.size();
+                sp.start = r;
+                sp.n = (uint32_t)std::min<uint64_t>(SINGLE_CHUNK, hbig[3 * b + 1] - r);
+                sp.pad = 0;
+                pieces.push_back(sp);
+            }
+        }
+        first[n_bigs] = (uint32_t)pieces.size();
+        UpPack up;
+        const uint64_t o_l = up.add(&lf, sizeof(lf));
+        const uint64_t o_p = up.add(pieces.data(), pieces.size() * sizeof(SinglePiece));
+        const uint64_t o_f = up.add(first.data(), first.size() * sizeof(uint32_t));
+        char* d = up.commit(E, A);
+        void* partials = A.take(pieces.size() * single_partial_bytes());
+        uint64_t big_rows = 0;
+        for (uint32_t b = 0; b < n_bigs; ++b) big_rows += hbig[3 * b + 1] - hbig[3 * b];
+        E.pbegin("k_single_partial");
+        launch_single_partial((const Leaf*)(d + o_l), (const SinglePiece*)(d + o_p), (uint32_t)pieces.size(), partials,
+                              E.stream);
+        E.pend(big_rows, 0);
+        launch_sorted_big_final(V, shift, bigs, n_bigs, (const uint32_t*)(d + o_f), partials, ov, cap, E.stream);
+        E.sync();
+    }
+    return groups;
+}
+
+}  // namespace
+
+extern "C" {
+
+isa_status isa_group_by_sorted(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_workspace ws, isa_output* out,
+                               void* stream) {
+    if (out) out->n_groups = 0;
+    if (!ctx || !valid_aggs(aggs)) return ISA_EINVAL;
+    isa_status s = check_input(in, aggs);
+    if (s != ISA_OK) return s;
+    s = check_output(out, aggs, true);
+    if (s != ISA_OK) return s;
+    if (in->n_rows == 0) return ISA_OK;
+    if (!ws.dev || ((uintptr_t)ws.dev & 255)) return ISA_EINVAL;
+    const Cols k = cols_of(aggs);
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    try {
+        ck(hipSetDevice(ctx->device), "hipSetDevice");
+        Engine& E = ctx->eng;
+        E.stream = (hipStream_t)stream;
+        Arena A;
+        A.base = (char*)ws.dev;
+        A.cap = ws.bytes;
+        const uint64_t g = sorted_group(E, A, input_view(*in, k), in->n_rows, 0, output_view(*out, aggs, 0),
+                                        out->capacity);
+        out->n_groups = g;
+        return g > out->capacity ? ISA_ETRUNC : ISA_OK;
+    } catch (const Fail& f) {
+        out->n_groups = 0;
+        return fail(ctx, f);
+    } catch (const std::bad_alloc&) {
+        out->n_groups = 0;
+        return ISA_ENOMEM;
+    }
+}
+
 isa_status isa_group_by_segmented(isa_ctx* ctx, const int32_t* a, const int32_t* b, const int64_t* v, uint64_t n,
                                   uint32_t aggs, isa_workspace ws, int32_t* out_a, int32_t* out_b, isa_output* out,
                                   void* stream) {

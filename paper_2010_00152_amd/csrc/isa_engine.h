@@ -20,6 +20,13 @@ void launch_scatter(const Region* regions, const Chunk* chunks, uint32_t n_chunk
 void launch_bucket_starts(const Region* regions, uint32_t n_regions, const uint64_t* offs, const uint64_t* bs_base,
                           uint64_t* bstart, hipStream_t st);
 void launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st);
+uint64_t sorted_tiles(uint64_t n);
+void launch_sorted_tiles(ColView V, uint64_t n, int shift, uint32_t* heads, uint32_t* bad, hipStream_t st);
+void launch_sorted_align(ColView V, uint64_t n, int shift, uint64_t* bounds, hipStream_t st);
+void launch_sorted_ranges(ColView V, uint64_t n, int shift, const uint64_t* bounds, const uint64_t* offs, OutView out,
+                          uint64_t cap, uint64_t* bigs, uint32_t* n_bigs, hipStream_t st);
+void launch_sorted_big_final(ColView V, int shift, const uint64_t* bigs, uint32_t n_bigs, const uint32_t* first,
+                             const void* partials, OutView out, uint64_t cap, hipStream_t st);
 void launch_sample_keys(ColView src, uint64_t n, uint64_t S, uint64_t* out, hipStream_t st);
 void launch_copy_words(const uint64_t* src, uint64_t* dst, uint64_t n, hipStream_t st);
 void launch_extract_keys(const uint64_t* rows, uint64_t n, uint32_t stride, uint64_t* keys, hipStream_t st);

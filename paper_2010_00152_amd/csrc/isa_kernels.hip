@@ -1164,6 +1164,288 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Sorted-input path: input already ordered on its key is grouped in one
+// stream, with no sort (in-stream aggregation).  Nominal tiles of SORTED_T
+// rows count their group heads (a row whose key differs from the row
+// before); tile boundaries move forward to the next head, so that every range
+// between moved boundaries holds whole groups.  One workgroup reduces a range;
+// a group longer than a tile is reduced in parallel pieces.  Keys may be
+// grouped on their high bits only (key >> shift).
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t SORTED_T = 3584;                 // nominal tile rows
+constexpr uint32_t SORTED_CAP = (uint32_t)LEAF_CAP;  // rows one workgroup reduces
+constexpr int SORTED_NT = 256;
+
+__device__ __forceinline__ uint64_t skey(const ColView& V, uint64_t i, int shift) { return V.key[i * V.stride] >> shift; }
+
+// heads[t]: group heads in tile t; *bad = 1 if some key is below its predecessor.
+__global__ void __launch_bounds__(SORTED_NT) k_sorted_tiles(ColView V, uint64_t n, int shift,
+                                                            uint32_t* __restrict__ heads, uint32_t* __restrict__ bad) {
+    __shared__ uint32_t s_tmp[SORTED_NT / 64 + 1];
+    const uint64_t t0 = (uint64_t)blockIdx.x * SORTED_T;
+    uint32_t c = 0;
+    bool desc = false;
+    for (uint32_t j = threadIdx.x; j < SORTED_T; j += SORTED_NT) {
+        const uint64_t i = t0 + j;
+        if (i >= n) break;
+        const uint64_t k = skey(V, i, shift);
+        if (i == 0) {
+            ++c;
+            continue;
+        }
+        const uint64_t q = skey(V, i - 1, shift);
+        c += k != q ? 1u : 0u;
+        desc |= k < q;
+    }
+    uint32_t tot;
+    block_exclusive_scan<SORTED_NT>(c, s_tmp, tot);
+    const bool any_desc = __syncthreads_or(desc);
+    if (threadIdx.x == 0) {
+        heads[blockIdx.x] = tot;
+        if (any_desc) atomicOr(bad, 1u);
+    }
+}
+
+// bounds[t] for t in [1, m): the first head at or after t*SORTED_T (or n);
+// bounds[0] = 0 and bounds[m] = n.  Galloping search: a long group costs
+// O(log length).
+__global__ void k_sorted_align(ColView V, uint64_t n, int shift, uint64_t m, uint64_t* __restrict__ bounds) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > m) return;
+    if (t == 0 || t == m) {
+        bounds[t] = t == 0 ? 0 : n;
+        return;
+    }
+    const uint64_t b = t * SORTED_T;
+    const uint64_t x = skey(V, b - 1, shift);
+    if (skey(V, b, shift) != x) {
+        bounds[t] = b;
+        return;
+    }
+    uint64_t lo = b, hi = n, step = 1;
+    for (;;) {
+        const uint64_t c = lo + step;
+        if (c >= n) {
+            hi = n;
+            break;
+        }
+        if (skey(V, c, shift) != x) {
+            hi = c;
+            break;
+        }
+        lo = c;
+        step <<= 1;
+    }
+    while (lo + 1 < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (skey(V, mid, shift) == x) lo = mid;
+        else hi = mid;
+    }
+    bounds[t] = hi;
+}
+
+struct SortedSmem {
+    uint64_t col[SORTED_CAP];  // one column of the range, for the striped-to-blocked transpose
+    uint64_t pre_cnt[SORTED_NT];
+    uint64_t pre_sum[SORTED_NT];
+    int64_t pre_mn[SORTED_NT];
+    int64_t pre_mx[SORTED_NT];
+    double pre_fs[SORTED_NT];
+    uint32_t pre_flags[SORTED_NT];
+    uint32_t tmp[SORTED_NT / 64 + 1];
+};
+
+constexpr int SORTED_IPT = (int)SORTED_CAP / SORTED_NT;
+
+// Words of column c of rows [s, s+n) into x[] in blocked order (thread t holds
+// rows t*ipt ..), through LDS with coalesced loads.
+__device__ __forceinline__ void sorted_column(const uint64_t* c, uint64_t stride, uint64_t s, uint32_t n, int shift,
+                                              uint32_t p0, uint32_t ipt, uint64_t (&x)[SORTED_IPT], SortedSmem& sm) {
+#pragma unroll
+    for (int j = 0; j < SORTED_IPT; ++j) {
+        const uint32_t q = (uint32_t)j * SORTED_NT + threadIdx.x;
+        if (q < n) sm.col[q] = c[(s + q) * stride] >> shift;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SORTED_IPT; ++j)
+        if ((uint32_t)j < ipt && p0 + j < n) x[j] = sm.col[p0 + j];
+    __syncthreads();
+}
+
+// Groups of rows [s, s+n) (n <= SORTED_CAP; row s starts a group) written at
+// out[g ..).  Blocked: thread t reduces rows t*ipt .. t*ipt+ipt-1; the group
+// open at a thread's end continues into the following threads.  Returns the
+// number of groups.
+__device__ uint32_t sorted_reduce_range(const ColView& V, int shift, uint64_t s, uint32_t n, const OutView& out,
+                                        uint64_t cap, uint64_t g, SortedSmem& sm) {
+    const int tid = threadIdx.x;
+    const uint32_t ipt = (n + SORTED_NT - 1) / SORTED_NT;
+    const uint32_t p0 = (uint32_t)tid * ipt;
+    const uint32_t p1 = p0 + ipt < n ? p0 + ipt : n;
+    uint64_t kk[SORTED_IPT], cc[SORTED_IPT], vv[SORTED_IPT], ff[SORTED_IPT];
+    // keys, and the key before the thread's first row
+#pragma unroll
+    for (int j = 0; j < SORTED_IPT; ++j) {
+        const uint32_t q = (uint32_t)j * SORTED_NT + tid;
+        if (q < n) sm.col[q] = skey(V, s + q, shift);
+    }
+    __syncthreads();
+    const uint64_t first_prev = p0 > 0 && p0 < n ? sm.col[p0 - 1] : 0;
+#pragma unroll
+    for (int j = 0; j < SORTED_IPT; ++j)
+        if ((uint32_t)j < ipt && p0 + j < n) kk[j] = sm.col[p0 + j];
+    __syncthreads();
+    if (V.cnt) sorted_column(V.cnt, V.stride, s, n, 0, p0, ipt, cc, sm);
+    if (V.sum) sorted_column((const uint64_t*)V.sum, V.stride, s, n, 0, p0, ipt, vv, sm);
+    if (V.fs) sorted_column((const uint64_t*)V.fs, V.stride, s, n, 0, p0, ipt, ff, sm);
+    uint32_t nh = 0;
+    {
+        uint64_t prev = first_prev;
+#pragma unroll
+        for (int j = 0; j < SORTED_IPT; ++j) {
+            const uint32_t p = p0 + j;
+            if (p < p1) {
+                if (p == 0 || kk[j] != prev) ++nh;
+                prev = kk[j];
+            }
+        }
+    }
+    uint32_t total;
+    const uint32_t obase = block_exclusive_scan<SORTED_NT>(nh, sm.tmp, total);
+    Agg acc;
+    empty_agg(acc);
+    bool have_head = false;
+    uint32_t h = 0;
+    uint64_t prev = first_prev;
+#pragma unroll
+    for (int j = 0; j < SORTED_IPT; ++j) {
+        const uint32_t p = p0 + j;
+        if (p >= p1) break;
+        Agg r;
+        r.key = kk[j];
+        r.cnt = V.cnt ? cc[j] : 1ull;
+        r.sum = V.sum ? vv[j] : 0ull;
+        r.mn = V.sum ? (int64_t)vv[j] : INT64_MAX;
+        r.mx = V.sum ? (int64_t)vv[j] : INT64_MIN;
+        r.fs = V.fs ? __longlong_as_double((long long)ff[j]) : 0.0;
+        if (p == 0 || r.key != prev) {
+            if (!have_head) {
+                sm.pre_cnt[tid] = acc.cnt;
+                sm.pre_sum[tid] = acc.sum;
+                sm.pre_mn[tid] = acc.mn;
+                sm.pre_mx[tid] = acc.mx;
+                sm.pre_fs[tid] = acc.fs;
+                have_head = true;
+            } else {
+                const uint64_t pos = g + obase + h - 1;
+                if (pos < cap) store_agg(out, pos, acc);
+            }
+            acc = r;
+            ++h;
+        } else {
+            combine(acc, r);
+        }
+        prev = r.key;
+    }
+    if (!have_head) {
+        sm.pre_cnt[tid] = acc.cnt;
+        sm.pre_sum[tid] = acc.sum;
+        sm.pre_mn[tid] = acc.mn;
+        sm.pre_mx[tid] = acc.mx;
+        sm.pre_fs[tid] = acc.fs;
+    }
+    sm.pre_flags[tid] = (have_head ? 1u : 0u) | (p1 > p0 ? 2u : 0u);
+    __syncthreads();
+    if (have_head) {
+        for (int u = tid + 1; u < SORTED_NT; ++u) {
+            const uint32_t f = sm.pre_flags[u];
+            if (!(f & 2u)) break;
+            Agg b;
+            b.cnt = sm.pre_cnt[u];
+            b.sum = sm.pre_sum[u];
+            b.mn = sm.pre_mn[u];
+            b.mx = sm.pre_mx[u];
+            b.fs = sm.pre_fs[u];
+            combine(acc, b);
+            if (f & 1u) break;
+        }
+        const uint64_t pos = g + obase + h - 1;
+        if (pos < cap) store_agg(out, pos, acc);
+    }
+    __syncthreads();
+    return total;
+}
+
+// One workgroup per range [bounds[t], bounds[t+1]).  A range longer than
+// SORTED_CAP ends with a group that crosses the next nominal boundary: its
+// rows before that group (less than a tile) are reduced here and the group
+// itself is listed in bigs (first row, end, output position) for the
+// piecewise reduction.
+__global__ void __launch_bounds__(SORTED_NT) k_sorted_ranges(ColView V, uint64_t n, int shift,
+                                                             const uint64_t* __restrict__ bounds,
+                                                             const uint64_t* __restrict__ offs, OutView out,
+                                                             uint64_t cap, uint64_t* __restrict__ bigs,
+                                                             uint32_t* __restrict__ n_bigs) {
+    __shared__ SortedSmem sm;
+    __shared__ uint32_t s_tmp2[SORTED_NT / 64 + 1];
+    __shared__ uint64_t s_last;
+    const uint64_t t = blockIdx.x;
+    const uint64_t a = bounds[t], e = bounds[t + 1];
+    if (a >= e) return;
+    const int tid = threadIdx.x;
+    // output position of the group starting at a: heads before a
+    const uint64_t u = a / SORTED_T, bu = u * SORTED_T;
+    uint32_t c = 0;
+    for (uint64_t i = bu + tid; i < a; i += SORTED_NT)
+        c += (i == 0 || skey(V, i, shift) != skey(V, i - 1, shift)) ? 1u : 0u;
+    uint32_t before;
+    block_exclusive_scan<SORTED_NT>(c, s_tmp2, before);
+    const uint64_t g = offs[u] + before;
+    if (e - a <= SORTED_CAP) {
+        sorted_reduce_range(V, shift, a, (uint32_t)(e - a), out, cap, g, sm);
+        return;
+    }
+    // the last head before the next nominal boundary starts the long group
+    const uint64_t nb = (t + 1) * SORTED_T;
+    if (tid == 0) s_last = a;
+    __syncthreads();
+    for (uint64_t i = a + 1 + tid; i < nb; i += SORTED_NT)
+        if (skey(V, i, shift) != skey(V, i - 1, shift)) atomicMax((unsigned long long*)&s_last, (unsigned long long)i);
+    __syncthreads();
+    const uint64_t L = s_last;
+    uint32_t small = 0;
+    if (L > a) small = sorted_reduce_range(V, shift, a, (uint32_t)(L - a), out, cap, g, sm);
+    if (tid == 0) {
+        const uint32_t k = atomicAdd(n_bigs, 1u);
+        bigs[3 * k] = L;
+        bigs[3 * k + 1] = e;
+        bigs[3 * k + 2] = g + small;
+    }
+}
+
+// Long groups: combine the partials of each group's pieces (k_single_partial)
+// with a fixed tree and write the group at its position.  big b owns partials
+// [first[b], first[b+1]).
+__global__ void __launch_bounds__(256) k_sorted_big_final(ColView V, int shift, const uint64_t* __restrict__ bigs,
+                                                          const uint32_t* __restrict__ first,
+                                                          const Agg* __restrict__ partials, OutView out,
+                                                          uint64_t cap) {
+    __shared__ Agg s_agg[256];
+    const uint32_t b = blockIdx.x;
+    Agg a;
+    empty_agg(a);
+    for (uint32_t i = first[b] + threadIdx.x; i < first[b + 1]; i += 256) combine(a, partials[i]);
+    block_reduce_agg<256>(a, s_agg);
+    if (threadIdx.x == 0) {
+        a.key = skey(V, bigs[3 * b], shift);
+        const uint64_t pos = bigs[3 * b + 2];
+        if (pos < cap) store_agg(out, pos, a);
+    }
+}
+
 // Copy n rows between strided views, writing only below `cap`.
 __global__ void __launch_bounds__(256) k_copy_rows(ColView src, uint64_t n, OutView dst, uint64_t cap) {
     const uint64_t lim = n < cap ? n : cap;
@@ -1462,6 +1744,29 @@ void launch_extract_keys(const uint64_t* rows, uint64_t n, uint32_t stride, uint
 void launch_sample_keys(ColView src, uint64_t n, uint64_t S, uint64_t* out, hipStream_t st) {
     if (!S) return;
     hipLaunchKernelGGL(k_sample_keys, dim3((uint32_t)((S + 255) / 256)), dim3(256), 0, st, src, n, S, out);
+}
+uint64_t sorted_tiles(uint64_t n) { return (n + SORTED_T - 1) / SORTED_T; }
+void launch_sorted_tiles(ColView V, uint64_t n, int shift, uint32_t* heads, uint32_t* bad, hipStream_t st) {
+    const uint64_t m = sorted_tiles(n);
+    if (!m) return;
+    hipLaunchKernelGGL(k_sorted_tiles, dim3((uint32_t)m), dim3(SORTED_NT), 0, st, V, n, shift, heads, bad);
+}
+void launch_sorted_align(ColView V, uint64_t n, int shift, uint64_t* bounds, hipStream_t st) {
+    const uint64_t m = sorted_tiles(n);
+    hipLaunchKernelGGL(k_sorted_align, dim3((uint32_t)((m + 1 + 255) / 256)), dim3(256), 0, st, V, n, shift, m, bounds);
+}
+void launch_sorted_ranges(ColView V, uint64_t n, int shift, const uint64_t* bounds, const uint64_t* offs, OutView out,
+                          uint64_t cap, uint64_t* bigs, uint32_t* n_bigs, hipStream_t st) {
+    const uint64_t m = sorted_tiles(n);
+    if (!m) return;
+    hipLaunchKernelGGL(k_sorted_ranges, dim3((uint32_t)m), dim3(SORTED_NT), 0, st, V, n, shift, bounds, offs, out, cap,
+                       bigs, n_bigs);
+}
+void launch_sorted_big_final(ColView V, int shift, const uint64_t* bigs, uint32_t n_bigs, const uint32_t* first,
+                             const void* partials, OutView out, uint64_t cap, hipStream_t st) {
+    if (!n_bigs) return;
+    hipLaunchKernelGGL(k_sorted_big_final, dim3(n_bigs), dim3(256), 0, st, V, shift, bigs, first, (const Agg*)partials,
+                       out, cap);
 }
 void launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st) {
     if (!n) return;

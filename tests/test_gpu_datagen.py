@@ -48,3 +48,9 @@ def test_device_zipf_approx_domain_and_head(s):
         p0 = (2.0 ** a - 1.0) / (dd ** a - 1.0)
     sigma = np.sqrt(n * p0 * (1 - p0))
     assert abs(top - n * p0) < 6 * sigma + 1, (top, n * p0)
+
+
+def test_device_uniform_ranks_match_host():
+    import datagen.device as dgd
+    r = dgd.uniform_ranks(81, 500_000, 12_345).cpu().numpy()
+    assert np.array_equal(r.astype(np.uint64), datagen.uniform_ranks(81, 500_000, 12_345))
