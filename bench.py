@@ -35,6 +35,9 @@ WORKLOADS = {
     # input already sorted on the key (in-stream aggregation, no sort): keys are
     # 1e8 ranks uniform over 1e7 values, sorted on the device
     "sorted_100M_1e7": (100_000_000, 10_000_000, 0.0, 8, 16, True, "all"),
+    # count(*) + count(distinct x) group by g: int32 g uniform over 1e3 values,
+    # int32 x uniform over 1e4 values (about 1e7 distinct pairs), 256 MiB workspace
+    "cdistinct_100M": (100_000_000, 10_000_000, 0.0, 9, 256, False, "count"),
 }
 # Forms beyond the plain operator (each prints its own JSON line):
 #   batch_c3:    instances with rows log-uniform 1e3..1e7 and distinct/rows
@@ -388,10 +391,17 @@ def main():
     import paper_2010_00152_amd as isa
 
     n, d, s, seed, budget_mib, with_f, aggs_name = WORKLOADS[args.workload]
-    aggs = isa.ISA_ALL if aggs_name == "all" else isa.ISA_INT_AGGS
+    aggs = {"all": isa.ISA_ALL, "int": isa.ISA_INT_AGGS, "count": isa.ISA_COUNT}[aggs_name]
     print("bench: workload %s, generating %d rows on the device" % (args.workload, n), file=sys.stderr,
           flush=True)
-    if args.workload.startswith("sorted_"):
+    if args.workload.startswith("cdistinct_"):
+        gd = dgd.uniform_ranks(datagen.substream_seed(seed, 1), n, 1000).to(torch.int32)
+        xd = dgd.uniform_ranks(datagen.substream_seed(seed, 2), n, 10_000).to(torch.int32)
+        kd, vd, fd = gd, None, None
+        cd_scratch = torch.empty(24 * n, dtype=torch.uint8, device="cuda")
+        cd_out = [torch.empty(1000, dtype=t, device="cuda") for t in (torch.int32, torch.int64, torch.int64)]
+        cd_n = isa.ctypes.c_uint64()
+    elif args.workload.startswith("sorted_"):
         kd = torch.sort(dgd.uniform_ranks(datagen.substream_seed(seed, 1), n, d)).values
         vd = dgd.uniform_i64(datagen.substream_seed(seed, 2), n)
         fd = dgd.normal_f64(datagen.substream_seed(seed, 3), n) if with_f else None
@@ -403,7 +413,8 @@ def main():
     budget = budget_mib << 20
     ws = torch.empty(budget, dtype=torch.uint8, device="cuda")
     row_b = L.isa_state_row_bytes(aggs)
-    spill = torch.empty(n * row_b, dtype=torch.uint8, pin_memory=True) if "spill_" in args.workload else None
+    spilling = "spill_" in args.workload or args.workload.startswith("cdistinct_")
+    spill = torch.empty(n * row_b, dtype=torch.uint8, pin_memory=True) if spilling else None
     cap = min(n, d)
     outs = isa._alloc_outputs(torch, cap, aggs, "cuda")
     out = isa._output_struct(outs, cap)
@@ -415,7 +426,12 @@ def main():
     sp = isa._stream_ptr(stream)
 
     def step():
-        if args.workload.startswith("sorted_"):
+        if args.workload.startswith("cdistinct_"):
+            rc = L.isa_count_distinct(ctx.handle, isa._ptr(gd), isa._ptr(xd), n, wss, sps, isa._ptr(cd_scratch),
+                                      cd_scratch.numel(), isa._ptr(cd_out[0]), isa._ptr(cd_out[1]),
+                                      isa._ptr(cd_out[2]), 1000, isa.ctypes.byref(cd_n), sp)
+            out.n_groups = cd_n.value
+        elif args.workload.startswith("sorted_"):
             rc = L.isa_group_by_sorted(ctx.handle, isa.ctypes.byref(inp), aggs, wss, isa.ctypes.byref(out), sp)
         else:
             rc = L.isa_group_by(ctx.handle, isa.ctypes.byref(inp), aggs, wss, sps, isa.ctypes.byref(out),
@@ -485,13 +501,20 @@ def main():
     if args.cpu_sample:
         import oracle
         m = min(args.cpu_sample, n)
-        k_h = kd[:m].cpu().numpy().view(np.uint64)
-        v_h = vd[:m].cpu().numpy()
-        f_h = fd[:m].cpu().numpy() if fd is not None else None
         print("bench: timing the CPU oracle on %d rows" % m, file=sys.stderr, flush=True)
-        c0 = time.perf_counter()
-        oracle.group_by(k_h, v_h, f_h)
-        c1 = time.perf_counter()
+        if args.workload.startswith("cdistinct_"):
+            g_h = gd[:m].cpu().numpy().astype(np.uint64)
+            x_h = xd[:m].cpu().numpy().astype(np.uint64)
+            c0 = time.perf_counter()
+            oracle.count_distinct(g_h, x_h)
+            c1 = time.perf_counter()
+        else:
+            k_h = kd[:m].cpu().numpy().view(np.uint64)
+            v_h = vd[:m].cpu().numpy()
+            f_h = fd[:m].cpu().numpy() if fd is not None else None
+            c0 = time.perf_counter()
+            oracle.group_by(k_h, v_h, f_h)
+            c1 = time.perf_counter()
         cpu = {"value": round(m / (c1 - c0), 1), "unit": "rows/s", "cores": 1, "kind": "oracle",
                "sample": "first %d rows of the same input, single-threaded C oracle "
                          "(merge sort then in-stream aggregation)" % m}

@@ -162,6 +162,28 @@ isa_status isa_group_by_sorted(isa_ctx* ctx, const isa_input* in, uint32_t aggs,
                                isa_output* out, void* stream);
 
 /*
+ * count(*) and count(distinct x) grouped by g, from one sort on (g, x): the
+ * paper's case for one sort serving duplicate removal and grouping together
+ * (§1; §6, Hypothesis 6).  The pair (g, x) of int32 columns becomes one
+ * normalized 64-bit key (signed order of g, then of x).  The pairs are grouped
+ * with count(*) by the path of isa_group_by (run generation under the budget
+ * `ws`, runs spilled to `spill`, wide merge), and the resulting sorted pairs
+ * are grouped again on g alone in one in-stream pass (count = sum of the pair
+ * counts, distinct = number of pairs).
+ * pair_scratch: device memory outside the budget, owned by the caller:
+ * 8 bytes per input row plus 16 per distinct pair; 24 * n_rows bytes always
+ * suffice.  Output (device, capacity rows): out_g ascending (signed),
+ * out_count, out_distinct; *n_groups is set as for isa_group_by.
+ * Errors: ISA_EINVAL (null columns), ISA_EBUDGET (workspace below the minimum,
+ * or pair_scratch too small for the distinct pairs), ISA_ESPILL, ISA_ETRUNC.
+ */
+isa_status isa_count_distinct(isa_ctx* ctx, const int32_t* g, const int32_t* x, uint64_t n_rows,
+                              isa_workspace ws, isa_spill spill, void* pair_scratch,
+                              uint64_t scratch_bytes, int32_t* out_g, uint64_t* out_count,
+                              uint64_t* out_distinct, uint64_t capacity, uint64_t* n_groups,
+                              void* stream);
+
+/*
  * Group on the pair (a, b) of int32 columns for input sorted on a only
  * (Section 1: with input sorted on a prefix of the grouping key, grouping
  * proceeds one segment at a time).  Each a-segment is grouped on b

@@ -89,6 +89,8 @@ SIGNATURES = {
                                               ctypes.POINTER(isa_output), P]),
     "isa_group_by_sorted": (ctypes.c_int, [P, ctypes.POINTER(isa_input), U32, isa_workspace,
                                            ctypes.POINTER(isa_output), P]),
+    "isa_count_distinct": (ctypes.c_int, [P, P, P, U64, isa_workspace, isa_spill, P, U64, P, P, P, U64,
+                                          ctypes.POINTER(U64), P]),
     "isa_batch_run": (ctypes.c_int, [P, U32, ctypes.POINTER(isa_input), U32, isa_workspace,
                                      ctypes.POINTER(isa_output), P]),
     "isa_batch_workspace_bytes": (U64, [U32, ctypes.POINTER(isa_input), U32]),
@@ -280,6 +282,35 @@ def group_by_sorted(ctx: Context, keys, v_i64=None, v_f64=None, aggs: int = ISA_
         raise InsortError(status, ctx.last_error())
     g = out.n_groups
     return {k: v[:min(g, cap)] for k, v in o.items()}, status, g
+
+
+def count_distinct(ctx: Context, g, x, mem_budget: int = 256 << 20, capacity: int | None = None,
+                   spill_bytes: int | None = None, workspace=None, scratch=None, stream=None, check: bool = True):
+    """count(*) and count(distinct x) per g for int32 CUDA tensors g, x
+    (isa_count_distinct).  Returns (dict g/count/distinct trimmed to
+    n_groups, status, n_groups)."""
+    import torch
+    dev = g.device
+    n = g.numel()
+    cap = n if capacity is None else capacity
+    if workspace is None:
+        workspace = torch.empty(mem_budget, dtype=torch.uint8, device=dev)
+    if scratch is None:
+        scratch = torch.empty(max(24 * n, 8), dtype=torch.uint8, device=dev)
+    sb = spill_bytes if spill_bytes is not None else n * lib().isa_state_row_bytes(ISA_COUNT)
+    spill = torch.empty(max(sb, 1), dtype=torch.uint8, pin_memory=True) if sb else None
+    og = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    oc = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+    od = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+    ng = U64()
+    ws = isa_workspace(_ptr(workspace), workspace.numel())
+    sp = isa_spill(_ptr(spill), spill.numel() if spill is not None else 0)
+    status = lib().isa_count_distinct(ctx.handle, _ptr(g), _ptr(x), n, ws, sp, _ptr(scratch), scratch.numel(),
+                                      _ptr(og), _ptr(oc), _ptr(od), cap, ctypes.byref(ng), _stream_ptr(stream))
+    if check and status != ISA_OK:
+        raise InsortError(status, ctx.last_error())
+    k = min(ng.value, cap)
+    return {"g": og[:k], "count": oc[:k], "distinct": od[:k]}, status, ng.value
 
 
 def group_by_segmented(ctx: Context, a, b, v=None, aggs: int = ISA_INT_AGGS, mem_budget: int = 256 << 20,

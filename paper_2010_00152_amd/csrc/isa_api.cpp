@@ -851,9 +851,10 @@ uint64_t sorted_group(Engine& E, Arena& A, const ColView& V, uint64_t n, int shi
     const uint64_t groups = *hg;
     if (groups > cap) return groups;
     launch_sorted_align(V, n, shift, bounds, E.stream);
+    const uint64_t row_bytes = 8 + (V.cnt ? 8 : 0) + (V.sum ? 8 : 0) + (V.fs ? 8 : 0);
     E.pbegin("k_sorted_ranges");
     launch_sorted_ranges(V, n, shift, bounds, offs, ov, cap, bigs, (uint32_t*)ctl + 1, E.stream);
-    E.pend(n, n * 24);
+    E.pend(n, n * row_bytes);
     const uint64_t* hb = (const uint64_t*)download_async(E, ctl, 8);
     E.sync();
     const uint32_t n_bigs = (uint32_t)(hb[0] >> 32);
@@ -930,6 +931,84 @@ isa_status isa_group_by_sorted(isa_ctx* ctx, const isa_input* in, uint32_t aggs,
         return fail(ctx, f);
     } catch (const std::bad_alloc&) {
         out->n_groups = 0;
+        return ISA_ENOMEM;
+    }
+}
+
+isa_status isa_count_distinct(isa_ctx* ctx, const int32_t* g, const int32_t* x, uint64_t n, isa_workspace ws,
+                              isa_spill spill, void* pair_scratch, uint64_t scratch_bytes, int32_t* out_g,
+                              uint64_t* out_count, uint64_t* out_distinct, uint64_t capacity, uint64_t* n_groups,
+                              void* stream) {
+    if (n_groups) *n_groups = 0;
+    if (!ctx || !n_groups) return ISA_EINVAL;
+    if (n == 0) return ISA_OK;
+    if (!g || !x || !out_g || !out_count || !out_distinct || !pair_scratch || ((uintptr_t)pair_scratch & 7))
+        return ISA_EINVAL;
+    if (scratch_bytes < 8 * n) return ISA_EBUDGET;
+    uint64_t* keys = (uint64_t*)pair_scratch;
+    const uint64_t pcap = (scratch_bytes - 8 * n) / 16;
+    uint64_t* pk = keys + n;
+    uint64_t* pc = pk + pcap;
+    {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        try {
+            ck(hipSetDevice(ctx->device), "hipSetDevice");
+            Engine& E = ctx->eng;
+            E.stream = (hipStream_t)stream;
+            launch_pack_pairs(g, x, n, keys, E.stream);
+            ck(hipGetLastError(), "pack");
+        } catch (const Fail& f) {
+            return fail(ctx, f);
+        }
+    }
+    // the pairs, grouped with count(*) (the stream orders the packing first)
+    isa_input in;
+    in.keys = keys;
+    in.v_i64 = nullptr;
+    in.v_f64 = nullptr;
+    in.n_rows = n;
+    isa_output po;
+    std::memset(&po, 0, sizeof(po));
+    po.keys = pk;
+    po.count = pc;
+    po.capacity = pcap;
+    isa_status st = isa_group_by(ctx, &in, ISA_COUNT, ws, spill, &po, nullptr, stream);
+    if (st == ISA_ETRUNC) {
+        ctx->last_error = "pair scratch below 16 bytes per distinct pair";
+        return ISA_EBUDGET;
+    }
+    if (st != ISA_OK) return st;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    try {
+        Engine& E = ctx->eng;
+        E.stream = (hipStream_t)stream;
+        Arena A;
+        A.base = (char*)ws.dev;
+        A.cap = ws.bytes;
+        ColView V;
+        V.key = pk;
+        V.cnt = nullptr;
+        V.sum = V.mn = V.mx = (const int64_t*)pc;
+        V.fs = nullptr;
+        V.stride = 1;
+        OutView ov;
+        ov.key = keys;  // the normalized g, converted below
+        ov.cnt = out_distinct;
+        ov.sum = (int64_t*)out_count;
+        ov.mn = ov.mx = nullptr;
+        ov.fs = nullptr;
+        ov.stride = 1;
+        const uint64_t groups = sorted_group(E, A, V, po.n_groups, 32, ov, capacity);
+        *n_groups = groups;
+        if (groups > capacity) return ISA_ETRUNC;
+        launch_unpack_hi(keys, groups, out_g, E.stream);
+        E.sync();
+        return ISA_OK;
+    } catch (const Fail& f) {
+        *n_groups = 0;
+        return fail(ctx, f);
+    } catch (const std::bad_alloc&) {
+        *n_groups = 0;
         return ISA_ENOMEM;
     }
 }

@@ -56,6 +56,7 @@ void launch_copy_rows(ColView src, uint64_t n, OutView dst, uint64_t cap, hipStr
 uint64_t scan_tiles(uint64_t n);
 void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* offs, hipStream_t st);
 void launch_pack_pairs(const int32_t* a, const int32_t* b, uint64_t n, uint64_t* keys, hipStream_t st);
+void launch_unpack_hi(const uint64_t* hi, uint64_t n, int32_t* a, hipStream_t st);
 void launch_unpack_pairs(const uint64_t* keys, uint64_t n, int32_t* a, int32_t* b, hipStream_t st);
 void launch_seg_count(const int32_t* a, uint64_t n, uint32_t chunk, uint32_t* counts, uint32_t* bad,
                       hipStream_t st);

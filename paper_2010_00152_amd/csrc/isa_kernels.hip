@@ -1551,6 +1551,12 @@ __global__ void k_unpack_pairs(const uint64_t* __restrict__ keys, uint64_t n, in
     }
 }
 
+// The int32 value held in the high half of a normalized pair key.
+__global__ void k_unpack_hi(const uint64_t* __restrict__ hi, uint64_t n, int32_t* __restrict__ a) {
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+        a[i] = (int32_t)((uint32_t)hi[i] ^ 0x80000000u);
+}
+
 // Segment starts of a non-decreasing column: counts per chunk; *bad is set
 // when a decreasing step is seen.
 __global__ void __launch_bounds__(256) k_seg_count(const int32_t* __restrict__ a, uint64_t n, uint32_t chunk,
@@ -1858,6 +1864,10 @@ static dim3 grid_rows(uint64_t n) {
 void launch_pack_pairs(const int32_t* a, const int32_t* b, uint64_t n, uint64_t* keys, hipStream_t st) {
     if (!n) return;
     hipLaunchKernelGGL(k_pack_pairs, grid_rows(n), dim3(256), 0, st, a, b, n, keys);
+}
+void launch_unpack_hi(const uint64_t* hi, uint64_t n, int32_t* a, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_unpack_hi, grid_rows(n), dim3(256), 0, st, hi, n, a);
 }
 void launch_unpack_pairs(const uint64_t* keys, uint64_t n, int32_t* a, int32_t* b, hipStream_t st) {
     if (!n) return;
