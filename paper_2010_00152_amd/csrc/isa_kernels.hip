@@ -1026,7 +1026,7 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restric
 // group counts.
 // ---------------------------------------------------------------------------
 
-constexpr int MG_NT = 128;
+constexpr int MG_NT = 256;
 constexpr int MG_PER = 4;
 constexpr int MG_D = MG_NT * MG_PER;
 constexpr int MG_MAXW = 6;
