@@ -353,9 +353,9 @@ __global__ void __launch_bounds__(LEAF_NT) k_sample(const Region* __restrict__ r
     block_sort_cnt<NT, IPT>(k, v, nbits > LEAF_TRUNC ? nbits - LEAF_TRUNC : 0, nbits, s);
     __shared__ uint64_t s_spl[MAX_BUCKETS];
     const uint32_t nb = R.nb;
-    if (tid < (int)nb - 1) {
-        const uint64_t q = ((uint64_t)(tid + 1) * S) / nb;
-        s_spl[tid] = s.key[pad16((int)q)] + mn;
+    for (int i = tid; i < (int)nb - 1; i += NT) {
+        const uint64_t q = ((uint64_t)(i + 1) * S) / nb;
+        s_spl[i] = s.key[pad16((int)q)] + mn;
     }
     __syncthreads();
     if (tid == 0) {
