@@ -720,24 +720,34 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     n_idx = gj;
                 }
             };
-            bp.enqueue(E, 0, 0, rb_sort(0));
-            ck(hipEventRecord(ev_sort(0), E.stream), "hipEventRecord");
+            // Batches are sorted on a stream of their own, so that the sort of
+            // batch i+1 runs beside the absorb of batch i.  A sort waits for
+            // everything enqueued on the main stream before it (among that, the
+            // absorbs that read the batch-run buffer it overwrites); an absorb
+            // waits for its batch's sort.
+            hipStream_t ss = E.side(1);
+            auto sort_batch = [&](uint64_t b) {
+                ck(hipEventRecord(E.sync_event(24), E.stream), "hipEventRecord");
+                ck(hipStreamWaitEvent(ss, E.sync_event(24), 0), "hipStreamWaitEvent");
+                bp.enqueue(E, b, (uint32_t)(b % 3), rb_sort(b), ss);
+                ck(hipEventRecord(ev_sort(b), ss), "hipEventRecord");
+            };
+            sort_batch(0);
             bool merge_out = false;  // a merge whose absorb is not decided yet
             uint64_t merge_batch = 0, merge_g = 0;
             int merge_tgt = 0;
             for (uint64_t i = 0; i < bp.batches; ++i) {
                 const uint32_t slot = (uint32_t)(i % 3);
-                if (i + 1 < bp.batches) {
-                    bp.enqueue(E, i + 1, (uint32_t)((i + 1) % 3), rb_sort(i + 1));
-                    ck(hipEventRecord(ev_sort(i + 1), E.stream), "hipEventRecord");
-                }
+                if (i + 1 < bp.batches) sort_batch(i + 1);
                 ck(hipEventSynchronize(ev_sort(i)), "hipEventSynchronize");
                 if (merge_out) ck(hipEventSynchronize(ev_merge(merge_batch)), "hipEventSynchronize");
                 uint64_t g = 0;
                 if (!bp.result(rb_sort(i), g)) {
                     // a bucket was too large for a leaf: redo the batch with the
-                    // general plan in the batch program's scratch (every queued
-                    // launch that uses it precedes this one on the stream)
+                    // general plan in the batch program's scratch, once the sort
+                    // stream (the scratch's other user) is idle; later sorts wait
+                    // for the main stream
+                    ck(hipStreamSynchronize(ss), "hipStreamSynchronize(sort)");
                     A.off = bp.scratch_off;
                     std::vector<Instance> inst(1);
                     inst[0].src = bp.batch_src(i);
@@ -760,6 +770,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 const int tgt = merge_target();
                 guard(tgt, (n_idx + g) * sw * 8);
                 const uint64_t parts = merge_parts(n_idx, g);
+                ck(hipStreamWaitEvent(E.stream, ev_sort(i), 0), "hipStreamWaitEvent");
                 launch_fill(m_ctl, parts + 2, 0, E.stream);
                 E.pbegin("k_merge");
                 launch_merge(ip, n_idx, brun[slot], g, idx[tgt], S, m_splits, m_ctl + 2, (uint32_t*)m_ctl, m_ctl + 1,
@@ -777,6 +788,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 decide(merge_batch, merge_g, merge_tgt);
             }
             if (!runs.empty()) ck(hipStreamSynchronize(cs), "hipStreamSynchronize(copy)");
+            ck(hipStreamSynchronize(ss), "hipStreamSynchronize(sort)");
             E.sync();
             const double t1 = now_ms();
             if (stats) {

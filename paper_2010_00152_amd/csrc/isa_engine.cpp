@@ -849,7 +849,7 @@ ColView BatchProgram::batch_src(uint64_t i) const {
     return v;
 }
 
-void BatchProgram::enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback) {
+void BatchProgram::enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback, hipStream_t st) {
     const uint64_t bn = batch_n(i);
     const bool last = i + 1 == batches;
     const Chunk* ch = last ? d_chunks_last : d_chunks_full;
@@ -863,7 +863,7 @@ void BatchProgram::enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback)
     r.n_chunks = nch;
     Region* reg = d_regs + (i % BP_CTL_RING);
     uint64_t* ctl = d_ctl + (i % BP_CTL_RING) * ctl_words();
-    hipStream_t st = E.stream;
+    
     launch_batch_prep(r, reg, ctl, (uint32_t)ctl_words(), st);
     E.pbegin("k_hist", st);
     launch_hist(reg, ch, nch, splitters, d_hist, st);

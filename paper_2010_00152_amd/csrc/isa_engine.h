@@ -233,7 +233,7 @@ struct BatchProgram {
     uint64_t ctl_words() const { return 2 + (uint64_t)nb; }
     void setup(Engine& E, Arena& A, const ColView& src, uint64_t n_rows, uint64_t batch_rows, const Cols& k,
                const SplitterHint& hint, const std::vector<Dest>& dests);
-    void enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback);
+    void enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback, hipStream_t st);
     // false when a bucket was too large for a leaf (the batch must be redone)
     bool result(const char* readback, uint64_t& groups) const;
     uint64_t batch_n(uint64_t i) const { return i + 1 < batches ? Bt : n - i * Bt; }
