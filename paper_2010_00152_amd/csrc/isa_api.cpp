@@ -140,7 +140,7 @@ uint64_t rungen_bytes(uint64_t Bt, uint64_t K, const Cols& k) {
 uint64_t batch_share() {
     const char* e = std::getenv("ISA_BATCH_SHARE");
     const long v = e ? std::atol(e) : 0;
-    return v >= 2 && v <= 64 ? (uint64_t)v : 6;
+    return v >= 2 && v <= 64 ? (uint64_t)v : 4;
 }
 
 bool plan_batches(uint64_t ws, uint64_t n, const Cols& k, Plan& p) {
