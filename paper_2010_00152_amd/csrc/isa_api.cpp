@@ -595,11 +595,20 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             uint64_t* d_gspl = A.take_n<uint64_t>(MAX_BUCKETS - 1);
             std::vector<uint64_t> h_gspl;
             std::vector<double> share;
-            choose_splitters(E, A, src, n, buckets_for(E, p.batch_rows), d_gspl, h_gspl, &share);
+            double light_share = 0;
+            const uint32_t nb_batch = buckets_for(E, p.batch_rows);
+            choose_splitters(E, A, src, n, nb_batch, d_gspl, h_gspl, &share, &light_share);
+            // heavy keys take buckets of their own; the largest bucket that
+            // spans several keys must stay well below a leaf, so skew that
+            // crowds the light keys into fewer buckets shortens the batches
+            if (light_share > 0) {
+                const double lim = 0.6 * LEAF_CAP / light_share;
+                if (lim < (double)p.batch_rows) p.batch_rows = std::max<uint64_t>(MIN_BATCH, (uint64_t)lim);
+            }
             SplitterHint hint;
             hint.dev = d_gspl;
             hint.host = h_gspl.data();
-            hint.nb = buckets_for(E, p.batch_rows);
+            hint.nb = nb_batch;
             hint.share = share.data();
             std::vector<Dest> bdest(3);
             for (int j = 0; j < 3; ++j) {

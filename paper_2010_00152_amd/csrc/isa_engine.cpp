@@ -258,7 +258,7 @@ uint64_t chunk_rows(const Engine& E, uint64_t n) {
 // share the remaining buckets evenly by sample count.  A bucket boundary never
 // falls inside a run of equal keys.
 void choose_splitters(Engine& E, Arena& A, const ColView& src, uint64_t n, uint32_t nb, uint64_t* dev_out,
-                      std::vector<uint64_t>& host_out, std::vector<double>* share) {
+                      std::vector<uint64_t>& host_out, std::vector<double>* share, double* light_share) {
     constexpr uint64_t WIDE_SAMPLE = 32768;
     const uint64_t mark = A.off;
     const uint64_t S = std::min<uint64_t>(n, WIDE_SAMPLE);
@@ -297,34 +297,53 @@ void choose_splitters(Engine& E, Arena& A, const ColView& src, uint64_t n, uint3
     }
     // buckets: two boundaries per heavy key at most, the rest for light keys
     const uint64_t light_buckets = nb > 2 * n_heavy + 1 ? nb - 2 * n_heavy : 1;
-    const uint64_t target = std::max<uint64_t>(1, (light + light_buckets - 1) / light_buckets);
+    uint64_t target = std::max<uint64_t>(1, (light + light_buckets - 1) / light_buckets);
     std::vector<uint64_t> spl;
-    uint64_t acc = 0;
-    auto cut = [&](uint64_t key) {  // a boundary below `key`
-        if (spl.size() + 1 < nb && key > 0 && (spl.empty() || spl.back() < key)) spl.push_back(key);
-    };
-    for (const auto& r : runs) {
-        if (r.second >= heavy_at) {
-            cut(r.first);
-            if (r.first != ~0ull) cut(r.first + 1);
-            acc = 0;
-            continue;
+    // Greedy packing wastes part of some buckets; when it wants more
+    // boundaries than there are, the surplus keys would all land in the last
+    // bucket, so the light target grows until every boundary fits.
+    for (;;) {
+        spl.clear();
+        uint64_t acc = 0, wanted = 0;
+        auto cut = [&](uint64_t key) {  // a boundary below `key`
+            if (spl.size() + 1 < nb && key > 0 && (spl.empty() || spl.back() < key)) spl.push_back(key);
+        };
+        for (const auto& r : runs) {
+            if (r.second >= heavy_at) {
+                cut(r.first);
+                if (r.first != ~0ull) cut(r.first + 1);
+                wanted += 2;
+                acc = 0;
+                continue;
+            }
+            if (acc > 0 && acc + r.second > target) {
+                cut(r.first);
+                ++wanted;
+                acc = 0;
+            }
+            acc += r.second;
         }
-        if (acc > 0 && acc + r.second > target) {
-            cut(r.first);
-            acc = 0;
-        }
-        acc += r.second;
+        if (wanted + 1 <= nb || target >= S) break;
+        target += std::max<uint64_t>(1, target / 16);
     }
     host_out.assign(MAX_BUCKETS - 1, ~0ull);
     for (size_t i = 0; i < spl.size() && i < (size_t)(nb - 1); ++i) host_out[i] = spl[i];
-    if (share) {
-        share->assign(nb, 0.0);
-        for (const auto& r : runs) {
-            const size_t b = std::upper_bound(spl.begin(), spl.end(), r.first) - spl.begin();
-            (*share)[std::min<size_t>(b, nb - 1)] += (double)r.second / (double)S;
-        }
+    std::vector<double> sh(nb, 0.0);
+    for (const auto& r : runs) {
+        const size_t b = std::upper_bound(spl.begin(), spl.end(), r.first) - spl.begin();
+        sh[std::min<size_t>(b, nb - 1)] += (double)r.second / (double)S;
     }
+    if (light_share) {
+        // the largest sampled share of a bucket spanning more than one key
+        double m = 0;
+        for (uint32_t b = 0; b < nb; ++b) {
+            const uint64_t lo = b ? host_out[b - 1] : 0ull;
+            const uint64_t hi = b + 1 < nb ? host_out[b] - 1 : ~0ull;
+            if (lo != hi) m = std::max(m, sh[b]);
+        }
+        *light_share = m;
+    }
+    if (share) *share = sh;
     E.upload(dev_out, host_out.data(), (MAX_BUCKETS - 1) * sizeof(uint64_t));
     E.sync();
     A.off = mark;

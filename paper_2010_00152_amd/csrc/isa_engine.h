@@ -176,8 +176,11 @@ struct UpPack {
 };
 
 // Choose splitters for `src` (n rows) with nb buckets from a sample of its keys.
+// *light_share (optional): the largest sampled share of rows in a bucket that
+// spans more than one key.
 void choose_splitters(Engine& E, Arena& A, const ColView& src, uint64_t n, uint32_t nb, uint64_t* dev_out,
-                      std::vector<uint64_t>& host_out, std::vector<double>* share = nullptr);
+                      std::vector<uint64_t>& host_out, std::vector<double>* share = nullptr,
+                      double* light_share = nullptr);
 
 // Sort and reduce every instance: the sorted unique state rows of instance i
 // are appended, in instance order, to dests[instance.dest].  Returns the
