@@ -114,6 +114,7 @@ typedef struct {
     uint64_t peak_ws_bytes;   /* workspace bytes actually used                    */
     double t_rungen_ms;       /* wall time of run generation                      */
     double t_merge_ms;        /* wall time of the wide merge and output           */
+    double t_plan_ms;         /* host time of the wide merge before its first read */
 } isa_stats;
 
 /* Create a context on HIP device `device`.  Returns ISA_EDEVICE if the device

@@ -59,7 +59,7 @@ class isa_stats(ctypes.Structure):
     _fields_ = [("runs", U64), ("spilled_rows", U64), ("spilled_bytes", U64), ("windows", U64),
                 ("batches", U64), ("index_capacity", U64), ("batch_rows", U64),
                 ("peak_ws_bytes", U64), ("t_rungen_ms", ctypes.c_double),
-                ("t_merge_ms", ctypes.c_double)]
+                ("t_merge_ms", ctypes.c_double), ("t_plan_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

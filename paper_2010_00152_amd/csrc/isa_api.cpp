@@ -206,6 +206,7 @@ constexpr uint64_t PIECE_CAP = FLAT_MAX * 3 / 4;
 void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::vector<RunInfo>& runs,
                 const char* host, uint64_t* idx, uint64_t n_idx, isa_output* out, isa_stats* st,
                 uint64_t& n_groups) {
+    const double t_enter = now_ms();
     const Layout S = state_layout(k);
     const Layout Rl = raw_layout(k);
     const uint64_t sw = (uint64_t)S.words, rw = (uint64_t)Rl.words;
@@ -340,16 +341,22 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
         }
         return c;
     };
-    // plan every window: its pieces and the gather tasks that lay the pieces
-    // out one after the other in the staging buffer
-    std::vector<GatherTask> tasks;
-    std::vector<uint32_t> task_first;
+    // Windows are planned one at a time, each just before its gather is
+    // issued, so that the host plans while earlier windows are read.  A
+    // window's gather tasks lay its pieces out one after the other in the
+    // staging buffer; they are written to a pinned table and uploaded on the
+    // gather stream ahead of the gather.
+    const uint64_t max_tasks = task_bound(W);
+    GatherTask* h_tasks = (GatherTask*)E.table_buf((max_tasks + 1) * sizeof(GatherTask));
+    GatherTask* d_tasks = A.take_n<GatherTask>(max_tasks + 1);
+    uint64_t n_tasks = 0;
+    std::vector<uint64_t> task_first(1, 0);
     std::vector<uint64_t> win_rows, win_host_bytes;
     std::vector<std::vector<uint64_t>> win_pieces;
     std::vector<uint64_t> end(ns);
     uint64_t left = total;
-    while (left) {
-        task_first.push_back((uint32_t)tasks.size());
+    auto plan_next = [&]() -> bool {
+        if (!left) return false;
         uint64_t at = 0, hb = 0;
         std::vector<uint64_t> pieces;
         while (left && at < W) {
@@ -359,7 +366,8 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
                 const uint64_t w = src[s].raw ? rw : sw;
                 for (uint64_t r = pos[s]; r < end[s]; r += GATHER_ROWS) {
                     const uint64_t len = std::min<uint64_t>(GATHER_ROWS, end[s] - r);
-                    tasks.push_back(GatherTask{src[s].rows + r * w, at, (uint32_t)len, src[s].raw ? 1u : 0u});
+                    if (n_tasks >= max_tasks) throw Fail{ISA_EDEVICE, "internal: gather task table overflow"};
+                    h_tasks[n_tasks++] = GatherTask{src[s].rows + r * w, at, (uint32_t)len, src[s].raw ? 1u : 0u};
                     at += len;
                     if (s + 1 < ns || !n_idx) hb += len * w * 8;
                 }
@@ -371,29 +379,37 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
         win_rows.push_back(at);
         win_host_bytes.push_back(hb);
         win_pieces.push_back(pieces);
-    }
-    task_first.push_back((uint32_t)tasks.size());
-    const size_t nw = win_rows.size();
-    GatherTask* d_tasks = A.take_n<GatherTask>(tasks.size() + 1);
-    E.upload(d_tasks, tasks.data(), tasks.size() * sizeof(GatherTask));
+        task_first.push_back(n_tasks);
+        return true;
+    };
+    size_t planned = 0;
+    auto have = [&](size_t w) {
+        while (planned <= w && plan_next()) ++planned;
+        return w < planned;
+    };
     uint64_t* stage[3];
     for (int j = 0; j < 3; ++j) stage[j] = A.take_n<uint64_t>(W * sw);
     const uint64_t mark = A.off;
     hipStream_t gs = E.side(0);
-    // the gathers read the task table uploaded on the caller's stream
+    // the gathers follow everything enqueued on the caller's stream so far
     ck(hipEventRecord(E.sync_event(4), E.stream), "hipEventRecord");
     ck(hipStreamWaitEvent(gs, E.sync_event(4), 0), "hipStreamWaitEvent");
     auto issue = [&](size_t w) {
         // stage[w % 3] was last read by window w-3, whose reduction has completed
+        const uint64_t t0 = task_first[w], nt = task_first[w + 1] - task_first[w];
+        if (nt)
+            ck(hipMemcpyAsync(d_tasks + t0, h_tasks + t0, nt * sizeof(GatherTask), hipMemcpyHostToDevice, gs),
+               "hipMemcpyAsync(gather tasks)");
         E.pbegin("merge_h2d", gs);
-        launch_gather(d_tasks + task_first[w], task_first[w + 1] - task_first[w], Rl, S, stage[w % 3], gs);
+        launch_gather(d_tasks + t0, (uint32_t)nt, Rl, S, stage[w % 3], gs);
         E.pend(win_rows[w], win_host_bytes[w], gs);
         ck(hipEventRecord(E.sync_event(5 + (w % 3)), gs), "hipEventRecord");
     };
-    for (size_t w = 0; w < std::min<size_t>(2, nw); ++w) issue(w);
+    for (size_t w = 0; w < 2 && have(w); ++w) issue(w);
+    if (st) st->t_plan_ms = now_ms() - t_enter;
     uint64_t cursor = 0;
-    for (size_t w = 0; w < nw; ++w) {
-        if (w + 2 < nw) issue(w + 2);
+    for (size_t w = 0; have(w); ++w) {
+        if (have(w + 2)) issue(w + 2);
         ck(hipStreamWaitEvent(E.stream, E.sync_event(5 + (w % 3)), 0), "hipStreamWaitEvent");
         A.off = mark;
         auto dest_at = [&](uint64_t c) {

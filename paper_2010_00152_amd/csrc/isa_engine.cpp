@@ -159,9 +159,26 @@ char* Engine::ring_slot(size_t i) {
     return ring + (i % SLOTS) * 64;
 }
 
+// The caller guarantees that no copy from the previous table is in flight.
+void* Engine::table_buf(uint64_t bytes) {
+    if (bytes > table_cap) {
+        if (table) hipHostFree(table);
+        table = nullptr;
+        table_cap = 0;
+        uint64_t cap = 1u << 20;
+        while (cap < bytes) cap *= 2;
+        ck(hipHostMalloc((void**)&table, cap, 0), "hipHostMalloc(table)");
+        table_cap = cap;
+    }
+    return table;
+}
+
 void Engine::release() {
     if (ring) hipHostFree(ring);
     ring = nullptr;
+    if (table) hipHostFree(table);
+    table = nullptr;
+    table_cap = 0;
     if (copy_stream) hipStreamDestroy(copy_stream);
     copy_stream = nullptr;
     for (hipStream_t& st : side_streams) {

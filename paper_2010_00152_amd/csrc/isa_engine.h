@@ -131,6 +131,11 @@ struct Engine {
     // (slots of 64 bytes, allocated once)
     char* ring = nullptr;
     char* ring_slot(size_t i);
+    // pinned host table for uploads that stay in flight across syncs of the
+    // main stream (the wide merge's gather tasks); grows, never shrinks
+    char* table = nullptr;
+    uint64_t table_cap = 0;
+    void* table_buf(uint64_t bytes);
 
     void* pinned_buf(uint64_t bytes);
     void upload(void* dev, const void* host, uint64_t bytes);

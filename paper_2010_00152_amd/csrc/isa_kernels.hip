@@ -410,7 +410,10 @@ __global__ void __launch_bounds__(PART_NT) k_hist(const Region* __restrict__ reg
 
 // ---------------------------------------------------------------------------
 // Scatter pass: stable partition of each chunk by bucket into a row-major
-// buffer at the scanned offsets.
+// buffer at the scanned offsets.  A tile's rows are first ranked into bucket
+// order in LDS (row index and bucket per sorted slot); consecutive threads
+// then move consecutive rows of one bucket, so the stores of a wave fill
+// contiguous spans of the destination instead of one line per lane.
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(PART_NT) k_scatter(const Region* __restrict__ regions,
@@ -418,11 +421,16 @@ __global__ void __launch_bounds__(PART_NT) k_scatter(const Region* __restrict__ 
                                                      const uint64_t* __restrict__ splitters,
                                                      const uint64_t* __restrict__ offs,
                                                      uint64_t* __restrict__ dst, Layout L) {
-    constexpr int NT = PART_NT, IPT = PART_IPT, NW = NT / 64;
+    constexpr int NT = PART_NT, IPT = PART_IPT, NW = NT / 64, TILE = NT * IPT;
+    static_assert(MAX_BUCKETS == NT, "one thread per bucket in the tile scan");
     __shared__ uint64_t s_spl[MAX_BUCKETS];
     __shared__ uint64_t s_run[MAX_BUCKETS];
     __shared__ uint32_t s_cnt[NW * MAX_BUCKETS];
     __shared__ uint32_t s_tot[MAX_BUCKETS];
+    __shared__ uint32_t s_lstart[MAX_BUCKETS];
+    __shared__ uint32_t s_tmp[NT / 64 + 1];
+    __shared__ uint16_t s_src[TILE];
+    __shared__ uint8_t s_dig[TILE];
     const Chunk C = chunks[blockIdx.x];
     const Region R = regions[C.region];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -435,17 +443,18 @@ __global__ void __launch_bounds__(PART_NT) k_scatter(const Region* __restrict__ 
     __syncthreads();
     const ColView V = R.src;
     const int dbits = bit_length(R.nb - 1);
-    for (uint32_t t0 = 0; t0 < C.n; t0 += NT * IPT) {
+    for (uint32_t t0 = 0; t0 < C.n; t0 += TILE) {
+        const uint32_t tn = C.n - t0 < (uint32_t)TILE ? C.n - t0 : (uint32_t)TILE;
         uint32_t* wc = s_cnt + w * MAX_BUCKETS;
         for (int i = lane; i < MAX_BUCKETS; i += 64) wc[i] = 0;
         uint32_t rank[IPT], dig[IPT];
         bool ok[IPT];
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
-            const uint32_t i = t0 + (uint32_t)(w * 64 * IPT + j * 64 + lane);
-            ok[j] = i < C.n;
+            const uint32_t i = (uint32_t)(w * 64 * IPT + j * 64 + lane);
+            ok[j] = i < tn;
             uint32_t d = 0;
-            if (ok[j]) d = bucket_of(s_spl, V.key[(C.start + i) * V.stride], R.nb);
+            if (ok[j]) d = bucket_of(s_spl, V.key[(C.start + t0 + i) * V.stride], R.nb);
             const uint64_t active = __ballot(ok[j]);
             const uint64_t match = wave_match(d, dbits, active);
             const uint32_t before = __popcll(match & lt);
@@ -458,27 +467,36 @@ __global__ void __launch_bounds__(PART_NT) k_scatter(const Region* __restrict__ 
             dig[j] = d;
         }
         __syncthreads();
-        // per bucket: exclusive scan over waves; s_tot = the tile's bucket total
-        for (int b = tid; b < MAX_BUCKETS; b += NT) {
+        {
+            // bucket b (thread b): exclusive scan over waves, tile total, and
+            // the bucket's first slot in the tile's bucket order
             uint32_t run = 0;
             for (int ww = 0; ww < NW; ++ww) {
-                const uint32_t c = s_cnt[ww * MAX_BUCKETS + b];
-                s_cnt[ww * MAX_BUCKETS + b] = run;
+                const uint32_t c = s_cnt[ww * MAX_BUCKETS + tid];
+                s_cnt[ww * MAX_BUCKETS + tid] = run;
                 run += c;
             }
-            s_tot[b] = run;
+            s_tot[tid] = run;
+            uint32_t all;
+            s_lstart[tid] = block_exclusive_scan<NT>(run, s_tmp, all);
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
             if (!ok[j]) continue;
-            const uint32_t i = t0 + (uint32_t)(w * 64 * IPT + j * 64 + lane);
-            const uint64_t dpos = s_run[dig[j]] + s_cnt[w * MAX_BUCKETS + dig[j]] + rank[j];
-            const Agg a = load_agg(V, C.start + i);
+            const uint32_t slot = s_lstart[dig[j]] + s_cnt[w * MAX_BUCKETS + dig[j]] + rank[j];
+            s_src[slot] = (uint16_t)(w * 64 * IPT + j * 64 + lane);
+            s_dig[slot] = (uint8_t)dig[j];
+        }
+        __syncthreads();
+        for (uint32_t x = tid; x < tn; x += NT) {
+            const uint32_t d = s_dig[x];
+            const uint64_t dpos = s_run[d] + (x - s_lstart[d]);
+            const Agg a = load_agg(V, C.start + t0 + s_src[x]);
             store_row(dst + dpos * (uint64_t)L.words, L, a);
         }
         __syncthreads();
-        for (int b = tid; b < MAX_BUCKETS; b += NT) s_run[b] += s_tot[b];
+        s_run[tid] += s_tot[tid];
         __syncthreads();
     }
 }
@@ -649,8 +667,16 @@ __global__ void __launch_bounds__(256) k_single_partial(const Leaf* __restrict__
 // pieces were reduced by k_single_partial; combined here with a fixed tree.
 // ---------------------------------------------------------------------------
 
+// Output rows of a leaf are staged in the sort area once the sort is done and
+// leave in contiguous stores (a lane per 8-byte word), so that one store
+// instruction writes whole cache lines instead of one row per lane.
+constexpr int LEAF_STAGE_WORDS = (int)(sizeof(CSortSmem<LEAF_NT, LEAF_IPT>) / 8);
+
 struct LeafSmem {
-    CSortSmem<LEAF_NT, LEAF_IPT> sort;
+    union alignas(16) {
+        CSortSmem<LEAF_NT, LEAF_IPT> sort;
+        uint64_t stage[LEAF_STAGE_WORDS];
+    };
     uint64_t mm[2 * LEAF_NT / 64];
     uint64_t pre_cnt[LEAF_NT];
     uint64_t pre_sum[LEAF_NT];
@@ -662,6 +688,61 @@ struct LeafSmem {
 };
 
 constexpr int LEAF_ROUND = 8;  // payload loads issued together
+
+// Words of one output row and whether the destination is row-major with the
+// fields in state order right after the key (then a leaf's rows form one
+// contiguous span).
+__device__ __forceinline__ int out_words(const OutView& o, bool& row_major) {
+    int w = 1;
+    bool rm = true;
+    auto at = [&](const void* p) {
+        if (!p) return;
+        rm = rm && (const uint64_t*)p == (const uint64_t*)o.key + w;
+        ++w;
+    };
+    at(o.cnt);
+    at(o.sum);
+    at(o.mn);
+    at(o.mx);
+    at(o.fs);
+    row_major = rm && o.stride == (uint64_t)w;
+    return w;
+}
+
+__device__ __forceinline__ void stage_agg(uint64_t* r, const OutView& o, const Agg& a) {
+    int i = 0;
+    r[i++] = a.key;
+    if (o.cnt) r[i++] = a.cnt;
+    if (o.sum) r[i++] = a.sum;
+    if (o.mn) r[i++] = (uint64_t)a.mn;
+    if (o.mx) r[i++] = (uint64_t)a.mx;
+    if (o.fs) r[i++] = (uint64_t)__double_as_longlong(a.fs);
+}
+
+// Copy the first `rows` staged rows to destination rows pos0.. (all threads).
+__device__ __forceinline__ void flush_stage(const uint64_t* st, uint32_t rows, int W, bool row_major,
+                                           const OutView& o, uint64_t pos0) {
+    const int tid = threadIdx.x;
+    if (row_major) {
+        uint64_t* dst = o.key + pos0 * (uint64_t)W;
+        const uint32_t nw = rows * (uint32_t)W;
+        for (uint32_t i = tid; i < nw; i += blockDim.x) dst[i] = st[i];
+        return;
+    }
+    int f = 0;
+    auto col = [&](void* p) {
+        if (!p && f > 0) return;
+        uint64_t* c = (uint64_t*)p;
+        for (uint32_t g = tid; g < rows; g += blockDim.x) c[(pos0 + g) * o.stride] = st[(uint64_t)g * W + f];
+        ++f;
+    };
+    col(o.key);
+    col(o.cnt);
+    col(o.sum);
+    col(o.mn);
+    col(o.mx);
+    col(o.fs);
+}
 
 // Sort, reduce and place one leaf of at most LEAF_CAP rows (workgroup-wide).
 // li is the leaf's ticket, [first, last] the tickets of its destination d.
@@ -752,7 +833,19 @@ __device__ __forceinline__ void leaf_sort_reduce(const ColView& V, const uint32_
         if (lane == 0) s_pre = pre;
     }
     __syncthreads();
-    const uint64_t base = s_pre + obase;
+    // the sort area is free from here on (the scan above synchronised)
+    bool row_major;
+    const int W = out_words(D.out, row_major);
+    const uint32_t stage_rows = (uint32_t)LEAF_STAGE_WORDS / (uint32_t)W;
+    const uint64_t pre0 = s_pre;
+    auto put = [&](uint32_t g, const Agg& a) {
+        if (g < stage_rows) {
+            stage_agg(s.stage + (uint64_t)g * W, D.out, a);
+        } else {
+            const uint64_t pos = pre0 + g;
+            if (pos < D.capacity) store_agg(D.out, pos, a);
+        }
+    };
 
     Agg acc;
     empty_agg(acc);
@@ -778,8 +871,7 @@ __device__ __forceinline__ void leaf_sort_reduce(const ColView& V, const uint32_
                     s.pre_fs[tid] = acc.fs;
                     have_head = true;
                 } else {
-                    const uint64_t pos = base + h - 1;
-                    if (pos < D.capacity) store_agg(D.out, pos, acc);
+                    put(obase + h - 1, acc);
                 }
                 acc = r;
                 ++h;
@@ -812,10 +904,13 @@ __device__ __forceinline__ void leaf_sort_reduce(const ColView& V, const uint32_
             combine(acc, b);
             if (f & 1u) break;
         }
-        const uint64_t pos = base + h - 1;
-        if (pos < D.capacity) store_agg(D.out, pos, acc);
+        put(obase + h - 1, acc);
     }
-    if (tid == 0 && li == last) totals[d] = s_pre + total;
+    __syncthreads();
+    const uint32_t staged = total < stage_rows ? total : stage_rows;
+    const uint64_t room = D.capacity > pre0 ? D.capacity - pre0 : 0;
+    flush_stage(s.stage, (uint64_t)staged < room ? staged : (uint32_t)room, W, row_major, D.out, pre0);
+    if (tid == 0 && li == last) totals[d] = pre0 + total;
 }
 
 // Reduce all rows of a single-key range of any size in one workgroup
@@ -1021,13 +1116,14 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restric
 // LDS-staged merge of two sorted runs of unique keys, both row-major with
 // the same layout, combining equal keys (A's row first).  Partition p covers
 // merge diagonals [p*MG_D, (p+1)*MG_D); its A and B rows are copied to LDS
-// with coalesced loads, merged there by merge path per thread, and each
-// thread writes its merged rows at the chained prefix of the partitions'
-// group counts.
+// with coalesced loads and merged there by merge path per thread.  Each
+// thread holds its merged rows in registers, writes them back over the LDS
+// input at their merged position, and the partition's output leaves in
+// contiguous stores at the chained prefix of the partitions' group counts.
 // ---------------------------------------------------------------------------
 
-constexpr int MG_NT = 256;
-constexpr int MG_PER = 4;
+constexpr int MG_NT = 512;
+constexpr int MG_PER = 2;
 constexpr int MG_D = MG_NT * MG_PER;
 constexpr int MG_MAXW = 6;
 
@@ -1115,23 +1211,45 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
     __syncthreads();
     const uint32_t i0 = s_li[tid], i1 = s_li[tid + 1] > i0 ? s_li[tid + 1] : i0;
     const uint32_t j0 = s_lj[tid], j1 = s_lj[tid + 1] > j0 ? s_lj[tid + 1] : j0;
+    // a thread's inputs span at most MG_PER + 1 rows (its end split may
+    // carry an equal pair's B row), so it makes at most MG_PER + 1 rows
+    constexpr int RMAX = MG_PER + 1;
+    uint64_t rows[RMAX][MG_MAXW];
     uint32_t c = 0;
     {
         uint32_t i = i0, j = j0;
-        while (i < i1 || j < j1) {
-            if (j >= j1) ++i;
-            else if (i >= i1) ++j;
-            else {
-                const uint64_t ka = a[i * W], kb = b[j * W];
-                if (ka < kb) ++i;
-                else if (kb < ka) ++j;
-                else { ++i; ++j; }
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (i < i1 || j < j1) {
+                const uint64_t* src;
+                const uint64_t* src2 = nullptr;
+                if (j >= j1 || (i < i1 && a[i * W] < b[j * W])) {
+                    src = a + i * W;
+                    ++i;
+                } else if (i >= i1 || b[j * W] < a[i * W]) {
+                    src = b + j * W;
+                    ++j;
+                } else {
+                    src = a + i * W;
+                    src2 = b + j * W;
+                    ++i;
+                    ++j;
+                }
+#pragma unroll
+                for (int x = 0; x < MG_MAXW; ++x) rows[r][x] = x < (int)W ? src[x] : 0;
+                if (src2) {
+                    uint64_t t[MG_MAXW];
+                    combine_rows(t, src, src2, L);
+#pragma unroll
+                    for (int x = 0; x < MG_MAXW; ++x)
+                        if (x < (int)W) rows[r][x] = t[x];
+                }
+                ++c;
             }
-            ++c;
         }
     }
     uint32_t tot;
-    const uint32_t off = block_exclusive_scan<MG_NT>(c, s_tmp, tot);
+    const uint32_t off = block_exclusive_scan<MG_NT>(c, s_tmp, tot);  // synchronises: the input is dead
     if (tid < 64) {
         const uint64_t pre = chained_prefix(status, part, 0, tot, &ctl[1]);
         if (tid == 0) {
@@ -1139,29 +1257,17 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
             if (part == gridDim.x - 1) *total_out = pre + tot;
         }
     }
-    __syncthreads();
-    {
-        // each thread writes its merged rows straight to their place: the
-        // rows of consecutive threads are adjacent, so a wave's stores fill
-        // whole cache lines between them
-        uint64_t* const ob = out + s_pre * W;
-        uint32_t o = off, i = i0, j = j0;
-        while (i < i1 || j < j1) {
-            uint64_t* dst = ob + (uint64_t)o * W;
-            if (j >= j1 || (i < i1 && a[i * W] < b[j * W])) {
-                for (uint32_t x = 0; x < W; ++x) dst[x] = a[i * W + x];
-                ++i;
-            } else if (i >= i1 || b[j * W] < a[i * W]) {
-                for (uint32_t x = 0; x < W; ++x) dst[x] = b[j * W + x];
-                ++j;
-            } else {
-                combine_rows(dst, a + i * W, b + j * W, L);
-                ++i;
-                ++j;
-            }
-            ++o;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+        if ((uint32_t)r < c) {
+#pragma unroll
+            for (int x = 0; x < MG_MAXW; ++x)
+                if (x < (int)W) s_in[(off + r) * W + x] = rows[r][x];
         }
     }
+    __syncthreads();
+    uint64_t* const ob = out + s_pre * W;
+    for (uint32_t x = tid; x < tot * W; x += MG_NT) ob[x] = s_in[x];
 }
 
 // ---------------------------------------------------------------------------
@@ -1530,6 +1636,39 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_final(const uint32_t* __restri
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_NT - 1) out[n] = tile_sums[gridDim.x];
 }
 
+// Single workgroup exclusive scan of a short count array (at most a few tiles
+// of SMALL_SCAN_TILE): one launch instead of three.
+constexpr int SMALL_SCAN_NT = 1024;
+constexpr int SMALL_SCAN_IPT = 16;
+constexpr uint64_t SMALL_SCAN_TILE = (uint64_t)SMALL_SCAN_NT * SMALL_SCAN_IPT;
+constexpr uint64_t SMALL_SCAN_MAX = 4 * SMALL_SCAN_TILE;
+
+__global__ void __launch_bounds__(SMALL_SCAN_NT) k_scan_small(const uint32_t* __restrict__ in, uint64_t n,
+                                                              uint64_t* __restrict__ out) {
+    __shared__ uint32_t s_tmp[SMALL_SCAN_NT / 64 + 1];
+    uint64_t carry = 0;
+    for (uint64_t b0 = 0; b0 < n; b0 += SMALL_SCAN_TILE) {
+        const uint64_t base = b0 + (uint64_t)threadIdx.x * SMALL_SCAN_IPT;
+        uint32_t loc[SMALL_SCAN_IPT];
+        uint32_t acc = 0;
+#pragma unroll
+        for (int j = 0; j < SMALL_SCAN_IPT; ++j) {
+            loc[j] = base + j < n ? in[base + j] : 0u;
+            acc += loc[j];
+        }
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<SMALL_SCAN_NT>(acc, s_tmp, tot);
+        uint64_t run = carry + ex;
+#pragma unroll
+        for (int j = 0; j < SMALL_SCAN_IPT; ++j) {
+            if (base + j < n) out[base + j] = run;
+            run += loc[j];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 // ---------------------------------------------------------------------------
 // Composite keys (A int32, B int32): an order-preserving normalized key
 // (Section 2.4: normalized keys compare as binary strings).  Flipping the sign
@@ -1850,6 +1989,10 @@ void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* 
     const uint64_t t = scan_tiles(n);
     if (t == 0) {
         launch_fill(offs, 1, 0, st);
+        return;
+    }
+    if (n <= SMALL_SCAN_MAX) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(SMALL_SCAN_NT), 0, st, in, n, offs);
         return;
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)t), dim3(SCAN_NT), 0, st, in, n, tile_sums);
