@@ -450,6 +450,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    # phase times of the last timed call (the profiled calls below add event records)
+    timed_phases = {k: round(v, 3) for k, v in st.as_dict().items() if k.startswith("t_")}
     # per-kernel HIP-event timing in separate steps, so that the event records
     # do not enter the timed steps above
     prof = {}
@@ -540,6 +542,7 @@ def main():
         "cpu_baseline": cpu,
         "host_link": host_link,
         "stats": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in stats.items()},
+        "phases_timed_ms": timed_phases,
         "kernels": kernels,
     }
     print(json.dumps(res))

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -389,35 +390,31 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     };
     uint64_t* stage[3];
     for (int j = 0; j < 3; ++j) stage[j] = A.take_n<uint64_t>(W * sw);
+    // output cursors on the device: window w starts at the end row that
+    // window w-1 wrote (cur[(w+1) % 2]) and writes its own end to cur[w % 2]
+    uint64_t* d_cur = A.take_n<uint64_t>(2);
     const uint64_t mark = A.off;
     hipStream_t gs = E.side(0);
-    // the gathers follow everything enqueued on the caller's stream so far
-    ck(hipEventRecord(E.sync_event(4), E.stream), "hipEventRecord");
-    ck(hipStreamWaitEvent(gs, E.sync_event(4), 0), "hipStreamWaitEvent");
+    // task uploads run on a stream of their own: a copy queued on the gather
+    // stream would wait for the gather ahead of it and then hold up the next
+    hipStream_t us = E.side(1);
+    auto ev_gather = [&](size_t w) { return E.sync_event(5 + (w % 3)); };
+    auto ev_upload = [&](size_t w) { return E.sync_event(9 + (w % 3)); };
+    auto ev_reduce = [&](size_t w) { return E.sync_event(12 + (w % 3)); };
     auto issue = [&](size_t w) {
-        // stage[w % 3] was last read by window w-3, whose reduction has completed
         const uint64_t t0 = task_first[w], nt = task_first[w + 1] - task_first[w];
-        if (nt)
-            ck(hipMemcpyAsync(d_tasks + t0, h_tasks + t0, nt * sizeof(GatherTask), hipMemcpyHostToDevice, gs),
+        if (nt) {
+            ck(hipMemcpyAsync(d_tasks + t0, h_tasks + t0, nt * sizeof(GatherTask), hipMemcpyHostToDevice, us),
                "hipMemcpyAsync(gather tasks)");
+            ck(hipEventRecord(ev_upload(w), us), "hipEventRecord");
+            ck(hipStreamWaitEvent(gs, ev_upload(w), 0), "hipStreamWaitEvent");
+        }
         E.pbegin("merge_h2d", gs);
         launch_gather(d_tasks + t0, (uint32_t)nt, Rl, S, stage[w % 3], gs);
         E.pend(win_rows[w], win_host_bytes[w], gs);
-        ck(hipEventRecord(E.sync_event(5 + (w % 3)), gs), "hipEventRecord");
+        ck(hipEventRecord(ev_gather(w), gs), "hipEventRecord");
     };
-    for (size_t w = 0; w < 2 && have(w); ++w) issue(w);
-    if (st) st->t_plan_ms = now_ms() - t_enter;
-    uint64_t cursor = 0;
-    for (size_t w = 0; have(w); ++w) {
-        if (have(w + 2)) issue(w + 2);
-        ck(hipStreamWaitEvent(E.stream, E.sync_event(5 + (w % 3)), 0), "hipStreamWaitEvent");
-        A.off = mark;
-        auto dest_at = [&](uint64_t c) {
-            Dest d;
-            d.out = output_view(*out, aggs, std::min(c, out->capacity));
-            d.capacity = out->capacity > c ? out->capacity - c : 0;
-            return d;
-        };
+    auto pieces_of = [&](size_t w) {
         std::vector<Instance> inst;
         uint64_t row = 0;
         for (uint64_t pc : win_pieces[w]) {
@@ -428,21 +425,90 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
             inst.push_back(x);
             row += pc;
         }
-        std::vector<uint64_t> g;
-        if (sort_reduce_flat(E, A, inst, std::vector<Dest>(1, dest_at(cursor)), k, true, nullptr, false, g)) {
-            cursor += g[0];
-        } else {
-            // a bucket too large for a leaf: reduce the pieces one at a time
-            // with the general plan
-            for (const Instance& x : inst) {
-                A.off = mark;
-                cursor += sort_reduce(E, A, std::vector<Instance>(1, x), std::vector<Dest>(1, dest_at(cursor)), k,
-                                      true)[0];
-            }
+        return inst;
+    };
+    // the gathers follow everything enqueued on the caller's stream so far
+    launch_fill(d_cur, 2, 0, E.stream);
+    ck(hipEventRecord(E.sync_event(4), E.stream), "hipEventRecord");
+    ck(hipStreamWaitEvent(gs, E.sync_event(4), 0), "hipStreamWaitEvent");
+
+    // First pass, without host round trips: every window's reduction is
+    // enqueued behind its gather and places its groups after the device-side
+    // cursor of the window before; a gather into stage[w % 3] waits for the
+    // reduction of window w-3, the buffer's last reader.
+    for (size_t w = 0; w < 2 && have(w); ++w) issue(w);
+    if (st) st->t_plan_ms = now_ms() - t_enter;
+    std::vector<const uint64_t*> win_ctl;
+    size_t nw = 0;
+    for (size_t w = 0; have(w); ++w) {
+        if (have(w + 2)) {
+            if (w >= 1) ck(hipStreamWaitEvent(gs, ev_reduce(w - 1), 0), "hipStreamWaitEvent");
+            issue(w + 2);
         }
-        if (st) st->windows++;
+        ck(hipStreamWaitEvent(E.stream, ev_gather(w), 0), "hipStreamWaitEvent");
+        A.off = mark;
+        Dest d;
+        d.out = output_view(*out, aggs, 0);
+        d.capacity = out->capacity;
+        d.base = d_cur + ((w + 1) % 2);
+        std::vector<uint64_t> g;
+        const uint64_t* hc = nullptr;
+        sort_reduce_flat(E, A, pieces_of(w), std::vector<Dest>(1, d), k, true, nullptr, false, g, d_cur + (w % 2),
+                         &hc);
+        if (!hc) throw Fail{ISA_EDEVICE, "internal: empty wide-merge window"};
+        win_ctl.push_back(hc);
+        ck(hipEventRecord(ev_reduce(w), E.stream), "hipEventRecord");
+        nw = w + 1;
     }
+    const uint64_t* h_end = (const uint64_t*)download_async(E, d_cur + ((nw + 1) % 2), 8);
     ck(hipStreamSynchronize(gs), "hipStreamSynchronize(gather)");
+    ck(hipStreamSynchronize(us), "hipStreamSynchronize(upload)");
+    ck(hipStreamSynchronize(E.stream), "hipStreamSynchronize");
+    bool redo = false;
+    for (const uint64_t* hc : win_ctl) {
+        const uint64_t err = hc[0] >> 32;
+        if (err & 1) throw Fail{ISA_EDEVICE, "leaf placement wait timed out"};
+        redo |= (err & 2) != 0;
+    }
+    uint64_t cursor = *h_end;
+    E.sync();
+    if (st) st->windows += nw;
+    // ISA_FORCE_MERGE_REDO=1 takes the second pass as if a window had failed
+    // (it lets tests reach that path with ordinary inputs)
+    if (const char* f = std::getenv("ISA_FORCE_MERGE_REDO")) redo |= f[0] == '1';
+    if (redo) {
+        // A window held a bucket too large for a leaf, so the placement of
+        // the windows after it is void.  Second pass, one window at a time
+        // with the output cursor on the host; a window whose flat plan fails
+        // reduces its pieces one at a time with the general plan.
+        cursor = 0;
+        for (size_t w = 0; w < 2 && w < nw; ++w) issue(w);
+        for (size_t w = 0; w < nw; ++w) {
+            if (w + 2 < nw) issue(w + 2);
+            ck(hipStreamWaitEvent(E.stream, ev_gather(w), 0), "hipStreamWaitEvent");
+            A.off = mark;
+            auto dest_at = [&](uint64_t c) {
+                Dest dd;
+                dd.out = output_view(*out, aggs, std::min(c, out->capacity));
+                dd.capacity = out->capacity > c ? out->capacity - c : 0;
+                return dd;
+            };
+            const std::vector<Instance> inst = pieces_of(w);
+            std::vector<uint64_t> g;
+            if (sort_reduce_flat(E, A, inst, std::vector<Dest>(1, dest_at(cursor)), k, true, nullptr, false, g)) {
+                cursor += g[0];
+            } else {
+                for (const Instance& x : inst) {
+                    A.off = mark;
+                    cursor += sort_reduce(E, A, std::vector<Instance>(1, x), std::vector<Dest>(1, dest_at(cursor)),
+                                          k, true)[0];
+                }
+            }
+            ck(hipEventRecord(ev_reduce(w), E.stream), "hipEventRecord");
+        }
+        ck(hipStreamSynchronize(gs), "hipStreamSynchronize(gather)");
+        ck(hipStreamSynchronize(us), "hipStreamSynchronize(upload)");
+    }
     A.off = mark;
     n_groups = cursor;
 }

@@ -644,7 +644,8 @@ static bool finish_flat(const uint64_t* h_ctl, size_t n_dests, std::vector<uint6
 
 bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, const std::vector<Dest>& dests,
                       const Cols& k, bool state_rows, const SplitterHint* hint, bool graph,
-                      std::vector<uint64_t>& totals) {
+                      std::vector<uint64_t>& totals, uint64_t* ext_totals, const uint64_t** async_ctl) {
+    if (async_ctl && graph) throw Fail{ISA_EINVAL, "internal: asynchronous flat plan with a graph"};
     const Layout L = state_rows ? state_layout(k) : raw_layout(k);
     totals.assign(dests.size(), 0);
     std::vector<Region> regs;
@@ -701,8 +702,8 @@ bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, co
     uint64_t* d_offs = A.take_n<uint64_t>(hist_total + 1);
     uint64_t* d_tiles = A.take_n<uint64_t>(scan_tiles(hist_total) + 1);
     uint64_t* d_ctl = A.take_n<uint64_t>(1 + dests.size() + slots.size());
-    uint64_t* d_totals = d_ctl + 1;
-    uint64_t* d_status = d_totals + dests.size();
+    uint64_t* d_totals = ext_totals ? ext_totals : d_ctl + 1;
+    uint64_t* d_status = d_ctl + 1 + dests.size();
 
     // descriptors are uploaded on the caller's stream before any capture
     UpPack up;
@@ -778,6 +779,11 @@ bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, co
     launches(E.stream);
     ck(hipGetLastError(), "flat launch");
     const uint64_t* h_ctl = (const uint64_t*)download_async(E, d_ctl, (1 + dests.size()) * sizeof(uint64_t));
+    if (async_ctl) {
+        *async_ctl = h_ctl;
+        totals.clear();
+        return true;
+    }
     E.sync();
     return finish_flat(h_ctl, dests.size(), totals);
 }

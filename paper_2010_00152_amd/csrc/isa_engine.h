@@ -204,9 +204,16 @@ const void* download_async(Engine& E, const void* dev, uint64_t bytes);
 // `graph` the launch sequence is captured and launched as one HIP graph.
 // Returns false, having written nothing reliable, when a bucket turned out too
 // large for a leaf; the caller then uses sort_reduce.
+// ext_totals (optional): device words that receive each destination's end
+// row instead of the plan's own control block.  async_ctl (optional): the
+// call returns once the launches are enqueued, leaving totals empty;
+// *async_ctl then points at the plan's pinned control-word readback (error
+// word first), valid after the stream is synchronised and until the next
+// Engine::sync.  Synchronous calls return false when a bucket is too large.
 bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, const std::vector<Dest>& dests,
                       const Cols& k, bool state_rows, const SplitterHint* hint, bool graph,
-                      std::vector<uint64_t>& totals);
+                      std::vector<uint64_t>& totals, uint64_t* ext_totals = nullptr,
+                      const uint64_t** async_ctl = nullptr);
 
 // The batches of one input sorted and reduced with the flat plan and fixed
 // splitters, every launch parameter prepared up front: batch i covers input

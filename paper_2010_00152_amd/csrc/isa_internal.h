@@ -117,6 +117,9 @@ struct FlatInst {
 struct Dest {
     OutView out;
     uint64_t capacity;
+    // rows already in the destination, read on the device when the leaves
+    // start (the end row an earlier launch wrote); nullptr means none
+    const uint64_t* base = nullptr;
 };
 
 // Rows per gather task of the wide merge (a raw slice is staged in LDS).

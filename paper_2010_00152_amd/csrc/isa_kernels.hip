@@ -689,6 +689,8 @@ struct LeafSmem {
 
 constexpr int LEAF_ROUND = 8;  // payload loads issued together
 
+__device__ __forceinline__ uint64_t dest_base(const Dest& D) { return D.base ? *D.base : 0ull; }
+
 // Words of one output row and whether the destination is row-major with the
 // fields in state order right after the key (then a leaf's rows form one
 // contiguous span).
@@ -830,7 +832,7 @@ __device__ __forceinline__ void leaf_sort_reduce(const ColView& V, const uint32_
     const uint32_t obase = block_exclusive_scan<NT>(nheads, s.scan_tmp, total);
     if (w == 0) {
         const uint64_t pre = chained_prefix(status, li, first, total, &ctl[1]);
-        if (lane == 0) s_pre = pre;
+        if (lane == 0) s_pre = pre + dest_base(D);
     }
     __syncthreads();
     // the sort area is free from here on (the scan above synchronised)
@@ -924,7 +926,7 @@ __device__ __forceinline__ void leaf_single_stream(const ColView& V, const uint6
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (w == 0) {
         const uint64_t pre = chained_prefix(status, li, first, 1, &ctl[1]);
-        if (lane == 0) s_pre = pre;
+        if (lane == 0) s_pre = pre + dest_base(D);
     }
     Agg a;
     empty_agg(a);
@@ -965,7 +967,7 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf(const Leaf* __restrict__ leave
     if (Lf.kind == 1) {
         if (w == 0) {
             const uint64_t pre = chained_prefix(status, li, first, 1, &ctl[1]);
-            if (lane == 0) s_pre = pre;
+            if (lane == 0) s_pre = pre + dest_base(D);
         }
         Agg a;
         empty_agg(a);
@@ -1083,7 +1085,7 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restric
         if (n > 0 && tid == 0) atomicOr(&ctl[1], 2u);
         if (w == 0) {
             const uint64_t pre = chained_prefix(status, li, first, 0, &ctl[1]);
-            if (lane == 0 && li == last) totals[d] = pre;
+            if (lane == 0 && li == last) totals[d] = pre + dest_base(D);
         }
         return;
     }
@@ -1092,7 +1094,7 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restric
         // combine them with a fixed tree
         if (w == 0) {
             const uint64_t pre = chained_prefix(status, li, first, 1, &ctl[1]);
-            if (lane == 0) s_pre = pre;
+            if (lane == 0) s_pre = pre + dest_base(D);
         }
         const Agg* pa = partials + (uint64_t)single_of[sl.bucket] * max_pieces;
         const uint32_t np = (uint32_t)((n + SINGLE_CHUNK - 1) / SINGLE_CHUNK);

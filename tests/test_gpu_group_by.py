@@ -213,3 +213,21 @@ def test_spilling_with_extreme_keys(ctx):
     assert st["runs"] > 0
     sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"])
     assert st["runs"] == sim["runs"] and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
+
+
+def test_wide_merge_second_pass(ctx, monkeypatch):
+    # the wide merge places every window's groups after a device-side cursor
+    # and falls back to a host-paced second pass when a window's flat plan
+    # fails; both passes must give the oracle's output
+    say("case wide merge second pass")
+    n = 900_000
+    k, v, f = datagen.plain_input(31, n, 300_000, 0.8, with_f64=True)
+    got1, st1, status1, g1 = run_gpu(ctx, k, v, f, budget=16 << 20)
+    compare(got1, k, v, f, isa.ISA_ALL, "first pass")
+    assert st1["runs"] > 0 and st1["windows"] > 1
+    monkeypatch.setenv("ISA_FORCE_MERGE_REDO", "1")
+    got2, st2, status2, g2 = run_gpu(ctx, k, v, f, budget=16 << 20)
+    compare(got2, k, v, f, isa.ISA_ALL, "second pass")
+    assert g2 == g1 and st2["windows"] == st1["windows"]
+    for col in ("keys", "count", "sum_i64", "min_i64", "max_i64"):
+        assert np.array_equal(got1[col], got2[col]), col
