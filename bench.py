@@ -343,8 +343,8 @@ def hbm_traffic(workload, label):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="spill_100M_zipf0.8", choices=sorted(WORKLOADS) + list(FORMS))
     ap.add_argument("--instances", type=int, default=10000, help="batch_*: number of instances")
     ap.add_argument("--requests", type=int, default=2000, help="serve_c4: number of requests")
@@ -445,8 +445,9 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
+        ts = time.perf_counter()
         step()
-        print("bench: step %d done" % i, file=sys.stderr, flush=True)
+        print("bench: step %d done (%.1f ms host)" % (i, (time.perf_counter() - ts) * 1e3), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
