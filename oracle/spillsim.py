@@ -1,4 +1,6 @@
-"""Spill-policy simulator for run generation with early aggregation.
+"""Spill-policy simulators for run generation with early aggregation:
+read-sort-write cycles (``simulate``) and replacement selection through the
+index (``simulate_replacement``).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -49,3 +51,54 @@ def model_spill_rows(I: float, M: float, O: float) -> float:
     if O <= M:
         return 0.0
     return M + (1.0 - M / O) * I
+
+
+def simulate_replacement(keys, batch_rows: int, capacity: int):
+    """Run generation by replacement selection through the in-memory index
+    (Section 3: the index supports replacement selection as well as
+    read-sort-write cycles; eviction scans the index in key order, so runs grow
+    to about twice the memory for random input with no extra comparison and no
+    run flag per row).
+
+    Batch-granular reading: a batch's distinct keys join the index.  If the
+    union holds e > capacity keys more than capacity, the e smallest keys at or
+    after the scan cursor are evicted in key order and appended to the open
+    run, and the cursor moves just past the last evicted key.  When the scan
+    passes the largest key before e keys are evicted, the open run ends and
+    the scan restarts at the smallest key with a new run.  Keys below the
+    cursor (inserted after the scan passed them) wait for the next run.  The
+    final index is not written out."""
+    if batch_rows <= 0 or capacity <= 0 or batch_rows > capacity:
+        raise ValueError("need 0 < batch_rows <= capacity")
+    keys = np.asarray(keys, dtype=np.uint64)
+    index = np.empty(0, np.uint64)
+    cursor = 0            # a Python int; 2**64 once the scan passed the largest key value
+    open_rows = 0
+    run_sizes = []
+    for start in range(0, keys.shape[0], batch_rows):
+        merged = np.union1d(index, np.unique(keys[start:start + batch_rows]))
+        m = merged.shape[0]
+        if m <= capacity:
+            index = merged
+            continue
+        e = m - capacity
+        p = m if cursor >= 1 << 64 else int(np.searchsorted(merged, np.uint64(cursor), "left"))
+        a = min(e, m - p)
+        keep = np.ones(m, bool)
+        keep[p:p + a] = False
+        open_rows += a
+        last = int(merged[p + a - 1]) if a else None
+        if a < e:
+            # the scan passed the largest key: the open run ends
+            if open_rows:
+                run_sizes.append(open_rows)
+            b = e - a
+            keep[:b] = False
+            open_rows = b
+            last = int(merged[b - 1])
+        cursor = last + 1
+        index = merged[keep]
+    if open_rows:
+        run_sizes.append(open_rows)
+    return {"runs": len(run_sizes), "spilled_rows": int(sum(run_sizes)),
+            "run_sizes": run_sizes, "final_index_rows": int(index.shape[0])}

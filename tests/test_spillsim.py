@@ -52,3 +52,103 @@ def test_model_endpoints():
     # Section 3 Example 2: O = 2M gives M + I/2; O <= M gives no spill
     assert spillsim.model_spill_rows(1_000_000, 100_000, 200_000) == 100_000 + 500_000
     assert spillsim.model_spill_rows(1_000_000, 100_000, 100_000) == 0.0
+
+
+# ---------------------------------------------------------------------------
+# Replacement selection through the index
+# ---------------------------------------------------------------------------
+
+def _classic_replacement_selection(keys, memory):
+    """Textbook replacement selection with a priority queue of `memory` records
+    tagged with their run: output the smallest key of the current run, read the
+    next record into the freed slot, and tag it for the next run if it is below
+    the key just written."""
+    import heapq
+    it = iter(int(x) for x in keys)
+    heap = []
+    for _ in range(memory):
+        x = next(it, None)
+        if x is None:
+            break
+        heap.append((0, x))
+    heapq.heapify(heap)
+    runs, cur = [], None
+    while heap:
+        r, x = heapq.heappop(heap)
+        if r != cur:
+            runs.append([])
+            cur = r
+        runs[-1].append(x)
+        nxt = next(it, None)
+        if nxt is not None:
+            heapq.heappush(heap, (r if nxt >= x else r + 1, nxt))
+    return runs
+
+
+def test_replacement_hand_worked():
+    # capacity 3, batches of 2 (worked by hand with the policy's steps):
+    # {1,5}; {1,3,5,7} evicts 1; {2,3,5,7,9} evicts 2,3; {0,5,6,7,9} evicts
+    # 5,6 (0 is below the cursor 4); {0,4,7,9,10} evicts 7,9; {0,4,8,10,11}
+    # evicts 10,11; {0,2,3,4,8}: nothing at or after 12, so the run of 9 rows
+    # ends and 0,2 start the next run
+    r = spillsim.simulate_replacement([5, 1, 7, 3, 9, 2, 0, 6, 4, 10, 8, 11, 2, 3], 2, 3)
+    assert r == {"runs": 2, "spilled_rows": 11, "run_sizes": [9, 2], "final_index_rows": 3}
+
+
+@pytest.mark.parametrize("seed,n,K", [(1, 3000, 50), (2, 5000, 200), (3, 800, 7)])
+def test_replacement_equals_priority_queue_with_one_row_batches(seed, n, K):
+    # with batches of one row, evicting the smallest key at or after the
+    # cursor from the index plus the new row is the textbook algorithm with
+    # K + 1 slots, up to the point where the input ends (the index's last K
+    # rows stay in memory)
+    keys = np.random.default_rng(seed).permutation(10 * n)[:n].astype(np.uint64)
+    r = spillsim.simulate_replacement(keys, 1, K)
+    classic = _classic_replacement_selection(keys, K + 1)
+    out = [x for run in classic for x in run][: n - K]
+    sizes, left = [], n - K
+    for run in classic:
+        if left <= 0:
+            break
+        sizes.append(min(len(run), left))
+        left -= len(run)
+    assert r["spilled_rows"] == n - K == len(out)
+    assert r["run_sizes"] == sizes
+
+
+def test_replacement_sorted_input_makes_one_run():
+    # the best case: ascending input never falls behind the scan
+    n, K = 20_000, 1000
+    r = spillsim.simulate_replacement(np.arange(n, dtype=np.uint64), 100, K)
+    assert r["runs"] == 1 and r["spilled_rows"] == n - K
+
+
+def test_replacement_descending_input_runs_are_memory_sized():
+    # the worst case: every new key is below the scan, so each run holds one
+    # memory load (K + 1 rows with one-row batches)
+    n, K = 5000, 100
+    r = spillsim.simulate_replacement(np.arange(n, 0, -1, dtype=np.uint64), 1, K)
+    assert all(s == K + 1 for s in r["run_sizes"][:-1])
+    assert r["spilled_rows"] == n - K
+
+
+def test_replacement_random_runs_average_twice_memory():
+    # random input: runs average about twice the memory (snowplow argument)
+    n, K = 200_000, 2000
+    keys = np.random.default_rng(7).permutation(n).astype(np.uint64)
+    r = spillsim.simulate_replacement(keys, 1, K)
+    full = r["run_sizes"][:-1]
+    assert 1.85 * K <= np.mean(full) <= 2.15 * K, np.mean(full) / K
+
+
+def test_replacement_no_spill_when_output_fits_and_never_more_runs():
+    rng = np.random.default_rng(11)
+    keys = rng.integers(0, 500, 20_000).astype(np.uint64)
+    r = spillsim.simulate_replacement(keys, 64, 500)
+    assert r["runs"] == 0 and r["spilled_rows"] == 0
+    # skewed input with duplicates: at most as many runs as read-sort-write,
+    # the same final index size, spilled rows at most the input
+    keys = rng.zipf(1.3, 60_000).astype(np.uint64)
+    rs = spillsim.simulate_replacement(keys, 256, 2048)
+    rw = spillsim.simulate(keys, 256, 2048)
+    assert rs["runs"] <= rw["runs"] and rs["final_index_rows"] == 2048
+    assert rs["spilled_rows"] <= keys.shape[0]
