@@ -28,6 +28,9 @@ WORKLOADS = {
     "spill_100M_zipf0.8": (100_000_000, 10_000_000, 0.8, 3, 256, True, "all"),
     "spill_100M_zipf0": (100_000_000, 10_000_000, 0.0, 2, 256, True, "all"),
     "spill_100M_zipf1.2": (100_000_000, 10_000_000, 1.2, 4, 256, True, "all"),
+    # the same inputs with run generation by replacement selection through the index
+    "spill_100M_zipf0.8_rs": (100_000_000, 10_000_000, 0.8, 3, 256, True, "all"),
+    "spill_100M_zipf0_rs": (100_000_000, 10_000_000, 0.0, 2, 256, True, "all"),
     "nospill_100M_zipf0.8": (100_000_000, 10_000_000, 0.8, 3, 12 * 1024, True, "all"),
     "nospill_100M_zipf0": (100_000_000, 10_000_000, 0.0, 2, 12 * 1024, True, "all"),
     "nospill_100M_zipf1.2": (100_000_000, 10_000_000, 1.2, 4, 12 * 1024, True, "all"),
@@ -409,6 +412,8 @@ def main():
         kd, vd, fd = dgd.plain_input(seed, n, d, s, with_f64=with_f)
     torch.cuda.synchronize()
     ctx = isa.Context(0)
+    if args.workload.endswith("_rs"):
+        ctx.set_run_generation(isa.ISA_RUNGEN_REPLACEMENT)
     L = isa.lib()
     budget = budget_mib << 20
     ws = torch.empty(budget, dtype=torch.uint8, device="cuda")
@@ -536,7 +541,8 @@ def main():
         "dtype": "u64+i64+f64" if with_f else "u64+i64",
         "data": "synthetic",
         "config": {"workload": args.workload, "rows": n, "distinct_domain": d, "zipf_s": s,
-                   "budget_bytes": budget, "aggs": aggs_name, "groups": groups},
+                   "budget_bytes": budget, "aggs": aggs_name, "groups": groups,
+                   "run_generation": "replacement" if args.workload.endswith("_rs") else "read-sort-write"},
         "hbm_algo_GBps_whole_step": round(step_gbs, 1),
         "hbm_roofline_frac_whole_step": round(step_gbs / HBM_PEAK_GBS, 4),
         "roofline": roofline,

@@ -216,6 +216,24 @@ isa_status isa_batch_run(isa_ctx* ctx, uint32_t n_inst, const isa_input* inst,
 uint64_t isa_batch_workspace_bytes(uint32_t n_inst, const isa_input* inst, uint32_t aggs);
 
 /*
+ * Run generation policy of isa_group_by when the index fills (Section 3: an
+ * ordered in-memory index supports both; the choice is the implementer's).
+ *  ISA_RUNGEN_READ_SORT_WRITE (default): the whole index is written as one run
+ *    (count-1 rows compacted to raw rows) and emptied.
+ *  ISA_RUNGEN_REPLACEMENT: replacement selection through the index.  A scan
+ *    cursor moves through the index in key order; when an absorbed batch makes
+ *    the index exceed its capacity, the excess rows at or after the cursor are
+ *    evicted in key order to the open run (state rows); when the scan passes
+ *    the largest key the run ends and the scan restarts at the smallest key.
+ *    Runs average about twice the index for random input and the whole input
+ *    for sorted input.
+ * Held per context; ISA_EINVAL for an unknown policy.
+ */
+enum { ISA_RUNGEN_READ_SORT_WRITE = 0, ISA_RUNGEN_REPLACEMENT = 1 };
+isa_status isa_set_run_generation(isa_ctx* ctx, int policy);
+int isa_get_run_generation(isa_ctx* ctx); /* the policy, or -1 for a NULL context */
+
+/*
  * Launch configuration of the device plans, held per context: the search
  * space of the autotuner below.  It changes speed only, never results.
  * Defaults: leaf_rows 2048, chunk_split 512, graph 1.

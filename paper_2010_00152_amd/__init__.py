@@ -32,6 +32,8 @@ ISA_MIN_I64 = 8
 ISA_MAX_I64 = 16
 ISA_ALL = ISA_COUNT | ISA_SUM_I64 | ISA_SUM_F64 | ISA_MIN_I64 | ISA_MAX_I64
 ISA_INT_AGGS = ISA_COUNT | ISA_SUM_I64 | ISA_MIN_I64 | ISA_MAX_I64
+ISA_RUNGEN_READ_SORT_WRITE = 0
+ISA_RUNGEN_REPLACEMENT = 1
 
 P = ctypes.c_void_p
 U64 = ctypes.c_uint64
@@ -105,6 +107,8 @@ SIGNATURES = {
     "isa_last_error": (ctypes.c_char_p, [P]),
     "isa_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
     "isa_profile_read": (ctypes.c_int, [P, ctypes.POINTER(isa_kernel_time), ctypes.c_int]),
+    "isa_set_run_generation": (ctypes.c_int, [P, ctypes.c_int]),
+    "isa_get_run_generation": (ctypes.c_int, [P]),
     "isa_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(isa_tuning)]),
     "isa_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(isa_tuning)]),
     "isa_tune_candidates": (U32, [ctypes.POINTER(isa_tuning), U32]),
@@ -181,6 +185,15 @@ class Context:
         st = lib().isa_profile_enable(self.handle, 1 if on else 0)
         if st != ISA_OK:
             raise InsortError(st)
+
+    def set_run_generation(self, policy: int):
+        """ISA_RUNGEN_READ_SORT_WRITE or ISA_RUNGEN_REPLACEMENT (isa_set_run_generation)."""
+        st = lib().isa_set_run_generation(self.handle, policy)
+        if st != ISA_OK:
+            raise InsortError(st, self.last_error())
+
+    def get_run_generation(self) -> int:
+        return lib().isa_get_run_generation(self.handle)
 
     def get_tuning(self) -> dict:
         t = isa_tuning()

@@ -18,6 +18,7 @@ using namespace isa;
 
 struct isa_ctx {
     int device = 0;
+    int rungen = ISA_RUNGEN_READ_SORT_WRITE;
     Engine eng;
     std::string last_error;
     std::mutex mu;
@@ -268,7 +269,8 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     };
     uint64_t W = avail0 / (3 * sw * 8);
     while (W > 2 * (ns + 1) && need(W, task_bound(W)) > avail0) W -= W / 32 + 1;
-    if (W < 2 * (ns + 1)) throw Fail{ISA_ESPILL, "workspace too small for a single wide merge of all runs"};
+    if (W < 2 * (ns + 1) || need(W, task_bound(W)) > avail0)
+        throw Fail{ISA_ESPILL, "workspace too small for a single wide merge of all runs"};
     // Fences: the key of every P-th row of each source, merged in key order.
     // A cut at key x ends source s at lb_s(x) = its first row >= x; with c_s
     // of its fences below x, lb_s(x) lies in [c_s P, (c_s + 1) P], so the
@@ -661,9 +663,14 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             uint64_t* brun[3];
             for (int j = 0; j < 3; ++j) brun[j] = A.take_n<uint64_t>(p.batch_rows * sw);
             const uint64_t mscr_parts = merge_parts(buf_rows, p.batch_rows) + 1;
-            // merge control block: [ticket, error], merged row count, per-partition
-            // status; then the partition splits
-            uint64_t* m_ctl = A.take_n<uint64_t>(mscr_parts + 2);
+            // merge control block: [ticket, error], merged row count, the
+            // replacement-selection cursor's row, per-partition status; then
+            // the partition splits
+            uint64_t* m_ctl = A.take_n<uint64_t>(mscr_parts + 3);
+            // replacement selection: the cursor key and its past-the-end flag
+            const bool rs = ctx->rungen == ISA_RUNGEN_REPLACEMENT;
+            uint64_t* rs_cur = A.take_n<uint64_t>(2);
+            launch_fill(rs_cur, 2, 0, E.stream);
             uint64_t* m_splits = A.take_n<uint64_t>(2 * (mscr_parts + 1));
             // compact runs need a count column and a raw row narrower than a state row
             const Layout Rl = raw_layout(k);
@@ -795,9 +802,53 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 pend_lo = compact ? buf_bytes - bytes : 0;
                 n_idx = 0;
             };
+            // replacement selection: the open run starts at rs_off in the
+            // spill buffer and holds rs_rows rows so far
+            uint64_t rs_off = 0, rs_rows = 0;
+            // memory is full under replacement selection: the merged index
+            // idx[target] (m rows) keeps K rows.  The excess rows at or after
+            // the cursor (row pc on) end the open run; if the scan passes the
+            // largest key, the run ends and the smallest keys start the next.
+            // The kept rows go to the front of the other index buffer, the
+            // evicted ones behind them, and are copied out on the copy stream.
+            auto evict = [&](int target, uint64_t m, uint64_t pc) {
+                const int o = target ^ 1;
+                const uint64_t K = p.capacity, e = m - K;
+                const uint64_t a = std::min(e, m - pc), b = e - a;
+                const uint64_t bytes = e * sw * 8;
+                if (!spill.host_pinned || spill_used + bytes > spill.bytes)
+                    throw Fail{ISA_ESPILL, "spill buffer too small"};
+                if (pend_buf == o) {
+                    ck(hipStreamWaitEvent(E.stream, E.sync_event(1), 0), "hipStreamWaitEvent");
+                    pend_buf = -1;
+                }
+                launch_rs_evict(idx[target], m, (uint32_t)sw, pc, a, b, idx[o], rs_cur, E.stream);
+                ck(hipEventRecord(E.sync_event(0), E.stream), "hipEventRecord");
+                ck(hipStreamWaitEvent(cs, E.sync_event(0), 0), "hipStreamWaitEvent");
+                E.pbegin("spill_d2h", cs);
+                ck(hipMemcpyAsync(spill_dev + spill_used, idx[o] + K * sw, bytes, hipMemcpyDeviceToDeviceNoCU, cs),
+                   "hipMemcpyAsync(spill)");
+                E.pend(e, bytes, cs);
+                ck(hipEventRecord(E.sync_event(1), cs), "hipEventRecord");
+                pend_buf = o;
+                pend_lo = K * sw * 8;
+                if (!rs_rows) rs_off = spill_used;
+                rs_rows += a;
+                if (b) {
+                    if (rs_rows) runs.push_back(RunInfo{rs_off, 0, rs_rows});
+                    rs_off = spill_used + a * sw * 8;
+                    rs_rows = b;
+                }
+                spill_used += bytes;
+                spilled += e;
+                spilled_bytes += bytes;
+                ip = idx[o];
+                n_idx = K;
+            };
             // absorb decision for the merge of batch j (g_j rows) into
-            // idx[target]: keep the merged index if it holds at most K keys,
+            // idx[target]: keep the merged index if it holds at most K keys;
             // else spill the old index and start a new one with the batch run
+            // (read-sort-write), or evict the excess (replacement selection)
             auto decide = [&](uint64_t j, uint64_t gj, int target) {
                 const uint64_t* h = (const uint64_t*)rb_merge(j);
                 if (h[0] >> 32) throw Fail{ISA_EDEVICE, "merge placement wait timed out"};
@@ -805,6 +856,8 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 if (m <= p.capacity) {
                     ip = idx[target];
                     n_idx = m;
+                } else if (rs) {
+                    evict(target, m, h[2]);
                 } else {
                     spill_index();
                     ip = brun[j % 3];
@@ -862,12 +915,13 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 guard(tgt, (n_idx + g) * sw * 8);
                 const uint64_t parts = merge_parts(n_idx, g);
                 ck(hipStreamWaitEvent(E.stream, ev_sort(i), 0), "hipStreamWaitEvent");
-                launch_fill(m_ctl, parts + 2, 0, E.stream);
+                launch_fill(m_ctl, parts + 3, 0, E.stream);
                 E.pbegin("k_merge");
-                launch_merge(ip, n_idx, brun[slot], g, idx[tgt], S, m_splits, m_ctl + 2, (uint32_t*)m_ctl, m_ctl + 1,
+                launch_merge(ip, n_idx, brun[slot], g, idx[tgt], S, m_splits, m_ctl + 3, (uint32_t*)m_ctl, m_ctl + 1,
                              E.stream);
                 E.pend(n_idx + g, (n_idx + g) * sw * 8);
-                ck(hipMemcpyAsync(rb_merge(i), m_ctl, 16, hipMemcpyDeviceToHost, E.stream), "hipMemcpyAsync(merge ctl)");
+                if (rs) launch_rs_probe(idx[tgt], m_ctl + 1, (uint32_t)sw, rs_cur, m_ctl + 2, E.stream);
+                ck(hipMemcpyAsync(rb_merge(i), m_ctl, 24, hipMemcpyDeviceToHost, E.stream), "hipMemcpyAsync(merge ctl)");
                 ck(hipEventRecord(ev_merge(i), E.stream), "hipEventRecord");
                 merge_out = true;
                 merge_batch = i;
@@ -878,6 +932,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 ck(hipEventSynchronize(ev_merge(merge_batch)), "hipEventSynchronize");
                 decide(merge_batch, merge_g, merge_tgt);
             }
+            if (rs_rows) runs.push_back(RunInfo{rs_off, 0, rs_rows});
             if (!runs.empty()) ck(hipStreamSynchronize(cs), "hipStreamSynchronize(copy)");
             ck(hipStreamSynchronize(ss), "hipStreamSynchronize(sort)");
             E.sync();
@@ -1301,6 +1356,19 @@ bool valid_tuning(const isa_tuning& t) {
            t.chunk_split <= 4096 && t.graph <= 1 && t.reserved == 0;
 }
 }  // namespace
+
+isa_status isa_set_run_generation(isa_ctx* ctx, int policy) {
+    if (!ctx || (policy != ISA_RUNGEN_READ_SORT_WRITE && policy != ISA_RUNGEN_REPLACEMENT)) return ISA_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->rungen = policy;
+    return ISA_OK;
+}
+
+int isa_get_run_generation(isa_ctx* ctx) {
+    if (!ctx) return -1;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    return ctx->rungen;
+}
 
 isa_status isa_get_tuning(isa_ctx* ctx, isa_tuning* out) {
     if (!ctx || !out) return ISA_EINVAL;

@@ -73,7 +73,8 @@ void* Arena::take(uint64_t bytes) {
     uint64_t o = (off + 255) & ~(uint64_t)255;
     if (o + bytes > cap)
         throw Fail{ISA_EBUDGET, "workspace exhausted: need " + std::to_string(o + bytes) + " of " +
-                                    std::to_string(cap) + " bytes"};
+                                    std::to_string(cap) + " bytes (" + std::to_string(bytes) + " at " +
+                                    std::to_string(o) + ")"};
     off = o + bytes;
     if (off > peak) peak = off;
     return base + o;

@@ -48,6 +48,12 @@ size_t single_partial_bytes();
 uint64_t merge_parts(uint64_t na, uint64_t nb);
 void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb, uint64_t* out, Layout L,
                   uint64_t* splits, uint64_t* status, uint32_t* ctl, uint64_t* total_out, hipStream_t st);
+// Replacement selection: cursor position in the merged index (*p_out) and
+// eviction of rows [p, p+a) and [0, b) (see the kernels).
+void launch_rs_probe(const uint64_t* U, const uint64_t* m_ptr, uint32_t w, const uint64_t* cur, uint64_t* p_out,
+                     hipStream_t st);
+void launch_rs_evict(const uint64_t* U, uint64_t m, uint32_t w, uint64_t p, uint64_t a, uint64_t b, uint64_t* out,
+                     uint64_t* cur, hipStream_t st);
 uint64_t split_blocks(uint64_t n);
 void launch_split(const uint64_t* rows, uint64_t n, Layout S, Layout R, uint32_t* counts, uint64_t* tiles,
                   uint64_t* offs, uint64_t* out, uint64_t end_words, hipStream_t st);

@@ -1273,6 +1273,68 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
 }
 
 // ---------------------------------------------------------------------------
+// Replacement selection through the index (Section 3): eviction scans the
+// index in key order from a cursor.  cur[0] is the cursor key and cur[1] is 1
+// once the scan has passed the largest key value.
+// ---------------------------------------------------------------------------
+
+// First row of the merged index U (*m rows, stride w words) whose key is at or
+// after the cursor, by a 64-way search (one wave); m when the scan is past
+// the end.
+__global__ void __launch_bounds__(64) k_rs_probe(const uint64_t* __restrict__ U, const uint64_t* __restrict__ m_ptr,
+                                                 uint32_t w, const uint64_t* __restrict__ cur,
+                                                 uint64_t* __restrict__ p_out) {
+    const int lane = threadIdx.x;
+    const uint64_t m = *m_ptr, c = cur[0];
+    uint64_t lo = 0, hi = cur[1] ? 0 : m;
+    if (cur[1]) lo = m;
+    while (lo < hi) {
+        // probes lo + k*step (k < 64); keys below c form a prefix
+        const uint64_t step = (hi - lo) / 65 + 1;
+        const uint64_t q = lo + (uint64_t)lane * step;
+        const bool in = q < hi;
+        const bool below = in && U[q * w] < c;
+        const uint64_t above = __ballot(in && !below);
+        if (above) {
+            const int f = __ffsll((long long)above) - 1;
+            const uint64_t nlo = f > 0 ? lo + (uint64_t)(f - 1) * step + 1 : lo;
+            hi = lo + (uint64_t)f * step;
+            lo = nlo;
+        } else {
+            const uint64_t bm = __ballot(below);
+            lo = lo + (uint64_t)(63 - __clzll((long long)bm)) * step + 1;
+        }
+    }
+    if (lane == 0) *p_out = lo;
+}
+
+// Evict e = a + b rows of U (m rows): rows [p, p+a) end the open run and rows
+// [0, b) start the next one.  The kept rows [b, p) and [p+a, m) go to out
+// rows [0, m-e) in order; the evicted rows follow at out rows [m-e, m) in run
+// order.  The cursor moves just past the last evicted key.
+__global__ void __launch_bounds__(256) k_rs_evict(const uint64_t* __restrict__ U, uint64_t m, uint32_t w, uint64_t p,
+                                                  uint64_t a, uint64_t b, uint64_t* __restrict__ out,
+                                                  uint64_t* __restrict__ cur) {
+    const uint64_t kept = m - a - b;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t o;
+        if (i < b) o = kept + a + i;
+        else if (i < p) o = i - b;
+        else if (i < p + a) o = kept + (i - p);
+        else o = i - a - b;
+        const uint64_t* src = U + i * w;
+        uint64_t* dst = out + o * w;
+        for (uint32_t x = 0; x < w; ++x) dst[x] = src[x];
+        const uint64_t last = b ? b - 1 : p + a - 1;
+        if (i == last) {
+            const uint64_t k = src[0];
+            cur[0] = k + 1;
+            cur[1] = k == ~0ull ? 1ull : 0ull;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Sorted-input path: input already ordered on its key is grouped in one
 // stream, with no sort (in-stream aggregation).  Nominal tiles of SORTED_T
 // rows count their group heads (a row whose key differs from the row
@@ -1961,6 +2023,17 @@ void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb
                        (uint32_t)L.words, parts, splits);
     hipLaunchKernelGGL(k_merge, dim3((uint32_t)parts), dim3(MG_NT), 0, st, A, na, B, nb, splits, out, L, status, ctl,
                        total_out);
+}
+void launch_rs_probe(const uint64_t* U, const uint64_t* m_ptr, uint32_t w, const uint64_t* cur, uint64_t* p_out,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_rs_probe, dim3(1), dim3(64), 0, st, U, m_ptr, w, cur, p_out);
+}
+void launch_rs_evict(const uint64_t* U, uint64_t m, uint32_t w, uint64_t p, uint64_t a, uint64_t b, uint64_t* out,
+                     uint64_t* cur, hipStream_t st) {
+    if (!m) return;
+    uint64_t g = (m + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_rs_evict, dim3((uint32_t)g), dim3(256), 0, st, U, m, w, p, a, b, out, cur);
 }
 void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* offs, hipStream_t st);
 uint64_t split_blocks(uint64_t n) { return (n + SPLIT_T - 1) / SPLIT_T; }
