@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -277,16 +278,38 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     // fences bound the rows below x from above without touching the runs,
     // and one short search per source makes the chosen cut exact.
     const uint64_t P = std::max<uint64_t>(1, std::min(W, PIECE_CAP) / (4 * (ns + 1)));
+    // The fences in key order come from a merge of the sources' fence
+    // sequences (each source is sorted, so its fences are), produced only as
+    // the sweep reaches them: the sweep for later windows runs while earlier
+    // windows are being read.
     struct Fence {
         uint64_t key;
         uint32_t src;
     };
-    std::vector<Fence> fl;
+    std::vector<uint64_t> nf(ns), fnext(ns, 1);  // fences of a source: rows c*P for c = 1..nf
+    uint64_t total_f = 0;
+    for (size_t s = 0; s < ns; ++s) {
+        nf[s] = src[s].n > P ? (src[s].n - 1) / P : 0;
+        total_f += nf[s];
+    }
+    auto fkey = [&](size_t s, uint64_t c) { return src[s].keys[c * P * src[s].stride]; };
+    using HeapEntry = std::pair<uint64_t, uint32_t>;
+    std::priority_queue<HeapEntry, std::vector<HeapEntry>, std::greater<HeapEntry>> heap;
     for (size_t s = 0; s < ns; ++s)
-        for (uint64_t i = P; i < src[s].n; i += P) fl.push_back(Fence{src[s].keys[i * src[s].stride], (uint32_t)s});
-    std::sort(fl.begin(), fl.end(), [](const Fence& x, const Fence& y) { return x.key < y.key; });
+        if (nf[s]) heap.push(HeapEntry{fkey(s, 1), (uint32_t)s});
+    std::vector<Fence> fl;
+    fl.reserve(total_f);
+    auto F = [&](uint64_t j) -> const Fence& {  // j < total_f
+        while (fl.size() <= j) {
+            const HeapEntry h = heap.top();
+            heap.pop();
+            fl.push_back(Fence{h.first, h.second});
+            if (++fnext[h.second] <= nf[h.second]) heap.push(HeapEntry{fkey(h.second, fnext[h.second]), h.second});
+        }
+        return fl[j];
+    };
     std::vector<uint64_t> cnt(ns, 0);  // fences of each source below the last cut key
-    size_t fi = 0;                     // first fence not below the last cut key
+    uint64_t fi = 0;                   // first fence not below the last cut key
     auto hi_of = [&](size_t s, uint64_t c) { return std::min<uint64_t>(src[s].n, (c + 1) * P); };
     auto lb_in = [&](size_t s, uint64_t x) {
         const uint64_t lo = std::max<uint64_t>(pos[s], cnt[s] * P);
@@ -304,37 +327,40 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
         }
         // (all remaining keys equal to the largest key value: at most one row per source)
         if (remaining <= cap || (must && min_key == ~0ull)) {
-            for (size_t s = 0; s < ns; ++s) end[s] = src[s].n;
-            while (fi < fl.size()) ++cnt[fl[fi++].src];
+            for (size_t s = 0; s < ns; ++s) {
+                end[s] = src[s].n;
+                cnt[s] = nf[s];
+            }
+            fi = total_f;
             return remaining;
         }
         if (min_key == ~0ull) return 0;
         uint64_t U = 0;
         for (size_t s = 0; s < ns; ++s) U += hi_of(s, cnt[s]) - pos[s];
-        size_t j = fi, best_j = fl.size();
+        uint64_t j = fi, best_j = total_f;
         uint64_t x = 0;
-        while (j < fl.size() && U <= cap) {
-            const uint64_t key = fl[j].key;
+        while (j < total_f && U <= cap) {
+            const uint64_t key = F(j).key;
             if (key > min_key) {
                 x = key;
                 best_j = j;
             }
-            for (; j < fl.size() && fl[j].key == key; ++j) {
+            for (; j < total_f && F(j).key == key; ++j) {
                 const uint32_t s = fl[j].src;
                 U += hi_of(s, cnt[s] + 1) - hi_of(s, cnt[s]);
                 ++cnt[s];
             }
         }
-        if (best_j == fl.size()) {
-            for (size_t t = fi; t < j; ++t) --cnt[fl[t].src];
+        if (best_j == total_f) {
+            for (uint64_t t = fi; t < j; ++t) --cnt[fl[t].src];
             if (!must) return 0;
             x = min_key + 1;
-            for (j = fi; j < fl.size() && fl[j].key <= min_key; ++j) ++cnt[fl[j].src];
+            for (j = fi; j < total_f && F(j).key <= min_key; ++j) ++cnt[fl[j].src];
             best_j = j;
             // every fence at or below min_key is counted: each source's cut lies
             // in its bounded range
         } else {
-            for (size_t t = best_j; t < j; ++t) --cnt[fl[t].src];
+            for (uint64_t t = best_j; t < j; ++t) --cnt[fl[t].src];
         }
         fi = best_j;
         uint64_t c = 0;
