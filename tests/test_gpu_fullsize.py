@@ -2,7 +2,8 @@
 
 * Spilling group-by: 100M rows, uint64 keys over 1e7 Zipf(s) ranks for s in
   {0, 0.8, 1.2}, int64 and float64 values, all aggregates, 256 MiB workspace
-  and a pinned spill buffer (runs and a wide merge).
+  and a pinned spill buffer (runs and a wide merge); at s = 0.8 also with run
+  generation by replacement selection.
 * Segmented grouping: 200M rows, (A, B) int32 with 1e3 A values and 1e5 B
   values per A, sorted on A only, 256 MiB workspace.
 
@@ -13,7 +14,7 @@ bit-exact, fp64 within 1e-12 * sum |x|).  Every key and count of the output is
 checked against a library sort of the whole input (numpy.unique), and the
 invariants (strictly increasing keys, total count, int64 sum mod 2^64, global
 min and max, total fp64 sum) hold over the whole output.  Spill statistics
-equal the read-sort-write simulator's.
+equal the simulator's for the call's run-generation policy.
 """
 import numpy as np
 import pytest
@@ -51,15 +52,19 @@ def _member(sorted_sample, x):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("s,seed", [(0.0, 2), (0.8, 3), (1.2, 4)])
-def test_spilling_100m_rows_full_size(ctx, s, seed):
+@pytest.mark.parametrize("s,seed,policy", [(0.0, 2, "rsw"), (0.8, 3, "rsw"), (1.2, 4, "rsw"), (0.8, 3, "rs")])
+def test_spilling_100m_rows_full_size(ctx, s, seed, policy):
     import torch
     import datagen.device as dgd
     n, d = 100_000_000, 10_000_000
-    say("case full-size spill n=%d d=%d s=%s seed=%d" % (n, d, s, seed))
+    say("case full-size spill n=%d d=%d s=%s seed=%d policy=%s" % (n, d, s, seed, policy))
     kd, vd, fd = dgd.plain_input(seed, n, d, s, with_f64=True)
-    res, st, status, g = isa.group_by(ctx, kd, vd, fd, aggs=isa.ISA_ALL, mem_budget=256 << 20,
-                                      capacity=min(n, d))
+    ctx.set_run_generation(isa.ISA_RUNGEN_REPLACEMENT if policy == "rs" else isa.ISA_RUNGEN_READ_SORT_WRITE)
+    try:
+        res, st, status, g = isa.group_by(ctx, kd, vd, fd, aggs=isa.ISA_ALL, mem_budget=256 << 20,
+                                          capacity=min(n, d))
+    finally:
+        ctx.set_run_generation(isa.ISA_RUNGEN_READ_SORT_WRITE)
     torch.cuda.synchronize()
     say("  groups %d runs %d spilled %d windows %d" % (g, st["runs"], st["spilled_rows"], st["windows"]))
     got = _host(res)
@@ -90,7 +95,8 @@ def test_spilling_100m_rows_full_size(ctx, s, seed):
     err = np.abs(got["sum_f64"][idx] - ref["sum_f64"])
     assert (err <= FP64_REL * absum).all(), float((err / np.maximum(absum, 1e-300)).max())
 
-    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"])
+    simulate = spillsim.simulate_replacement if policy == "rs" else spillsim.simulate
+    sim = simulate(k, st["batch_rows"], st["index_capacity"])
     assert st["runs"] == sim["runs"] and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
     assert st["spilled_rows"] <= n
     assert st["peak_ws_bytes"] <= 256 << 20
