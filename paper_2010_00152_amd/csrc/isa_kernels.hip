@@ -416,13 +416,19 @@ __global__ void __launch_bounds__(PART_NT) k_hist(const Region* __restrict__ reg
 // contiguous spans of the destination instead of one line per lane.
 // ---------------------------------------------------------------------------
 
+// SW > 0: rows of at most SW words are also loaded with the keys (coalesced)
+// into LDS in input order and move from there; SW = 0: they are gathered
+// from the source in bucket order.
+template <int SW, int IPT>
 __global__ void __launch_bounds__(PART_NT) k_scatter(const Region* __restrict__ regions,
                                                      const Chunk* __restrict__ chunks,
                                                      const uint64_t* __restrict__ splitters,
                                                      const uint64_t* __restrict__ offs,
                                                      uint64_t* __restrict__ dst, Layout L) {
-    constexpr int NT = PART_NT, IPT = PART_IPT, NW = NT / 64, TILE = NT * IPT;
+    constexpr int NT = PART_NT, NW = NT / 64, TILE = NT * IPT;
+    static_assert(TILE <= 65536, "tile slots are 16-bit");
     static_assert(MAX_BUCKETS == NT, "one thread per bucket in the tile scan");
+    __shared__ uint64_t s_rows[SW > 0 ? TILE * SW : 1];
     __shared__ uint64_t s_spl[MAX_BUCKETS];
     __shared__ uint64_t s_run[MAX_BUCKETS];
     __shared__ uint32_t s_cnt[NW * MAX_BUCKETS];
@@ -454,7 +460,15 @@ __global__ void __launch_bounds__(PART_NT) k_scatter(const Region* __restrict__ 
             const uint32_t i = (uint32_t)(w * 64 * IPT + j * 64 + lane);
             ok[j] = i < tn;
             uint32_t d = 0;
-            if (ok[j]) d = bucket_of(s_spl, V.key[(C.start + t0 + i) * V.stride], R.nb);
+            if (ok[j]) {
+                if (SW > 0) {
+                    const Agg a = load_agg(V, C.start + t0 + i);
+                    store_row(s_rows + i * (uint32_t)L.words, L, a);
+                    d = bucket_of(s_spl, a.key, R.nb);
+                } else {
+                    d = bucket_of(s_spl, V.key[(C.start + t0 + i) * V.stride], R.nb);
+                }
+            }
             const uint64_t active = __ballot(ok[j]);
             const uint64_t match = wave_match(d, dbits, active);
             const uint32_t before = __popcll(match & lt);
@@ -492,8 +506,16 @@ __global__ void __launch_bounds__(PART_NT) k_scatter(const Region* __restrict__ 
         for (uint32_t x = tid; x < tn; x += NT) {
             const uint32_t d = s_dig[x];
             const uint64_t dpos = s_run[d] + (x - s_lstart[d]);
-            const Agg a = load_agg(V, C.start + t0 + s_src[x]);
-            store_row(dst + dpos * (uint64_t)L.words, L, a);
+            if (SW > 0) {
+                const uint64_t* r = s_rows + (uint32_t)s_src[x] * (uint32_t)L.words;
+                uint64_t* o = dst + dpos * (uint64_t)L.words;
+#pragma unroll
+                for (int q = 0; q < SW; ++q)
+                    if (q < L.words) o[q] = r[q];
+            } else {
+                const Agg a = load_agg(V, C.start + t0 + s_src[x]);
+                store_row(dst + dpos * (uint64_t)L.words, L, a);
+            }
         }
         __syncthreads();
         s_run[tid] += s_tot[tid];
@@ -1929,7 +1951,13 @@ void launch_hist(const Region* regions, const Chunk* chunks, uint32_t n_chunks, 
 }
 void launch_scatter(const Region* regions, const Chunk* chunks, uint32_t n_chunks, const uint64_t* splitters,
                     const uint64_t* offs, uint64_t* dst, Layout L, hipStream_t st) {
-    hipLaunchKernelGGL(k_scatter, dim3(n_chunks), dim3(PART_NT), 0, st, regions, chunks, splitters, offs, dst, L);
+    // narrow rows: tiles of 2048 rows staged in LDS (48 KB, two workgroups per CU)
+    if (L.words <= 3)
+        hipLaunchKernelGGL((k_scatter<3, PART_IPT / 2>), dim3(n_chunks), dim3(PART_NT), 0, st, regions, chunks,
+                           splitters, offs, dst, L);
+    else
+        hipLaunchKernelGGL((k_scatter<0, PART_IPT>), dim3(n_chunks), dim3(PART_NT), 0, st, regions, chunks,
+                           splitters, offs, dst, L);
 }
 void launch_bucket_starts(const Region* regions, uint32_t n_regions, const uint64_t* offs, const uint64_t* bs_base,
                           uint64_t* bstart, hipStream_t st) {
