@@ -121,9 +121,11 @@ struct Plan {
 constexpr uint64_t MIN_BATCH = 4 * (uint64_t)LEAF_CAP;
 constexpr uint64_t MERGE_MARGIN = 2u << 20;
 
+// Two merge control blocks of parts + 3 words, the splits (2 per part + 2)
+// and the replacement-selection cursor.
 uint64_t merge_scratch_bytes(uint64_t rows) {
     const uint64_t parts = merge_parts(rows, 0) + 2;
-    return (3 * parts + 5) * 8 + 1024;
+    return (4 * parts + 12) * 8 + 1024;
 }
 
 // Workspace used by run generation with batch Bt and index capacity K: two
@@ -692,7 +694,13 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             // merge control block: [ticket, error], merged row count, the
             // replacement-selection cursor's row, per-partition status; then
             // the partition splits
-            uint64_t* m_ctl = A.take_n<uint64_t>(mscr_parts + 3);
+            // two control blocks, used by alternate merges; each merge clears
+            // the other one for the next merge
+            const uint64_t mctl_words = mscr_parts + 3;
+            uint64_t* m_ctl2[2];
+            m_ctl2[0] = A.take_n<uint64_t>(2 * mctl_words);
+            m_ctl2[1] = m_ctl2[0] + mctl_words;
+            launch_fill(m_ctl2[0], 2 * mctl_words, 0, E.stream);
             // replacement selection: the cursor key and its past-the-end flag
             const bool rs = ctx->rungen == ISA_RUNGEN_REPLACEMENT;
             uint64_t* rs_cur = A.take_n<uint64_t>(2);
@@ -941,10 +949,10 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 guard(tgt, (n_idx + g) * sw * 8);
                 const uint64_t parts = merge_parts(n_idx, g);
                 ck(hipStreamWaitEvent(E.stream, ev_sort(i), 0), "hipStreamWaitEvent");
-                launch_fill(m_ctl, parts + 3, 0, E.stream);
+                uint64_t* m_ctl = m_ctl2[i % 2];
                 E.pbegin("k_merge");
                 launch_merge(ip, n_idx, brun[slot], g, idx[tgt], S, m_splits, m_ctl + 3, (uint32_t*)m_ctl, m_ctl + 1,
-                             E.stream);
+                             E.stream, m_ctl2[(i + 1) % 2], (uint32_t)mctl_words);
                 E.pend(n_idx + g, (n_idx + g) * sw * 8);
                 if (rs) launch_rs_probe(idx[tgt], m_ctl + 1, (uint32_t)sw, rs_cur, m_ctl + 2, E.stream);
                 ck(hipMemcpyAsync(rb_merge(i), m_ctl, 24, hipMemcpyDeviceToHost, E.stream), "hipMemcpyAsync(merge ctl)");

@@ -46,8 +46,10 @@ void launch_single_partial(const Leaf* leaves, const SinglePiece* pieces, uint32
                            hipStream_t st);
 size_t single_partial_bytes();
 uint64_t merge_parts(uint64_t na, uint64_t nb);
+// next_ctl (optional): next_words words cleared by the merge for the next one.
 void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb, uint64_t* out, Layout L,
-                  uint64_t* splits, uint64_t* status, uint32_t* ctl, uint64_t* total_out, hipStream_t st);
+                  uint64_t* splits, uint64_t* status, uint32_t* ctl, uint64_t* total_out, hipStream_t st,
+                  uint64_t* next_ctl = nullptr, uint32_t next_words = 0);
 // Replacement selection: cursor position in the merged index (*p_out) and
 // eviction of rows [p, p+a) and [0, b) (see the kernels).
 void launch_rs_probe(const uint64_t* U, const uint64_t* m_ptr, uint32_t w, const uint64_t* cur, uint64_t* p_out,

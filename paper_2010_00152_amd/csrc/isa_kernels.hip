@@ -1150,6 +1150,7 @@ constexpr int MG_NT = 512;
 constexpr int MG_PER = 2;
 constexpr int MG_D = MG_NT * MG_PER;
 constexpr int MG_MAXW = 6;
+constexpr uint64_t MG_GRID = 256;
 
 // Split of diagonal d over row-major key columns (stride w words); an equal
 // pair is never separated (its B row goes with the A row before the split).
@@ -1190,11 +1191,14 @@ __device__ __forceinline__ void combine_rows(uint64_t* o, const uint64_t* a, con
     if (L.fs >= 0) o[L.fs] = __double_as_longlong(__longlong_as_double(a[L.fs]) + __longlong_as_double(b[L.fs]));
 }
 
+// next_ctl (optional, next_words words): the control block of the next merge
+// on the stream, cleared here so that it needs no launch of its own.
 __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A, uint64_t na,
                                                  const uint64_t* __restrict__ B, uint64_t nb,
                                                  const uint64_t* __restrict__ splits, uint64_t* __restrict__ out,
                                                  Layout L, uint64_t* __restrict__ status, uint32_t* __restrict__ ctl,
-                                                 uint64_t* __restrict__ total_out) {
+                                                 uint64_t* __restrict__ total_out, uint64_t* __restrict__ next_ctl,
+                                                 uint32_t next_words, uint32_t nparts) {
     __shared__ uint64_t s_in[(MG_D + 2) * MG_MAXW];
     __shared__ uint32_t s_li[MG_NT + 1], s_lj[MG_NT + 1];
     __shared__ uint32_t s_tmp[MG_NT / 64 + 1];
@@ -1202,96 +1206,102 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
     __shared__ uint64_t s_pre;
     const int tid = threadIdx.x;
     const uint32_t W = (uint32_t)L.words;
-    if (tid == 0) s_part = atomicAdd(&ctl[0], 1u);
-    __syncthreads();
-    const uint32_t part = s_part;
-    const uint64_t ia0 = splits[2 * part], ja0 = splits[2 * part + 1];
-    const uint64_t ia1 = splits[2 * part + 2], ja1 = splits[2 * part + 3];
-    const uint32_t la = (uint32_t)(ia1 - ia0), lb = (uint32_t)(ja1 - ja0);
-    for (uint32_t x = tid; x < la * W; x += MG_NT) s_in[x] = A[ia0 * W + x];
-    for (uint32_t x = tid; x < lb * W; x += MG_NT) s_in[la * W + x] = B[ja0 * W + x];
-    __syncthreads();
-    const uint64_t* a = s_in;
-    const uint64_t* b = s_in + la * W;
-    {
-        // local split of this thread's diagonal
-        uint32_t d = (uint32_t)tid * MG_PER;
-        if (d > la + lb) d = la + lb;
-        uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (a[mid * W] <= b[(d - 1 - mid) * W]) lo = mid + 1;
-            else hi = mid;
-        }
-        uint32_t i = lo, j = d - lo;
-        if (i > 0 && j < lb && a[(i - 1) * W] == b[j * W]) ++j;
-        s_li[tid] = i;
-        s_lj[tid] = j;
-        if (tid == 0) {
-            s_li[MG_NT] = la;
-            s_lj[MG_NT] = lb;
-        }
-    }
-    __syncthreads();
-    const uint32_t i0 = s_li[tid], i1 = s_li[tid + 1] > i0 ? s_li[tid + 1] : i0;
-    const uint32_t j0 = s_lj[tid], j1 = s_lj[tid + 1] > j0 ? s_lj[tid + 1] : j0;
-    // a thread's inputs span at most MG_PER + 1 rows (its end split may
-    // carry an equal pair's B row), so it makes at most MG_PER + 1 rows
-    constexpr int RMAX = MG_PER + 1;
-    uint64_t rows[RMAX][MG_MAXW];
-    uint32_t c = 0;
-    {
-        uint32_t i = i0, j = j0;
-#pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-            if (i < i1 || j < j1) {
-                const uint64_t* src;
-                const uint64_t* src2 = nullptr;
-                if (j >= j1 || (i < i1 && a[i * W] < b[j * W])) {
-                    src = a + i * W;
-                    ++i;
-                } else if (i >= i1 || b[j * W] < a[i * W]) {
-                    src = b + j * W;
-                    ++j;
-                } else {
-                    src = a + i * W;
-                    src2 = b + j * W;
-                    ++i;
-                    ++j;
-                }
-#pragma unroll
-                for (int x = 0; x < MG_MAXW; ++x) rows[r][x] = x < (int)W ? src[x] : 0;
-                if (src2) {
-                    uint64_t t[MG_MAXW];
-                    combine_rows(t, src, src2, L);
-#pragma unroll
-                    for (int x = 0; x < MG_MAXW; ++x)
-                        if (x < (int)W) rows[r][x] = t[x];
-                }
-                ++c;
+    for (uint32_t x = blockIdx.x * MG_NT + tid; x < next_words; x += gridDim.x * MG_NT) next_ctl[x] = 0;
+    // a persistent grid: each workgroup takes partitions in ticket order
+    for (;;) {
+        if (tid == 0) s_part = atomicAdd(&ctl[0], 1u);
+        __syncthreads();
+        const uint32_t part = s_part;
+        if (part >= nparts) break;
+        const uint64_t ia0 = splits[2 * part], ja0 = splits[2 * part + 1];
+        const uint64_t ia1 = splits[2 * part + 2], ja1 = splits[2 * part + 3];
+        const uint32_t la = (uint32_t)(ia1 - ia0), lb = (uint32_t)(ja1 - ja0);
+        for (uint32_t x = tid; x < la * W; x += MG_NT) s_in[x] = A[ia0 * W + x];
+        for (uint32_t x = tid; x < lb * W; x += MG_NT) s_in[la * W + x] = B[ja0 * W + x];
+        __syncthreads();
+        const uint64_t* a = s_in;
+        const uint64_t* b = s_in + la * W;
+        {
+            // local split of this thread's diagonal
+            uint32_t d = (uint32_t)tid * MG_PER;
+            if (d > la + lb) d = la + lb;
+            uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (a[mid * W] <= b[(d - 1 - mid) * W]) lo = mid + 1;
+                else hi = mid;
+            }
+            uint32_t i = lo, j = d - lo;
+            if (i > 0 && j < lb && a[(i - 1) * W] == b[j * W]) ++j;
+            s_li[tid] = i;
+            s_lj[tid] = j;
+            if (tid == 0) {
+                s_li[MG_NT] = la;
+                s_lj[MG_NT] = lb;
             }
         }
-    }
-    uint32_t tot;
-    const uint32_t off = block_exclusive_scan<MG_NT>(c, s_tmp, tot);  // synchronises: the input is dead
-    if (tid < 64) {
-        const uint64_t pre = chained_prefix(status, part, 0, tot, &ctl[1]);
-        if (tid == 0) {
-            s_pre = pre;
-            if (part == gridDim.x - 1) *total_out = pre + tot;
-        }
-    }
+        __syncthreads();
+        const uint32_t i0 = s_li[tid], i1 = s_li[tid + 1] > i0 ? s_li[tid + 1] : i0;
+        const uint32_t j0 = s_lj[tid], j1 = s_lj[tid + 1] > j0 ? s_lj[tid + 1] : j0;
+        // a thread's inputs span at most MG_PER + 1 rows (its end split may
+        // carry an equal pair's B row), so it makes at most MG_PER + 1 rows
+        constexpr int RMAX = MG_PER + 1;
+        uint64_t rows[RMAX][MG_MAXW];
+        uint32_t c = 0;
+        {
+            uint32_t i = i0, j = j0;
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-        if ((uint32_t)r < c) {
+            for (int r = 0; r < RMAX; ++r) {
+                if (i < i1 || j < j1) {
+                    const uint64_t* src;
+                    const uint64_t* src2 = nullptr;
+                    if (j >= j1 || (i < i1 && a[i * W] < b[j * W])) {
+                        src = a + i * W;
+                        ++i;
+                    } else if (i >= i1 || b[j * W] < a[i * W]) {
+                        src = b + j * W;
+                        ++j;
+                    } else {
+                        src = a + i * W;
+                        src2 = b + j * W;
+                        ++i;
+                        ++j;
+                    }
 #pragma unroll
-            for (int x = 0; x < MG_MAXW; ++x)
-                if (x < (int)W) s_in[(off + r) * W + x] = rows[r][x];
+                    for (int x = 0; x < MG_MAXW; ++x) rows[r][x] = x < (int)W ? src[x] : 0;
+                    if (src2) {
+                        uint64_t t[MG_MAXW];
+                        combine_rows(t, src, src2, L);
+#pragma unroll
+                        for (int x = 0; x < MG_MAXW; ++x)
+                            if (x < (int)W) rows[r][x] = t[x];
+                    }
+                    ++c;
+                }
+            }
         }
+        uint32_t tot;
+        const uint32_t off = block_exclusive_scan<MG_NT>(c, s_tmp, tot);  // synchronises: the input is dead
+        if (tid < 64) {
+            const uint64_t pre = chained_prefix(status, part, 0, tot, &ctl[1]);
+            if (tid == 0) {
+                s_pre = pre;
+                if (part == nparts - 1) *total_out = pre + tot;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if ((uint32_t)r < c) {
+#pragma unroll
+                for (int x = 0; x < MG_MAXW; ++x)
+                    if (x < (int)W) s_in[(off + r) * W + x] = rows[r][x];
+            }
+        }
+        __syncthreads();
+        uint64_t* const ob = out + s_pre * W;
+        for (uint32_t x = tid; x < tot * W; x += MG_NT) ob[x] = s_in[x];
+        __syncthreads();  // the LDS input and s_part are reused by the next partition
     }
-    __syncthreads();
-    uint64_t* const ob = out + s_pre * W;
-    for (uint32_t x = tid; x < tot * W; x += MG_NT) ob[x] = s_in[x];
 }
 
 // ---------------------------------------------------------------------------
@@ -2044,13 +2054,17 @@ uint64_t merge_parts(uint64_t na, uint64_t nb) { return (na + nb + MG_D - 1) / M
 // A, B, out: row-major state rows of layout L.  splits: 2*(parts+1) words;
 // status: parts words and ctl: 2 words, both zeroed.
 void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb, uint64_t* out, Layout L,
-                  uint64_t* splits, uint64_t* status, uint32_t* ctl, uint64_t* total_out, hipStream_t st) {
+                  uint64_t* splits, uint64_t* status, uint32_t* ctl, uint64_t* total_out, hipStream_t st,
+                  uint64_t* next_ctl, uint32_t next_words) {
     const uint64_t parts = merge_parts(na, nb);
     if (parts == 0) return;
     hipLaunchKernelGGL(k_merge_splits, dim3((uint32_t)((parts + 1 + 255) / 256)), dim3(256), 0, st, A, na, B, nb,
                        (uint32_t)L.words, parts, splits);
-    hipLaunchKernelGGL(k_merge, dim3((uint32_t)parts), dim3(MG_NT), 0, st, A, na, B, nb, splits, out, L, status, ctl,
-                       total_out);
+    // a grid of at most MG_GRID workgroups leaves compute units to the batch
+    // sort running beside the merge
+    const uint32_t grid = (uint32_t)(parts < MG_GRID ? parts : MG_GRID);
+    hipLaunchKernelGGL(k_merge, dim3(grid), dim3(MG_NT), 0, st, A, na, B, nb, splits, out, L, status, ctl, total_out,
+                       next_ctl, next_words, (uint32_t)parts);
 }
 void launch_rs_probe(const uint64_t* U, const uint64_t* m_ptr, uint32_t w, const uint64_t* cur, uint64_t* p_out,
                      hipStream_t st) {
