@@ -131,7 +131,7 @@ def bench_batch(args, lo, hi):
                 raise isa.InsortError(rc, ctx.last_error())
             tuned = best.as_dict()
             cands = isa.tune_candidates()
-            dflt = cands.index({"leaf_rows": 2048, "chunk_split": 512, "graph": 1})
+            dflt = cands.index(isa.Context.default_tuning())
             tune_info.update({"first_wave_ms_default": round(times[dflt], 3),
                               "first_wave_ms_tuned": round(min(times[i] for i in range(nc)), 3),
                               "candidates": nc})

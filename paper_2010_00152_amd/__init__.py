@@ -202,6 +202,11 @@ class Context:
             raise InsortError(st)
         return t.as_dict()
 
+    @staticmethod
+    def default_tuning() -> dict:
+        """The launch configuration a new context starts with."""
+        return {"leaf_rows": 2048, "chunk_split": 512, "graph": 1}
+
     def set_tuning(self, leaf_rows: int = 2048, chunk_split: int = 512, graph: int = 1):
         t = isa_tuning(leaf_rows, chunk_split, graph, 0)
         st = lib().isa_set_tuning(self.handle, ctypes.byref(t))

@@ -123,7 +123,7 @@ def test_tuning_rejects_out_of_range(ctx):
         with pytest.raises(isa.InsortError) as e:
             ctx.set_tuning(**bad)
         assert e.value.status == isa.ISA_EINVAL
-    assert ctx.get_tuning() == dict(leaf_rows=2048, chunk_split=512, graph=1)
+    assert ctx.get_tuning() == isa.Context.default_tuning()
 
 
 def test_autotuner_picks_a_candidate_and_keeps_results(ctx):
