@@ -364,7 +364,7 @@ def main():
                     help="only run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); "
+        print("bench.py: the library runs on one GPU (--gpus %d requested); "
               "multi-GPU sharding is a design note, not built" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
