@@ -951,11 +951,13 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 ck(hipStreamWaitEvent(E.stream, ev_sort(i), 0), "hipStreamWaitEvent");
                 uint64_t* m_ctl = m_ctl2[i % 2];
                 E.pbegin("k_merge");
+                // the merge's last partition (and the probe) write the result
+                // words straight to the pinned readback slot
+                uint64_t* rb_dev = E.ring_dev_of(rb_merge(i));
                 launch_merge(ip, n_idx, brun[slot], g, idx[tgt], S, m_splits, m_ctl + 3, (uint32_t*)m_ctl, m_ctl + 1,
-                             E.stream, m_ctl2[(i + 1) % 2], (uint32_t)mctl_words);
+                             E.stream, m_ctl2[(i + 1) % 2], (uint32_t)mctl_words, rb_dev);
                 E.pend(n_idx + g, (n_idx + g) * sw * 8);
-                if (rs) launch_rs_probe(idx[tgt], m_ctl + 1, (uint32_t)sw, rs_cur, m_ctl + 2, E.stream);
-                ck(hipMemcpyAsync(rb_merge(i), m_ctl, 24, hipMemcpyDeviceToHost, E.stream), "hipMemcpyAsync(merge ctl)");
+                if (rs) launch_rs_probe(idx[tgt], m_ctl + 1, (uint32_t)sw, rs_cur, rb_dev + 2, E.stream);
                 ck(hipEventRecord(ev_merge(i), E.stream), "hipEventRecord");
                 merge_out = true;
                 merge_batch = i;

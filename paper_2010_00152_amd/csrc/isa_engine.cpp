@@ -160,6 +160,16 @@ char* Engine::ring_slot(size_t i) {
     return ring + (i % SLOTS) * 64;
 }
 
+uint64_t* Engine::ring_dev(size_t i) {
+    char* h = ring_slot(i);
+    if (!ring_dev_base) {
+        void* d = nullptr;
+        ck(hipHostGetDevicePointer(&d, ring, 0), "hipHostGetDevicePointer(ring)");
+        ring_dev_base = (char*)d;
+    }
+    return (uint64_t*)(ring_dev_base + (h - ring));
+}
+
 // The caller guarantees that no copy from the previous table is in flight.
 void* Engine::table_buf(uint64_t bytes) {
     if (bytes > table_cap) {
@@ -177,6 +187,7 @@ void* Engine::table_buf(uint64_t bytes) {
 void Engine::release() {
     if (ring) hipHostFree(ring);
     ring = nullptr;
+    ring_dev_base = nullptr;
     if (table) hipHostFree(table);
     table = nullptr;
     table_cap = 0;
@@ -921,10 +932,11 @@ void BatchProgram::enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback,
         E.pend(bn, 0, st);
     }
     E.pbegin("k_leaf", st);
+    // the last leaf writes the control word and the group count straight to
+    // the pinned readback slot (no copy after the launch)
     launch_leaf_flat(d_slots, nb, nullptr, reg, splitters, d_offs, part, L, d_first, d_dests + slot, ctl + 2, ctl + 1,
-                     (uint32_t*)ctl, st, d_single_of, d_partials, max_pieces);
+                     (uint32_t*)ctl, st, d_single_of, d_partials, max_pieces, E.ring_dev_of(readback));
     E.pend(bn, bn * (uint64_t)L.words * 8, st);
-    ck(hipMemcpyAsync(readback, ctl, 16, hipMemcpyDeviceToHost, st), "hipMemcpyAsync(batch ctl)");
 }
 
 bool BatchProgram::result(const char* readback, uint64_t& groups) const {

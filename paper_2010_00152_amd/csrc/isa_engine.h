@@ -38,7 +38,7 @@ void launch_leaf_flat(const FlatSlot* slots, uint32_t n_slots, const FlatInst* i
                       const uint64_t* splitters, const uint64_t* offs, const uint64_t* part, Layout L,
                       const uint32_t* first_slot, const Dest* dests, uint64_t* status, uint64_t* totals,
                       uint32_t* ctl, hipStream_t st, const uint32_t* single_of = nullptr,
-                      const void* partials = nullptr, uint32_t max_pieces = 0);
+                      const void* partials = nullptr, uint32_t max_pieces = 0, uint64_t* host_out = nullptr);
 void launch_flat_single_partial(const Region* regions, const uint64_t* offs, const uint64_t* part, Layout L,
                                 const uint32_t* single_buckets, uint32_t n_single, uint32_t max_pieces, void* partials,
                                 hipStream_t st);
@@ -49,7 +49,7 @@ uint64_t merge_parts(uint64_t na, uint64_t nb);
 // next_ctl (optional): next_words words cleared by the merge for the next one.
 void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb, uint64_t* out, Layout L,
                   uint64_t* splits, uint64_t* status, uint32_t* ctl, uint64_t* total_out, hipStream_t st,
-                  uint64_t* next_ctl = nullptr, uint32_t next_words = 0);
+                  uint64_t* next_ctl = nullptr, uint32_t next_words = 0, uint64_t* host_out = nullptr);
 // Replacement selection: cursor position in the merged index (*p_out) and
 // eviction of rows [p, p+a) and [0, b) (see the kernels).
 void launch_rs_probe(const uint64_t* U, const uint64_t* m_ptr, uint32_t w, const uint64_t* cur, uint64_t* p_out,
@@ -138,7 +138,10 @@ struct Engine {
     // small pinned ring for readbacks that stay in flight across host waits
     // (slots of 64 bytes, allocated once)
     char* ring = nullptr;
+    char* ring_dev_base = nullptr;
     char* ring_slot(size_t i);
+    uint64_t* ring_dev(size_t i);  // the slot's device mapping
+    uint64_t* ring_dev_of(const char* slot) { return ring_dev((size_t)(slot - ring) / 64); }
     // pinned host table for uploads that stay in flight across syncs of the
     // main stream (the wide merge's gather tasks); grows, never shrinks
     char* table = nullptr;

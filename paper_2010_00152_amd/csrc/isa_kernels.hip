@@ -596,6 +596,7 @@ __device__ uint64_t chained_prefix(uint64_t* status, uint32_t i, uint32_t first,
         if (zero_mask & needed) {
             if (++spins >= LOOKBACK_SPINS) {
                 if (lane == 0) atomicOr(err, 1u);
+                __threadfence();  // the error bit is visible before this item's prefix
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
@@ -1062,20 +1063,16 @@ __global__ void __launch_bounds__(256) k_flat_single_partial(const Region* __res
     }
 }
 
-__global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restrict__ slots,
-                                                       const FlatInst* __restrict__ insts,
-                                                       const Region* __restrict__ regions,
-                                                       const uint64_t* __restrict__ splitters,
-                                                       const uint64_t* __restrict__ offs,
-                                                       const uint64_t* __restrict__ part, Layout L,
-                                                       const uint32_t* __restrict__ first_slot,
-                                                       const Dest* __restrict__ dests, uint64_t* __restrict__ status,
-                                                       uint64_t* __restrict__ totals, uint32_t* __restrict__ ctl,
-                                                       const uint32_t* __restrict__ single_of,
-                                                       const Agg* __restrict__ partials, uint32_t max_pieces) {
-    __shared__ LeafSmem s;
-    __shared__ uint32_t s_li;
-    __shared__ uint64_t s_pre;
+__device__ __forceinline__ void leaf_flat_slot(const FlatSlot* __restrict__ slots, const FlatInst* __restrict__ insts,
+                                               const Region* __restrict__ regions,
+                                               const uint64_t* __restrict__ splitters,
+                                               const uint64_t* __restrict__ offs, const uint64_t* __restrict__ part,
+                                               Layout L, const uint32_t* __restrict__ first_slot,
+                                               const Dest* __restrict__ dests, uint64_t* __restrict__ status,
+                                               uint64_t* __restrict__ totals, uint32_t* __restrict__ ctl,
+                                               const uint32_t* __restrict__ single_of,
+                                               const Agg* __restrict__ partials, uint32_t max_pieces, LeafSmem& s,
+                                               uint32_t& s_li, uint64_t& s_pre) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0) s_li = atomicAdd(&ctl[0], 1u);
     __syncthreads();
@@ -1104,7 +1101,10 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restric
         single = n > 0 && lo == hi;
     }
     if (n == 0 || (n > (uint64_t)LEAF_CAP && !single)) {
-        if (n > 0 && tid == 0) atomicOr(&ctl[1], 2u);
+        if (n > 0 && tid == 0) {
+            atomicOr(&ctl[1], 2u);
+            __threadfence();  // the error bit is visible before this slot's prefix
+        }
         if (w == 0) {
             const uint64_t pre = chained_prefix(status, li, first, 0, &ctl[1]);
             if (lane == 0 && li == last) totals[d] = pre + dest_base(D);
@@ -1134,6 +1134,33 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restric
     }
     if (single) leaf_single_stream(V, n, D, li, first, last, d, status, totals, ctl, s, s_pre);
     else leaf_sort_reduce(V, (uint32_t)n, D, li, first, last, d, status, totals, ctl, s, s_pre);
+}
+
+// host_out (optional): a device-mapped pinned slot.  The last slot hands
+// the control word (ticket, error bits) and destination 0's end row to the
+// host there, so that no copy needs to follow the launch.
+__global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restrict__ slots,
+                                                       const FlatInst* __restrict__ insts,
+                                                       const Region* __restrict__ regions,
+                                                       const uint64_t* __restrict__ splitters,
+                                                       const uint64_t* __restrict__ offs,
+                                                       const uint64_t* __restrict__ part, Layout L,
+                                                       const uint32_t* __restrict__ first_slot,
+                                                       const Dest* __restrict__ dests, uint64_t* __restrict__ status,
+                                                       uint64_t* __restrict__ totals, uint32_t* __restrict__ ctl,
+                                                       const uint32_t* __restrict__ single_of,
+                                                       const Agg* __restrict__ partials, uint32_t max_pieces,
+                                                       uint64_t* __restrict__ host_out) {
+    __shared__ LeafSmem s;
+    __shared__ uint32_t s_li;
+    __shared__ uint64_t s_pre;
+    leaf_flat_slot(slots, insts, regions, splitters, offs, part, L, first_slot, dests, status, totals, ctl, single_of,
+                   partials, max_pieces, s, s_li, s_pre);
+    if (host_out && threadIdx.x == 0 && s_li + 1 == gridDim.x) {
+        __threadfence();
+        host_out[1] = totals[0];
+        host_out[0] = __hip_atomic_load(reinterpret_cast<uint64_t*>(ctl), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1198,7 +1225,8 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
                                                  const uint64_t* __restrict__ splits, uint64_t* __restrict__ out,
                                                  Layout L, uint64_t* __restrict__ status, uint32_t* __restrict__ ctl,
                                                  uint64_t* __restrict__ total_out, uint64_t* __restrict__ next_ctl,
-                                                 uint32_t next_words, uint32_t nparts) {
+                                                 uint32_t next_words, uint32_t nparts,
+                                                 uint64_t* __restrict__ host_out) {
     __shared__ uint64_t s_in[(MG_D + 2) * MG_MAXW];
     __shared__ uint32_t s_li[MG_NT + 1], s_lj[MG_NT + 1];
     __shared__ uint32_t s_tmp[MG_NT / 64 + 1];
@@ -1286,7 +1314,15 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
             const uint64_t pre = chained_prefix(status, part, 0, tot, &ctl[1]);
             if (tid == 0) {
                 s_pre = pre;
-                if (part == nparts - 1) *total_out = pre + tot;
+                if (part == nparts - 1) {
+                    *total_out = pre + tot;
+                    if (host_out) {
+                        __threadfence();
+                        host_out[1] = pre + tot;
+                        host_out[0] = __hip_atomic_load(reinterpret_cast<uint64_t*>(ctl), __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
             }
         }
 #pragma unroll
@@ -2032,10 +2068,11 @@ void launch_leaf_flat(const FlatSlot* slots, uint32_t n_slots, const FlatInst* i
                       const uint64_t* splitters, const uint64_t* offs, const uint64_t* part, Layout L,
                       const uint32_t* first_slot, const Dest* dests, uint64_t* status, uint64_t* totals,
                       uint32_t* ctl, hipStream_t st, const uint32_t* single_of, const void* partials,
-                      uint32_t max_pieces) {
+                      uint32_t max_pieces, uint64_t* host_out) {
     if (!n_slots) return;
     hipLaunchKernelGGL(k_leaf_flat, dim3(n_slots), dim3(LEAF_NT), 0, st, slots, insts, regions, splitters, offs, part,
-                       L, first_slot, dests, status, totals, ctl, single_of, (const Agg*)partials, max_pieces);
+                       L, first_slot, dests, status, totals, ctl, single_of, (const Agg*)partials, max_pieces,
+                       host_out);
 }
 void launch_flat_single_partial(const Region* regions, const uint64_t* offs, const uint64_t* part, Layout L,
                                 const uint32_t* single_buckets, uint32_t n_single, uint32_t max_pieces, void* partials,
@@ -2055,7 +2092,7 @@ uint64_t merge_parts(uint64_t na, uint64_t nb) { return (na + nb + MG_D - 1) / M
 // status: parts words and ctl: 2 words, both zeroed.
 void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb, uint64_t* out, Layout L,
                   uint64_t* splits, uint64_t* status, uint32_t* ctl, uint64_t* total_out, hipStream_t st,
-                  uint64_t* next_ctl, uint32_t next_words) {
+                  uint64_t* next_ctl, uint32_t next_words, uint64_t* host_out) {
     const uint64_t parts = merge_parts(na, nb);
     if (parts == 0) return;
     hipLaunchKernelGGL(k_merge_splits, dim3((uint32_t)((parts + 1 + 255) / 256)), dim3(256), 0, st, A, na, B, nb,
@@ -2064,7 +2101,7 @@ void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb
     // sort running beside the merge
     const uint32_t grid = (uint32_t)(parts < MG_GRID ? parts : MG_GRID);
     hipLaunchKernelGGL(k_merge, dim3(grid), dim3(MG_NT), 0, st, A, na, B, nb, splits, out, L, status, ctl, total_out,
-                       next_ctl, next_words, (uint32_t)parts);
+                       next_ctl, next_words, (uint32_t)parts, host_out);
 }
 void launch_rs_probe(const uint64_t* U, const uint64_t* m_ptr, uint32_t w, const uint64_t* cur, uint64_t* p_out,
                      hipStream_t st) {
