@@ -917,10 +917,8 @@ void BatchProgram::enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback,
     r.n_chunks = nch;
     Region* reg = d_regs + (i % BP_CTL_RING);
     uint64_t* ctl = d_ctl + (i % BP_CTL_RING) * ctl_words();
-    
-    launch_batch_prep(r, reg, ctl, (uint32_t)ctl_words(), st);
     E.pbegin("k_hist", st);
-    launch_hist(reg, ch, nch, splitters, d_hist, st);
+    launch_hist_batch(r, reg, ctl, (uint32_t)ctl_words(), ch, nch, splitters, d_hist, st);
     E.pend(bn, bn * 8, st);
     launch_scan(d_hist, (uint64_t)nb * nch, d_tiles, d_offs, st);
     E.pbegin("k_scatter", st);

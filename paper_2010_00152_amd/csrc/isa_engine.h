@@ -30,7 +30,10 @@ void launch_sorted_big_final(ColView V, int shift, const uint64_t* bigs, uint32_
 void launch_sample_keys(ColView src, uint64_t n, uint64_t S, uint64_t* out, hipStream_t st);
 void launch_copy_words(const uint64_t* src, uint64_t* dst, uint64_t n, hipStream_t st);
 void launch_extract_keys(const uint64_t* rows, uint64_t n, uint32_t stride, uint64_t* keys, hipStream_t st);
-void launch_batch_prep(const Region& r, Region* reg, uint64_t* ctl, uint32_t ctl_words, hipStream_t st);
+// Histogram of one run-generation batch that also stores its region
+// descriptor at reg and clears its control block (ctl_words words).
+void launch_hist_batch(const Region& r, Region* reg, uint64_t* ctl, uint32_t ctl_words, const Chunk* chunks,
+                       uint32_t n_chunks, const uint64_t* splitters, uint32_t* hist, hipStream_t st);
 void launch_leaf(const Leaf* leaves, uint32_t n_leaves, const uint32_t* leaf_dest, const uint32_t* first_seg,
                  const Dest* dests, const void* partials, uint64_t* status, uint64_t* totals, uint32_t* ctl,
                  hipStream_t st);

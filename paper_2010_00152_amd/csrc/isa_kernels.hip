@@ -383,6 +383,9 @@ __device__ __forceinline__ uint32_t bucket_of(const uint64_t* s_spl, uint64_t ke
 // Histogram pass: rows per (bucket, chunk), bucket-major per region.
 // ---------------------------------------------------------------------------
 
+__device__ __forceinline__ void hist_chunk(const Region& R, const Chunk& C, const uint64_t* __restrict__ splitters,
+                                           uint32_t* __restrict__ hist, uint64_t* s_spl, uint32_t* s_hist);
+
 __global__ void __launch_bounds__(PART_NT) k_hist(const Region* __restrict__ regions,
                                                   const Chunk* __restrict__ chunks,
                                                   const uint64_t* __restrict__ splitters,
@@ -390,7 +393,26 @@ __global__ void __launch_bounds__(PART_NT) k_hist(const Region* __restrict__ reg
     __shared__ uint64_t s_spl[MAX_BUCKETS];
     __shared__ uint32_t s_hist[MAX_BUCKETS];
     const Chunk C = chunks[blockIdx.x];
-    const Region R = regions[C.region];
+    hist_chunk(regions[C.region], C, splitters, hist, s_spl, s_hist);
+}
+
+// The histogram of one batch of run generation, which also sets the batch up
+// for the launches after it: the region descriptor (passed by value) is
+// stored for them and the batch's control block is cleared.
+__global__ void __launch_bounds__(PART_NT) k_hist_batch(Region r, Region* __restrict__ reg,
+                                                        uint64_t* __restrict__ ctl, uint32_t ctl_words,
+                                                        const Chunk* __restrict__ chunks,
+                                                        const uint64_t* __restrict__ splitters,
+                                                        uint32_t* __restrict__ hist) {
+    __shared__ uint64_t s_spl[MAX_BUCKETS];
+    __shared__ uint32_t s_hist[MAX_BUCKETS];
+    for (uint32_t i = blockIdx.x * PART_NT + threadIdx.x; i < ctl_words; i += gridDim.x * PART_NT) ctl[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *reg = r;
+    hist_chunk(r, chunks[blockIdx.x], splitters, hist, s_spl, s_hist);
+}
+
+__device__ __forceinline__ void hist_chunk(const Region& R, const Chunk& C, const uint64_t* __restrict__ splitters,
+                                           uint32_t* __restrict__ hist, uint64_t* s_spl, uint32_t* s_hist) {
     const int tid = threadIdx.x;
     for (int i = tid; i < MAX_BUCKETS; i += PART_NT) {
         s_spl[i] = i < MAX_BUCKETS - 1 ? splitters[(uint64_t)C.region * (MAX_BUCKETS - 1) + i] : ~0ull;
@@ -610,12 +632,6 @@ __device__ uint64_t chained_prefix(uint64_t* status, uint32_t i, uint32_t first,
     return sum;
 }
 
-// Per-batch set-up of run generation: store the batch's region descriptor
-// (passed by value) and clear its control block.
-__global__ void k_batch_prep(Region r, Region* __restrict__ reg, uint64_t* __restrict__ ctl, uint32_t ctl_words) {
-    for (uint32_t i = threadIdx.x; i < ctl_words; i += blockDim.x) ctl[i] = 0;
-    if (threadIdx.x == 0) *reg = r;
-}
 
 // Plain word copy (device to device) and strided key extraction.
 __global__ void k_copy_words(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, uint64_t n) {
@@ -2009,8 +2025,10 @@ void launch_bucket_starts(const Region* regions, uint32_t n_regions, const uint6
                           uint64_t* bstart, hipStream_t st) {
     hipLaunchKernelGGL(k_bucket_starts, dim3(n_regions), dim3(256), 0, st, regions, offs, bs_base, bstart);
 }
-void launch_batch_prep(const Region& r, Region* reg, uint64_t* ctl, uint32_t ctl_words, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_prep, dim3(1), dim3(256), 0, st, r, reg, ctl, ctl_words);
+void launch_hist_batch(const Region& r, Region* reg, uint64_t* ctl, uint32_t ctl_words, const Chunk* chunks,
+                       uint32_t n_chunks, const uint64_t* splitters, uint32_t* hist, hipStream_t st) {
+    hipLaunchKernelGGL(k_hist_batch, dim3(n_chunks), dim3(PART_NT), 0, st, r, reg, ctl, ctl_words, chunks, splitters,
+                       hist);
 }
 void launch_copy_words(const uint64_t* src, uint64_t* dst, uint64_t n, hipStream_t st) {
     if (!n) return;
