@@ -920,9 +920,8 @@ void BatchProgram::enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback,
     E.pbegin("k_hist", st);
     launch_hist_batch(r, reg, ctl, (uint32_t)ctl_words(), ch, nch, splitters, d_hist, st);
     E.pend(bn, bn * 8, st);
-    launch_scan(d_hist, (uint64_t)nb * nch, d_tiles, d_offs, st);
     E.pbegin("k_scatter", st);
-    launch_scatter(reg, ch, nch, splitters, d_offs, part, L, st);
+    launch_scatter(reg, ch, nch, splitters, d_offs, part, L, st, d_hist, d_offs);
     E.pend(bn, bn * (uint64_t)L.words * 8, st);
     if (n_single) {
         E.pbegin("k_single_partial", st);

@@ -15,8 +15,12 @@ namespace isa {
 void launch_sample(const Region* regions, uint32_t n_regions, uint64_t* splitters, hipStream_t st);
 void launch_hist(const Region* regions, const Chunk* chunks, uint32_t n_chunks, const uint64_t* splitters,
                  uint32_t* hist, hipStream_t st);
+// hist_self (optional, one region only): the raw histogram; the scatter then
+// derives the chunk offsets itself (no scan launch) and writes them to
+// offs_out for the launches after it.
 void launch_scatter(const Region* regions, const Chunk* chunks, uint32_t n_chunks, const uint64_t* splitters,
-                    const uint64_t* offs, uint64_t* dst, Layout L, hipStream_t st);
+                    const uint64_t* offs, uint64_t* dst, Layout L, hipStream_t st,
+                    const uint32_t* hist_self = nullptr, uint64_t* offs_out = nullptr);
 void launch_bucket_starts(const Region* regions, uint32_t n_regions, const uint64_t* offs, const uint64_t* bs_base,
                           uint64_t* bstart, hipStream_t st);
 void launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st);

@@ -446,7 +446,9 @@ __global__ void __launch_bounds__(PART_NT) k_scatter(const Region* __restrict__ 
                                                      const Chunk* __restrict__ chunks,
                                                      const uint64_t* __restrict__ splitters,
                                                      const uint64_t* __restrict__ offs,
-                                                     uint64_t* __restrict__ dst, Layout L) {
+                                                     uint64_t* __restrict__ dst, Layout L,
+                                                     const uint32_t* __restrict__ hist_self,
+                                                     uint64_t* __restrict__ offs_out) {
     constexpr int NT = PART_NT, NW = NT / 64, TILE = NT * IPT;
     static_assert(TILE <= 65536, "tile slots are 16-bit");
     static_assert(MAX_BUCKETS == NT, "one thread per bucket in the tile scan");
@@ -463,10 +465,33 @@ __global__ void __launch_bounds__(PART_NT) k_scatter(const Region* __restrict__ 
     const Region R = regions[C.region];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
-    const uint64_t rbase = offs[R.hist_base];
-    for (int i = tid; i < MAX_BUCKETS; i += NT) {
+    for (int i = tid; i < MAX_BUCKETS; i += NT)
         s_spl[i] = i < MAX_BUCKETS - 1 ? splitters[(uint64_t)C.region * (MAX_BUCKETS - 1) + i] : ~0ull;
-        s_run[i] = i < (int)R.nb ? offs[R.hist_base + (uint64_t)i * R.n_chunks + C.idx] - rbase + R.out_pos : 0;
+    if (hist_self) {
+        // one region and no separate scan: thread b sums bucket b over all
+        // chunks and over the chunks before this one; a scan over buckets
+        // gives the bucket starts.  The offsets go to offs_out for the leaves.
+        uint32_t tot = 0, before = 0;
+        if (tid < (int)R.nb) {
+            const uint32_t* hb = hist_self + R.hist_base + (uint64_t)tid * R.n_chunks;
+            for (uint32_t c = 0; c < R.n_chunks; ++c) {
+                const uint32_t h = hb[c];
+                tot += h;
+                before += c < C.idx ? h : 0u;
+            }
+        }
+        uint32_t all;
+        const uint32_t base = block_exclusive_scan<NT>(tot, s_tmp, all);
+        if (tid < (int)R.nb) {
+            s_run[tid] = (uint64_t)(base + before) + R.out_pos;
+            offs_out[R.hist_base + (uint64_t)tid * R.n_chunks + C.idx] = base + before;
+        } else {
+            s_run[tid] = 0;
+        }
+    } else {
+        const uint64_t rbase = offs[R.hist_base];
+        for (int i = tid; i < MAX_BUCKETS; i += NT)
+            s_run[i] = i < (int)R.nb ? offs[R.hist_base + (uint64_t)i * R.n_chunks + C.idx] - rbase + R.out_pos : 0;
     }
     __syncthreads();
     const ColView V = R.src;
@@ -2012,14 +2037,15 @@ void launch_hist(const Region* regions, const Chunk* chunks, uint32_t n_chunks, 
     hipLaunchKernelGGL(k_hist, dim3(n_chunks), dim3(PART_NT), 0, st, regions, chunks, splitters, hist);
 }
 void launch_scatter(const Region* regions, const Chunk* chunks, uint32_t n_chunks, const uint64_t* splitters,
-                    const uint64_t* offs, uint64_t* dst, Layout L, hipStream_t st) {
+                    const uint64_t* offs, uint64_t* dst, Layout L, hipStream_t st, const uint32_t* hist_self,
+                    uint64_t* offs_out) {
     // narrow rows: tiles of 2048 rows staged in LDS (48 KB, two workgroups per CU)
     if (L.words <= 3)
         hipLaunchKernelGGL((k_scatter<3, PART_IPT / 2>), dim3(n_chunks), dim3(PART_NT), 0, st, regions, chunks,
-                           splitters, offs, dst, L);
+                           splitters, offs, dst, L, hist_self, offs_out);
     else
         hipLaunchKernelGGL((k_scatter<0, PART_IPT>), dim3(n_chunks), dim3(PART_NT), 0, st, regions, chunks,
-                           splitters, offs, dst, L);
+                           splitters, offs, dst, L, hist_self, offs_out);
 }
 void launch_bucket_starts(const Region* regions, uint32_t n_regions, const uint64_t* offs, const uint64_t* bs_base,
                           uint64_t* bstart, hipStream_t st) {
