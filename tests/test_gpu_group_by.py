@@ -231,3 +231,22 @@ def test_wide_merge_second_pass(ctx, monkeypatch):
     assert g2 == g1 and st2["windows"] == st1["windows"]
     for col in ("keys", "count", "sum_i64", "min_i64", "max_i64"):
         assert np.array_equal(got1[col], got2[col]), col
+
+
+@pytest.mark.parametrize("redo", ["0", "1"])
+def test_truncation_while_spilling(ctx, monkeypatch, redo):
+    # an output capacity below the group count while the wide merge places
+    # windows behind a device-side cursor (first pass) or a host cursor
+    # (second pass): ETRUNC, the full group count, and the first rows exact
+    say("case truncation while spilling redo=%s" % redo)
+    monkeypatch.setenv("ISA_FORCE_MERGE_REDO", redo)
+    k, v, _ = datagen.plain_input(16, 900_000, 300_000, 0.5)
+    ref = oracle.group_by(k, v)
+    G = ref["keys"].shape[0]
+    for cap in (G // 3, G - 1234):
+        got, st, status, g = run_gpu(ctx, k, v, None, aggs=isa.ISA_INT_AGGS, budget=16 << 20, capacity=cap,
+                                     check=False)
+        assert st["runs"] > 0 and st["windows"] > 1
+        assert status == isa.ISA_ETRUNC and g == G
+        for col in ("keys", "count", "sum_i64", "min_i64", "max_i64"):
+            assert np.array_equal(got[col], ref[col][:cap]), (cap, col)
