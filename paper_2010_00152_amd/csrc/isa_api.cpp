@@ -993,8 +993,36 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 // is merge space
                 if (ip != idx[0]) launch_copy_words(ip, idx[0], n_idx * sw, E.stream);
                 A.off = (uint64_t)((char*)idx[0] - A.base) + n_idx * sw * 8;
-                wide_merge(E, A, k, aggs, runs, (const char*)spill.host_pinned, idx[0], n_idx, out, stats,
-                           n_groups);
+                try {
+                    wide_merge(E, A, k, aggs, runs, (const char*)spill.host_pinned, idx[0], n_idx, out, stats,
+                               n_groups);
+                } catch (const Fail& f) {
+                    // No window fits beside the final index (a full index under
+                    // replacement selection in a small workspace): write the
+                    // index out as one more run, which frees its room, and merge
+                    // from host memory alone.  Every spilled state row still
+                    // stands for at least one input row, so the spill buffer
+                    // of one state row per input row holds it.
+                    if (f.status != ISA_ESPILL || n_idx == 0) throw;
+                    const uint64_t bytes = n_idx * sw * 8;
+                    if (spill_used + bytes > spill.bytes) throw;
+                    ck(hipMemcpyAsync(spill_dev + spill_used, idx[0], bytes, hipMemcpyDeviceToDeviceNoCU, E.stream),
+                       "hipMemcpyAsync(spill index)");
+                    E.sync();
+                    runs.push_back(RunInfo{spill_used, 0, n_idx});
+                    spill_used += bytes;
+                    spilled += n_idx;
+                    spilled_bytes += bytes;
+                    if (stats) {
+                        stats->runs = runs.size();
+                        stats->spilled_rows = spilled;
+                        stats->spilled_bytes = spilled_bytes;
+                        stats->windows = 0;
+                    }
+                    A.off = (uint64_t)((char*)idx[0] - A.base);
+                    wide_merge(E, A, k, aggs, runs, (const char*)spill.host_pinned, idx[0], 0, out, stats,
+                               n_groups);
+                }
             }
             if (stats) {
                 stats->peak_ws_bytes = A.peak;
