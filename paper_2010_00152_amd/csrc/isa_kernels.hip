@@ -474,7 +474,22 @@ __global__ void __launch_bounds__(PART_NT) k_scatter(const Region* __restrict__ 
         uint32_t tot = 0, before = 0;
         if (tid < (int)R.nb) {
             const uint32_t* hb = hist_self + R.hist_base + (uint64_t)tid * R.n_chunks;
-            for (uint32_t c = 0; c < R.n_chunks; ++c) {
+            uint32_t c = 0;
+            if ((((uintptr_t)hb) & 15) == 0) {
+                // four chunks per 16-byte load, several loads in flight
+                const uint4* h4 = reinterpret_cast<const uint4*>(hb);
+                const uint32_t n4 = R.n_chunks / 4;
+#pragma unroll 8
+                for (uint32_t q = 0; q < n4; ++q) {
+                    const uint4 h = h4[q];
+                    const uint32_t c0 = 4 * q;
+                    tot += h.x + h.y + h.z + h.w;
+                    before += (c0 < C.idx ? h.x : 0u) + (c0 + 1 < C.idx ? h.y : 0u) + (c0 + 2 < C.idx ? h.z : 0u) +
+                              (c0 + 3 < C.idx ? h.w : 0u);
+                }
+                c = 4 * n4;
+            }
+            for (; c < R.n_chunks; ++c) {
                 const uint32_t h = hb[c];
                 tot += h;
                 before += c < C.idx ? h : 0u;
