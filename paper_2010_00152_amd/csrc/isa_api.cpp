@@ -544,7 +544,10 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
 }
 
 isa_status fail(isa_ctx* ctx, const Fail& f) {
-    if (ctx) ctx->last_error = f.what;
+    if (ctx) {
+        ctx->eng.drain();
+        ctx->last_error = f.what;
+    }
     return (isa_status)f.status;
 }
 
@@ -779,9 +782,42 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 if (ip == idx[1]) return 0;
                 return pend_buf == 0 ? 1 : 0;
             };
+            // a compact run whose size the host has not read yet: its copy to
+            // host memory is enqueued by flush_copy once the split count is in
+            struct {
+                bool active = false;
+                int buf = 0;
+                uint64_t rows = 0;
+            } deferred;
+            auto flush_copy = [&]() {
+                if (!deferred.active) return;
+                deferred.active = false;
+                ck(hipEventSynchronize(E.sync_event(2)), "hipEventSynchronize(split count)");
+                const uint64_t n_run = deferred.rows;
+                const uint64_t n_single = *(const uint64_t*)E.ring_slot(16);
+                const uint64_t bytes = n_single * Rl.words * 8 + (n_run - n_single) * sw * 8;
+                if (spill_used + bytes > spill.bytes) throw Fail{ISA_ESPILL, "spill buffer too small"};
+                const char* run_src = (const char*)idx[deferred.buf] + buf_bytes - bytes;
+                ck(hipStreamWaitEvent(cs, E.sync_event(2), 0), "hipStreamWaitEvent");
+                E.pbegin("spill_d2h", cs);
+                ck(hipMemcpyAsync(spill_dev + spill_used, run_src, bytes, hipMemcpyDeviceToDeviceNoCU, cs),
+                   "hipMemcpyAsync(spill)");
+                E.pend(n_run, bytes, cs);
+                ck(hipEventRecord(E.sync_event(1), cs), "hipEventRecord");
+                RunInfo ri;
+                ri.byte_off = spill_used;
+                ri.n_single = n_single;
+                ri.n_multi = n_run - n_single;
+                runs.push_back(ri);
+                spill_used += bytes;
+                spilled += n_run;
+                spilled_bytes += bytes;
+                pend_lo = buf_bytes - bytes;
+            };
             // order the stream after the pending run's copy when [0, end) of
             // idx[buf] is about to be written over it
             auto guard = [&](int buf, uint64_t end) {
+                if (pend_buf == buf) flush_copy();
                 if (pend_buf == buf && end > pend_lo) {
                     ck(hipStreamWaitEvent(E.stream, E.sync_event(1), 0), "hipStreamWaitEvent");
                     pend_buf = -1;
@@ -790,50 +826,58 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             // memory is full: write the index as one sorted run (read-sort-write).
             // The run is split into its count-1 rows (raw layout) and the others,
             // placed at the end of the other index buffer, and copied to host
-            // memory on the copy stream while run generation continues.
+            // memory on the copy stream while run generation continues.  The
+            // copy's size depends on the split's count, so the copy is enqueued
+            // after the next absorb (flush_copy), which then need not wait for a
+            // host round trip.
             auto spill_index = [&]() {
+                flush_copy();
                 // an index that fails to absorb a batch holds more than one
                 // batch, so it lives in an index buffer
                 if (ip != idx[0] && ip != idx[1]) throw Fail{ISA_EDEVICE, "internal: spilling a batch run"};
+                if (!spill.host_pinned) throw Fail{ISA_ESPILL, "spill buffer too small"};
                 const int own = ip == idx[0] ? 0 : 1;
                 const int spare = own ^ 1;
                 if (pend_buf >= 0) {
                     ck(hipStreamWaitEvent(E.stream, E.sync_event(1), 0), "hipStreamWaitEvent");
                     pend_buf = -1;
                 }
-                uint64_t n_single = 0, bytes = n_idx * sw * 8;
-                const uint64_t* run_src = ip;
                 if (compact) {
                     launch_split(ip, n_idx, S, Rl, sp_counts, sp_tiles, sp_offs, idx[spare], buf_rows * sw, E.stream);
-                    char* rb = E.ring_slot(16);
-                    ck(hipMemcpyAsync(rb, sp_offs + split_blocks(n_idx), 8, hipMemcpyDeviceToHost, E.stream),
+                    ck(hipMemcpyAsync(E.ring_slot(16), sp_offs + split_blocks(n_idx), 8, hipMemcpyDeviceToHost,
+                                      E.stream),
                        "hipMemcpyAsync(split count)");
-                    ck(hipStreamSynchronize(E.stream), "hipStreamSynchronize");
-                    n_single = *(const uint64_t*)rb;
-                    bytes = n_single * Rl.words * 8 + (n_idx - n_single) * sw * 8;
-                    run_src = (const uint64_t*)((const char*)idx[spare] + buf_bytes - bytes);
+                    ck(hipEventRecord(E.sync_event(2), E.stream), "hipEventRecord");
+                    deferred.active = true;
+                    deferred.buf = spare;
+                    deferred.rows = n_idx;
+                    // the whole spare buffer counts as in use until the size is known
+                    pend_buf = spare;
+                    pend_lo = 0;
+                    n_idx = 0;
+                    return;
                 }
-                if (!spill.host_pinned || spill_used + bytes > spill.bytes)
-                    throw Fail{ISA_ESPILL, "spill buffer too small"};
+                const uint64_t bytes = n_idx * sw * 8;
+                if (spill_used + bytes > spill.bytes) throw Fail{ISA_ESPILL, "spill buffer too small"};
                 ck(hipEventRecord(E.sync_event(0), E.stream), "hipEventRecord");
                 ck(hipStreamWaitEvent(cs, E.sync_event(0), 0), "hipStreamWaitEvent");
                 // one runtime copy on the copy stream: a kernel of our own
                 // writing host memory slows the concurrent kernels far more
                 E.pbegin("spill_d2h", cs);
-                ck(hipMemcpyAsync(spill_dev + spill_used, run_src, bytes, hipMemcpyDeviceToDeviceNoCU, cs),
+                ck(hipMemcpyAsync(spill_dev + spill_used, ip, bytes, hipMemcpyDeviceToDeviceNoCU, cs),
                    "hipMemcpyAsync(spill)");
                 E.pend(n_idx, bytes, cs);
                 ck(hipEventRecord(E.sync_event(1), cs), "hipEventRecord");
                 RunInfo ri;
                 ri.byte_off = spill_used;
-                ri.n_single = n_single;
-                ri.n_multi = n_idx - n_single;
+                ri.n_single = 0;
+                ri.n_multi = n_idx;
                 runs.push_back(ri);
                 spill_used += bytes;
                 spilled += n_idx;
                 spilled_bytes += bytes;
-                pend_buf = compact ? spare : own;
-                pend_lo = compact ? buf_bytes - bytes : 0;
+                pend_buf = own;
+                pend_lo = 0;
                 n_idx = 0;
             };
             // replacement selection: the open run starts at rs_off in the
@@ -846,6 +890,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             // The kept rows go to the front of the other index buffer, the
             // evicted ones behind them, and are copied out on the copy stream.
             auto evict = [&](int target, uint64_t m, uint64_t pc) {
+                flush_copy();
                 const int o = target ^ 1;
                 const uint64_t K = p.capacity, e = m - K;
                 const uint64_t a = std::min(e, m - pc), b = e - a;
@@ -959,6 +1004,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 E.pend(n_idx + g, (n_idx + g) * sw * 8);
                 if (rs) launch_rs_probe(idx[tgt], m_ctl + 1, (uint32_t)sw, rs_cur, rb_dev + 2, E.stream);
                 ck(hipEventRecord(ev_merge(i), E.stream), "hipEventRecord");
+                flush_copy();
                 merge_out = true;
                 merge_batch = i;
                 merge_g = g;
@@ -968,6 +1014,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 ck(hipEventSynchronize(ev_merge(merge_batch)), "hipEventSynchronize");
                 decide(merge_batch, merge_g, merge_tgt);
             }
+            flush_copy();
             if (rs_rows) runs.push_back(RunInfo{rs_off, 0, rs_rows});
             if (!runs.empty()) ck(hipStreamSynchronize(cs), "hipStreamSynchronize(copy)");
             ck(hipStreamSynchronize(ss), "hipStreamSynchronize(sort)");

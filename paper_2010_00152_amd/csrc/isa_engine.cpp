@@ -224,6 +224,11 @@ void Engine::sync() {
     pinned_used = 0;
 }
 
+void Engine::drain() {
+    for (hipStream_t st : {stream, copy_stream, side_streams[0], side_streams[1], side_streams[2], capture_stream})
+        if (st) (void)hipStreamSynchronize(st);
+}
+
 // Device-to-host copy into pinned staging; the data is valid after sync() and
 // until the next upload/download.
 const void* download_async(Engine& E, const void* dev, uint64_t bytes) {

@@ -158,6 +158,9 @@ struct Engine {
     void* pinned_buf(uint64_t bytes);
     void upload(void* dev, const void* host, uint64_t bytes);
     void sync();
+    // wait for every stream of the engine, ignoring errors (after a failed
+    // call, so that no work still reads or writes the caller's buffers)
+    void drain();
     void release();
     hipStream_t copier();             // created on first use
     hipStream_t side(int i);          // extra copy streams 0..2, created on first use

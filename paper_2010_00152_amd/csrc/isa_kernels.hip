@@ -703,7 +703,7 @@ __global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t value)
 // ---------------------------------------------------------------------------
 
 template <int NT>
-__device__ void block_reduce_agg(Agg& a, Agg* s_agg) {
+__device__ __forceinline__ void block_reduce_agg(Agg& a, Agg* s_agg) {
     const int tid = threadIdx.x;
     s_agg[tid] = a;
     __syncthreads();
