@@ -944,14 +944,21 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 }
             };
             // Batches are sorted on a stream of their own, so that the sort of
-            // batch i+1 runs beside the absorb of batch i.  A sort waits for
-            // everything enqueued on the main stream before it (among that, the
-            // absorbs that read the batch-run buffer it overwrites); an absorb
-            // waits for its batch's sort.
+            // batch i+1 runs beside the absorb of batch i.  A sort waits for the
+            // last absorb that reads the batch-run buffer it overwrites (as the
+            // batch run, or as the index that a spill left in it); the first
+            // sorts wait for everything enqueued on the main stream before
+            // them.  An absorb waits for its batch's sort.
             hipStream_t ss = E.side(1);
+            int64_t last_reader[3] = {-1, -1, -1};
+            bool merged = false;
             auto sort_batch = [&](uint64_t b) {
-                ck(hipEventRecord(E.sync_event(24), E.stream), "hipEventRecord");
-                ck(hipStreamWaitEvent(ss, E.sync_event(24), 0), "hipStreamWaitEvent");
+                if (!merged) {
+                    ck(hipEventRecord(E.sync_event(24), E.stream), "hipEventRecord");
+                    ck(hipStreamWaitEvent(ss, E.sync_event(24), 0), "hipStreamWaitEvent");
+                } else if (last_reader[b % 3] >= 0) {
+                    ck(hipStreamWaitEvent(ss, ev_merge((uint64_t)last_reader[b % 3]), 0), "hipStreamWaitEvent");
+                }
                 bp.enqueue(E, b, (uint32_t)(b % 3), rb_sort(b), ss);
                 ck(hipEventRecord(ev_sort(b), ss), "hipEventRecord");
             };
@@ -978,6 +985,8 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     inst[0].dest = 0;
                     g = sort_reduce(E, A, inst, std::vector<Dest>(1, bdest[slot]), k, false, &hint)[0];
                     A.off = top;
+                    ck(hipEventRecord(E.sync_event(25), E.stream), "hipEventRecord");
+                    ck(hipStreamWaitEvent(ss, E.sync_event(25), 0), "hipStreamWaitEvent");
                 }
                 ++batches;
                 if (merge_out) {
@@ -1004,6 +1013,10 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 E.pend(n_idx + g, (n_idx + g) * sw * 8);
                 if (rs) launch_rs_probe(idx[tgt], m_ctl + 1, (uint32_t)sw, rs_cur, rb_dev + 2, E.stream);
                 ck(hipEventRecord(ev_merge(i), E.stream), "hipEventRecord");
+                merged = true;
+                last_reader[slot] = (int64_t)i;
+                for (int j = 0; j < 3; ++j)
+                    if (ip == brun[j]) last_reader[j] = (int64_t)i;
                 flush_copy();
                 merge_out = true;
                 merge_batch = i;
