@@ -172,13 +172,15 @@ bool plan_batches(uint64_t ws, uint64_t n, const Cols& k, Plan& p) {
     }
 }
 
-// A run in the spill buffer: n_single rows in raw layout (count 1) followed
-// by n_multi rows in state layout, both sorted on the key.  Runs written
-// without count information hold only state rows (n_single = 0).
+// A run in the spill buffer: n_single count-1 rows stored column by column
+// (single_bytes) followed by n_multi rows in state layout, both sorted on the
+// key.  Runs written without count information hold only state rows
+// (n_single = 0).
 struct RunInfo {
     uint64_t byte_off;
     uint64_t n_single;
     uint64_t n_multi;
+    bool narrow = false;  // the count-1 part's integer values take 4 bytes
 };
 
 // First row of [pos, n) whose key is >= x in a strided host array.
@@ -214,7 +216,7 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     const double t_enter = now_ms();
     const Layout S = state_layout(k);
     const Layout Rl = raw_layout(k);
-    const uint64_t sw = (uint64_t)S.words, rw = (uint64_t)Rl.words;
+    const uint64_t sw = (uint64_t)S.words;
     void* hdev = nullptr;
     if (hipHostGetDevicePointer(&hdev, (void*)host, 0) != hipSuccess || !hdev)
         throw Fail{ISA_EINVAL, "spill buffer is not device-mapped pinned memory"};
@@ -231,48 +233,53 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
         std::memcpy(idx_keys.data(), p, n_idx * 8);
         A.off = mark0;
     }
-    // Sources: every run contributes its count-1 sub-run (raw rows) and its
+    // Sources: every run contributes its count-1 sub-run (columns) and its
     // other rows (state rows); the last source is the index (state rows,
     // device).  keys: host view of the keys, strided; rows: device-visible
-    // address of the rows.
+    // address of the rows (of the key column, for a count-1 sub-run).
     struct Src {
         const uint64_t* keys;
         uint64_t stride, n;
         const uint64_t* rows;
-        bool raw;
+        bool raw, narrow;
     };
     std::vector<Src> src;
     auto on_dev = [&](const uint64_t* hp) { return (const uint64_t*)(host_dev + ((const char*)hp - host)); };
     uint64_t total = 0;
     for (const RunInfo& r : runs) {
         const uint64_t* base = (const uint64_t*)(host + r.byte_off);
-        if (r.n_single) src.push_back(Src{base, rw, r.n_single, on_dev(base), true});
-        const uint64_t* mb = base + r.n_single * rw;
-        if (r.n_multi) src.push_back(Src{mb, sw, r.n_multi, on_dev(mb), false});
+        // the count-1 part is stored column by column, keys first
+        if (r.n_single) src.push_back(Src{base, 1, r.n_single, on_dev(base), true, r.narrow});
+        const uint64_t* mb = base + single_bytes(r.n_single, Rl, r.narrow) / 8;
+        if (r.n_multi) src.push_back(Src{mb, sw, r.n_multi, on_dev(mb), false, false});
         total += r.n_single + r.n_multi;
     }
-    if (n_idx) src.push_back(Src{idx_keys.data(), 1, n_idx, idx, false});
+    if (n_idx) src.push_back(Src{idx_keys.data(), 1, n_idx, idx, false, false});
     total += n_idx;
     const size_t ns = src.size();
     std::vector<uint64_t> pos(ns, 0);
 
     // window capacity W: three staging buffers (two windows gathered ahead of
-    // the one being reduced), the gather task table and the flat plan of a
+    // the one being reduced), their gather task tables and the flat plan of a
     // window; a piece that falls back to the general plan is reduced alone
     const uint64_t avail0 = A.left() > (8u << 20) ? A.left() - (8u << 20) : 0;
     const uint64_t piece_fallback = sort_reduce_bytes(PIECE_CAP, 1, k, true);
-    auto need = [&](uint64_t w, uint64_t tasks) {
+    // gather tasks of one window: its pieces (at least PIECE_CAP/2 rows but
+    // the last) each take one slice of every source, plus one per GATHER_ROWS
+    auto win_task_bound = [&](uint64_t w) { return w / GATHER_ROWS + (ns + 1) * (w / (PIECE_CAP / 2) + 2) + 16; };
+    auto need = [&](uint64_t w) {
         const uint64_t pieces = w / (PIECE_CAP / 2) + 2;
-        return 3 * w * sw * 8 + tasks * sizeof(GatherTask) +
+        return 3 * w * sw * 8 + 3 * win_task_bound(w) * sizeof(GatherTask) +
                std::max(flat_bytes(w, pieces, k, true), std::min(piece_fallback, sort_reduce_bytes(w, 1, k, true)));
     };
     // every window but the last holds at least 3/4 W rows (fences every P rows)
-    auto task_bound = [&](uint64_t w) {
-        return total / GATHER_ROWS + (total / (w - w / 4) + 2) * (ns + 1) * (w / (PIECE_CAP / 2) + 2) + 16;
-    };
+    auto task_bound = [&](uint64_t w) { return (total / (w - w / 4) + 2) * win_task_bound(w); };
     uint64_t W = avail0 / (3 * sw * 8);
-    while (W > 2 * (ns + 1) && need(W, task_bound(W)) > avail0) W -= W / 32 + 1;
-    if (W < 2 * (ns + 1) || need(W, task_bound(W)) > avail0)
+    while (W > 2 * (ns + 1) && need(W) > avail0) W -= W / 32 + 1;
+    // ISA_FORCE_INDEX_SPILL=1 treats a merge beside an in-memory index as not
+    // fitting (it lets tests reach the caller's fallback with ordinary inputs)
+    const char* force = std::getenv("ISA_FORCE_INDEX_SPILL");
+    if (W < 2 * (ns + 1) || need(W) > avail0 || (n_idx && force && force[0] == '1'))
         throw Fail{ISA_ESPILL, "workspace too small for a single wide merge of all runs"};
     // Fences: the key of every P-th row of each source, merged in key order.
     // A cut at key x ends source s at lb_s(x) = its first row >= x; with c_s
@@ -375,11 +382,13 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     // Windows are planned one at a time, each just before its gather is
     // issued, so that the host plans while earlier windows are read.  A
     // window's gather tasks lay its pieces out one after the other in the
-    // staging buffer; they are written to a pinned table and uploaded on the
-    // gather stream ahead of the gather.
+    // staging buffer; they are written to a pinned table (all windows, kept
+    // for a second pass) and uploaded ahead of the gather into one of three
+    // device tables, used in turn like the staging buffers.
     const uint64_t max_tasks = task_bound(W);
+    const uint64_t win_tasks = win_task_bound(W);
     GatherTask* h_tasks = (GatherTask*)E.table_buf((max_tasks + 1) * sizeof(GatherTask));
-    GatherTask* d_tasks = A.take_n<GatherTask>(max_tasks + 1);
+    GatherTask* d_tasks = A.take_n<GatherTask>(3 * win_tasks);
     uint64_t n_tasks = 0;
     std::vector<uint64_t> task_first(1, 0);
     std::vector<uint64_t> win_rows, win_host_bytes;
@@ -394,13 +403,34 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
             const uint64_t c = next_cut(std::min(PIECE_CAP, W - at), at == 0, end);
             if (c == 0) break;  // the next piece would not fit this window
             for (size_t s = 0; s < ns; ++s) {
-                const uint64_t w = src[s].raw ? rw : sw;
+                const Src& q = src[s];
+                // host bytes per row; a count-1 part's columns
+                const uint64_t row_bytes =
+                    q.raw ? 8 + (Rl.fs >= 0 ? 8 : 0) + (Rl.sum >= 0 ? (q.narrow ? 4 : 8) : 0) : sw * 8;
+                const uint64_t* fs_c = q.rows + q.n;
+                const uint64_t* int_c = q.rows + q.n * (Rl.fs >= 0 ? 2 : 1);
                 for (uint64_t r = pos[s]; r < end[s]; r += GATHER_ROWS) {
                     const uint64_t len = std::min<uint64_t>(GATHER_ROWS, end[s] - r);
-                    if (n_tasks >= max_tasks) throw Fail{ISA_EDEVICE, "internal: gather task table overflow"};
-                    h_tasks[n_tasks++] = GatherTask{src[s].rows + r * w, at, (uint32_t)len, src[s].raw ? 1u : 0u};
+                    if (n_tasks >= max_tasks || n_tasks - task_first.back() >= win_tasks)
+                        throw Fail{ISA_EDEVICE, "internal: gather task table overflow"};
+                    GatherTask& t = h_tasks[n_tasks++];
+                    t.dst_row = at;
+                    t.n = (uint32_t)len;
+                    if (q.raw) {
+                        t.src = q.rows + r;
+                        t.fv = Rl.fs >= 0 ? fs_c + r : nullptr;
+                        t.iv = Rl.sum < 0 ? nullptr
+                               : q.narrow ? (const void*)((const int32_t*)int_c + r)
+                                          : (const void*)(int_c + r);
+                        t.raw = q.narrow ? 2u : 1u;
+                    } else {
+                        t.src = q.rows + r * sw;
+                        t.fv = nullptr;
+                        t.iv = nullptr;
+                        t.raw = 0;
+                    }
                     at += len;
-                    if (s + 1 < ns || !n_idx) hb += len * w * 8;
+                    if (s + 1 < ns || !n_idx) hb += len * row_bytes;
                 }
             }
             pieces.push_back(c);
@@ -433,14 +463,18 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     auto ev_reduce = [&](size_t w) { return E.sync_event(12 + (w % 3)); };
     auto issue = [&](size_t w) {
         const uint64_t t0 = task_first[w], nt = task_first[w + 1] - task_first[w];
+        GatherTask* dt = d_tasks + (w % 3) * win_tasks;
         if (nt) {
-            ck(hipMemcpyAsync(d_tasks + t0, h_tasks + t0, nt * sizeof(GatherTask), hipMemcpyHostToDevice, us),
+            // the device table's last reader: the gather of window w-3, whose
+            // completion event this window's gather records anew
+            ck(hipStreamWaitEvent(us, ev_gather(w), 0), "hipStreamWaitEvent");
+            ck(hipMemcpyAsync(dt, h_tasks + t0, nt * sizeof(GatherTask), hipMemcpyHostToDevice, us),
                "hipMemcpyAsync(gather tasks)");
             ck(hipEventRecord(ev_upload(w), us), "hipEventRecord");
             ck(hipStreamWaitEvent(gs, ev_upload(w), 0), "hipStreamWaitEvent");
         }
         E.pbegin("merge_h2d", gs);
-        launch_gather(d_tasks + t0, (uint32_t)nt, Rl, S, stage[w % 3], gs);
+        launch_gather(dt, (uint32_t)nt, Rl, S, stage[w % 3], gs);
         E.pend(win_rows[w], win_host_bytes[w], gs);
         ck(hipEventRecord(ev_gather(w), gs), "hipEventRecord");
     };
@@ -794,8 +828,9 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 deferred.active = false;
                 ck(hipEventSynchronize(E.sync_event(2)), "hipEventSynchronize(split count)");
                 const uint64_t n_run = deferred.rows;
-                const uint64_t n_single = *(const uint64_t*)E.ring_slot(16);
-                const uint64_t bytes = n_single * Rl.words * 8 + (n_run - n_single) * sw * 8;
+                const uint64_t n_single = ((const uint64_t*)E.ring_slot(16))[0];
+                const bool narrow = ((const uint64_t*)E.ring_slot(16))[1] != 0;
+                const uint64_t bytes = single_bytes(n_single, Rl, narrow) + (n_run - n_single) * sw * 8;
                 if (spill_used + bytes > spill.bytes) throw Fail{ISA_ESPILL, "spill buffer too small"};
                 const char* run_src = (const char*)idx[deferred.buf] + buf_bytes - bytes;
                 ck(hipStreamWaitEvent(cs, E.sync_event(2), 0), "hipStreamWaitEvent");
@@ -808,6 +843,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 ri.byte_off = spill_used;
                 ri.n_single = n_single;
                 ri.n_multi = n_run - n_single;
+                ri.narrow = narrow;
                 runs.push_back(ri);
                 spill_used += bytes;
                 spilled += n_run;
@@ -844,7 +880,8 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 }
                 if (compact) {
                     launch_split(ip, n_idx, S, Rl, sp_counts, sp_tiles, sp_offs, idx[spare], buf_rows * sw, E.stream);
-                    ck(hipMemcpyAsync(E.ring_slot(16), sp_offs + split_blocks(n_idx), 8, hipMemcpyDeviceToHost,
+                    // the count-1 rows and the narrow flag
+                    ck(hipMemcpyAsync(E.ring_slot(16), sp_offs + split_blocks(n_idx), 16, hipMemcpyDeviceToHost,
                                       E.stream),
                        "hipMemcpyAsync(split count)");
                     ck(hipEventRecord(E.sync_event(2), E.stream), "hipEventRecord");

@@ -55,6 +55,17 @@ struct Layout {
     int32_t cnt, sum, mn, mx, fs;
 };
 
+// Compact run format, count-1 part: n rows of raw layout R stored column by
+// column (keys, then the f64 values when R has them, then the integer values
+// when R has them, 4 bytes each when every value of the run fits in 32 bits,
+// else 8), padded to a multiple of 8 bytes.
+__host__ __device__ inline uint64_t single_bytes(uint64_t n, const Layout& R, bool narrow) {
+    uint64_t b = n * 8;
+    if (R.fs >= 0) b += n * 8;
+    if (R.sum >= 0) b += n * (narrow ? 4 : 8);
+    return (b + 7) & ~7ull;
+}
+
 // One region being partitioned at the current level.
 struct Region {
     ColView src;        // its rows are src[0, n)
@@ -127,10 +138,14 @@ constexpr uint32_t GATHER_ROWS = 1024;
 
 // One slice of a wide-merge window copied into the window's staging buffer.
 struct GatherTask {
-    const uint64_t* src;  // first row: host-mapped pinned memory or device memory
+    const uint64_t* src;  // first row (state rows) or first key (count-1 rows):
+                          // host-mapped pinned memory or device memory
+    const uint64_t* fv;   // count-1 rows: their f64 values (when present)
+    const void* iv;       // count-1 rows: their integer values (when present)
     uint64_t dst_row;     // first state row written in the staging buffer
     uint32_t n;           // rows, at most GATHER_ROWS
-    uint32_t raw;         // 1: raw-layout rows with count 1, expanded to state rows
+    uint32_t raw;         // 0: state rows; count-1 rows, expanded to state rows,
+                          // with 8-byte (1) or 4-byte (2) integer values
 };
 
 // A span of gapped output copied into its final place.

@@ -1925,29 +1925,40 @@ __global__ void __launch_bounds__(256) k_seg_write(const int32_t* __restrict__ a
 // ---------------------------------------------------------------------------
 // Compact run format.  A state row whose count is 1 holds a single input row,
 // so key plus raw value columns describe it; a run is written as the sorted
-// sub-run of such rows in raw layout followed by the sorted sub-run of the
-// other rows in state layout (stable split, two passes).
+// sub-run of such rows, column by column (single_bytes), followed by the
+// sorted sub-run of the other rows in state layout (stable split, two
+// passes).  The integer column of the count-1 part takes 4 bytes per value
+// when every value in it fits in 32 bits.
 // ---------------------------------------------------------------------------
 
 constexpr int SPLIT_T = 4096;  // rows per workgroup
 
+__device__ __forceinline__ bool fits_i32(uint64_t v) { return (int64_t)v == (int64_t)(int32_t)(int64_t)v; }
+
+// counts[b]: count-1 rows of block b.  *narrow (set to 1 beforehand) is
+// cleared when a count-1 row's integer value needs more than 32 bits.
 __global__ void __launch_bounds__(256) k_split_count(const uint64_t* __restrict__ rows, uint64_t n, Layout S,
-                                                     uint32_t* __restrict__ counts) {
+                                                     uint32_t* __restrict__ counts, uint64_t* __restrict__ narrow) {
     __shared__ uint32_t s_tmp[256 / 64 + 1];
     const uint64_t r0 = (uint64_t)blockIdx.x * SPLIT_T;
     uint32_t c = 0;
+    bool wide = false;
     for (uint32_t i = threadIdx.x; i < SPLIT_T; i += 256) {
         const uint64_t r = r0 + i;
-        if (r < n && rows[r * S.words + S.cnt] == 1) ++c;
+        if (r < n && rows[r * S.words + S.cnt] == 1) {
+            ++c;
+            if (S.sum >= 0) wide |= !fits_i32(rows[r * S.words + S.sum]);
+        }
     }
     uint32_t tot;
     block_exclusive_scan<256>(c, s_tmp, tot);
+    if (__syncthreads_or(wide) && threadIdx.x == 0) *narrow = 0;
     if (threadIdx.x == 0) counts[blockIdx.x] = tot;
 }
 
-// offs: exclusive scan of the counts (offs[nblocks] = all singles).  Singles
-// go first in raw layout R, the rest after them in state layout S; the block
-// starts at out[0], or ends at out[end_words] when end_words is nonzero.
+// offs: exclusive scan of the counts (offs[nblocks] = all count-1 rows),
+// offs[nblocks + 1]: the narrow flag.  The run starts at out[0], or ends at
+// out[end_words] when end_words is nonzero.
 __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict__ rows, uint64_t n, Layout S,
                                                      Layout R, const uint64_t* __restrict__ offs, uint64_t nblocks,
                                                      uint64_t* __restrict__ out, uint64_t end_words) {
@@ -1962,19 +1973,27 @@ __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict_
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan<256>(c, s_tmp, tot);
     const uint64_t n_single = offs[nblocks];
-    if (end_words) out += end_words - (n_single * R.words + (n - n_single) * S.words);
-    uint64_t so = offs[blockIdx.x] + ex;                       // singles before this thread
-    uint64_t mo = r0 - so;                                     // others before this thread
-    uint64_t* multi = out + n_single * R.words;
+    const bool narrow = offs[nblocks + 1] != 0;
+    const uint64_t s_words = single_bytes(n_single, R, narrow) / 8;
+    if (end_words) out += end_words - (s_words + (n - n_single) * S.words);
+    // columns of the count-1 part
+    uint64_t* key_c = out;
+    uint64_t* fs_c = out + n_single;
+    void* int_c = out + n_single * (R.fs >= 0 ? 2 : 1);
+    uint64_t so = offs[blockIdx.x] + ex;  // count-1 rows before this thread
+    uint64_t mo = r0 - so;                // others before this thread
+    uint64_t* multi = out + s_words;
     for (int i = 0; i < PER; ++i) {
         const uint64_t r = r0 + i;
         if (r >= n) break;
         const uint64_t* src = rows + r * S.words;
         if (src[S.cnt] == 1) {
-            uint64_t* d = out + so * R.words;
-            d[0] = src[0];
-            if (R.sum >= 0) d[R.sum] = src[S.sum];
-            if (R.fs >= 0) d[R.fs] = src[S.fs];
+            key_c[so] = src[0];
+            if (R.fs >= 0) fs_c[so] = src[S.fs];
+            if (R.sum >= 0) {
+                if (narrow) ((int32_t*)int_c)[so] = (int32_t)(int64_t)src[S.sum];
+                else ((uint64_t*)int_c)[so] = src[S.sum];
+            }
             ++so;
         } else {
             uint64_t* d = multi + mo * S.words;
@@ -2014,16 +2033,43 @@ __global__ void __launch_bounds__(GATHER_NT) k_gather(const GatherTask* __restri
             for (; i < words; i += GATHER_NT) out[i] = in[i];
             continue;
         }
-        const uint32_t words = t.n * rw;
-        uint32_t i = threadIdx.x;
-        for (; i + 7 * GATHER_NT < words; i += 8 * GATHER_NT) {
+        // count-1 rows: the key column, the f64 column and the integer
+        // column of the slice, loaded into raw rows in LDS with 8-byte loads,
+        // eight in flight per thread.  A 4-byte integer column is read in
+        // 8-byte words; a slice that starts at an odd row starts in the upper
+        // half of its first word (column starts are 8-byte aligned).
+        const uint32_t n = t.n;
+        const bool nar = t.raw == 2;
+        const uint32_t odd = nar ? (uint32_t)(((uintptr_t)t.iv >> 2) & 1u) : 0u;
+        const uint64_t* iw = (const uint64_t*)((const char*)t.iv - 4 * odd);
+        const uint32_t e0 = n, e1 = e0 + (R.fs >= 0 ? n : 0u);
+        const uint32_t e2 = e1 + (R.sum < 0 ? 0u : nar ? (n + odd + 1) / 2 : n);
+        for (uint32_t i = threadIdx.x; i < e2; i += 8 * GATHER_NT) {
             uint64_t r[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) r[q] = in[i + q * GATHER_NT];
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t x = i + q * GATHER_NT;
+                if (x < e2) r[q] = x < e0 ? in[x] : x < e1 ? t.fv[x - e0] : iw[x - e1];
+            }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) s_raw[i + q * GATHER_NT] = r[q];
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t x = i + q * GATHER_NT;
+                if (x >= e2) continue;
+                if (x < e0) {
+                    s_raw[x * rw] = r[q];
+                } else if (x < e1) {
+                    s_raw[(x - e0) * rw + (uint32_t)R.fs] = r[q];
+                } else if (!nar) {
+                    s_raw[(x - e1) * rw + (uint32_t)R.sum] = r[q];
+                } else {
+                    // little endian: the lower half is the earlier row
+                    const int lo = 2 * (int)(x - e1) - (int)odd;
+                    if (lo >= 0) s_raw[(uint32_t)lo * rw + (uint32_t)R.sum] = (uint64_t)(int64_t)(int32_t)(uint32_t)r[q];
+                    if (lo + 1 < (int)n)
+                        s_raw[(uint32_t)(lo + 1) * rw + (uint32_t)R.sum] = (uint64_t)(int64_t)(int32_t)(uint32_t)(r[q] >> 32);
+                }
+            }
         }
-        for (; i < words; i += GATHER_NT) s_raw[i] = in[i];
         __syncthreads();
         const uint32_t owords = t.n * sw;
         for (uint32_t o = threadIdx.x; o < owords; o += GATHER_NT) {
@@ -2175,12 +2221,15 @@ void launch_rs_evict(const uint64_t* U, uint64_t m, uint32_t w, uint64_t p, uint
 }
 void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* offs, hipStream_t st);
 uint64_t split_blocks(uint64_t n) { return (n + SPLIT_T - 1) / SPLIT_T; }
-// counts: split_blocks(n) words; offs/tiles as for launch_scan.
+// counts: split_blocks(n) words; tiles as for launch_scan; offs: split_blocks(n) + 2
+// words (the scan, then the narrow flag of the count-1 part).
 void launch_split(const uint64_t* rows, uint64_t n, Layout S, Layout R, uint32_t* counts, uint64_t* tiles,
                   uint64_t* offs, uint64_t* out, uint64_t end_words, hipStream_t st) {
     const uint64_t nb = split_blocks(n);
     if (!nb) return;
-    hipLaunchKernelGGL(k_split_count, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, counts);
+    // offs[nb + 1] (beyond the scan's entries) holds the narrow flag
+    launch_fill(offs + nb + 1, 1, 1, st);
+    hipLaunchKernelGGL(k_split_count, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, counts, offs + nb + 1);
     launch_scan(counts, nb, tiles, offs, st);
     hipLaunchKernelGGL(k_split_write, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, R, offs, nb, out, end_words);
 }

@@ -215,6 +215,34 @@ def test_spilling_with_extreme_keys(ctx):
     assert st["runs"] == sim["runs"] and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
 
 
+@pytest.mark.parametrize("aggs", [isa.ISA_ALL, isa.ISA_INT_AGGS, isa.ISA_COUNT | isa.ISA_SUM_F64,
+                                  isa.ISA_COUNT | isa.ISA_MIN_I64])
+def test_spilling_count1_value_widths(ctx, aggs):
+    # a run's count-1 rows keep their integer values in 4 bytes when all of
+    # them fit in 32 bits: the early batches hold only such values (the 32-bit
+    # limits included), the later ones also values just outside them, so runs
+    # of both widths meet in the wide merge
+    say("case spill count-1 widths aggs=%d" % aggs)
+    n = 1_200_000
+    rng = np.random.default_rng(41)
+    k, v, f = datagen.plain_input(42, n, 400_000, 0.5, with_f64=True)
+    v = v.copy()
+    lim = np.array([-(1 << 31), (1 << 31) - 1], np.int64)
+    early = rng.random(n) < 0.05
+    early[n * 3 // 5:] = False
+    v[early] = lim[rng.integers(0, 2, int(early.sum()))]
+    late = rng.random(n) < 0.05
+    late[:n * 3 // 5] = False
+    out = np.array([-(1 << 31) - 1, 1 << 31, -(1 << 40), 1 << 40], np.int64)
+    v[late] = out[rng.integers(0, 4, int(late.sum()))]
+    vv = v if aggs & (isa.ISA_SUM_I64 | isa.ISA_MIN_I64 | isa.ISA_MAX_I64) else None
+    ff = f if aggs & isa.ISA_SUM_F64 else None
+    got, st, status, g = run_gpu(ctx, k, vv, ff, aggs=aggs, budget=16 << 20)
+    assert status == isa.ISA_OK
+    assert st["runs"] > 1
+    compare(got, k, vv, ff, aggs, "count-1 widths")
+
+
 def test_wide_merge_second_pass(ctx, monkeypatch):
     # the wide merge places every window's groups after a device-side cursor
     # and falls back to a host-paced second pass when a window's flat plan

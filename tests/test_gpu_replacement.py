@@ -79,17 +79,23 @@ def test_replacement_aggregate_subsets(ctx, aggs):
     check_sim(k, st)
 
 
-def test_replacement_small_workspace_spills_the_final_index(ctx):
+@pytest.mark.parametrize("force", ["0", "1"])
+def test_replacement_small_workspace_spills_the_final_index(ctx, monkeypatch, force):
     # the final index stays full under replacement selection; when the rest
     # of a small workspace cannot stage a wide merge beside it, the index is
     # written out as one more run and the merge reads host memory alone
-    say("case replacement small workspace")
+    # (ISA_FORCE_INDEX_SPILL=1 takes that path whatever the room)
+    say("case replacement small workspace force=%s" % force)
+    monkeypatch.setenv("ISA_FORCE_INDEX_SPILL", force)
     k, v, f = datagen.plain_input(43, 900_000, 300_000, 0.3, with_f64=True)
     got, st, status, g = run_gpu(ctx, k, v, f, aggs=isa.ISA_SUM_F64, budget=14 << 20)
     compare(got, k, v, f, isa.ISA_SUM_F64, "small")
     sim = spillsim.simulate_replacement(k, st["batch_rows"], st["index_capacity"])
-    assert st["runs"] == sim["runs"] + 1
-    assert st["spilled_rows"] == sim["spilled_rows"] + sim["final_index_rows"]
+    extra = 1 if st["runs"] == sim["runs"] + 1 else 0
+    if force == "1":
+        assert extra == 1
+    assert st["runs"] == sim["runs"] + extra
+    assert st["spilled_rows"] == sim["spilled_rows"] + extra * sim["final_index_rows"]
 
 
 def test_replacement_same_output_as_read_sort_write(ctx):
