@@ -717,7 +717,6 @@ bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, co
     uint64_t* d_spl = fixed ? (uint64_t*)hint->dev : A.take_n<uint64_t>(std::max<size_t>(1, regs.size()) * (MAX_BUCKETS - 1));
     uint32_t* d_hist = A.take_n<uint32_t>(hist_total + 1);
     uint64_t* d_offs = A.take_n<uint64_t>(hist_total + 1);
-    uint64_t* d_tiles = A.take_n<uint64_t>(scan_tiles(hist_total) + 1);
     uint64_t* d_ctl = A.take_n<uint64_t>(1 + dests.size() + slots.size());
     uint64_t* d_totals = ext_totals ? ext_totals : d_ctl + 1;
     uint64_t* d_status = d_ctl + 1 + dests.size();
@@ -750,9 +749,11 @@ bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, co
             E.pbegin("k_hist", st);
             launch_hist(d_regs, d_chunks, (uint32_t)chunks.size(), d_spl, d_hist, st);
             E.pend(rows, rows * 8, st);
-            launch_scan(d_hist, hist_total, d_tiles, d_offs, st);
+            // no scan launch: a region of the flat plan has at most FLAT_MAX
+            // rows, so every scatter workgroup sums its region's histogram
+            // itself and writes its chunk's region-relative offsets
             E.pbegin("k_scatter", st);
-            launch_scatter(d_regs, d_chunks, (uint32_t)chunks.size(), d_spl, d_offs, part, L, st);
+            launch_scatter(d_regs, d_chunks, (uint32_t)chunks.size(), d_spl, d_offs, part, L, st, d_hist, d_offs);
             E.pend(rows, rows * (uint64_t)L.words * 8, st);
         }
         E.pbegin("k_leaf", st);

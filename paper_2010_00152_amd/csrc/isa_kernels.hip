@@ -468,9 +468,10 @@ __global__ void __launch_bounds__(PART_NT) k_scatter(const Region* __restrict__ 
     for (int i = tid; i < MAX_BUCKETS; i += NT)
         s_spl[i] = i < MAX_BUCKETS - 1 ? splitters[(uint64_t)C.region * (MAX_BUCKETS - 1) + i] : ~0ull;
     if (hist_self) {
-        // one region and no separate scan: thread b sums bucket b over all
-        // chunks and over the chunks before this one; a scan over buckets
-        // gives the bucket starts.  The offsets go to offs_out for the leaves.
+        // no separate scan: thread b sums bucket b over all chunks of the
+        // region and over its chunks before this one; a scan over buckets
+        // gives the bucket starts.  The region-relative offsets go to
+        // offs_out for the leaves.
         uint32_t tot = 0, before = 0;
         if (tid < (int)R.nb) {
             const uint32_t* hb = hist_self + R.hist_base + (uint64_t)tid * R.n_chunks;
