@@ -2101,9 +2101,13 @@ void launch_hist(const Region* regions, const Chunk* chunks, uint32_t n_chunks, 
 void launch_scatter(const Region* regions, const Chunk* chunks, uint32_t n_chunks, const uint64_t* splitters,
                     const uint64_t* offs, uint64_t* dst, Layout L, hipStream_t st, const uint32_t* hist_self,
                     uint64_t* offs_out) {
-    // narrow rows: tiles of 2048 rows staged in LDS (48 KB, two workgroups per CU)
+    // rows of up to 3 words: tiles of 2048 rows staged in LDS; up to 6 words
+    // (state rows): tiles of 1024 rows (48 KB either way, two workgroups per CU)
     if (L.words <= 3)
         hipLaunchKernelGGL((k_scatter<3, PART_IPT / 2>), dim3(n_chunks), dim3(PART_NT), 0, st, regions, chunks,
+                           splitters, offs, dst, L, hist_self, offs_out);
+    else if (L.words <= 6)
+        hipLaunchKernelGGL((k_scatter<6, PART_IPT / 4>), dim3(n_chunks), dim3(PART_NT), 0, st, regions, chunks,
                            splitters, offs, dst, L, hist_self, offs_out);
     else
         hipLaunchKernelGGL((k_scatter<0, PART_IPT>), dim3(n_chunks), dim3(PART_NT), 0, st, regions, chunks,
