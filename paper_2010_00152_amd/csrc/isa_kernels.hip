@@ -358,14 +358,26 @@ __global__ void __launch_bounds__(LEAF_NT) k_sample(const Region* __restrict__ r
         s_spl[i] = s.key[pad16((int)q)] + mn;
     }
     __syncthreads();
-    if (tid == 0) {
-        for (uint32_t i = 1; i + 1 < nb; ++i) {
-            if (s_spl[i] <= s_spl[i - 1]) s_spl[i] = s_spl[i - 1] == ~0ull ? ~0ull : s_spl[i - 1] + 1;
+    // Strictly increasing splitters: t[i] = max(s[i], t[i-1] + 1), saturating
+    // at the largest key value, which is t[i] = max over j <= i of
+    // s[j] + (i - j); a doubling scan over the nb-1 splitters (one per thread)
+    // computes it in log2(nb) steps.
+    {
+        static_assert(MAX_BUCKETS <= NT, "one splitter per thread");
+        const int m = (int)nb - 1;
+        uint64_t t = tid < m ? s_spl[tid] : 0;
+        for (int d = 1; d < m; d <<= 1) {
+            const uint64_t prev = tid >= d && tid < m ? s_spl[tid - d] : 0;
+            __syncthreads();
+            if (tid >= d && tid < m) {
+                const uint64_t c = prev + (uint64_t)d;
+                const uint64_t sat = c < prev ? ~0ull : c;
+                t = sat > t ? sat : t;
+                s_spl[tid] = t;
+            }
+            __syncthreads();
         }
-        // a heavy key that is the first splitter: isolate it from below too
-        // (keys below it form bucket 0, the key itself bucket 1)
     }
-    __syncthreads();
     uint64_t* out = splitters + (uint64_t)blockIdx.x * (MAX_BUCKETS - 1);
     for (int i = tid; i < MAX_BUCKETS - 1; i += NT) out[i] = i < (int)nb - 1 ? s_spl[i] : ~0ull;
 }
