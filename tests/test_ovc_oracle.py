@@ -1,0 +1,98 @@
+"""Pins for the offset-value-code oracle: the paper's worked table, the
+ordering property of codes against a common base (brute force over a small
+domain), the property that lets a merge keep a loser's code, and duplicate
+removal against numpy's unique rows."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ovc
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "ovc_table.txt")
+
+
+def _golden():
+    rows = []
+    for line in open(GOLDEN):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append([int(x) for x in line.split()])
+    return np.array(rows, dtype=np.int64)
+
+
+def test_paper_table():
+    g = _golden()
+    rows, offs, desc, asc = g[:, :4], g[:, 4], g[:, 5], g[:, 6]
+    d, a = ovc.stream_codes(rows, domain=100)
+    assert np.array_equal(d, desc)
+    assert np.array_equal(a, asc)
+    got_offs = [0] + [ovc.offset_of(rows[i], rows[i - 1]) for i in range(1, len(rows))]
+    assert got_offs == list(offs)
+
+
+def _lex_gt(x, y):
+    return tuple(x) > tuple(y)
+
+
+# all rows of 3 columns over values 0..3
+DOMAIN, K = 4, 3
+ALL = [tuple(r) for r in itertools.product(range(DOMAIN), repeat=K)]
+
+
+def test_codes_order_rows_coded_against_one_base():
+    # for x, y >= base: a larger ascending code (a smaller descending code)
+    # means a larger row; equal codes leave the rows undecided only when they
+    # agree up to and including the column the codes describe
+    for b in ALL:
+        above = [r for r in ALL if r >= b]
+        codes = {r: ovc.code_pair(r, b, DOMAIN) for r in above}
+        for x in above:
+            dx, ax = codes[x]
+            for y in above:
+                dy, ay = codes[y]
+                if ax > ay:
+                    assert _lex_gt(x, y), (b, x, y)
+                if dx < dy:
+                    assert _lex_gt(x, y), (b, x, y)
+                assert (ax == ay) == (dx == dy)
+                if ax == ay:
+                    off = ovc.offset_of(x, b)
+                    assert off == ovc.offset_of(y, b)
+                    assert x[:off + 1] == y[:off + 1]
+
+
+def test_loser_keeps_its_code():
+    # two rows coded against one base: the smaller one (the winner of an
+    # ascending merge) has the smaller ascending code, and the larger one's
+    # code against the winner equals its code against the base
+    for b in ALL:
+        above = [r for r in ALL if r >= b]
+        for x in above:
+            ax = ovc.code_pair(x, b, DOMAIN)[1]
+            for y in above:
+                ay = ovc.code_pair(y, b, DOMAIN)[1]
+                if ay < ax:
+                    assert ovc.code_pair(x, y, DOMAIN)[1] == ax, (b, x, y)
+
+
+def test_first_row_and_duplicates():
+    d, a = ovc.stream_codes([(0, 0, 0), (0, 0, 0), (0, 0, 1)], domain=DOMAIN)
+    assert list(a) == [K * DOMAIN + 0, 0, 1 * DOMAIN + 1]
+    assert list(d) == [DOMAIN, K * DOMAIN, 2 * DOMAIN + DOMAIN - 1]
+
+
+@pytest.mark.parametrize("n,k,dom,seed", [(0, 3, 5, 0), (1, 2, 3, 1), (500, 3, 4, 2), (2000, 5, 3, 3),
+                                          (3000, 2, 100, 4)])
+def test_distinct_rows_match_numpy(n, k, dom, seed):
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, dom, size=(n, k), dtype=np.int64)
+    u, c = ovc.distinct_rows(rows, dom)
+    if n == 0:
+        assert u.shape[0] == 0 and c.shape[0] == 0
+        return
+    ref_u, ref_c = np.unique(rows, axis=0, return_counts=True)
+    assert np.array_equal(u, ref_u)
+    assert np.array_equal(c, ref_c)
+    assert c.sum() == n
