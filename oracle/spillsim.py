@@ -102,3 +102,33 @@ def simulate_replacement(keys, batch_rows: int, capacity: int):
         run_sizes.append(open_rows)
     return {"runs": len(run_sizes), "spilled_rows": int(sum(run_sizes)),
             "run_sizes": run_sizes, "final_index_rows": int(index.shape[0])}
+
+
+def preliminary_merges(run_rows, fan_in: int, out_bound: float):
+    """Traditional merge steps that bring the run count down to the fan-in of
+    a final merge (Section 4, Example 4 and its note on the merge steps;
+    Section 4.4: such steps precede a wide merge that cannot absorb all runs).
+
+    Each step merges the smallest runs.  The first step takes just enough runs
+    that every later step can merge a full fan-in and the last one leaves
+    exactly ``fan_in`` runs: with n runs it merges (n - fan_in) mod
+    (fan_in - 1) + 1 of them when that remainder is nonzero.  Aggregation
+    within a merge bounds a step's output by the final output size
+    ``out_bound``.  Returns the run count after each step and the rows the
+    steps write (their spill volume beyond the initial runs)."""
+    runs = sorted(float(r) for r in run_rows)
+    counts = [len(runs)]
+    written = 0.0
+    F = int(fan_in)
+    if F < 2:
+        raise ValueError("fan-in below 2")
+    first = True
+    while len(runs) > F:
+        extra = (len(runs) - F) % (F - 1)
+        take = extra + 1 if first and extra else F
+        first = False
+        merged = min(sum(runs[:take]), float(out_bound))
+        runs = sorted(runs[take:] + [merged])
+        written += merged
+        counts.append(len(runs))
+    return {"counts": counts, "written_rows": written, "final_runs": runs}

@@ -152,3 +152,26 @@ def test_replacement_no_spill_when_output_fits_and_never_more_runs():
     rw = spillsim.simulate(keys, 256, 2048)
     assert rs["runs"] <= rw["runs"] and rs["final_index_rows"] == 2048
     assert rs["spilled_rows"] <= keys.shape[0]
+
+
+def test_preliminary_merges_example_4():
+    # Section 4, Example 4: 500 runs of about 200,000 rows, fan-in 100, final
+    # output 8,000,000 rows: the steps leave 496, 397, 298, 199 and 100 runs,
+    # and the total spill volume is I + 1,000,000 + 4 x 8,000,000
+    r = spillsim.preliminary_merges([200_000] * 500, 100, 8_000_000)
+    assert r["counts"] == [500, 496, 397, 298, 199, 100]
+    assert 100_000_000 + r["written_rows"] == 133_000_000
+
+
+@pytest.mark.parametrize("n,F", [(1, 2), (7, 7), (8, 7), (13, 7), (100, 2), (376, 6), (1000, 100)])
+def test_preliminary_merges_step_count(n, F):
+    # ceil((n - F) / (F - 1)) steps, ending at exactly F runs (n > F), each
+    # step after the first merging a full fan-in
+    r = spillsim.preliminary_merges([1.0] * n, F, float("inf"))
+    steps = max(0, -(-(n - F) // (F - 1)))
+    assert len(r["counts"]) - 1 == steps
+    assert r["counts"][-1] == (F if n > F else n)
+    drops = [a - b for a, b in zip(r["counts"], r["counts"][1:])]
+    assert all(d == F - 1 for d in drops[1:])
+    # without an output bound the rows are conserved
+    assert sum(r["final_runs"]) == n
