@@ -219,7 +219,8 @@ uint64_t isa_batch_workspace_bytes(uint32_t n_inst, const isa_input* inst, uint3
  * Run generation policy of isa_group_by when the index fills (Section 3: an
  * ordered in-memory index supports both; the choice is the implementer's).
  *  ISA_RUNGEN_READ_SORT_WRITE (default): the whole index is written as one run
- *    (count-1 rows compacted to raw rows) and emptied.
+ *    (count-1 rows compacted to raw columns, integer values in 4 bytes when
+ *    all of the run's fit) and emptied.
  *  ISA_RUNGEN_REPLACEMENT: replacement selection through the index.  A scan
  *    cursor moves through the index in key order; when an absorbed batch makes
  *    the index exceed its capacity, the excess rows at or after the cursor are
