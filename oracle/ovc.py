@@ -77,3 +77,23 @@ def distinct_rows(rows, domain: int):
     heads = np.flatnonzero(asc != 0)
     counts = np.diff(np.append(heads, srt.shape[0]))
     return srt[heads], counts
+
+
+def group_rows(rows, values, domain: int):
+    """Grouping on a multi-column key with count(*) and sum of an int64 value:
+    sort on all key columns, then one in-stream pass in which a nonzero
+    ascending code against the predecessor starts a group (in-stream grouping
+    of sorted input, Section 2.1, decided by offset-value codes).  Returns
+    (group keys, counts, sums); sums wrap modulo 2^64 like int64 addition."""
+    rows = np.asarray(rows, dtype=np.int64)
+    values = np.asarray(values, dtype=np.int64)
+    if rows.shape[0] == 0:
+        return rows, np.zeros(0, np.int64), np.zeros(0, np.int64)
+    order = np.lexsort(rows.T[::-1])
+    srt, val = rows[order], values[order]
+    _, asc = stream_codes(srt, domain)
+    heads = np.flatnonzero(asc != 0)
+    counts = np.diff(np.append(heads, srt.shape[0]))
+    with np.errstate(over="ignore"):
+        sums = np.add.reduceat(val, heads)
+    return srt[heads], counts, sums

@@ -96,3 +96,19 @@ def test_distinct_rows_match_numpy(n, k, dom, seed):
     assert np.array_equal(u, ref_u)
     assert np.array_equal(c, ref_c)
     assert c.sum() == n
+
+
+@pytest.mark.parametrize("n,k,dom,seed", [(1, 3, 4, 5), (800, 3, 4, 6), (2000, 4, 3, 7)])
+def test_group_rows_match_brute_force(n, k, dom, seed):
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, dom, size=(n, k), dtype=np.int64)
+    vals = rng.integers(-(1 << 62), 1 << 62, size=n, dtype=np.int64)
+    keys, cnt, sums = ovc.group_rows(rows, vals, dom)
+    ref = {}
+    for r, v in zip(map(tuple, rows.tolist()), vals.tolist()):
+        c, s = ref.get(r, (0, 0))
+        ref[r] = (c + 1, (s + v + (1 << 63)) % (1 << 64) - (1 << 63))
+    want = sorted(ref)
+    assert [tuple(x) for x in keys.tolist()] == want
+    assert cnt.tolist() == [ref[r][0] for r in want]
+    assert sums.tolist() == [ref[r][1] for r in want]
