@@ -1038,7 +1038,6 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 }
                 const int tgt = merge_target();
                 guard(tgt, (n_idx + g) * sw * 8);
-                const uint64_t parts = merge_parts(n_idx, g);
                 ck(hipStreamWaitEvent(E.stream, ev_sort(i), 0), "hipStreamWaitEvent");
                 uint64_t* m_ctl = m_ctl2[i % 2];
                 E.pbegin("k_merge");

@@ -406,7 +406,6 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
                                   const std::vector<Dest>& dests, const Cols& k, bool state_rows,
                                   const SplitterHint* hint) {
     const Layout L = state_rows ? state_layout(k) : raw_layout(k);
-    const Layout S = state_layout(k);
     // bytes of one source row as the caller's columns hold it
     const uint64_t src_row_bytes = (uint64_t)L.words * 8;
     std::vector<uint64_t> totals(dests.size(), 0);
