@@ -97,3 +97,88 @@ def group_rows(rows, values, domain: int):
     with np.errstate(over="ignore"):
         sums = np.add.reduceat(val, heads)
     return srt[heads], counts, sums
+
+
+def merge_runs(runs, domain: int):
+    """Merge sorted runs of K-column rows with a tree-of-losers priority queue
+    whose comparisons use offset-value codes (Section 2: tree-of-losers
+    priority queues and offset-value coding; Section 5: column accesses).
+
+    Every row enters with its ascending code against its run predecessor (a
+    run's first row against a base below every row: offset 0).  All codes
+    compared at a node are relative to the same row, the last one output, so
+    unequal codes decide a comparison alone; equal codes continue with the
+    columns after their offset, and the loser's code is recomputed from the
+    first differing column.  Returns (output rows, their codes against their
+    output predecessors, column comparisons made)."""
+    runs = [[tuple(int(x) for x in r) for r in run] for run in runs]
+    runs = [r for r in runs if r]
+    if not runs:
+        return [], [], 0
+    K = len(runs[0][0])
+    INF = None  # an exhausted input: loses to every row
+    k = 1
+    while k < len(runs):
+        k *= 2
+    pos = [0] * k
+    cur = [None] * k
+    code = [INF] * k
+    for i, run in enumerate(runs):
+        cur[i] = run[0]
+        code[i] = K * domain + run[0][0] if K else 0
+    comparisons = 0
+
+    def play(a, b):
+        """Winner and loser of inputs a, b (codes against one base); updates
+        the loser's code against the winner."""
+        nonlocal comparisons
+        ca, cb = code[a], code[b]
+        if ca is INF:
+            return b, a
+        if cb is INF:
+            return a, b
+        if ca != cb:
+            return (a, b) if ca < cb else (b, a)
+        off = K - ca // domain if ca else K
+        for c in range(off + 1, K):
+            comparisons += 1
+            if cur[a][c] != cur[b][c]:
+                w, l = (a, b) if cur[a][c] < cur[b][c] else (b, a)
+                code[l] = (K - c) * domain + cur[l][c]
+                return w, l
+        w, l = (a, b) if a < b else (b, a)
+        code[l] = 0
+        return w, l
+
+    # tree[1..k-1]: losers at internal nodes; leaves k..2k-1 are the inputs
+    tree = [0] * k
+    win = [0] * (2 * k)
+    for i in range(k):
+        win[k + i] = i
+    for n in range(k - 1, 0, -1):
+        w, l = play(win[2 * n], win[2 * n + 1])
+        win[n], tree[n] = w, l
+    champion = win[1] if k > 1 else 0
+    out, out_codes = [], []
+    while code[champion] is not INF:
+        w = champion
+        out.append(cur[w])
+        out_codes.append(code[w])
+        run = runs[w]
+        pos[w] += 1
+        if pos[w] < len(run):
+            prev, row = run[pos[w] - 1], run[pos[w]]
+            cur[w] = row
+            code[w] = code_pair(row, prev, domain)[1]
+        else:
+            cur[w], code[w] = None, INF
+        # replay from the leaf to the root against the stored losers
+        cand = w
+        n = (k + w) // 2
+        while n >= 1:
+            wn, ln = play(cand, tree[n])
+            tree[n] = ln
+            cand = wn
+            n //= 2
+        champion = cand
+    return out, out_codes, comparisons

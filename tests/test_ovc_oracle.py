@@ -112,3 +112,38 @@ def test_group_rows_match_brute_force(n, k, dom, seed):
     assert [tuple(x) for x in keys.tolist()] == want
     assert cnt.tolist() == [ref[r][0] for r in want]
     assert sums.tolist() == [ref[r][1] for r in want]
+
+
+def _runs(rng, n_runs, k, dom, max_len):
+    return [sorted(map(tuple, rng.integers(0, dom, size=(int(rng.integers(0, max_len + 1)), k)).tolist()))
+            for _ in range(n_runs)]
+
+
+@pytest.mark.parametrize("n_runs,k,dom,seed", [(1, 3, 3, 0), (2, 4, 2, 1), (3, 2, 5, 2), (5, 4, 3, 3),
+                                               (8, 3, 4, 4), (13, 5, 2, 5), (6, 1, 7, 6)])
+def test_tree_of_losers_merge_with_codes(n_runs, k, dom, seed):
+    # the merge outputs every row in order, the codes it carries out are the
+    # output stream's own codes, and it compares at most N x K column values
+    # (Section 5: offset-value codes bound column comparisons by rows times
+    # columns)
+    rng = np.random.default_rng(seed)
+    for _ in range(20):
+        runs = _runs(rng, n_runs, k, dom, 40)
+        out, codes, cmp = ovc.merge_runs(runs, dom)
+        rows = sorted(r for run in runs for r in run)
+        assert out == rows
+        if rows:
+            assert list(codes) == list(ovc.stream_codes(out, dom)[1])
+        assert cmp <= len(rows) * k
+
+
+def test_merge_with_unique_leading_column_reads_no_other_column():
+    # Section 5's first extreme case: when the first column is unique, codes
+    # decide every comparison and no further column is compared
+    rng = np.random.default_rng(9)
+    lead = rng.permutation(600)
+    rows = [(int(a),) + tuple(int(x) for x in rng.integers(0, 5, 3)) for a in lead]
+    runs = [sorted(rows[i::7]) for i in range(7)]
+    out, codes, cmp = ovc.merge_runs(runs, 600)
+    assert out == sorted(rows)
+    assert cmp == 0
