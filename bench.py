@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+LINK_PEAK_GBS = 64.0   # host link: PCIe 5.0 x16, published rate per direction
 
 WORKLOADS = {
     # name: (rows, distinct domain, zipf s, seed, budget MiB, with f64, aggs name)
@@ -318,6 +319,20 @@ KERNELS_OF_LABEL = {"k_leaf": ["k_leaf_flat", "k_leaf"], "k_merge": ["k_merge"],
                     "k_hist": ["k_hist"], "k_sample": ["k_sample", "k_sample_keys"]}
 
 
+def link_summary(spilled_bytes, link_ms, ms_per_step):
+    """Host-link figures of a spilling step: runs go out during run generation
+    and come back during the wide merge, which starts only once every run is
+    written, so the step's link floor is both volumes at the link's peak."""
+    hb = 2 * spilled_bytes
+    gbs = hb / (link_ms * 1e-3) / 1e9 if link_ms else None
+    floor_ms = hb / (LINK_PEAK_GBS * 1e9) * 1e3
+    return {"bytes_per_step": hb, "copy_ms_per_step": round(link_ms, 2),
+            "GBps": round(gbs, 1) if gbs else None, "peak_GBps": LINK_PEAK_GBS,
+            "frac": round(gbs / LINK_PEAK_GBS, 3) if gbs else None,
+            "floor_ms_per_step": round(floor_ms, 2),
+            "step_frac_of_floor": round(floor_ms / ms_per_step, 3) if ms_per_step else None}
+
+
 def hbm_traffic(workload, label):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) of the kernels
     behind a profile label, from profiles/hbm_traffic.json; None when the
@@ -500,10 +515,8 @@ def main():
 
     host_link = None
     if stats["spilled_rows"]:
-        hb = 2 * stats["spilled_bytes"]
         hl_ms = sum(prof[k]["total_ms"] for k in ("spill_d2h", "merge_h2d") if k in prof) / max(1, prof_steps)
-        host_link = {"bytes_per_step": hb, "copy_ms_per_step": round(hl_ms, 2),
-                     "GBps": round(hb / (hl_ms * 1e-3) / 1e9, 1) if hl_ms else None}
+        host_link = link_summary(stats["spilled_bytes"], hl_ms, ms_per_step)
 
     cpu = None
     if args.cpu_sample:
