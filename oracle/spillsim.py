@@ -132,3 +132,40 @@ def preliminary_merges(run_rows, fan_in: int, out_bound: float):
         written += merged
         counts.append(len(runs))
     return {"counts": counts, "written_rows": written, "final_runs": runs}
+
+
+def hybrid_plan(I: float, M: float, O: float, F: int, P: float = None):
+    """Hybrid run generation (Section 5, hybrid algorithms): the smallest
+    fan-out f with O <= f*M + (1 - f/F)*M, i.e. f = ceil((O - M)/(M - P)),
+    gives the memory fraction f/F to run generation and the rest to an
+    in-memory index that absorbs (1 - f/F)*M of the output, i.e. that share
+    of the input.  Runs of read-sort-write cycles hold f/F*M rows.  Returns
+    f, the output fraction the index absorbs, the spilled rows, the run
+    count, and whether one wide merge suffices (O <= F*M).  P defaults to
+    M/F (pages per memory load equal to the fan-in)."""
+    import math
+    if P is None:
+        P = M / F
+    f = max(0, math.ceil((O - M) / (M - P))) if O > M else 0
+    f = min(f, F)
+    index_out = (1.0 - f / F) * M
+    absorbed = min(1.0, index_out / O)
+    spilled = (1.0 - absorbed) * I
+    run_rows = f / F * M
+    runs = spilled / run_rows if run_rows else 0.0
+    return {"f": f, "index_output_fraction": absorbed, "spilled_rows": spilled, "run_rows": run_rows,
+            "runs": runs, "single_wide_merge": O <= F * M}
+
+
+def traditional_levels(n_runs: int, F: int):
+    """Level-wise traditional merging of n equal runs with fan-in F: merge
+    levels and merge steps until one run remains (Section 5's hybrid example:
+    1,000 runs at fan-in 10 take three levels and 111 steps)."""
+    levels = steps = 0
+    n = int(n_runs)
+    while n > 1:
+        m = -(-n // F)
+        steps += m
+        n = m
+        levels += 1
+    return levels, steps

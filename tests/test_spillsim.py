@@ -175,3 +175,30 @@ def test_preliminary_merges_step_count(n, F):
     assert all(d == F - 1 for d in drops[1:])
     # without an output bound the rows are conserved
     assert sum(r["final_runs"]) == n
+
+
+def test_hybrid_plan_example():
+    # Section 5's hybrid example: I = 275 M, F = 10, O = 2.75 M: f = 2, the
+    # index holds 8/10 of memory and absorbs about 3/11 of the output, runs
+    # store about 200 M rows in about 1,000 runs of 0.2 M, and one wide merge
+    # suffices (O <= F M) where traditional merging needs 3 levels, 111 steps
+    M = 100_000.0
+    h = spillsim.hybrid_plan(275 * M, M, 2.75 * M, 10)
+    assert h["f"] == 2
+    assert abs(h["index_output_fraction"] - 0.8 / 2.75) < 1e-12
+    # exactly 0.8/2.75 of the output: 195 M rows spill in 975 runs; the
+    # paper rounds the fraction to 3/11, which gives its 200 M and 1,000
+    assert abs(h["spilled_rows"] / M - 195.0) < 1e-6
+    assert abs(h["run_rows"] - 0.2 * M) < 1e-9
+    assert abs(h["runs"] - 975.0) < 1e-6
+    assert abs(275 * (1 - 3 / 11) - 200.0) < 1e-9
+    assert abs(275 * (1 - 3 / 11) * M / h["run_rows"] - 1000.0) < 1e-6
+    assert h["single_wide_merge"]
+    assert spillsim.traditional_levels(1000, 10) == (3, 111)
+
+
+@pytest.mark.parametrize("O_over_M", [0.5, 1.0])
+def test_hybrid_plan_in_memory_case(O_over_M):
+    # O <= M: no fan-out, nothing spills
+    h = spillsim.hybrid_plan(1e9, 1e5, O_over_M * 1e5, 10)
+    assert h["f"] == 0 and h["spilled_rows"] == 0.0 and h["runs"] == 0.0
