@@ -32,10 +32,13 @@
  * Pair keys (grouping on two int32 columns A, B): the output is ordered
  * lexicographically on (A, B) with both compared as signed 32-bit integers.
  */
+#define _POSIX_C_SOURCE 200809L
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <pthread.h>
+#include <unistd.h>
 
 /* ------------------------------------------------------------------------ */
 /* Exact fp64 summation: a long fixed-point accumulator (Kulisch's exact     */
@@ -243,17 +246,15 @@ static void group_emit(const group_state* g, uint64_t o, uint64_t* out_count,
 }
 
 /*
- * Group n rows on a uint64 key.  v_i64 and v_f64 may be NULL (then the
- * aggregates over them are not produced).  Output pointers may be NULL to skip
- * a column; every non-NULL output array must hold at least the number of
- * distinct keys (n is always enough).  Returns the number of groups.
+ * In-stream aggregation of rows taken in the order idx[0..n) (sorted on the
+ * key): every row either continues the group of its predecessor or opens a
+ * new one.  Returns the number of groups written.
  */
-uint64_t oracle_group_by(uint64_t n, const uint64_t* keys, const int64_t* v_i64,
-                         const double* v_f64, uint64_t* out_keys, uint64_t* out_count,
-                         int64_t* out_sum, double* out_fsum, int64_t* out_min,
-                         int64_t* out_max) {
+static uint64_t group_scan(const uint64_t* idx, uint64_t n, const uint64_t* keys,
+                           const int64_t* v_i64, const double* v_f64, uint64_t* out_keys,
+                           uint64_t* out_count, int64_t* out_sum, double* out_fsum,
+                           int64_t* out_min, int64_t* out_max) {
     if (n == 0) return 0;
-    uint64_t* idx = sorted_row_order(n, key_less, keys);
     group_state g;
     g.fsum = (exact_acc*)malloc(sizeof(exact_acc));
     uint64_t groups = 0;
@@ -273,7 +274,156 @@ uint64_t oracle_group_by(uint64_t n, const uint64_t* keys, const int64_t* v_i64,
     group_emit(&g, groups, out_count, out_sum, v_f64 ? out_fsum : NULL, out_min, out_max);
     groups++;
     free(g.fsum);
+    return groups;
+}
+
+/*
+ * Group n rows on a uint64 key.  v_i64 and v_f64 may be NULL (then the
+ * aggregates over them are not produced).  Output pointers may be NULL to skip
+ * a column; every non-NULL output array must hold at least the number of
+ * distinct keys (n is always enough).  Returns the number of groups.
+ */
+uint64_t oracle_group_by(uint64_t n, const uint64_t* keys, const int64_t* v_i64,
+                         const double* v_f64, uint64_t* out_keys, uint64_t* out_count,
+                         int64_t* out_sum, double* out_fsum, int64_t* out_min,
+                         int64_t* out_max) {
+    if (n == 0) return 0;
+    uint64_t* idx = sorted_row_order(n, key_less, keys);
+    uint64_t groups = group_scan(idx, n, keys, v_i64, v_f64, out_keys, out_count, out_sum,
+                                 out_fsum, out_min, out_max);
     free(idx);
+    return groups;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same plan on several host threads: the key space is cut into ranges  */
+/* at splitters drawn from a sample of the keys, the rows of each range are   */
+/* collected in input order, and each thread sorts and scans one range.     */
+/* Every group lies in one range and the ranges are concatenated in key      */
+/* order, so the result is the single-threaded one, bit for bit.             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const uint64_t* keys;
+    const int64_t* v;
+    const double* f;
+    uint64_t* rows;   /* the range's row ids, in input order; sorted in place */
+    uint64_t n;
+    uint64_t* ok;
+    uint64_t* oc;
+    int64_t* os;
+    double* of;
+    int64_t* omn;
+    int64_t* omx;
+    uint64_t groups;
+} range_job;
+
+static void* range_worker(void* arg) {
+    range_job* j = (range_job*)arg;
+    if (j->n) {
+        uint64_t* tmp = (uint64_t*)malloc(j->n * sizeof(uint64_t));
+        merge_sort_rec(j->rows, tmp, 0, j->n, key_less, j->keys);
+        free(tmp);
+    }
+    j->groups = group_scan(j->rows, j->n, j->keys, j->v, j->f, j->ok, j->oc, j->os, j->of,
+                           j->omn, j->omx);
+    return NULL;
+}
+
+static int u64_cmp(const void* a, const void* b) {
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : x > y;
+}
+
+int oracle_nproc(void) {
+    long p = sysconf(_SC_NPROCESSORS_ONLN);
+    return p > 0 ? (int)p : 1;
+}
+
+#define MAX_RANGES 256
+
+uint64_t oracle_group_by_parallel(uint64_t n, const uint64_t* keys, const int64_t* v_i64,
+                                  const double* v_f64, uint64_t* out_keys, uint64_t* out_count,
+                                  int64_t* out_sum, double* out_fsum, int64_t* out_min,
+                                  int64_t* out_max, int threads) {
+    if (n == 0) return 0;
+    if (threads <= 0) threads = oracle_nproc();
+    if (threads > MAX_RANGES) threads = MAX_RANGES;
+    /* splitters: equally spaced order statistics of a strided key sample,
+     * duplicates dropped; range r holds keys in [spl[r-1], spl[r]) */
+    uint64_t ns = (uint64_t)threads * 64;
+    if (ns > n) ns = n;
+    uint64_t* sample = (uint64_t*)malloc(ns * sizeof(uint64_t));
+    for (uint64_t i = 0; i < ns; ++i) sample[i] = keys[i * (n / ns)];
+    qsort(sample, ns, sizeof(uint64_t), u64_cmp);
+    uint64_t spl[MAX_RANGES];
+    int nspl = 0;
+    for (int r = 1; r < threads; ++r) {
+        uint64_t x = sample[(uint64_t)r * ns / (uint64_t)threads];
+        if (nspl == 0 || x > spl[nspl - 1]) spl[nspl++] = x;
+    }
+    free(sample);
+    const int nr = nspl + 1;
+    /* range of every row (count of splitters <= key), then a stable scatter */
+    uint8_t* rid = (uint8_t*)malloc(n);
+    uint64_t cnt[MAX_RANGES + 1];
+    memset(cnt, 0, sizeof(cnt));
+    for (uint64_t i = 0; i < n; ++i) {
+        int lo = 0, hi = nspl;
+        while (lo < hi) {
+            int mid = (lo + hi) / 2;
+            if (spl[mid] <= keys[i]) lo = mid + 1;
+            else hi = mid;
+        }
+        rid[i] = (uint8_t)lo;
+        cnt[lo]++;
+    }
+    uint64_t start[MAX_RANGES + 1], fill[MAX_RANGES];
+    start[0] = 0;
+    for (int r = 0; r < nr; ++r) start[r + 1] = start[r] + cnt[r];
+    memcpy(fill, start, sizeof(uint64_t) * (size_t)nr);
+    uint64_t* rows = (uint64_t*)malloc(n * sizeof(uint64_t));
+    for (uint64_t i = 0; i < n; ++i) rows[fill[rid[i]]++] = i;
+    free(rid);
+    /* each range writes its groups at its first row's position (a range has
+     * no more groups than rows); the ranges are then packed in order */
+    range_job job[MAX_RANGES];
+    pthread_t tid[MAX_RANGES];
+    int started[MAX_RANGES];
+    for (int r = 0; r < nr; ++r) {
+        const uint64_t o = start[r];
+        range_job* j = &job[r];
+        j->keys = keys;
+        j->v = v_i64;
+        j->f = v_f64;
+        j->rows = rows + o;
+        j->n = cnt[r];
+        j->ok = out_keys ? out_keys + o : NULL;
+        j->oc = out_count ? out_count + o : NULL;
+        j->os = out_sum ? out_sum + o : NULL;
+        j->of = out_fsum ? out_fsum + o : NULL;
+        j->omn = out_min ? out_min + o : NULL;
+        j->omx = out_max ? out_max + o : NULL;
+        j->groups = 0;
+        started[r] = pthread_create(&tid[r], NULL, range_worker, j) == 0;
+        if (!started[r]) range_worker(j);
+    }
+    for (int r = 0; r < nr; ++r)
+        if (started[r]) pthread_join(tid[r], NULL);
+    uint64_t groups = 0;
+    for (int r = 0; r < nr; ++r) {
+        const uint64_t o = start[r], g = job[r].groups;
+        if (groups != o) {
+            if (out_keys) memmove(out_keys + groups, out_keys + o, g * sizeof(uint64_t));
+            if (out_count) memmove(out_count + groups, out_count + o, g * sizeof(uint64_t));
+            if (out_sum) memmove(out_sum + groups, out_sum + o, g * sizeof(int64_t));
+            if (out_fsum && v_f64) memmove(out_fsum + groups, out_fsum + o, g * sizeof(double));
+            if (out_min) memmove(out_min + groups, out_min + o, g * sizeof(int64_t));
+            if (out_max) memmove(out_max + groups, out_max + o, g * sizeof(int64_t));
+        }
+        groups += g;
+    }
+    free(rows);
     return groups;
 }
 

@@ -217,3 +217,44 @@ def test_count_distinct_brute_force():
     assert got["keys"].tolist() == ks
     assert got["count"].tolist() == [len(rows[kk]) for kk in ks]
     assert got["distinct"].tolist() == [len(set(rows[kk])) for kk in ks]
+
+
+@pytest.mark.parametrize("threads", [2, 3, 8, 0])
+@pytest.mark.parametrize("seed,n,d,s", [(11, 1, 1, 0), (12, 5, 5, 0), (13, 1000, 1, 0),
+                                        (14, 20000, 300, 1.2), (15, 200000, 50000, 0.8),
+                                        (16, 100000, 100000, 0)])
+def test_threaded_oracle_equals_single_thread(threads, seed, n, d, s):
+    # the key-range split over threads gives the single-threaded result, bit for bit
+    k, v, f = datagen.plain_input(seed, n, d, s, with_f64=True)
+    one = oracle.group_by(k, v, f)
+    many = oracle.group_by(k, v, f, threads=threads)
+    for col in one:
+        assert one[col].tobytes() == many[col].tobytes(), col
+
+
+def test_threaded_oracle_brute_force_and_extreme_keys():
+    rng = np.random.default_rng(17)
+    k = rng.choice(np.array([0, 1, 2, 1 << 63, (1 << 64) - 2, (1 << 64) - 1], np.uint64), 3000)
+    v = rng.integers(-(1 << 62), 1 << 62, 3000, dtype=np.int64)
+    f = rng.standard_normal(3000)
+    f[5] = np.inf
+    got = oracle.group_by(k, v, f, threads=4)
+    want = brute_force(k, v, f)
+    assert got["keys"].tolist() == want["keys"]
+    assert got["count"].tolist() == want["count"]
+    assert got["sum_i64"].tolist() == want["sum_i64"]
+    assert got["min_i64"].tolist() == want["min_i64"]
+    assert got["max_i64"].tolist() == want["max_i64"]
+    # finite groups: correctly rounded; the group holding +inf sums to +inf
+    fin = np.isfinite(np.array(want["sum_f64"]))
+    assert np.array_equal(got["sum_f64"][fin], np.array(want["sum_f64"])[fin])
+    assert np.isinf(got["sum_f64"][~fin]).all()
+
+
+def test_threaded_oracle_without_value_columns():
+    k, _, _ = datagen.plain_input(18, 50000, 700, 0.5, with_f64=False)
+    one = oracle.group_by(k)
+    many = oracle.group_by(k, threads=5)
+    assert set(one) == set(many) == {"keys", "count"}
+    for col in one:
+        assert np.array_equal(one[col], many[col])
