@@ -42,6 +42,9 @@ WORKLOADS = {
     # count(*) + count(distinct x) group by g: int32 g uniform over 1e3 values,
     # int32 x uniform over 1e4 values (about 1e7 distinct pairs), 256 MiB workspace
     "cdistinct_100M": (100_000_000, 10_000_000, 0.0, 9, 256, False, "count"),
+    # (A, B) int32 pairs, 1e3 A values sorted, 1e5 B values per A, int64 value,
+    # grouped one A-segment at a time (rows, -, -, seed, budget MiB, -, aggs)
+    "segmented_200M": (200_000_000, 0, 0.0, 5, 256, False, "int"),
 }
 # Forms beyond the plain operator (each prints its own JSON line):
 #   batch_c3:    instances with rows log-uniform 1e3..1e7 and distinct/rows
@@ -181,8 +184,8 @@ def bench_batch(args, lo, hi):
         "ms": {"batched_tuned": round(1e3 * t_batch, 2), "batched_default_config": round(1e3 * t_graphless, 2),
                "plain": round(1e3 * t_plain, 2)},
     }
-    print(json.dumps(res))
     ctx.close()
+    return res
 
 
 def bench_serve(args):
@@ -270,7 +273,7 @@ def bench_serve(args):
                             raise isa.InsortError(st, "request %d" % pending[tk][0])
                         j, late = pending.pop(tk)
                         lat[j] = lat_ms + late
-                        srv.live.pop(tk, None)
+                        srv.release(tk)
             else:
                 plain(k, v)
                 lat[i] = 1e3 * (time.perf_counter() - start - arrivals[i])
@@ -310,13 +313,16 @@ def bench_serve(args):
                        "rows_per_s": round(tot / wall_f, 1), "wall_s": round(wall_f, 3)},
         "plain_rate_rows_per_s": round(r_plain, 1),
     }
-    print(json.dumps(res))
     ctx.close()
+    return res
 
 
 # Profile labels of the library's launches -> kernel names in rocprofv3 output
 KERNELS_OF_LABEL = {"k_leaf": ["k_leaf_flat", "k_leaf"], "k_merge": ["k_merge"], "k_scatter": ["k_scatter"],
-                    "k_hist": ["k_hist"], "k_sample": ["k_sample", "k_sample_keys"]}
+                    "k_hist": ["k_hist", "k_hist_batch"], "k_sample": ["k_sample", "k_sample_keys"]}
+# input generators: not part of a step, left out of the step's counter bytes
+GENERATORS = ("k_zipf_keys", "k_normal_f64", "k_uniform_i64", "k_uniform_ranks", "k_keys_uniform",
+              "k_seg_", "k_zipf_approx")
 
 
 def link_summary(spilled_bytes, link_ms, ms_per_step):
@@ -333,29 +339,273 @@ def link_summary(spilled_bytes, link_ms, ms_per_step):
             "step_frac_of_floor": round(floor_ms / ms_per_step, 3) if ms_per_step else None}
 
 
-def hbm_traffic(workload, label):
-    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) of the kernels
-    behind a profile label, from profiles/hbm_traffic.json; None when the
-    workload was not profiled or the kernels changed since (source hash)."""
+def _profiles(name):
+    """A committed profile table (profiles/<name>) if it was taken on the
+    current kernel source (same sha256 prefix), else None."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     try:
-        with open(os.path.join(here, "profiles", "hbm_traffic.json")) as f:
+        with open(os.path.join(here, "profiles", name)) as f:
             t = json.load(f)
         src = open(os.path.join(here, "paper_2010_00152_amd", "csrc", "isa_kernels.hip"), "rb").read()
     except OSError:
-        return None, None
+        return None
     if hashlib.sha256(src).hexdigest()[:16] != t.get("kernel_source_sha256_16"):
-        return None, None
-    wl = t.get("workloads", {}).get(workload)
+        return None
+    return t
+
+
+def step_traffic(workload):
+    """HBM bytes of one step from rocprofv3 FETCH_SIZE and WRITE_SIZE
+    (copy-calibrated), summed over the step's kernels; None when the workload
+    was not profiled on the current kernel source."""
+    t = _profiles("hbm_traffic.json")
+    wl = (t or {}).get("workloads", {}).get(workload)
     if not wl:
-        return None, None
-    n = b = 0.0
-    for k in KERNELS_OF_LABEL.get(label, [label]):
-        if k in wl:
-            n += wl[k]["launches"]
-            b += wl[k]["launches"] * (wl[k]["fetch_bytes_per_launch"] + wl[k]["write_bytes_per_launch"])
-    return (b / n, None) if n else (None, None)
+        return None
+    return sum(r["launches"] * (r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"])
+               for k, r in wl.items() if not k.startswith(GENERATORS)) / max(1, t.get("steps", {}).get(workload, 1))
+
+
+def rocprof_dominant(workload):
+    """(kernel, avg us, launches per step) of the kernel with the most time in
+    the committed rocprofv3 summary of this workload, or None."""
+    t = _profiles("kernel_stats.json")
+    wl = (t or {}).get("workloads", {}).get(workload)
+    if not wl:
+        return None
+    ks = {k: r for k, r in wl["kernels"].items() if not k.startswith(GENERATORS) and not k.startswith("__")}
+    k = max(ks, key=lambda x: ks[x]["total_us"])
+    return k, ks[k]["avg_us"], ks[k]["calls"] / max(1, wl.get("calls", 1))
+
+
+def host_info():
+    import platform
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ram = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = round(int(line.split()[1]) / 2**20, 1)
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc_online": os.cpu_count(), "cpus_usable": usable, "ram_GiB": ram}
+
+
+# host threads given to the parallel oracle: the CPU share of a one-GPU box
+ORACLE_THREADS = 16
+
+
+def cpu_oracle(kd, vd, fd, n, sample_rows, parallel):
+    """The C oracle on this host: single-threaded on the first sample_rows rows
+    (a bounded sample), and, with `parallel`, its multi-threaded form (the same
+    sort-then-scan over sampled key ranges) on the whole input."""
+    import numpy as np
+    import oracle
+    m = min(sample_rows, n)
+    print("bench: timing the CPU oracle on %d rows (1 thread)" % m, file=sys.stderr, flush=True)
+    k_h = kd.cpu().numpy().view(np.uint64)
+    v_h = vd.cpu().numpy() if vd is not None else None
+    f_h = fd.cpu().numpy() if fd is not None else None
+    c0 = time.perf_counter()
+    oracle.group_by(k_h[:m], None if v_h is None else v_h[:m], None if f_h is None else f_h[:m])
+    c1 = time.perf_counter()
+    one = {"value": round(m / (c1 - c0), 1), "unit": "rows/s", "cores": 1, "kind": "oracle",
+           "sample": "first %d rows of the same input, single-threaded C oracle "
+                     "(merge sort then in-stream aggregation), %.1f s" % (m, c1 - c0)}
+    par = None
+    if parallel:
+        threads = min(ORACLE_THREADS, oracle.nproc())
+        print("bench: timing the CPU oracle on %d rows (%d threads)" % (n, threads), file=sys.stderr, flush=True)
+        c0 = time.perf_counter()
+        oracle.group_by(k_h, v_h, f_h, threads=threads)
+        c1 = time.perf_counter()
+        par = {"value": round(n / (c1 - c0), 1), "unit": "rows/s", "cores": threads, "kind": "oracle",
+               "sample": "the whole input (%d rows), the C oracle's sort-then-scan over sampled key ranges on "
+                         "%d host threads, %.1f s" % (n, threads, c1 - c0)}
+    return one, par
+
+
+def make_input(torch, dgd, datagen, workload):
+    n, d, s, seed, budget_mib, with_f, aggs_name = WORKLOADS[workload]
+    if workload.startswith("cdistinct_"):
+        gd = dgd.uniform_ranks(datagen.substream_seed(seed, 1), n, 1000).to(torch.int32)
+        xd = dgd.uniform_ranks(datagen.substream_seed(seed, 2), n, 10_000).to(torch.int32)
+        return gd, xd, None
+    if workload.startswith("segmented_"):
+        return dgd.segmented_input(seed, n)
+    if workload.startswith("sorted_"):
+        kd = torch.sort(dgd.uniform_ranks(datagen.substream_seed(seed, 1), n, d)).values
+        vd = dgd.uniform_i64(datagen.substream_seed(seed, 2), n)
+        fd = dgd.normal_f64(datagen.substream_seed(seed, 3), n) if with_f else None
+        return kd, vd, fd
+    return dgd.plain_input(seed, n, d, s, with_f64=with_f)
+
+
+def run_workload(args, workload, steps, warmup, detail):
+    """Time `steps` whole calls of one workload (inputs resident in HBM) and
+    return its figures; with `detail`, also the per-kernel event timing, the
+    dominant kernel and the CPU oracle."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import datagen.device as dgd
+    import paper_2010_00152_amd as isa
+
+    n, d, s, seed, budget_mib, with_f, aggs_name = WORKLOADS[workload]
+    aggs = {"all": isa.ISA_ALL, "int": isa.ISA_INT_AGGS, "count": isa.ISA_COUNT}[aggs_name]
+    print("bench: workload %s, generating %d rows on the device" % (workload, n), file=sys.stderr, flush=True)
+    a0, a1, a2 = make_input(torch, dgd, datagen, workload)
+    torch.cuda.synchronize()
+    ctx = isa.Context(0)
+    if workload.endswith("_rs"):
+        ctx.set_run_generation(isa.ISA_RUNGEN_REPLACEMENT)
+    L = isa.lib()
+    budget = budget_mib << 20
+    ws = torch.empty(budget, dtype=torch.uint8, device="cuda")
+    wss = isa.isa_workspace(isa._ptr(ws), budget)
+    row_b = L.isa_state_row_bytes(aggs)
+    spilling = "spill_" in workload or workload.startswith("cdistinct_")
+    spill = torch.empty(n * row_b, dtype=torch.uint8, pin_memory=True) if spilling else None
+    sps = isa.isa_spill(isa._ptr(spill), spill.numel() if spill is not None else 0)
+    st = isa.isa_stats()
+    stream = torch.cuda.current_stream()
+    sp = isa._stream_ptr(stream)
+    segmented = workload.startswith("segmented_")
+    cap = n if segmented else min(n, d)
+    outs = isa._alloc_outputs(torch, cap, aggs, "cuda", with_keys=not segmented)
+    out = isa._output_struct(outs, cap)
+    if segmented:
+        seg_a = torch.empty(cap, dtype=torch.int32, device="cuda")
+        seg_b = torch.empty(cap, dtype=torch.int32, device="cuda")
+    if workload.startswith("cdistinct_"):
+        cd_scratch = torch.empty(24 * n, dtype=torch.uint8, device="cuda")
+        cd_out = [torch.empty(1000, dtype=t, device="cuda") for t in (torch.int32, torch.int64, torch.int64)]
+        cd_n = isa.ctypes.c_uint64()
+    inp = isa.isa_input(isa._ptr(a0), isa._ptr(a1), isa._ptr(a2), n)
+
+    def step():
+        if workload.startswith("cdistinct_"):
+            rc = L.isa_count_distinct(ctx.handle, isa._ptr(a0), isa._ptr(a1), n, wss, sps, isa._ptr(cd_scratch),
+                                      cd_scratch.numel(), isa._ptr(cd_out[0]), isa._ptr(cd_out[1]),
+                                      isa._ptr(cd_out[2]), 1000, isa.ctypes.byref(cd_n), sp)
+            out.n_groups = cd_n.value
+        elif workload.startswith("sorted_"):
+            rc = L.isa_group_by_sorted(ctx.handle, isa.ctypes.byref(inp), aggs, wss, isa.ctypes.byref(out), sp)
+        elif segmented:
+            rc = L.isa_group_by_segmented(ctx.handle, isa._ptr(a0), isa._ptr(a1), isa._ptr(a2), n, aggs, wss,
+                                          isa._ptr(seg_a), isa._ptr(seg_b), isa.ctypes.byref(out), sp)
+        else:
+            rc = L.isa_group_by(ctx.handle, isa.ctypes.byref(inp), aggs, wss, sps, isa.ctypes.byref(out),
+                                isa.ctypes.byref(st), sp)
+        if rc != isa.ISA_OK:
+            raise isa.InsortError(rc, ctx.last_error())
+
+    for i in range(warmup):
+        step()
+        print("bench: %s warmup %d done" % (workload, i), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ts = time.perf_counter()
+        step()
+        print("bench: %s step %d done (%.1f ms host)" % (workload, i, (time.perf_counter() - ts) * 1e3),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    timed_phases = {k: round(v, 3) for k, v in st.as_dict().items() if k.startswith("t_")}
+    groups = out.n_groups
+    stats = st.as_dict()
+    if segmented:
+        in_row = 4 + 4 + 8
+        out_row = 4 + 4 + 8 * 4
+    elif workload.startswith("cdistinct_"):
+        in_row, out_row = 8, 4 + 8 + 8
+    else:
+        in_row = 8 + (8 if aggs & (isa.ISA_SUM_I64 | isa.ISA_MIN_I64 | isa.ISA_MAX_I64) else 0) + (8 if with_f else 0)
+        out_row = row_b
+    # algorithmic HBM bytes of a step: every input column read once, every
+    # output row written once (runs crossing the host link are counted apart)
+    algo_bytes = n * in_row + groups * out_row
+    achieved = algo_bytes / (ms_per_step * 1e-3) / 1e9
+    traffic = step_traffic(workload)
+    roofline = {"bound": "hbm", "scope": "whole step", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "algo_bytes_per_step": int(algo_bytes),
+                "traffic": int(traffic) if traffic else None,
+                "traffic_over_algo": round(traffic / algo_bytes, 2) if traffic else None}
+    res = {"ms_per_step": round(ms_per_step, 3), "rows_per_s": round(n / (ms_per_step * 1e-3), 1),
+           "groups": groups, "roofline": roofline, "steps": steps, "warmup": warmup,
+           "config": {"workload": workload, "rows": n, "distinct_domain": d, "zipf_s": s,
+                      "budget_bytes": budget, "aggs": aggs_name, "groups": groups,
+                      "run_generation": "replacement" if workload.endswith("_rs") else "read-sort-write"},
+           "dtype": "u64+i64+f64" if with_f else ("i32+i32+i64" if segmented else "u64+i64")}
+    if stats["spilled_rows"] or spilling:
+        res["stats"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in stats.items()}
+        res["phases_timed_ms"] = timed_phases
+    if detail:
+        # per-kernel HIP-event timing in separate calls, so that the event
+        # records do not enter the timed calls above
+        prof = {}
+        if args.profile_steps:
+            ctx.profile(True)
+            for i in range(args.profile_steps):
+                step()
+            torch.cuda.synchronize()
+            prof = ctx.profile_read()
+            ctx.profile(False)
+            print("bench: %d profiled call(s) done" % args.profile_steps, file=sys.stderr, flush=True)
+        kernels = {}
+        for name, r in prof.items():
+            kernels[name] = {"launches": r["launches"] / args.profile_steps,
+                             "avg_us": round(1e3 * r["total_ms"] / max(1, r["launches"]), 2),
+                             "ms_per_step": round(r["total_ms"] / args.profile_steps, 3)}
+        res["kernels_event_timed"] = kernels
+        dom = rocprof_dominant(workload)
+        if dom:
+            name, avg_us, per_step = dom
+            label = next((lb for lb, ks in KERNELS_OF_LABEL.items() if name in ks), name)
+            ev = kernels.get(label)
+            roofline["dominant_kernel"] = {
+                "name": name, "source": "committed rocprofv3 summary (same kernel source)",
+                "rocprof_avg_us": avg_us, "launches_per_step": round(per_step, 1),
+                "event_avg_us": ev["avg_us"] if ev else None,
+                "share_of_step": round(avg_us * per_step / (ms_per_step * 1e3), 3)}
+        if stats["spilled_rows"]:
+            hl_ms = sum(prof[k]["total_ms"] for k in ("spill_d2h", "merge_h2d") if k in prof) / max(1, args.profile_steps)
+            res["host_link"] = link_summary(stats["spilled_bytes"], hl_ms, ms_per_step)
+            # the combined floor: HBM bytes at peak or both link volumes at the link's peak
+            floor = max(algo_bytes / (HBM_PEAK_GBS * 1e9), 2 * stats["spilled_bytes"] / (LINK_PEAK_GBS * 1e9)) * 1e3
+            roofline["combined_floor_ms"] = round(floor, 3)
+            roofline["frac_of_combined_floor"] = round(floor / ms_per_step, 4)
+        if args.cpu_sample and not segmented and not workload.startswith("cdistinct_"):
+            one, par = cpu_oracle(a0, a1, a2, n, args.cpu_sample, not args.no_parallel_oracle)
+            res["cpu_baseline"] = one
+            res["cpu_baseline_parallel"] = par
+            res["host"] = host_info()
+    del a0, a1, a2, ws, spill, outs
+    ctx.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+# the other configurations reported beside the headline, with fewer calls
+SIDE_WORKLOADS = ["plain_1M_10k", "spill_100M_zipf0", "spill_100M_zipf1.2", "nospill_100M_zipf0.8",
+                  "segmented_200M"]
 
 
 def main():
@@ -364,17 +614,20 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="spill_100M_zipf0.8", choices=sorted(WORKLOADS) + list(FORMS))
+    ap.add_argument("--only", action="store_true",
+                    help="the named workload alone (default for the headline: every configuration)")
+    ap.add_argument("--side-steps", type=int, default=3, help="timed calls of each side configuration")
     ap.add_argument("--instances", type=int, default=10000, help="batch_*: number of instances")
     ap.add_argument("--requests", type=int, default=2000, help="serve_c4: number of requests")
     ap.add_argument("--rho", type=float, default=0.8, help="serve_c4: offered load vs the plain rate")
     ap.add_argument("--slots", type=int, default=3, help="serve_c4: concurrent server batches")
     ap.add_argument("--tuning-file", default=None,
                     help="batch_*: JSON table of autotuned launch configurations (read, and written when tuning)")
-    ap.add_argument("--cpu-sample", type=int, default=10_000_000,
-                    help="rows of the input the CPU oracle is timed on (0 = skip)")
-    ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--cpu-sample", type=int, default=20_000_000,
+                    help="rows of the input the single-threaded CPU oracle is timed on (0 = skip the oracle)")
+    ap.add_argument("--no-parallel-oracle", action="store_true", help="skip the multi-threaded oracle timing")
     ap.add_argument("--profile-steps", type=int, default=2,
-                    help="extra untimed steps with per-kernel HIP-event timing")
+                    help="extra untimed calls with per-kernel HIP-event timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -382,8 +635,8 @@ def main():
         print("bench.py: the library runs on one GPU (--gpus %d requested); "
               "multi-GPU sharding is a design note, not built" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    t_start = time.perf_counter()
 
-    import numpy as np
     import torch
 
     if args.calibrate_copy:
@@ -397,176 +650,56 @@ def main():
                           "launches": 3}))
         return
 
-    if args.workload == "batch_c3":
-        return bench_batch(args, 1e3, 1e7)
-    if args.workload == "batch_small":
-        return bench_batch(args, 1e3, 1e5)
-    if args.workload == "serve_c4":
-        return bench_serve(args)
-
-    import datagen
-    import datagen.device as dgd
-    import paper_2010_00152_amd as isa
-
-    n, d, s, seed, budget_mib, with_f, aggs_name = WORKLOADS[args.workload]
-    aggs = {"all": isa.ISA_ALL, "int": isa.ISA_INT_AGGS, "count": isa.ISA_COUNT}[aggs_name]
-    print("bench: workload %s, generating %d rows on the device" % (args.workload, n), file=sys.stderr,
-          flush=True)
-    if args.workload.startswith("cdistinct_"):
-        gd = dgd.uniform_ranks(datagen.substream_seed(seed, 1), n, 1000).to(torch.int32)
-        xd = dgd.uniform_ranks(datagen.substream_seed(seed, 2), n, 10_000).to(torch.int32)
-        kd, vd, fd = gd, None, None
-        cd_scratch = torch.empty(24 * n, dtype=torch.uint8, device="cuda")
-        cd_out = [torch.empty(1000, dtype=t, device="cuda") for t in (torch.int32, torch.int64, torch.int64)]
-        cd_n = isa.ctypes.c_uint64()
-    elif args.workload.startswith("sorted_"):
-        kd = torch.sort(dgd.uniform_ranks(datagen.substream_seed(seed, 1), n, d)).values
-        vd = dgd.uniform_i64(datagen.substream_seed(seed, 2), n)
-        fd = dgd.normal_f64(datagen.substream_seed(seed, 3), n) if with_f else None
-    else:
-        kd, vd, fd = dgd.plain_input(seed, n, d, s, with_f64=with_f)
-    torch.cuda.synchronize()
-    ctx = isa.Context(0)
-    if args.workload.endswith("_rs"):
-        ctx.set_run_generation(isa.ISA_RUNGEN_REPLACEMENT)
-    L = isa.lib()
-    budget = budget_mib << 20
-    ws = torch.empty(budget, dtype=torch.uint8, device="cuda")
-    row_b = L.isa_state_row_bytes(aggs)
-    spilling = "spill_" in args.workload or args.workload.startswith("cdistinct_")
-    spill = torch.empty(n * row_b, dtype=torch.uint8, pin_memory=True) if spilling else None
-    cap = min(n, d)
-    outs = isa._alloc_outputs(torch, cap, aggs, "cuda")
-    out = isa._output_struct(outs, cap)
-    inp = isa.isa_input(isa._ptr(kd), isa._ptr(vd), isa._ptr(fd), n)
-    wss = isa.isa_workspace(isa._ptr(ws), budget)
-    sps = isa.isa_spill(isa._ptr(spill), spill.numel() if spill is not None else 0)
-    st = isa.isa_stats()
-    stream = torch.cuda.current_stream()
-    sp = isa._stream_ptr(stream)
-
-    def step():
-        if args.workload.startswith("cdistinct_"):
-            rc = L.isa_count_distinct(ctx.handle, isa._ptr(gd), isa._ptr(xd), n, wss, sps, isa._ptr(cd_scratch),
-                                      cd_scratch.numel(), isa._ptr(cd_out[0]), isa._ptr(cd_out[1]),
-                                      isa._ptr(cd_out[2]), 1000, isa.ctypes.byref(cd_n), sp)
-            out.n_groups = cd_n.value
-        elif args.workload.startswith("sorted_"):
-            rc = L.isa_group_by_sorted(ctx.handle, isa.ctypes.byref(inp), aggs, wss, isa.ctypes.byref(out), sp)
+    if args.workload in FORMS:
+        if args.workload == "serve_c4":
+            r = bench_serve(args)
         else:
-            rc = L.isa_group_by(ctx.handle, isa.ctypes.byref(inp), aggs, wss, sps, isa.ctypes.byref(out),
-                                isa.ctypes.byref(st), sp)
-        if rc != isa.ISA_OK:
-            raise isa.InsortError(rc, ctx.last_error())
+            r = bench_batch(args, 1e3, 1e7 if args.workload == "batch_c3" else 1e5)
+        r["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
+        print(json.dumps(r))
+        return
 
-    for i in range(args.warmup):
-        step()
-        print("bench: warmup %d done" % i, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        step()
-        print("bench: step %d done (%.1f ms host)" % (i, (time.perf_counter() - ts) * 1e3), file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    # phase times of the last timed call (the profiled calls below add event records)
-    timed_phases = {k: round(v, 3) for k, v in st.as_dict().items() if k.startswith("t_")}
-    # per-kernel HIP-event timing in separate steps, so that the event records
-    # do not enter the timed steps above
-    prof = {}
-    prof_steps = 0 if args.no_profile else args.profile_steps
-    if prof_steps:
-        ctx.profile(True)
-        for i in range(prof_steps):
-            step()
-        torch.cuda.synchronize()
-        prof = ctx.profile_read()
-        ctx.profile(False)
-        print("bench: %d profiled step(s) done" % prof_steps, file=sys.stderr, flush=True)
-    groups = out.n_groups
-    stats = st.as_dict()
-
-    in_row = 8 + (8 if aggs & (isa.ISA_SUM_I64 | isa.ISA_MIN_I64 | isa.ISA_MAX_I64) else 0) + (8 if with_f else 0)
-    algo_bytes = n * in_row + groups * row_b
-    step_gbs = algo_bytes / (ms_per_step * 1e-3) / 1e9
-
-    roofline = None
-    kernels = {}
-    if prof:
-        for name, r in prof.items():
-            kernels[name] = {"launches": r["launches"], "avg_us": 1e3 * r["total_ms"] / max(1, r["launches"]),
-                             "ms_per_step": r["total_ms"] / prof_steps,
-                             "rows_per_launch": r["rows"] / max(1, r["launches"]),
-                             "algo_GBps": (r["bytes"] / (r["total_ms"] * 1e-3) / 1e9) if r["total_ms"] else None}
-        dev_kernels = {k: v for k, v in prof.items() if k.startswith("k_")}
-        dom = max(dev_kernels, key=lambda k: dev_kernels[k]["total_ms"])
-        r = dev_kernels[dom]
-        achieved = r["bytes"] / (r["total_ms"] * 1e-3) / 1e9
-        algo_pl = r["bytes"] / r["launches"]
-        traffic, ratio = hbm_traffic(args.workload, dom)
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": int(traffic) if traffic else None,
-                    "traffic_over_algo": round(traffic / algo_pl, 3) if traffic else None,
-                    "avg_launch_us": round(1e3 * r["total_ms"] / r["launches"], 2),
-                    "algo_bytes_per_launch": int(algo_pl)}
-
-    host_link = None
-    if stats["spilled_rows"]:
-        hl_ms = sum(prof[k]["total_ms"] for k in ("spill_d2h", "merge_h2d") if k in prof) / max(1, prof_steps)
-        host_link = link_summary(stats["spilled_bytes"], hl_ms, ms_per_step)
-
-    cpu = None
-    if args.cpu_sample:
-        import oracle
-        m = min(args.cpu_sample, n)
-        print("bench: timing the CPU oracle on %d rows" % m, file=sys.stderr, flush=True)
-        if args.workload.startswith("cdistinct_"):
-            g_h = gd[:m].cpu().numpy().astype(np.uint64)
-            x_h = xd[:m].cpu().numpy().astype(np.uint64)
-            c0 = time.perf_counter()
-            oracle.count_distinct(g_h, x_h)
-            c1 = time.perf_counter()
-        else:
-            k_h = kd[:m].cpu().numpy().view(np.uint64)
-            v_h = vd[:m].cpu().numpy()
-            f_h = fd[:m].cpu().numpy() if fd is not None else None
-            c0 = time.perf_counter()
-            oracle.group_by(k_h, v_h, f_h)
-            c1 = time.perf_counter()
-        cpu = {"value": round(m / (c1 - c0), 1), "unit": "rows/s", "cores": 1, "kind": "oracle",
-               "sample": "first %d rows of the same input, single-threaded C oracle "
-                         "(merge sort then in-stream aggregation)" % m}
-
+    head = run_workload(args, args.workload, args.steps, args.warmup, detail=True)
     res = {
         "metric": "input rows/s aggregated (% HBM roofline)",
-        "value": round(n / (ms_per_step * 1e-3), 1),
+        "value": head["rows_per_s"],
         "unit": "rows/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64+i64+f64" if with_f else "u64+i64",
+        "dtype": head["dtype"],
         "data": "synthetic",
-        "config": {"workload": args.workload, "rows": n, "distinct_domain": d, "zipf_s": s,
-                   "budget_bytes": budget, "aggs": aggs_name, "groups": groups,
-                   "run_generation": "replacement" if args.workload.endswith("_rs") else "read-sort-write"},
-        "hbm_algo_GBps_whole_step": round(step_gbs, 1),
-        "hbm_roofline_frac_whole_step": round(step_gbs / HBM_PEAK_GBS, 4),
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "host_link": host_link,
-        "stats": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in stats.items()},
-        "phases_timed_ms": timed_phases,
-        "kernels": kernels,
+        "config": head["config"],
+        "roofline": head["roofline"],
+        "cpu_baseline": head.get("cpu_baseline"),
     }
+    for k in ("cpu_baseline_parallel", "host", "host_link", "stats", "phases_timed_ms", "kernels_event_timed"):
+        if k in head:
+            res[k] = head[k]
+    if not args.only and args.workload == "spill_100M_zipf0.8":
+        side = {}
+        for w in SIDE_WORKLOADS:
+            r = run_workload(args, w, args.side_steps, 1, detail=False)
+            side[w] = {k: r[k] for k in ("ms_per_step", "rows_per_s", "groups", "roofline") if k in r}
+            if "stats" in r:
+                side[w]["runs"] = r["stats"]["runs"]
+                side[w]["spilled_rows"] = r["stats"]["spilled_rows"]
+            print("bench: %s %.3f ms" % (w, r["ms_per_step"]), file=sys.stderr, flush=True)
+        args.workload = "batch_c3"
+        b = bench_batch(args, 1e3, 1e7)
+        side["batch_c3"] = {k: b[k] for k in ("batched_tuned_rows_per_s", "batched_default_config_rows_per_s",
+                                              "plain_per_instance_rows_per_s", "speedup_vs_plain", "ms",
+                                              "tuning", "config")}
+        args.workload = "serve_c4"
+        sv = bench_serve(args)
+        side["serve_c4"] = {k: sv[k] for k in ("server", "fifo_plain", "plain_rate_rows_per_s", "config")}
+        res["configs"] = side
+    res["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(res))
-    ctx.close()
 
 
 if __name__ == "__main__":

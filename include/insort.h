@@ -288,6 +288,11 @@ isa_status isa_server_submit(isa_server* s, const isa_input* in, uint32_t aggs,
 /* *done = 1 once the request finished; then *latency_ms is arrival-to-ready
  * time, out->n_groups is set and the return value is the request's status. */
 isa_status isa_server_poll(isa_server* s, uint64_t ticket, int* done, double* latency_ms);
+/* Forget a finished request: its record is freed and its ticket becomes
+ * unknown (a long-lived server calls this once it has read a result).
+ * ISA_EBUSY if the request has not finished, ISA_EINVAL for an unknown ticket.
+ * The caller's output buffers are untouched. */
+isa_status isa_server_release(isa_server* s, uint64_t ticket);
 /* Block until every submitted request finished. */
 isa_status isa_server_drain(isa_server* s);
 void isa_server_destroy(isa_server* s);

@@ -102,6 +102,7 @@ SIGNATURES = {
     "isa_server_poll": (ctypes.c_int, [P, U64, ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_double)]),
     "isa_server_drain": (ctypes.c_int, [P]),
+    "isa_server_release": (ctypes.c_int, [P, U64]),
     "isa_server_destroy": (None, [P]),
     "isa_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "isa_last_error": (ctypes.c_char_p, [P]),
@@ -461,6 +462,16 @@ class Server:
         _, _, _, o, out, _ = self.live[ticket]
         g = out.n_groups
         return {c: t[:g] for c, t in o.items()}
+
+    def release(self, ticket):
+        """Forget a finished request (isa_server_release) and return its result
+        columns; the binding drops its references to the request's buffers."""
+        st = lib().isa_server_release(self.handle, ticket)
+        if st != ISA_OK:
+            raise InsortError(st)
+        res = self.result(ticket)
+        del self.live[ticket]
+        return res
 
     def drain(self):
         st = lib().isa_server_drain(self.handle)

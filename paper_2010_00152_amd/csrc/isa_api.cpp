@@ -1838,6 +1838,17 @@ isa_status isa_server_poll(isa_server* S, uint64_t ticket, int* done, double* la
     return r->status;
 }
 
+isa_status isa_server_release(isa_server* S, uint64_t ticket) {
+    if (!S) return ISA_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return ISA_EINVAL;
+    if (!it->second->done) return ISA_EBUSY;
+    delete it->second;
+    S->reqs.erase(it);
+    return ISA_OK;
+}
+
 isa_status isa_server_drain(isa_server* S) {
     if (!S) return ISA_EINVAL;
     std::unique_lock<std::mutex> lk(S->mu);

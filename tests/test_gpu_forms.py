@@ -142,6 +142,11 @@ def test_autotuner_picks_a_candidate_and_keeps_results(ctx):
 
 
 def test_server_results_alone_and_in_the_mix(ctx):
+    # 60 requests of different sizes arrive while others run (3 slots, so
+    # their device work overlaps); every result matches the oracle, and a
+    # subset run again alone (a one-slot server with one request in flight)
+    # gives the same result as in the mix: integers bit-equal, the fp64 sum
+    # within 1e-12 * sum |x|
     say("case server")
     import torch
     insts = batch_instances(7, 60, 1_000, 300_000)
@@ -154,12 +159,30 @@ def test_server_results_alone_and_in_the_mix(ctx):
         if i % 7 == 0:
             time.sleep(0.002)  # requests keep arriving while others run
     srv.drain()
+    mix = {}
     for i, t in enumerate(tickets):
         done, lat, st = srv.poll(t)
         assert done and st == isa.ISA_OK and lat > 0
         k, v, f = insts[i]
-        compare(np_out(srv.result(t)), k, v, f, isa.ISA_ALL, "req %d" % i)
+        mix[i] = np_out(srv.release(t))
+        compare(mix[i], k, v, f, isa.ISA_ALL, "req %d" % i)
+        assert srv.poll(t)[2] == isa.ISA_EINVAL        # a released ticket is unknown
+    assert not srv.live
     srv.close()
+
+    alone = isa.Server(ctx, 1 << 30, slots=1)
+    for i in range(0, len(insts), 4):
+        k, v, f = dev[i]
+        t = alone.submit(k, v, f, aggs=isa.ISA_ALL)
+        alone.drain()
+        done, lat, st = alone.poll(t)
+        assert done and st == isa.ISA_OK
+        got = np_out(alone.release(t))
+        for col in ("keys", "count", "sum_i64", "min_i64", "max_i64"):
+            assert np.array_equal(got[col], mix[i][col]), (i, col)
+        absum = oracle.group_by(insts[i][0], None, np.abs(insts[i][2]))["sum_f64"]
+        assert (np.abs(got["sum_f64"] - mix[i]["sum_f64"]) <= FP64_REL * absum).all(), i
+    alone.close()
 
 
 def test_server_rejects_oversized_request(ctx):
