@@ -150,6 +150,28 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs,
                         isa_stats* stats, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * grouping as isa_group_by for an input whose whole sort fits the library's
+ * own device scratch, with no workspace argument and no spill.  The scratch is
+ * one file-scope device array of 64 MiB per GPU, held until the process ends;
+ * its address is looked up once per device by isa_ctx_create.  The call
+ * allocates no device or pinned memory and creates no stream, event or graph
+ * (the pinned staging and events it uses are set up by isa_ctx_create); were
+ * it to need any, it returns ISA_ENOMEM instead.  Results are those of
+ * isa_group_by (the same kernels).  Every call on a GPU shares that GPU's
+ * scratch: calls that overlap on one GPU (from different contexts, or
+ * different streams) race and must be serialised by the caller.
+ * Errors: ISA_EBUDGET when in->n_rows > isa_noalloc_max_rows(aggs); otherwise
+ * as for isa_group_by (ISA_EINVAL, ISA_ETRUNC, ISA_EDEVICE).
+ */
+isa_status isa_group_by_noalloc(isa_ctx* ctx, const isa_input* in, uint32_t aggs,
+                                isa_output* out, void* stream);
+/* Largest n_rows isa_group_by_noalloc accepts for these aggregates
+ * (0 for unknown aggregate bits).  Host-only. */
+uint64_t isa_noalloc_max_rows(uint32_t aggs);
+
+/*
  * Group input that is already sorted on its key (ascending, unsigned): the
  * in-stream aggregation of the paper's decision table for sorted input (§1,
  * and §2.1 on in-stream grouping) with no sort and no run.  One pass finds the

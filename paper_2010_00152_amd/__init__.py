@@ -87,6 +87,8 @@ SIGNATURES = {
     "isa_min_workspace_bytes": (U64, [U32]),
     "isa_group_by": (ctypes.c_int, [P, ctypes.POINTER(isa_input), U32, isa_workspace, isa_spill,
                                     ctypes.POINTER(isa_output), ctypes.POINTER(isa_stats), P]),
+    "isa_group_by_noalloc": (ctypes.c_int, [P, ctypes.POINTER(isa_input), U32, ctypes.POINTER(isa_output), P]),
+    "isa_noalloc_max_rows": (U64, [U32]),
     "isa_group_by_segmented": (ctypes.c_int, [P, P, P, P, U64, U32, isa_workspace, P, P,
                                               ctypes.POINTER(isa_output), P]),
     "isa_group_by_sorted": (ctypes.c_int, [P, ctypes.POINTER(isa_input), U32, isa_workspace,

@@ -20,6 +20,9 @@ using namespace isa;
 struct isa_ctx {
     int device = 0;
     int rungen = ISA_RUNGEN_READ_SORT_WRITE;
+    // device address of the library-owned scratch on this context's device
+    // (looked up at creation), used only by isa_group_by_noalloc
+    void* scratch = nullptr;
     Engine eng;
     std::string last_error;
     std::mutex mu;
@@ -614,10 +617,24 @@ isa_status isa_ctx_create(int device, isa_ctx** out) {
     hipDeviceProp_t p;
     if (hipGetDeviceProperties(&p, device) != hipSuccess) return ISA_EDEVICE;
     if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) return ISA_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return ISA_EDEVICE;
     isa_ctx* c = new (std::nothrow) isa_ctx();
     if (!c) return ISA_ENOMEM;
     c->device = device;
     c->eng.device = device;
+    // set-up for the entry point that must not allocate: the scratch's address
+    // on this device, and the host-side staging it uses
+    if (noalloc_scratch(device, &c->scratch) != hipSuccess || !c->scratch) {
+        delete c;
+        return ISA_EDEVICE;
+    }
+    try {
+        c->eng.prepare_no_alloc();
+    } catch (const Fail& f) {
+        c->eng.release();
+        delete c;
+        return (isa_status)f.status;
+    }
     *out = c;
     return ISA_OK;
 }
@@ -668,6 +685,65 @@ uint64_t isa_state_row_bytes(uint32_t aggs) { return (uint64_t)state_layout(cols
 uint64_t isa_min_workspace_bytes(uint32_t aggs) {
     const Cols k = cols_of(aggs);
     return rungen_bytes(MIN_BATCH, 2 * MIN_BATCH, k);
+}
+
+uint64_t isa_noalloc_max_rows(uint32_t aggs) {
+    if (!valid_aggs(aggs)) return 0;
+    const Cols k = cols_of(aggs);
+    uint64_t lo = 0, hi = NOALLOC_SCRATCH_BYTES;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) / 2;
+        if (sort_reduce_bytes(mid, 1, k, false) <= NOALLOC_SCRATCH_BYTES) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+isa_status isa_group_by_noalloc(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_output* out, void* stream) {
+    if (out) out->n_groups = 0;
+    if (!ctx || !valid_aggs(aggs)) return ISA_EINVAL;
+    isa_status s = check_input(in, aggs);
+    if (s != ISA_OK) return s;
+    s = check_output(out, aggs, true);
+    if (s != ISA_OK) return s;
+    if (in->n_rows == 0) return ISA_OK;
+    if (in->n_rows > isa_noalloc_max_rows(aggs)) return ISA_EBUDGET;
+    if (!ctx->scratch) return ISA_EDEVICE;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    Engine& E = ctx->eng;
+    struct NoAlloc {  // the engine refuses to allocate until the call returns
+        Engine& e;
+        explicit NoAlloc(Engine& x) : e(x) { e.no_alloc = true; }
+        ~NoAlloc() { e.no_alloc = false; }
+    } guard(E);
+    try {
+        ck(hipSetDevice(ctx->device), "hipSetDevice");
+        E.stream = (hipStream_t)stream;
+        const Cols k = cols_of(aggs);
+        // the scratch takes the place of the workspace; nothing in it needs
+        // to start at zero (every buffer a plan reads is written or cleared
+        // by that plan's own launches on this stream)
+        Arena A;
+        A.base = (char*)ctx->scratch;
+        A.cap = NOALLOC_SCRATCH_BYTES;
+        Dest d;
+        d.out = output_view(*out, aggs, 0);
+        d.capacity = out->capacity;
+        std::vector<Instance> inst(1);
+        inst[0].src = input_view(*in, k);
+        inst[0].n = in->n_rows;
+        inst[0].dest = 0;
+        const uint64_t g = run_instances(E, A, inst, std::vector<Dest>(1, d), k, false, nullptr, false)[0];
+        E.sync();
+        out->n_groups = g;
+        return g > out->capacity ? ISA_ETRUNC : ISA_OK;
+    } catch (const Fail& f) {
+        out->n_groups = 0;
+        return fail(ctx, f);
+    } catch (const std::bad_alloc&) {
+        out->n_groups = 0;
+        return ISA_ENOMEM;
+    }
 }
 
 isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_workspace ws, isa_spill spill,

@@ -87,6 +87,7 @@ void* Arena::take(uint64_t bytes) {
 void* Engine::pinned_buf(uint64_t bytes) {
     uint64_t need = ((pinned_used + 255) & ~(uint64_t)255) + bytes;
     if (need > pinned_cap) {
+        if (no_alloc) throw Fail{ISA_ENOMEM, "pinned staging would grow"};
         // Older buffers may still be the target of copies in flight or hold
         // readbacks not yet consumed: retire them, free them at destruction.
         uint64_t cap = pinned_cap ? 2 * pinned_cap : (8u << 20);
@@ -104,6 +105,7 @@ void* Engine::pinned_buf(uint64_t bytes) {
 
 static hipEvent_t pool_event(Engine& E) {
     if (E.ev_used == E.ev_pool.size()) {
+        if (E.no_alloc) throw Fail{ISA_ENOMEM, "profiling events would be created"};
         hipEvent_t e;
         ck(hipEventCreate(&e), "hipEventCreate");
         E.ev_pool.push_back(e);
@@ -131,22 +133,26 @@ void Engine::pend(uint64_t rows, uint64_t bytes, hipStream_t st) {
 }
 
 hipStream_t Engine::copier() {
+    if (!copy_stream && no_alloc) throw Fail{ISA_ENOMEM, "a copy stream would be created"};
     if (!copy_stream) ck(hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking), "hipStreamCreate");
     return copy_stream;
 }
 
 hipStream_t Engine::side(int i) {
+    if (!side_streams[i] && no_alloc) throw Fail{ISA_ENOMEM, "a side stream would be created"};
     if (!side_streams[i]) ck(hipStreamCreateWithFlags(&side_streams[i], hipStreamNonBlocking), "hipStreamCreate");
     return side_streams[i];
 }
 
 hipStream_t Engine::capturer() {
+    if (!capture_stream && no_alloc) throw Fail{ISA_ENOMEM, "a capture stream would be created"};
     if (!capture_stream) ck(hipStreamCreateWithFlags(&capture_stream, hipStreamNonBlocking), "hipStreamCreate");
     return capture_stream;
 }
 
 hipEvent_t Engine::sync_event(size_t i) {
     while (sync_events.size() <= i) {
+        if (no_alloc) throw Fail{ISA_ENOMEM, "an event would be created"};
         hipEvent_t e;
         ck(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
         sync_events.push_back(e);
@@ -156,6 +162,7 @@ hipEvent_t Engine::sync_event(size_t i) {
 
 char* Engine::ring_slot(size_t i) {
     constexpr size_t SLOTS = 64;
+    if (!ring && no_alloc) throw Fail{ISA_ENOMEM, "the readback ring would be allocated"};
     if (!ring) ck(hipHostMalloc((void**)&ring, SLOTS * 64, 0), "hipHostMalloc(ring)");
     return ring + (i % SLOTS) * 64;
 }
@@ -173,6 +180,7 @@ uint64_t* Engine::ring_dev(size_t i) {
 // The caller guarantees that no copy from the previous table is in flight.
 void* Engine::table_buf(uint64_t bytes) {
     if (bytes > table_cap) {
+        if (no_alloc) throw Fail{ISA_ENOMEM, "the task table would grow"};
         if (table) hipHostFree(table);
         table = nullptr;
         table_cap = 0;
@@ -182,6 +190,15 @@ void* Engine::table_buf(uint64_t bytes) {
         table_cap = cap;
     }
     return table;
+}
+
+void Engine::prepare_no_alloc() {
+    (void)ring_dev(0);
+    if (pinned_cap < NOALLOC_PINNED_BYTES) {
+        (void)pinned_buf(NOALLOC_PINNED_BYTES - 256);
+        pinned_used = 0;
+    }
+    (void)sync_event(NOALLOC_EVENTS - 1);
 }
 
 void Engine::release() {

@@ -78,6 +78,15 @@ void launch_seg_count(const int32_t* a, uint64_t n, uint32_t chunk, uint32_t* co
 void launch_seg_write(const int32_t* a, uint64_t n, uint32_t chunk, const uint64_t* offs, uint64_t* starts,
                       hipStream_t st);
 
+// Pinned staging and synchronisation events set up once per context for the
+// entry point that must not allocate (enough for every call it accepts).
+constexpr uint64_t NOALLOC_PINNED_BYTES = 8ull << 20;
+constexpr size_t NOALLOC_EVENTS = 32;
+
+// Device address of the library-owned scratch (NOALLOC_SCRATCH_BYTES) on
+// `device`, which must be current; looked up once per device.
+hipError_t noalloc_scratch(int device, void** out);
+
 // Error carried out of the engine as an isa_status value.
 struct Fail {
     int status;
@@ -132,6 +141,10 @@ struct Engine {
     uint64_t pinned_used = 0;
     std::vector<char*> retired;
     bool prof_on = false;
+    // set while an entry point that must not allocate runs: growing a pinned
+    // buffer, creating a stream or an event, or capturing a graph then fails
+    // with ISA_ENOMEM instead of allocating
+    bool no_alloc = false;
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -162,6 +175,9 @@ struct Engine {
     // call, so that no work still reads or writes the caller's buffers)
     void drain();
     void release();
+    // allocate, once, what the no-allocation entry point uses: the pinned
+    // staging, the readback ring and the synchronisation events
+    void prepare_no_alloc();
     hipStream_t copier();             // created on first use
     hipStream_t side(int i);          // extra copy streams 0..2, created on first use
     hipStream_t capturer();           // private stream for graph capture

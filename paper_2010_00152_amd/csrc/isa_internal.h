@@ -124,6 +124,10 @@ struct FlatInst {
     uint64_t n;
 };
 
+// Bytes of the library-owned device scratch used by the entry point for
+// callers that cannot allocate (one copy per GPU).
+constexpr uint64_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+
 // Destination of one instance's sorted unique output.
 struct Dest {
     OutView out;

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "isa_internal.h"
 
 namespace isa {
@@ -2306,6 +2308,41 @@ void launch_seg_write(const int32_t* a, uint64_t n, uint32_t chunk, const uint64
     const uint64_t g = (n + chunk - 1) / chunk;
     if (!g) return;
     hipLaunchKernelGGL(k_seg_write, dim3((uint32_t)g), dim3(256), 0, st, a, n, chunk, offs, starts);
+}
+
+// ---------------------------------------------------------------------------
+// Library-owned scratch for callers that cannot allocate: a file-scope device
+// array that each GPU the library runs on holds until the process ends.  Its
+// device address differs per GPU and is looked up once per device, with that
+// device current; host code uses only the looked-up address, never the
+// array's name (a host-side stand-in).
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the device must be current
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr || ((uintptr_t)ptr & 255)) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 }  // namespace isa
