@@ -94,9 +94,54 @@ def bench_batch(args, lo, hi):
     table = TuningTable(args.tuning_file)
     sig = signature(rows, aggs)
     tuned = table.lookup(sig)
-    tune_info = {"source": "table" if tuned else "autotuned on the first wave"}
+    tune_info = {"source": "table" if tuned else "autotuned on a sample of the whole workload"}
     if tuned:
         ctx.set_tuning(**tuned)
+    else:
+        # a stratified sample across the instance-size range: instances taken
+        # in order of size at even steps until about 1e8 rows
+        order = np.argsort(rows, kind="stable")
+        pick, acc = [], 0
+        step = max(1, count // 400)
+        for j in range(0, count, step):
+            i = int(order[j])
+            if acc + int(rows[i]) > 100_000_000:
+                continue
+            pick.append(i)
+            acc += int(rows[i])
+        n_s = len(pick)
+        keys_s = torch.empty(acc, dtype=torch.int64, device="cuda")
+        vals_s = torch.empty(acc, dtype=torch.int64, device="cuda")
+        outs_s = [torch.empty(acc, dtype=torch.int64, device="cuda") for _ in range(5)]
+        ins_s = (isa.isa_input * n_s)()
+        outs_st = (isa.isa_output * n_s)()
+        off = 0
+        for j, i in enumerate(pick):
+            n = int(rows[i])
+            seed = datagen.substream_seed(6, i)
+            dgd.keys(datagen.substream_seed(seed, 1), n, int(d[i]), 0.0, out=keys_s[off:off + n])
+            dgd.uniform_i64(datagen.substream_seed(seed, 2), n, out=vals_s[off:off + n])
+            ins_s[j] = isa.isa_input(keys_s[off:].data_ptr(), vals_s[off:].data_ptr(), None, n)
+            outs_st[j] = isa.isa_output(outs_s[0][off:].data_ptr(), outs_s[1][off:].data_ptr(),
+                                        outs_s[2][off:].data_ptr(), None, outs_s[3][off:].data_ptr(),
+                                        outs_s[4][off:].data_ptr(), n, 0)
+            off += n
+        torch.cuda.synchronize()
+        nc = L.isa_tune_candidates(None, 0)
+        times = (isa.ctypes.c_double * nc)()
+        best = isa.isa_tuning()
+        rc = L.isa_tune_batch(ctx.handle, n_s, ins_s, aggs, wss, outs_st, sp, isa.ctypes.byref(best), times, nc)
+        if rc != isa.ISA_OK:
+            raise isa.InsortError(rc, ctx.last_error())
+        tuned = best.as_dict()
+        cands = isa.tune_candidates()
+        dflt = cands.index(isa.Context.default_tuning())
+        tune_info.update({"sample_instances": n_s, "sample_rows": acc,
+                          "sample_ms_default": round(times[dflt], 3),
+                          "sample_ms_tuned": round(min(times[i] for i in range(nc)), 3), "candidates": nc})
+        table.record(sig, tuned, min(times[i] for i in range(nc)))
+        print("bench: tuned %s on %d sampled instances" % (tuned, n_s), file=sys.stderr, flush=True)
+        del keys_s, vals_s, outs_s
     while i0 < count:
         i1, acc = i0, 0
         while i1 < count and (acc + rows[i1] <= wave_rows or i1 == i0):
@@ -126,21 +171,6 @@ def bench_batch(args, lo, hi):
             if rc != isa.ISA_OK:
                 raise isa.InsortError(rc, ctx.last_error())
 
-        if tuned is None:
-            nc = L.isa_tune_candidates(None, 0)
-            times = (isa.ctypes.c_double * nc)()
-            best = isa.isa_tuning()
-            rc = L.isa_tune_batch(ctx.handle, n_w, ins, aggs, wss, outs, sp, isa.ctypes.byref(best), times, nc)
-            if rc != isa.ISA_OK:
-                raise isa.InsortError(rc, ctx.last_error())
-            tuned = best.as_dict()
-            cands = isa.tune_candidates()
-            dflt = cands.index(isa.Context.default_tuning())
-            tune_info.update({"first_wave_ms_default": round(times[dflt], 3),
-                              "first_wave_ms_tuned": round(min(times[i] for i in range(nc)), 3),
-                              "candidates": nc})
-            table.record(sig, tuned, min(times[i] for i in range(nc)))
-            print("bench: tuned %s" % tuned, file=sys.stderr, flush=True)
         batched()  # warm
         ctx.set_tuning(**tuned)
         torch.cuda.synchronize()

@@ -115,6 +115,10 @@ typedef struct {
     double t_rungen_ms;       /* wall time of run generation                      */
     double t_merge_ms;        /* wall time of the wide merge and output           */
     double t_plan_ms;         /* host time of the wide merge before its first read */
+    uint64_t merge_steps;     /* preliminary merge steps before the wide merge    */
+    uint64_t merge_rows;      /* rows those steps wrote to temporary storage      */
+    uint64_t resident_capacity; /* hybrid: keys the resident index may hold (else 0) */
+    uint64_t run_capacity;    /* keys the run-generation index may hold           */
 } isa_stats;
 
 /* Create a context on HIP device `device`.  Returns ISA_EDEVICE if the device
@@ -148,6 +152,39 @@ uint64_t isa_min_workspace_bytes(uint32_t aggs);
 isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs,
                         isa_workspace ws, isa_spill spill, isa_output* out,
                         isa_stats* stats, void* stream);
+
+/*
+ * Group on a key of n_cols int64 columns (ascending, lexicographic, each
+ * column signed), with offset-value codes deciding the groups (Section 2: the
+ * table of offset-value codes and duplicate removal with them; Section 5: a
+ * row's columns are compared at most once, N x K column accesses in all).
+ * The rows are ordered by a stable radix sort, one column at a time; every
+ * row of the sorted stream is then coded against its predecessor: its offset
+ * is the number of leading columns equal to the predecessor's, its value the
+ * row's value in the first column that differs (the first row: offset 0).  A
+ * row starts a group exactly when its offset is below n_cols (a duplicate has
+ * offset n_cols), so the in-stream grouping decides each row with one code.
+ *
+ * key_cols, out_cols: HOST arrays of n_cols device pointers (input columns of
+ * n_rows values; output columns of out->capacity values, the group keys in
+ * order).  v_i64: the value column (device), required for SUM_I64, MIN_I64,
+ * MAX_I64.  aggs: any of ISA_COUNT, ISA_SUM_I64, ISA_MIN_I64, ISA_MAX_I64 (0:
+ * duplicate removal); out->keys is unused.  code_offset (uint32) and
+ * code_value (int64), both optional device arrays of n_rows entries, receive
+ * the sorted stream's codes (code_value is 0 for a duplicate).
+ * *column_compares (optional, host) receives the column values compared to
+ * code the stream: at most (n_rows - 1) * n_cols.  No spilling: the
+ * workspace must hold isa_columns_workspace_bytes(n_rows, n_cols).
+ * Errors: ISA_EINVAL (null pointers, n_cols outside 1..ISA_MAX_KEY_COLUMNS,
+ * ISA_SUM_F64 requested, n_rows >= 2^32), ISA_EBUDGET, ISA_ETRUNC
+ * (out->n_groups = required), ISA_EDEVICE.
+ */
+enum { ISA_MAX_KEY_COLUMNS = 16 };
+isa_status isa_group_by_columns(isa_ctx* ctx, const int64_t* const* key_cols, uint32_t n_cols,
+                                const int64_t* v_i64, uint64_t n_rows, uint32_t aggs, isa_workspace ws,
+                                int64_t* const* out_cols, isa_output* out, uint32_t* code_offset,
+                                int64_t* code_value, uint64_t* column_compares, void* stream);
+uint64_t isa_columns_workspace_bytes(uint64_t n_rows, uint32_t n_cols);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph
@@ -252,14 +289,30 @@ uint64_t isa_batch_workspace_bytes(uint32_t n_inst, const isa_input* inst, uint3
  *    for sorted input.
  * Held per context; ISA_EINVAL for an unknown policy.
  */
-enum { ISA_RUNGEN_READ_SORT_WRITE = 0, ISA_RUNGEN_REPLACEMENT = 1 };
+enum { ISA_RUNGEN_READ_SORT_WRITE = 0, ISA_RUNGEN_REPLACEMENT = 1, ISA_RUNGEN_HYBRID = 2 };
 isa_status isa_set_run_generation(isa_ctx* ctx, int policy);
+/*
+ * ISA_RUNGEN_HYBRID, hybrid run generation (Section 5, hybrid algorithms):
+ * the index memory is divided between a resident index, which removes the
+ * duplicates of the key values assigned to it for good, and a run-generation
+ * index for the other key values, written as a run whenever it cannot absorb a
+ * batch (read-sort-write).  Key values are assigned as the input arrives:
+ * keys below a cut stay resident; the cut starts above every key, and when the
+ * resident index outgrows its share, its keys beyond the first three quarters
+ * of that share are written as one run and the cut moves down to the first
+ * of them.  Both indexes join the final wide merge.  isa_set_resident_share
+ * sets the resident index's share of the index memory in thousandths
+ * (default 800, the share of the paper's example; the run-generation index
+ * keeps at least one batch); a share that leaves the resident index smaller
+ * than a batch means no resident index.  ISA_EINVAL above 1000.
+ */
+isa_status isa_set_resident_share(isa_ctx* ctx, uint32_t permille);
 int isa_get_run_generation(isa_ctx* ctx); /* the policy, or -1 for a NULL context */
 
 /*
  * Launch configuration of the device plans, held per context: the search
  * space of the autotuner below.  It changes speed only, never results.
- * Defaults: leaf_rows 2048, chunk_split 512, graph 1.
+ * Defaults: leaf_rows 2048, chunk_split 512, graph 1, merge_fanin 0.
  */
 typedef struct {
     uint32_t leaf_rows;    /* target rows per sort leaf (buckets per partition = rows / leaf_rows,
@@ -268,7 +321,11 @@ typedef struct {
                               to 4096..16384; 64..4096 */
     uint32_t graph;        /* 1: a wave of small batched instances launches as one captured HIP
                               graph; 0: direct launches */
-    uint32_t reserved;     /* must be 0 */
+    uint32_t merge_fanin;  /* runs one merge step of isa_group_by may take (Section 4's merge
+                              fan-in F): 0 = every run in one wide merge while a window fits
+                              the workspace; 2..65536 = when more runs were written, preliminary
+                              merge steps of the smallest runs come first (Section 4, Example 4)
+                              so that the final wide merge takes at most this many */
 } isa_tuning;
 isa_status isa_get_tuning(isa_ctx* ctx, isa_tuning* out);
 /* ISA_EINVAL when a field is outside its range. */

@@ -25,12 +25,16 @@ from __future__ import annotations
 import numpy as np
 
 
-def simulate(keys, batch_rows: int, capacity: int):
+def simulate(keys, batch_rows: int, capacity: int, keep_runs: bool = False):
+    """Read-sort-write cycles at batch granularity (see the module docstring).
+    With ``keep_runs`` the result also holds ``run_keys``: each run's sorted
+    keys, in the order the runs were written."""
     if batch_rows <= 0 or capacity <= 0 or batch_rows > capacity:
         raise ValueError("need 0 < batch_rows <= capacity")
     keys = np.asarray(keys, dtype=np.uint64)
     index = np.empty(0, np.uint64)
     run_sizes = []
+    run_keys = []
     for start in range(0, keys.shape[0], batch_rows):
         batch = np.unique(keys[start:start + batch_rows])
         merged = np.union1d(index, batch)
@@ -38,9 +42,72 @@ def simulate(keys, batch_rows: int, capacity: int):
             index = merged
         else:
             run_sizes.append(int(index.shape[0]))
+            if keep_runs:
+                run_keys.append(index)
             index = batch
-    return {"runs": len(run_sizes), "spilled_rows": int(sum(run_sizes)),
-            "run_sizes": run_sizes, "final_index_rows": int(index.shape[0])}
+    out = {"runs": len(run_sizes), "spilled_rows": int(sum(run_sizes)),
+           "run_sizes": run_sizes, "final_index_rows": int(index.shape[0])}
+    if keep_runs:
+        out["run_keys"] = run_keys
+    return out
+
+
+def simulate_hybrid(keys, batch_rows: int, resident_capacity: int, run_capacity: int):
+    """Hybrid run generation (Section 5, hybrid algorithms): part of memory
+    holds an in-memory index that removes duplicates of the key values
+    assigned to it, for good; the rest generates runs for the other key
+    values by read-sort-write cycles.
+
+    Batch-granular reading, with the assignment of key values made as the
+    input arrives: the resident index holds every key below a cut, which
+    starts above every key.  A batch's distinct keys below the cut join the
+    resident index; when it then holds more than ``resident_capacity`` keys,
+    its largest keys beyond the smallest three quarters of that capacity are
+    written, in key order, as one run and the cut moves down to the smallest
+    of them (those key values are from then on assigned to runs).  The batch's
+    keys at or above the cut are absorbed into the run-generation index if
+    the union fits ``run_capacity`` keys; otherwise that index is written as
+    a run and those keys start the next one.  A batch's keys at or above the
+    cut are split off before the demotion that the batch may cause.  Both
+    indexes stay in memory at the end.  Runs are listed in the order they are
+    written (per batch: the run-generation index first, then a demotion)."""
+    if batch_rows <= 0 or batch_rows > run_capacity or (0 < resident_capacity < 4) or resident_capacity < 0:
+        raise ValueError("need 0 < batch_rows <= run_capacity and resident_capacity 0 or >= 4")
+    keys = np.asarray(keys, dtype=np.uint64)
+    keep = resident_capacity * 3 // 4
+    resident = np.empty(0, np.uint64)
+    gen = np.empty(0, np.uint64)
+    # a Python int: every key is below it; with no resident index every key
+    # is assigned to runs from the start
+    cut = 1 << 64 if resident_capacity else 0
+    run_sizes = []
+    kinds = []
+    for start in range(0, keys.shape[0], batch_rows):
+        batch = np.unique(keys[start:start + batch_rows])
+        if cut >= 1 << 64:
+            p = batch.shape[0]
+        else:
+            p = int(np.searchsorted(batch, np.uint64(cut), "left"))
+        lo, hi = batch[:p], batch[p:]
+        # run generation for the keys assigned to runs
+        merged = np.union1d(gen, hi)
+        if merged.shape[0] <= run_capacity:
+            gen = merged
+        else:
+            run_sizes.append(int(gen.shape[0]))
+            kinds.append("run")
+            gen = hi
+        # the resident index
+        resident = np.union1d(resident, lo)
+        if resident.shape[0] > resident_capacity:
+            demoted = resident[keep:]
+            run_sizes.append(int(demoted.shape[0]))
+            kinds.append("demotion")
+            cut = int(demoted[0])
+            resident = resident[:keep]
+    return {"runs": len(run_sizes), "spilled_rows": int(sum(run_sizes)), "run_sizes": run_sizes,
+            "run_kinds": kinds, "final_index_rows": int(resident.shape[0] + gen.shape[0]),
+            "resident_rows": int(resident.shape[0]), "cut": cut}
 
 
 def model_spill_rows(I: float, M: float, O: float) -> float:
@@ -132,6 +199,36 @@ def preliminary_merges(run_rows, fan_in: int, out_bound: float):
         written += merged
         counts.append(len(runs))
     return {"counts": counts, "written_rows": written, "final_runs": runs}
+
+
+def preliminary_merges_exact(run_keys, fan_in: int):
+    """The same merge steps on actual runs (their sorted key sets): a step
+    takes the smallest runs, ties broken by the order in which runs were
+    written (a merged run counts as written when its step ends), and writes
+    the union of their keys as one run, since equal keys combine.  Returns the
+    run count after each step, the rows each step wrote, their total, and the
+    final runs' sizes in written order."""
+    F = int(fan_in)
+    if F < 2:
+        raise ValueError("fan-in below 2")
+    runs = [(np.asarray(r, dtype=np.uint64), i) for i, r in enumerate(run_keys)]
+    seq = len(runs)
+    counts = [len(runs)]
+    step_rows = []
+    first = True
+    while len(runs) > F:
+        extra = (len(runs) - F) % (F - 1)
+        take = extra + 1 if first and extra else F
+        first = False
+        order = sorted(range(len(runs)), key=lambda j: (runs[j][0].shape[0], runs[j][1]))
+        chosen = set(order[:take])
+        merged = np.unique(np.concatenate([runs[j][0] for j in order[:take]]))
+        runs = [r for j, r in enumerate(runs) if j not in chosen] + [(merged, seq)]
+        seq += 1
+        step_rows.append(int(merged.shape[0]))
+        counts.append(len(runs))
+    return {"counts": counts, "step_rows": step_rows, "written_rows": int(sum(step_rows)),
+            "final_run_sizes": [int(r[0].shape[0]) for r in runs]}
 
 
 def hybrid_plan(I: float, M: float, O: float, F: int, P: float = None):

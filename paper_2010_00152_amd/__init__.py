@@ -34,6 +34,7 @@ ISA_ALL = ISA_COUNT | ISA_SUM_I64 | ISA_SUM_F64 | ISA_MIN_I64 | ISA_MAX_I64
 ISA_INT_AGGS = ISA_COUNT | ISA_SUM_I64 | ISA_MIN_I64 | ISA_MAX_I64
 ISA_RUNGEN_READ_SORT_WRITE = 0
 ISA_RUNGEN_REPLACEMENT = 1
+ISA_RUNGEN_HYBRID = 2
 
 P = ctypes.c_void_p
 U64 = ctypes.c_uint64
@@ -61,7 +62,9 @@ class isa_stats(ctypes.Structure):
     _fields_ = [("runs", U64), ("spilled_rows", U64), ("spilled_bytes", U64), ("windows", U64),
                 ("batches", U64), ("index_capacity", U64), ("batch_rows", U64),
                 ("peak_ws_bytes", U64), ("t_rungen_ms", ctypes.c_double),
-                ("t_merge_ms", ctypes.c_double), ("t_plan_ms", ctypes.c_double)]
+                ("t_merge_ms", ctypes.c_double), ("t_plan_ms", ctypes.c_double),
+                ("merge_steps", U64), ("merge_rows", U64), ("resident_capacity", U64),
+                ("run_capacity", U64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -73,10 +76,11 @@ class isa_kernel_time(ctypes.Structure):
 
 
 class isa_tuning(ctypes.Structure):
-    _fields_ = [("leaf_rows", U32), ("chunk_split", U32), ("graph", U32), ("reserved", U32)]
+    _fields_ = [("leaf_rows", U32), ("chunk_split", U32), ("graph", U32), ("merge_fanin", U32)]
 
     def as_dict(self):
-        return {"leaf_rows": self.leaf_rows, "chunk_split": self.chunk_split, "graph": self.graph}
+        return {"leaf_rows": self.leaf_rows, "chunk_split": self.chunk_split, "graph": self.graph,
+                "merge_fanin": self.merge_fanin}
 
 
 # Every function the header declares: name -> (restype, argtypes)
@@ -89,6 +93,10 @@ SIGNATURES = {
                                     ctypes.POINTER(isa_output), ctypes.POINTER(isa_stats), P]),
     "isa_group_by_noalloc": (ctypes.c_int, [P, ctypes.POINTER(isa_input), U32, ctypes.POINTER(isa_output), P]),
     "isa_noalloc_max_rows": (U64, [U32]),
+    "isa_group_by_columns": (ctypes.c_int, [P, ctypes.POINTER(P), U32, P, U64, U32, isa_workspace,
+                                            ctypes.POINTER(P), ctypes.POINTER(isa_output), P, P,
+                                            ctypes.POINTER(U64), P]),
+    "isa_columns_workspace_bytes": (U64, [U64, U32]),
     "isa_group_by_segmented": (ctypes.c_int, [P, P, P, P, U64, U32, isa_workspace, P, P,
                                               ctypes.POINTER(isa_output), P]),
     "isa_group_by_sorted": (ctypes.c_int, [P, ctypes.POINTER(isa_input), U32, isa_workspace,
@@ -112,6 +120,7 @@ SIGNATURES = {
     "isa_profile_read": (ctypes.c_int, [P, ctypes.POINTER(isa_kernel_time), ctypes.c_int]),
     "isa_set_run_generation": (ctypes.c_int, [P, ctypes.c_int]),
     "isa_get_run_generation": (ctypes.c_int, [P]),
+    "isa_set_resident_share": (ctypes.c_int, [P, U32]),
     "isa_get_tuning": (ctypes.c_int, [P, ctypes.POINTER(isa_tuning)]),
     "isa_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(isa_tuning)]),
     "isa_tune_candidates": (U32, [ctypes.POINTER(isa_tuning), U32]),
@@ -195,6 +204,11 @@ class Context:
         if st != ISA_OK:
             raise InsortError(st, self.last_error())
 
+    def set_resident_share(self, permille: int):
+        st = lib().isa_set_resident_share(self.handle, permille)
+        if st != ISA_OK:
+            raise InsortError(st, self.last_error())
+
     def get_run_generation(self) -> int:
         return lib().isa_get_run_generation(self.handle)
 
@@ -208,10 +222,10 @@ class Context:
     @staticmethod
     def default_tuning() -> dict:
         """The launch configuration a new context starts with."""
-        return {"leaf_rows": 2048, "chunk_split": 512, "graph": 1}
+        return {"leaf_rows": 2048, "chunk_split": 512, "graph": 1, "merge_fanin": 0}
 
-    def set_tuning(self, leaf_rows: int = 2048, chunk_split: int = 512, graph: int = 1):
-        t = isa_tuning(leaf_rows, chunk_split, graph, 0)
+    def set_tuning(self, leaf_rows: int = 2048, chunk_split: int = 512, graph: int = 1, merge_fanin: int = 0):
+        t = isa_tuning(leaf_rows, chunk_split, graph, merge_fanin)
         st = lib().isa_set_tuning(self.handle, ctypes.byref(t))
         if st != ISA_OK:
             raise InsortError(st, "tuning %r" % (t.as_dict(),))
@@ -332,6 +346,40 @@ def count_distinct(ctx: Context, g, x, mem_budget: int = 256 << 20, capacity: in
         raise InsortError(status, ctx.last_error())
     k = min(ng.value, cap)
     return {"g": og[:k], "count": oc[:k], "distinct": od[:k]}, status, ng.value
+
+
+def group_by_columns(ctx: Context, cols, v=None, aggs: int = ISA_COUNT | ISA_SUM_I64, mem_budget: int | None = None,
+                     capacity: int | None = None, codes: bool = False, check: bool = True, workspace=None):
+    """isa_group_by_columns: group on the int64 columns `cols` (device tensors
+    of equal length).  Returns (result dict with "cols" (list of key columns)
+    and the aggregate columns, codes dict or None, column compares, status,
+    n_groups)."""
+    import torch
+    K = len(cols)
+    n = cols[0].numel()
+    dev = cols[0].device
+    cap = n if capacity is None else capacity
+    need = lib().isa_columns_workspace_bytes(n, K)
+    budget = need if mem_budget is None else mem_budget
+    ws = workspace if workspace is not None else torch.empty(max(budget, 256), dtype=torch.uint8, device=dev)
+    o = _alloc_outputs(torch, cap, aggs, dev, with_keys=False)
+    outc = [torch.empty(max(cap, 1), dtype=torch.int64, device=dev) for _ in range(K)]
+    out = _output_struct(o, cap)
+    kin = (P * K)(*[_ptr(c) for c in cols])
+    kout = (P * K)(*[_ptr(c) for c in outc])
+    co = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if codes else None
+    cv = torch.empty(max(n, 1), dtype=torch.int64, device=dev) if codes else None
+    cmp = U64()
+    st = lib().isa_group_by_columns(ctx.handle, kin, K, _ptr(v), n, aggs, isa_workspace(_ptr(ws), budget), kout,
+                                    ctypes.byref(out), _ptr(co), _ptr(cv), ctypes.byref(cmp), _stream_ptr())
+    if check and st not in (ISA_OK, ISA_ETRUNC):
+        raise InsortError(st, ctx.last_error())
+    g = out.n_groups
+    k = min(g, cap)
+    res = {c: t[:k] for c, t in o.items()}
+    res["cols"] = [c[:k] for c in outc]
+    cd = {"offset": co[:n], "value": cv[:n]} if codes else None
+    return res, cd, cmp.value, st, g
 
 
 def group_by_segmented(ctx: Context, a, b, v=None, aggs: int = ISA_INT_AGGS, mem_budget: int = 256 << 20,

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <queue>
 #include <string>
@@ -20,6 +21,8 @@ using namespace isa;
 struct isa_ctx {
     int device = 0;
     int rungen = ISA_RUNGEN_READ_SORT_WRITE;
+    // hybrid run generation: the resident index's share of the index memory
+    uint32_t resident_permille = 800;
     // device address of the library-owned scratch on this context's device
     // (looked up at creation), used only by isa_group_by_noalloc
     void* scratch = nullptr;
@@ -213,9 +216,20 @@ uint64_t lower_bound_strided(const uint64_t* keys, uint64_t stride, uint64_t pos
 // sequence as key-ordered instances sharing the window's destination.
 constexpr uint64_t PIECE_CAP = FLAT_MAX * 3 / 4;
 
+// A preliminary merge step (Section 4, Example 4: steps that merge the
+// smallest runs before a wide merge) writes its merged rows as one more run
+// of state rows into the spill buffer, from byte `off` on, instead of into
+// the caller's output.
+struct RunSink {
+    char* host = nullptr;  // the spill buffer (host address)
+    uint64_t off = 0;      // where the run starts
+    uint64_t cap = 0;      // bytes available from off
+    uint64_t rows = 0;     // rows written
+};
+
 void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::vector<RunInfo>& runs,
                 const char* host, uint64_t* idx, uint64_t n_idx, isa_output* out, isa_stats* st,
-                uint64_t& n_groups) {
+                uint64_t& n_groups, RunSink* sink = nullptr) {
     const double t_enter = now_ms();
     const Layout S = state_layout(k);
     const Layout Rl = raw_layout(k);
@@ -272,12 +286,12 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     auto win_task_bound = [&](uint64_t w) { return w / GATHER_ROWS + (ns + 1) * (w / (PIECE_CAP / 2) + 2) + 16; };
     auto need = [&](uint64_t w) {
         const uint64_t pieces = w / (PIECE_CAP / 2) + 2;
-        return 3 * w * sw * 8 + 3 * win_task_bound(w) * sizeof(GatherTask) +
+        return (sink ? 4 : 3) * w * sw * 8 + 3 * win_task_bound(w) * sizeof(GatherTask) +
                std::max(flat_bytes(w, pieces, k, true), std::min(piece_fallback, sort_reduce_bytes(w, 1, k, true)));
     };
     // every window but the last holds at least 3/4 W rows (fences every P rows)
     auto task_bound = [&](uint64_t w) { return (total / (w - w / 4) + 2) * win_task_bound(w); };
-    uint64_t W = avail0 / (3 * sw * 8);
+    uint64_t W = avail0 / ((sink ? 4 : 3) * sw * 8);
     while (W > 2 * (ns + 1) && need(W) > avail0) W -= W / 32 + 1;
     // ISA_FORCE_INDEX_SPILL=1 treats a merge beside an in-memory index as not
     // fitting (it lets tests reach the caller's fallback with ordinary inputs)
@@ -453,6 +467,7 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     };
     uint64_t* stage[3];
     for (int j = 0; j < 3; ++j) stage[j] = A.take_n<uint64_t>(W * sw);
+    uint64_t* sink_rows = sink ? A.take_n<uint64_t>(W * sw) : nullptr;
     // output cursors on the device: window w starts at the end row that
     // window w-1 wrote (cur[(w+1) % 2]) and writes its own end to cur[w % 2]
     uint64_t* d_cur = A.take_n<uint64_t>(2);
@@ -499,6 +514,54 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     ck(hipEventRecord(E.sync_event(4), E.stream), "hipEventRecord");
     ck(hipStreamWaitEvent(gs, E.sync_event(4), 0), "hipStreamWaitEvent");
 
+    if (sink) {
+        // A preliminary merge step: windows one at a time, each reduced into
+        // a device buffer whose rows are then appended to the new run in the
+        // spill buffer.
+        for (size_t w = 0; w < 2 && have(w); ++w) issue(w);
+        for (size_t w = 0; have(w); ++w) {
+            if (have(w + 2)) {
+                if (w >= 1) ck(hipStreamWaitEvent(gs, ev_reduce(w - 1), 0), "hipStreamWaitEvent");
+                issue(w + 2);
+            }
+            ck(hipStreamWaitEvent(E.stream, ev_gather(w), 0), "hipStreamWaitEvent");
+            A.off = mark;
+            Dest d;
+            d.out = aos_out(sink_rows, S);
+            d.capacity = W;
+            const std::vector<Instance> inst = pieces_of(w);
+            uint64_t g = 0;
+            std::vector<uint64_t> gv;
+            if (sort_reduce_flat(E, A, inst, std::vector<Dest>(1, d), k, true, nullptr, false, gv)) {
+                g = gv[0];
+            } else {
+                for (const Instance& x : inst) {
+                    A.off = mark;
+                    Dest dx = d;
+                    dx.out = aos_out(sink_rows + g * sw, S);
+                    dx.capacity = W - g;
+                    g += sort_reduce(E, A, std::vector<Instance>(1, x), std::vector<Dest>(1, dx), k, true)[0];
+                }
+            }
+            ck(hipEventRecord(ev_reduce(w), E.stream), "hipEventRecord");
+            const uint64_t bytes = g * sw * 8;
+            if ((sink->rows * sw * 8) + bytes > sink->cap) throw Fail{ISA_ESPILL, "spill buffer too small"};
+            if (g) {
+                E.pbegin("merge_d2h");
+                ck(hipMemcpyAsync(sink->host + sink->off + sink->rows * sw * 8, sink_rows, bytes,
+                                  hipMemcpyDeviceToHost, E.stream),
+                   "hipMemcpyAsync(merged run)");
+                E.pend(g, bytes);
+            }
+            E.sync();  // the device buffer is reused by the next window
+            sink->rows += g;
+        }
+        ck(hipStreamSynchronize(gs), "hipStreamSynchronize(gather)");
+        ck(hipStreamSynchronize(us), "hipStreamSynchronize(upload)");
+        A.off = mark;
+        n_groups = sink->rows;
+        return;
+    }
     // First pass, without host round trips: every window's reduction is
     // enqueued behind its gather and places its groups after the device-side
     // cursor of the window before; a gather into stage[w % 3] waits for the
@@ -796,6 +859,31 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
         } else {
             Plan p;
             if (!plan_batches(ws.bytes, n, k, p)) return ISA_EBUDGET;
+            // Hybrid run generation: the index memory is shared by a resident
+            // index (Kr keys) and a run-generation index (Kw keys, at least a
+            // batch), and runs are compacted in a staging area of their own
+            // (a run-generation index and a demotion at most).
+            const bool hy = ctx->rungen == ISA_RUNGEN_HYBRID;
+            uint64_t Kr = 0, Kw = 0, st_rows = 0;
+            if (hy) {
+                // plan with the staging area set aside, until the plan and
+                // its staging area fit together
+                const uint64_t swb = (uint64_t)S.words * 8;
+                uint64_t stage_bytes = 0;
+                bool fits = false;
+                for (int it = 0; it < 16 && !fits; ++it) {
+                    if (stage_bytes >= ws.bytes || !plan_batches(ws.bytes - stage_bytes, n, k, p)) return ISA_EBUDGET;
+                    Kw = std::max<uint64_t>(p.batch_rows, p.capacity * (1000 - ctx->resident_permille) / 1000);
+                    Kr = p.capacity > Kw ? p.capacity - Kw : 0;
+                    // a resident index smaller than a batch is no resident index
+                    if (Kr < p.batch_rows) Kr = 0;
+                    st_rows = Kr / 4 + Kw + p.batch_rows;
+                    const uint64_t need = st_rows * swb + 4096;
+                    fits = rungen_bytes(p.batch_rows, p.capacity, k) + need <= ws.bytes;
+                    stage_bytes = std::max(need, stage_bytes + stage_bytes / 8 + 4096);
+                }
+                if (!fits) return ISA_EBUDGET;
+            }
             const uint64_t buf_rows = p.capacity + p.batch_rows;
             const uint64_t buf_bytes = buf_rows * sw * 8;
             uint64_t* idx[2];
@@ -818,7 +906,11 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             const bool rs = ctx->rungen == ISA_RUNGEN_REPLACEMENT;
             uint64_t* rs_cur = A.take_n<uint64_t>(2);
             launch_fill(rs_cur, 2, 0, E.stream);
+            // hybrid: the cut below which keys stay resident, in the same two
+            // words (key, above-every-key flag); it starts above every key
+            if (hy && Kr) launch_fill(rs_cur + 1, 1, 1, E.stream);
             uint64_t* m_splits = A.take_n<uint64_t>(2 * (mscr_parts + 1));
+            uint64_t* hy_stage = hy ? A.take_n<uint64_t>(st_rows * sw) : nullptr;
             // compact runs need a count column and a raw row narrower than a state row
             const Layout Rl = raw_layout(k);
             const bool compact = S.cnt >= 0 && Rl.words < S.words;
@@ -1041,7 +1133,110 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             // idx[target]: keep the merged index if it holds at most K keys;
             // else spill the old index and start a new one with the batch run
             // (read-sort-write), or evict the excess (replacement selection)
+            // Hybrid run generation (Section 5, hybrid algorithms).  The
+            // index is one sorted array: the resident rows (keys below the
+            // cut) followed by the run-generation rows (keys at or above it).
+            // After an absorb, with p resident rows of m: if the run-generation
+            // part exceeds Kw, the old index's run-generation part is written
+            // as a run and the batch's rows at or above the cut replace it; if
+            // the resident part exceeds Kr, its rows beyond the first
+            // 3/4 Kr are written as a run (a demotion) and the cut moves down
+            // to the first of them.  Runs are compacted into the staging area
+            // and copied out on the copy stream.
+            uint64_t n_res = 0;  // resident rows of the index
+            auto write_runs = [&](const std::vector<std::pair<const uint64_t*, uint64_t>>& rr) {
+                if (!spill.host_pinned) throw Fail{ISA_ESPILL, "spill buffer too small"};
+                // the staging area's last copy must be done
+                ck(hipStreamWaitEvent(E.stream, E.sync_event(1), 0), "hipStreamWaitEvent");
+                uint64_t at = 0;
+                std::vector<uint64_t> at_of;
+                for (size_t r = 0; r < rr.size(); ++r) {
+                    at_of.push_back(at);
+                    if (compact) {
+                        launch_split(rr[r].first, rr[r].second, S, Rl, sp_counts, sp_tiles, sp_offs,
+                                     hy_stage + at, 0, E.stream);
+                        ck(hipMemcpyAsync(E.ring_slot(16 + r), sp_offs + split_blocks(rr[r].second), 16,
+                                          hipMemcpyDeviceToHost, E.stream),
+                           "hipMemcpyAsync(split count)");
+                    } else {
+                        launch_copy_words(rr[r].first, hy_stage + at, rr[r].second * sw, E.stream);
+                    }
+                    at += rr[r].second * sw;
+                }
+                ck(hipEventRecord(E.sync_event(2), E.stream), "hipEventRecord");
+                ck(hipEventSynchronize(E.sync_event(2)), "hipEventSynchronize(split count)");
+                ck(hipStreamWaitEvent(cs, E.sync_event(2), 0), "hipStreamWaitEvent");
+                for (size_t r = 0; r < rr.size(); ++r) {
+                    const uint64_t n_run = rr[r].second;
+                    uint64_t n_single = 0, bytes = n_run * sw * 8;
+                    bool narrow = false;
+                    if (compact) {
+                        n_single = ((const uint64_t*)E.ring_slot(16 + r))[0];
+                        narrow = ((const uint64_t*)E.ring_slot(16 + r))[1] != 0;
+                        bytes = single_bytes(n_single, Rl, narrow) + (n_run - n_single) * sw * 8;
+                    }
+                    if (spill_used + bytes > spill.bytes) throw Fail{ISA_ESPILL, "spill buffer too small"};
+                    E.pbegin("spill_d2h", cs);
+                    ck(hipMemcpyAsync(spill_dev + spill_used, hy_stage + at_of[r], bytes, hipMemcpyDeviceToDeviceNoCU,
+                                      cs),
+                       "hipMemcpyAsync(spill)");
+                    E.pend(n_run, bytes, cs);
+                    RunInfo ri;
+                    ri.byte_off = spill_used;
+                    ri.n_single = n_single;
+                    ri.n_multi = n_run - n_single;
+                    ri.narrow = narrow;
+                    runs.push_back(ri);
+                    spill_used += bytes;
+                    spilled += n_run;
+                    spilled_bytes += bytes;
+                }
+                ck(hipEventRecord(E.sync_event(1), cs), "hipEventRecord");
+            };
+            auto decide_hybrid = [&](uint64_t j, uint64_t gj, int target) {
+                const uint64_t* h = (const uint64_t*)rb_merge(j);
+                if (h[0] >> 32) throw Fail{ISA_EDEVICE, "merge placement wait timed out"};
+                const uint64_t m = h[1], pr = h[2], pb = h[3];
+                const bool spill_w = m - pr > Kw;
+                const bool demote = pr > Kr;
+                uint64_t* U = idx[target];
+                if (!spill_w && !demote) {
+                    ip = U;
+                    n_idx = m;
+                    n_res = pr;
+                    return;
+                }
+                const uint64_t q = demote ? Kr * 3 / 4 : pr;  // resident rows kept
+                std::vector<std::pair<const uint64_t*, uint64_t>> rr;
+                if (spill_w && n_idx > n_res) rr.push_back({ip + n_res * sw, n_idx - n_res});
+                if (demote) rr.push_back({U + q * sw, pr - q});
+                write_runs(rr);
+                if (demote) {
+                    launch_copy_words(U + q * sw, rs_cur, 1, E.stream);
+                    launch_fill(rs_cur + 1, 1, 0, E.stream);
+                }
+                uint64_t nw;
+                if (spill_w) {
+                    nw = gj - pb;
+                    launch_copy_words(brun[j % 3] + pb * sw, U + q * sw, nw * sw, E.stream);
+                } else {
+                    // move the run-generation rows down behind the kept
+                    // resident rows, in chunks no longer than the distance
+                    nw = m - pr;
+                    const uint64_t dist = pr - q;
+                    for (uint64_t c = 0; c < nw; c += dist) {
+                        const uint64_t len = std::min(dist, nw - c);
+                        launch_copy_words(U + (pr + c) * sw, U + (q + c) * sw, len * sw, E.stream);
+                    }
+                }
+                // the batch run and the index are read up to here
+                ck(hipEventRecord(ev_merge(j), E.stream), "hipEventRecord");
+                ip = U;
+                n_res = q;
+                n_idx = q + nw;
+            };
             auto decide = [&](uint64_t j, uint64_t gj, int target) {
+                if (hy) return decide_hybrid(j, gj, target);
                 const uint64_t* h = (const uint64_t*)rb_merge(j);
                 if (h[0] >> 32) throw Fail{ISA_EDEVICE, "merge placement wait timed out"};
                 const uint64_t m = h[1];
@@ -1098,6 +1293,9 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     inst[0].dest = 0;
                     g = sort_reduce(E, A, inst, std::vector<Dest>(1, bdest[slot]), k, false, &hint)[0];
                     A.off = top;
+                    // the batch's group count where the device reads it (the
+                    // hybrid policy's probe of the batch run)
+                    ((uint64_t*)rb_sort(i))[1] = g;
                     ck(hipEventRecord(E.sync_event(25), E.stream), "hipEventRecord");
                     ck(hipStreamWaitEvent(ss, E.sync_event(25), 0), "hipStreamWaitEvent");
                 }
@@ -1107,9 +1305,11 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     merge_out = false;
                 }
                 if (!ip) {
-                    // the first batch run is the index
+                    // the first batch run is the index (all resident under
+                    // hybrid run generation, unless no resident index)
                     ip = brun[slot];
                     n_idx = g;
+                    n_res = hy && Kr ? g : 0;
                     continue;
                 }
                 const int tgt = merge_target();
@@ -1124,6 +1324,12 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                              E.stream, m_ctl2[(i + 1) % 2], (uint32_t)mctl_words, rb_dev);
                 E.pend(n_idx + g, (n_idx + g) * sw * 8);
                 if (rs) launch_rs_probe(idx[tgt], m_ctl + 1, (uint32_t)sw, rs_cur, rb_dev + 2, E.stream);
+                if (hy) {
+                    // resident rows of the merged index and of the batch run
+                    launch_rs_probe(idx[tgt], m_ctl + 1, (uint32_t)sw, rs_cur, rb_dev + 2, E.stream);
+                    launch_rs_probe(brun[slot], E.ring_dev_of(rb_sort(i)) + 1, (uint32_t)sw, rs_cur, rb_dev + 3,
+                                    E.stream);
+                }
                 ck(hipEventRecord(ev_merge(i), E.stream), "hipEventRecord");
                 merged = true;
                 last_reader[slot] = (int64_t)i;
@@ -1149,6 +1355,8 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 stats->batches = batches;
                 stats->batch_rows = p.batch_rows;
                 stats->index_capacity = p.capacity;
+                stats->resident_capacity = hy ? Kr : 0;
+                stats->run_capacity = hy ? Kw : p.capacity;
                 stats->runs = runs.size();
                 stats->spilled_rows = spilled;
                 stats->spilled_bytes = spilled_bytes;
@@ -1164,36 +1372,153 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 // keep only the live index, at the front; everything after it
                 // is merge space
                 if (ip != idx[0]) launch_copy_words(ip, idx[0], n_idx * sw, E.stream);
-                A.off = (uint64_t)((char*)idx[0] - A.base) + n_idx * sw * 8;
-                try {
-                    wide_merge(E, A, k, aggs, runs, (const char*)spill.host_pinned, idx[0], n_idx, out, stats,
-                               n_groups);
-                } catch (const Fail& f) {
-                    // No window fits beside the final index (a full index under
-                    // replacement selection in a small workspace): write the
-                    // index out as one more run, which frees its room, and merge
-                    // from host memory alone.  Every spilled state row still
-                    // stands for at least one input row, so the spill buffer
-                    // of one state row per input row holds it.
-                    if (f.status != ISA_ESPILL || n_idx == 0) throw;
-                    const uint64_t bytes = n_idx * sw * 8;
-                    if (spill_used + bytes > spill.bytes) throw;
-                    ck(hipMemcpyAsync(spill_dev + spill_used, idx[0], bytes, hipMemcpyDeviceToDeviceNoCU, E.stream),
-                       "hipMemcpyAsync(spill index)");
-                    E.sync();
-                    runs.push_back(RunInfo{spill_used, 0, n_idx});
-                    spill_used += bytes;
-                    spilled += n_idx;
-                    spilled_bytes += bytes;
-                    if (stats) {
-                        stats->runs = runs.size();
-                        stats->spilled_rows = spilled;
-                        stats->spilled_bytes = spilled_bytes;
-                        stats->windows = 0;
+                const uint64_t idx_off = (uint64_t)((char*)idx[0] - A.base);
+                A.off = idx_off + n_idx * sw * 8;
+                // Preliminary merge steps (Section 4, Example 4): the smallest
+                // runs are merged first, so that a final merge of at most F
+                // runs remains.  The first step takes just enough runs that
+                // every later step merges F; each writes one run of state rows
+                // to the spill buffer.  Runs are ranked by rows, then by the
+                // order in which they were written.
+                std::vector<uint64_t> run_seq(runs.size());
+                for (size_t j = 0; j < runs.size(); ++j) run_seq[j] = j;
+                uint64_t next_seq = runs.size(), merge_steps = 0, merge_rows = 0;
+                auto run_rows = [](const RunInfo& r) { return r.n_single + r.n_multi; };
+                auto run_bytes = [&](const RunInfo& r) {
+                    return single_bytes(r.n_single, Rl, r.narrow) + r.n_multi * sw * 8;
+                };
+                // space of the spill buffer given back by merged runs (offset ->
+                // bytes), reused first fit; new space comes after spill_used
+                std::map<uint64_t, uint64_t> free_ext;
+                auto give_back = [&](uint64_t off, uint64_t bytes) {
+                    if (!bytes) return;
+                    auto it = free_ext.emplace(off, bytes).first;
+                    auto nx = std::next(it);
+                    if (nx != free_ext.end() && it->first + it->second == nx->first) {
+                        it->second += nx->second;
+                        free_ext.erase(nx);
                     }
-                    A.off = (uint64_t)((char*)idx[0] - A.base);
-                    wide_merge(E, A, k, aggs, runs, (const char*)spill.host_pinned, idx[0], 0, out, stats,
-                               n_groups);
+                    if (it != free_ext.begin()) {
+                        auto pv = std::prev(it);
+                        if (pv->first + pv->second == it->first) {
+                            pv->second += it->second;
+                            free_ext.erase(it);
+                        }
+                    }
+                };
+                auto take_space = [&](uint64_t bytes) -> uint64_t {
+                    for (auto it = free_ext.begin(); it != free_ext.end(); ++it) {
+                        if (it->second >= bytes) {
+                            const uint64_t off = it->first, rest = it->second - bytes;
+                            free_ext.erase(it);
+                            if (rest) free_ext[off + bytes] = rest;
+                            return off;
+                        }
+                    }
+                    if (spill_used + bytes > spill.bytes) throw Fail{ISA_ESPILL, "spill buffer too small"};
+                    const uint64_t off = spill_used;
+                    spill_used += bytes;
+                    return off;
+                };
+                auto prelim = [&](uint64_t F) {
+                    bool first = true;
+                    while (runs.size() > F) {
+                        const uint64_t nr = runs.size();
+                        const uint64_t extra = (nr - F) % (F - 1);
+                        const uint64_t take = first && extra ? extra + 1 : F;
+                        first = false;
+                        std::vector<size_t> order(nr);
+                        for (size_t j = 0; j < nr; ++j) order[j] = j;
+                        std::sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+                            const uint64_t rx = run_rows(runs[x]), ry = run_rows(runs[y]);
+                            return rx != ry ? rx < ry : run_seq[x] < run_seq[y];
+                        });
+                        std::vector<bool> used(nr, false);
+                        std::vector<RunInfo> sel;
+                        for (uint64_t j = 0; j < take; ++j) {
+                            used[order[j]] = true;
+                            sel.push_back(runs[order[j]]);
+                        }
+                        // the merged run has at most the rows of its inputs
+                        uint64_t bound = 0;
+                        for (const RunInfo& r : sel) bound += run_rows(r) * sw * 8;
+                        RunSink sk;
+                        sk.host = (char*)spill.host_pinned;
+                        sk.off = take_space(bound);
+                        sk.cap = bound;
+                        uint64_t g = 0;
+                        A.off = idx_off + n_idx * sw * 8;
+                        wide_merge(E, A, k, aggs, sel, (const char*)spill.host_pinned, idx[0], 0, out, nullptr, g,
+                                   &sk);
+                        std::vector<RunInfo> keep;
+                        std::vector<uint64_t> keep_seq;
+                        for (size_t j = 0; j < nr; ++j)
+                            if (!used[j]) {
+                                keep.push_back(runs[j]);
+                                keep_seq.push_back(run_seq[j]);
+                            }
+                        keep.push_back(RunInfo{sk.off, 0, sk.rows});
+                        keep_seq.push_back(next_seq++);
+                        runs.swap(keep);
+                        run_seq.swap(keep_seq);
+                        // the merged inputs' space and the unused end of the bound
+                        give_back(sk.off + sk.rows * sw * 8, bound - sk.rows * sw * 8);
+                        for (const RunInfo& r : sel) give_back(r.byte_off, run_bytes(r));
+                        ++merge_steps;
+                        merge_rows += sk.rows;
+                    }
+                };
+                if (E.tune.merge_fanin && runs.size() > E.tune.merge_fanin) prelim(E.tune.merge_fanin);
+                bool halved = false;
+                for (;;) {
+                    try {
+                        A.off = idx_off + n_idx * sw * 8;
+                        wide_merge(E, A, k, aggs, runs, (const char*)spill.host_pinned, idx[0], n_idx, out, stats,
+                                   n_groups);
+                        break;
+                    } catch (const Fail& f) {
+                        if (f.status != ISA_ESPILL) throw;
+                        if (n_idx) {
+                            // No window fits beside the final index (a full index
+                            // under replacement selection in a small workspace):
+                            // write the index out as one more run, which frees its
+                            // room, and merge from host memory alone.  Every
+                            // spilled state row still stands for at least one
+                            // input row, so the spill buffer of one state row per
+                            // input row holds it.
+                            const uint64_t bytes = n_idx * sw * 8;
+                            if (spill_used + bytes > spill.bytes) throw;
+                            ck(hipMemcpyAsync(spill_dev + spill_used, idx[0], bytes, hipMemcpyDeviceToDeviceNoCU,
+                                              E.stream),
+                               "hipMemcpyAsync(spill index)");
+                            E.sync();
+                            runs.push_back(RunInfo{spill_used, 0, n_idx});
+                            run_seq.push_back(next_seq++);
+                            spill_used += bytes;
+                            spilled += n_idx;
+                            spilled_bytes += bytes;
+                            if (stats) {
+                                stats->runs = runs.size();
+                                stats->spilled_rows = spilled;
+                                stats->spilled_bytes = spilled_bytes;
+                                stats->windows = 0;
+                            }
+                            n_idx = 0;
+                            continue;
+                        }
+                        // still no window fits all runs: merge the smallest runs
+                        // first, down to half as many
+                        if (!halved && runs.size() > 2) {
+                            halved = true;
+                            prelim(std::max<uint64_t>(2, runs.size() / 2));
+                            continue;
+                        }
+                        throw;
+                    }
+                }
+                if (stats) {
+                    stats->merge_steps = merge_steps;
+                    stats->merge_rows = merge_rows;
                 }
             }
             if (stats) {
@@ -1296,6 +1621,137 @@ uint64_t sorted_group(Engine& E, Arena& A, const ColView& V, uint64_t n, int shi
 }  // namespace
 
 extern "C" {
+
+uint64_t isa_columns_workspace_bytes(uint64_t n_rows, uint32_t n_cols) {
+    if (n_cols == 0 || n_cols > ISA_MAX_KEY_COLUMNS) return 0;
+    const uint64_t nb = rdx_blocks(n_rows) + 1;
+    const uint64_t hist = nb * 256;
+    // two (key, row) buffers, the histogram and its scan, heads and their
+    // scan, group numbers, group heads, the value column in sorted order, the
+    // sorted grouping's bookkeeping and the column pointer tables
+    return n_rows * (2 * 8 + 2 * 4) + hist * 4 + (hist + 1) * 8 + (scan_tiles(hist) + 1) * 8 + n_rows * 4 +
+           (n_rows + 1) * 8 + (scan_tiles(n_rows) + 1) * 8 + 3 * n_rows * 8 + (n_rows / 3584 + 8) * 64 +
+           (1u << 20);
+}
+
+isa_status isa_group_by_columns(isa_ctx* ctx, const int64_t* const* key_cols, uint32_t n_cols,
+                                const int64_t* v_i64, uint64_t n_rows, uint32_t aggs, isa_workspace ws,
+                                int64_t* const* out_cols, isa_output* out, uint32_t* code_offset,
+                                int64_t* code_value, uint64_t* column_compares, void* stream) {
+    if (out) out->n_groups = 0;
+    if (column_compares) *column_compares = 0;
+    if (!ctx || !key_cols || !out_cols || !out || n_cols == 0 || n_cols > ISA_MAX_KEY_COLUMNS) return ISA_EINVAL;
+    if ((aggs & ~(uint32_t)(ISA_COUNT | ISA_SUM_I64 | ISA_MIN_I64 | ISA_MAX_I64)) != 0) return ISA_EINVAL;
+    if ((aggs & (ISA_SUM_I64 | ISA_MIN_I64 | ISA_MAX_I64)) && !v_i64) return ISA_EINVAL;
+    isa_status s = check_output(out, aggs, false);
+    if (s != ISA_OK) return s;
+    if (n_rows == 0) return ISA_OK;
+    if (n_rows > 0xFFFFFFFFull) return ISA_EINVAL;  // rows are numbered in 32 bits
+    for (uint32_t c = 0; c < n_cols; ++c)
+        if (!key_cols[c] || !out_cols[c]) return ISA_EINVAL;
+    if (!ws.dev || ((uintptr_t)ws.dev & 255)) return ISA_EINVAL;
+    if (ws.bytes < isa_columns_workspace_bytes(n_rows, n_cols)) return ISA_EBUDGET;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    try {
+        ck(hipSetDevice(ctx->device), "hipSetDevice");
+        Engine& E = ctx->eng;
+        E.stream = (hipStream_t)stream;
+        Arena A;
+        A.base = (char*)ws.dev;
+        A.cap = ws.bytes;
+        const uint64_t n = n_rows;
+        const uint64_t nb = rdx_blocks(n);
+        const uint64_t hn = nb * 256;
+        uint64_t* keys[2] = {A.take_n<uint64_t>(n), A.take_n<uint64_t>(n)};
+        uint32_t* perm[2] = {A.take_n<uint32_t>(n), A.take_n<uint32_t>(n)};
+        uint32_t* hist = A.take_n<uint32_t>(hn);
+        uint64_t* hoffs = A.take_n<uint64_t>(hn + 1);
+        uint64_t* htiles = A.take_n<uint64_t>(scan_tiles(hn) + 1);
+        uint64_t* mm = A.take_n<uint64_t>(2);
+        // column pointer tables on the device
+        UpPack up;
+        const uint64_t o_in = up.add(key_cols, n_cols * sizeof(int64_t*));
+        const uint64_t o_out = up.add(out_cols, n_cols * sizeof(int64_t*));
+        char* d_up = up.commit(E, A);
+        const int64_t* const* d_cols = (const int64_t* const*)(d_up + o_in);
+        int64_t* const* d_out_cols = (int64_t* const*)(d_up + o_out);
+        // Stable LSD sort of the row order, the last column first; each
+        // column's passes cover only the bits in which its values differ.
+        const uint32_t* cur_perm = nullptr;  // the identity until a pass moves rows
+        int cur = 0;
+        for (int c = (int)n_cols - 1; c >= 0; --c) {
+            const uint64_t init[2] = {~0ull, 0ull};
+            E.upload(mm, init, 16);
+            launch_col_minmax(key_cols[c], n, mm, E.stream);
+            const uint64_t* h = (const uint64_t*)download_async(E, mm, 16);
+            E.sync();
+            const uint64_t lo = h[0], range = h[1] - h[0];
+            if (range == 0) continue;  // one value: the column orders nothing
+            int nbits = 0;
+            while (nbits < 64 && (range >> nbits)) ++nbits;
+            launch_col_keys(key_cols[c], cur_perm, n, lo, keys[cur], E.stream);
+            for (int shift = 0; shift < nbits; shift += 8) {
+                E.pbegin("k_rdx_hist");
+                launch_rdx_hist(keys[cur], n, shift, hist, E.stream);
+                E.pend(n, n * 8);
+                launch_scan(hist, hn, htiles, hoffs, E.stream);
+                E.pbegin("k_rdx_scatter");
+                launch_rdx_scatter(keys[cur], cur_perm, n, shift, hoffs, keys[cur ^ 1], perm[cur ^ 1], E.stream);
+                E.pend(n, n * 24);
+                cur ^= 1;
+                cur_perm = perm[cur];
+            }
+        }
+        // codes against the predecessor decide the group boundaries
+        uint32_t* heads = A.take_n<uint32_t>(n);
+        uint64_t* goffs = A.take_n<uint64_t>(n + 1);
+        uint64_t* gtiles = A.take_n<uint64_t>(scan_tiles(n) + 1);
+        uint64_t* cmp = A.take_n<uint64_t>(1);
+        launch_fill(cmp, 1, 0, E.stream);
+        E.pbegin("k_ovc");
+        launch_ovc(d_cols, n_cols, cur_perm, n, heads, code_offset, code_value, cmp, E.stream);
+        E.pend(n, n * 8 * n_cols);
+        launch_scan(heads, n, gtiles, goffs, E.stream);
+        uint64_t* gid = A.take_n<uint64_t>(n);
+        uint64_t* head_pos = A.take_n<uint64_t>(n);
+        int64_t* vs = v_i64 && (aggs & (ISA_SUM_I64 | ISA_MIN_I64 | ISA_MAX_I64)) ? A.take_n<int64_t>(n) : nullptr;
+        launch_group_ids(heads, goffs, cur_perm, vs ? v_i64 : nullptr, n, gid, head_pos, vs, E.stream);
+        const uint64_t* hg = (const uint64_t*)download_async(E, goffs + n, 8);
+        const uint64_t* hc = (const uint64_t*)download_async(E, cmp, 8);
+        E.sync();
+        const uint64_t groups = *hg;
+        if (column_compares) *column_compares = *hc;
+        out->n_groups = groups;
+        if (groups > out->capacity) return ISA_ETRUNC;
+        launch_group_keys(d_cols, n_cols, cur_perm, head_pos, groups, d_out_cols, E.stream);
+        // the aggregates: in-stream grouping of the sorted rows on their group
+        // numbers (the sorted-input path)
+        const Cols k = cols_of(aggs);
+        ColView V;
+        V.key = gid;
+        V.cnt = nullptr;
+        V.sum = V.mn = V.mx = vs;
+        V.fs = nullptr;
+        V.stride = 1;
+        // the sorted path writes a key column: the group numbers go to the
+        // first key buffer, free once the rows are ordered
+        OutView ov = output_view(*out, aggs, 0);
+        ov.key = keys[0];
+        (void)k;
+        if (aggs) {
+            const uint64_t g2 = sorted_group(E, A, V, n, 0, ov, out->capacity);
+            if (g2 != groups) throw Fail{ISA_EDEVICE, "internal: group count mismatch"};
+        }
+        E.sync();
+        return ISA_OK;
+    } catch (const Fail& f) {
+        out->n_groups = 0;
+        return fail(ctx, f);
+    } catch (const std::bad_alloc&) {
+        out->n_groups = 0;
+        return ISA_ENOMEM;
+    }
+}
 
 isa_status isa_group_by_sorted(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_workspace ws, isa_output* out,
                                void* stream) {
@@ -1589,12 +2045,21 @@ namespace {
 bool valid_tuning(const isa_tuning& t) {
     // leaves up to half the leaf capacity on average keep sampled buckets within it
     return t.leaf_rows >= 256 && t.leaf_rows <= (uint32_t)LEAF_CAP / 2 && t.chunk_split >= 64 &&
-           t.chunk_split <= 4096 && t.graph <= 1 && t.reserved == 0;
+           t.chunk_split <= 4096 && t.graph <= 1 && (t.merge_fanin == 0 || (t.merge_fanin >= 2 && t.merge_fanin <= 65536));
 }
 }  // namespace
 
+isa_status isa_set_resident_share(isa_ctx* ctx, uint32_t permille) {
+    if (!ctx || permille > 1000) return ISA_EINVAL;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->resident_permille = permille;
+    return ISA_OK;
+}
+
 isa_status isa_set_run_generation(isa_ctx* ctx, int policy) {
-    if (!ctx || (policy != ISA_RUNGEN_READ_SORT_WRITE && policy != ISA_RUNGEN_REPLACEMENT)) return ISA_EINVAL;
+    if (!ctx || (policy != ISA_RUNGEN_READ_SORT_WRITE && policy != ISA_RUNGEN_REPLACEMENT &&
+                 policy != ISA_RUNGEN_HYBRID))
+        return ISA_EINVAL;
     std::lock_guard<std::mutex> lock(ctx->mu);
     ctx->rungen = policy;
     return ISA_OK;
@@ -1612,7 +2077,7 @@ isa_status isa_get_tuning(isa_ctx* ctx, isa_tuning* out) {
     out->leaf_rows = ctx->eng.tune.leaf_rows;
     out->chunk_split = ctx->eng.tune.chunk_split;
     out->graph = ctx->eng.tune.graph;
-    out->reserved = 0;
+    out->merge_fanin = ctx->eng.tune.merge_fanin;
     return ISA_OK;
 }
 
@@ -1622,6 +2087,7 @@ isa_status isa_set_tuning(isa_ctx* ctx, const isa_tuning* t) {
     ctx->eng.tune.leaf_rows = t->leaf_rows;
     ctx->eng.tune.chunk_split = t->chunk_split;
     ctx->eng.tune.graph = t->graph;
+    ctx->eng.tune.merge_fanin = t->merge_fanin;
     return ISA_OK;
 }
 

@@ -87,6 +87,22 @@ constexpr size_t NOALLOC_EVENTS = 32;
 // `device`, which must be current; looked up once per device.
 hipError_t noalloc_scratch(int device, void** out);
 
+// Multi-column keys: LSD radix sort of a row permutation and offset-value
+// codes of the sorted stream (see the kernels).
+uint64_t rdx_blocks(uint64_t n);
+void launch_col_minmax(const int64_t* col, uint64_t n, uint64_t* out, hipStream_t st);
+void launch_col_keys(const int64_t* col, const uint32_t* perm, uint64_t n, uint64_t lo, uint64_t* keys,
+                     hipStream_t st);
+void launch_rdx_hist(const uint64_t* keys, uint64_t n, int shift, uint32_t* hist, hipStream_t st);
+void launch_rdx_scatter(const uint64_t* keys, const uint32_t* perm, uint64_t n, int shift, const uint64_t* offs,
+                        uint64_t* keys_out, uint32_t* perm_out, hipStream_t st);
+void launch_ovc(const int64_t* const* cols, uint32_t K, const uint32_t* perm, uint64_t n, uint32_t* heads,
+                uint32_t* code_off, int64_t* code_val, uint64_t* compares, hipStream_t st);
+void launch_group_ids(const uint32_t* heads, const uint64_t* offs, const uint32_t* perm, const int64_t* v,
+                      uint64_t n, uint64_t* gid, uint64_t* head_pos, int64_t* v_sorted, hipStream_t st);
+void launch_group_keys(const int64_t* const* cols, uint32_t K, const uint32_t* perm, const uint64_t* head_pos,
+                       uint64_t groups, int64_t* const* out_cols, hipStream_t st);
+
 // Error carried out of the engine as an isa_status value.
 struct Fail {
     int status;
@@ -129,6 +145,7 @@ struct Tuning {
     uint32_t leaf_rows = 2048;  // target rows per leaf bucket (buckets = rows / leaf_rows, 2..MAX_BUCKETS)
     uint32_t chunk_split = 512; // partition chunks per region: chunk rows = rows / chunk_split, in [PART_TILE, PART_CHUNK]
     uint32_t graph = 1;         // batched waves of small instances launch as one captured graph
+    uint32_t merge_fanin = 0;   // runs per merge step of a spilling group-by (0: all in one wide merge)
 };
 
 struct Engine {

@@ -1974,47 +1974,86 @@ __global__ void __launch_bounds__(256) k_split_count(const uint64_t* __restrict_
 // offs: exclusive scan of the counts (offs[nblocks] = all count-1 rows),
 // offs[nblocks + 1]: the narrow flag.  The run starts at out[0], or ends at
 // out[end_words] when end_words is nonzero.
+// A workgroup takes its SPLIT_T rows in tiles of SPLIT_TILE rows: a tile is
+// loaded into LDS with consecutive threads on consecutive words, each thread
+// then ranks the rows of its stripes (rows t, t + 256, ...) by ballots, the
+// count-1 rows' columns leave in contiguous stores, and the other rows are
+// copied word by word from LDS into their contiguous span of the run.
+constexpr int SPLIT_TILE = 1024;
+constexpr int SPLIT_MAXW = 6;
 __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict__ rows, uint64_t n, Layout S,
                                                      Layout R, const uint64_t* __restrict__ offs, uint64_t nblocks,
                                                      uint64_t* __restrict__ out, uint64_t end_words) {
-    __shared__ uint32_t s_tmp[256 / 64 + 1];
-    constexpr int PER = SPLIT_T / 256;
-    const uint64_t r0 = (uint64_t)blockIdx.x * SPLIT_T + (uint64_t)threadIdx.x * PER;
-    uint32_t c = 0;
-    for (int i = 0; i < PER; ++i) {
-        const uint64_t r = r0 + i;
-        if (r < n && rows[r * S.words + S.cnt] == 1) ++c;
-    }
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<256>(c, s_tmp, tot);
+    __shared__ uint64_t s_rows[SPLIT_TILE * SPLIT_MAXW];
+    __shared__ uint16_t s_msrc[SPLIT_TILE];
+    __shared__ uint32_t s_wave[4];
+    constexpr int STRIPES = SPLIT_TILE / 256;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint32_t W = (uint32_t)S.words;
     const uint64_t n_single = offs[nblocks];
     const bool narrow = offs[nblocks + 1] != 0;
     const uint64_t s_words = single_bytes(n_single, R, narrow) / 8;
     if (end_words) out += end_words - (s_words + (n - n_single) * S.words);
-    // columns of the count-1 part
     uint64_t* key_c = out;
     uint64_t* fs_c = out + n_single;
     void* int_c = out + n_single * (R.fs >= 0 ? 2 : 1);
-    uint64_t so = offs[blockIdx.x] + ex;  // count-1 rows before this thread
-    uint64_t mo = r0 - so;                // others before this thread
     uint64_t* multi = out + s_words;
-    for (int i = 0; i < PER; ++i) {
-        const uint64_t r = r0 + i;
-        if (r >= n) break;
-        const uint64_t* src = rows + r * S.words;
-        if (src[S.cnt] == 1) {
-            key_c[so] = src[0];
-            if (R.fs >= 0) fs_c[so] = src[S.fs];
-            if (R.sum >= 0) {
-                if (narrow) ((int32_t*)int_c)[so] = (int32_t)(int64_t)src[S.sum];
-                else ((uint64_t*)int_c)[so] = src[S.sum];
+    const uint64_t blk0 = (uint64_t)blockIdx.x * SPLIT_T;
+    uint64_t so = offs[blockIdx.x];  // count-1 rows before the current tile
+    for (uint64_t t0 = blk0; t0 < blk0 + SPLIT_T && t0 < n; t0 += SPLIT_TILE) {
+        const uint32_t tn = (uint32_t)(n - t0 < (uint64_t)SPLIT_TILE ? n - t0 : (uint64_t)SPLIT_TILE);
+        const uint64_t* src = rows + t0 * W;
+        for (uint32_t x = tid; x < tn * W; x += 256) s_rows[x] = src[x];
+        __syncthreads();
+        // ranks of the count-1 rows, stripe by stripe (row order is stripe-major)
+        uint32_t srank[STRIPES];
+        bool single[STRIPES];
+        uint32_t before = 0;  // count-1 rows of the tile in earlier stripes
+#pragma unroll
+        for (int i = 0; i < STRIPES; ++i) {
+            const uint32_t r = (uint32_t)(i * 256 + tid);
+            single[i] = r < tn && s_rows[r * W + S.cnt] == 1;
+            const uint64_t bal = __ballot(single[i]);
+            if (lane == 0) s_wave[wv] = (uint32_t)__popcll(bal);
+            __syncthreads();
+            uint32_t wbase = 0, stot = 0;
+            for (int q = 0; q < 4; ++q) {
+                wbase += q < wv ? s_wave[q] : 0u;
+                stot += s_wave[q];
             }
-            ++so;
-        } else {
-            uint64_t* d = multi + mo * S.words;
-            for (int x = 0; x < S.words; ++x) d[x] = src[x];
-            ++mo;
+            srank[i] = before + wbase + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+            before += stot;
+            __syncthreads();
         }
+        const uint32_t t_single = before;
+        // columns of the count-1 rows: consecutive ranks of a stripe are
+        // consecutive rows, so a wave's stores are contiguous
+#pragma unroll
+        for (int i = 0; i < STRIPES; ++i) {
+            const uint32_t r = (uint32_t)(i * 256 + tid);
+            if (single[i]) {
+                const uint64_t* q = s_rows + r * W;
+                const uint64_t o = so + srank[i];
+                key_c[o] = q[0];
+                if (R.fs >= 0) fs_c[o] = q[S.fs];
+                if (R.sum >= 0) {
+                    if (narrow) ((int32_t*)int_c)[o] = (int32_t)(int64_t)q[S.sum];
+                    else ((uint64_t*)int_c)[o] = q[S.sum];
+                }
+            } else if (r < tn) {
+                s_msrc[r - srank[i]] = (uint16_t)r;  // its rank among the other rows
+            }
+        }
+        __syncthreads();
+        // the other rows, word by word from LDS into their contiguous span
+        const uint32_t t_multi = tn - t_single;
+        uint64_t* md = multi + (t0 - so) * W;  // rows before the tile that are not count-1
+        for (uint32_t x = tid; x < t_multi * W; x += 256) {
+            const uint32_t j = x / W, wd = x - j * W;
+            md[x] = s_rows[(uint32_t)s_msrc[j] * W + wd];
+        }
+        so += t_single;
+        __syncthreads();  // the tile's LDS is reused by the next tile
     }
 }
 
@@ -2308,6 +2347,211 @@ void launch_seg_write(const int32_t* a, uint64_t n, uint32_t chunk, const uint64
     const uint64_t g = (n + chunk - 1) / chunk;
     if (!g) return;
     hipLaunchKernelGGL(k_seg_write, dim3((uint32_t)g), dim3(256), 0, st, a, n, chunk, offs, starts);
+}
+
+// ---------------------------------------------------------------------------
+// Multi-column keys with offset-value codes (Section 2: the table of
+// offset-value codes; Section 5: column accesses).  Rows are ordered on K
+// signed int64 columns, lexicographically: a stable LSD radix sort of a row
+// permutation, one column at a time from the last to the first, 8-bit digits
+// of the column value relative to its minimum.  Each row of the sorted stream
+// is then coded against its predecessor (offset = leading columns equal,
+// value = the row's value in the first differing column); a row whose offset
+// is below K starts a group, so the in-stream grouping takes one test per row
+// and never compares more than K column values for a row.
+// ---------------------------------------------------------------------------
+
+constexpr int RDX_NT = 256;
+constexpr int RDX_IPT = 16;
+constexpr int RDX_TILE = RDX_NT * RDX_IPT;
+constexpr uint64_t SIGN64 = 1ull << 63;
+
+// min and max of a column as order-preserving unsigned values (x ^ 2^63);
+// out[0] starts at ~0 and out[1] at 0
+__global__ void __launch_bounds__(256) k_col_minmax(const int64_t* __restrict__ col, uint64_t n,
+                                                    unsigned long long* __restrict__ out) {
+    uint64_t lo = ~0ull, hi = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        const uint64_t u = (uint64_t)col[i] ^ SIGN64;
+        lo = u < lo ? u : lo;
+        hi = u > hi ? u : hi;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t a = __shfl_xor(lo, o), b = __shfl_xor(hi, o);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&out[0], (unsigned long long)lo);
+        atomicMax(&out[1], (unsigned long long)hi);
+    }
+}
+
+// keys[i] = the column value of row perm[i] (row i without a permutation),
+// as an unsigned offset from the column's minimum
+__global__ void k_col_keys(const int64_t* __restrict__ col, const uint32_t* __restrict__ perm, uint64_t n,
+                           uint64_t lo, uint64_t* __restrict__ keys) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = perm ? perm[i] : i;
+        keys[i] = ((uint64_t)col[r] ^ SIGN64) - lo;
+    }
+}
+
+// digit counts of each tile, digit-major: hist[d * nblocks + b]
+__global__ void __launch_bounds__(RDX_NT) k_rdx_hist(const uint64_t* __restrict__ keys, uint64_t n, int shift,
+                                                    uint32_t nblocks, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t t0 = (uint64_t)blockIdx.x * RDX_TILE;
+    for (int j = 0; j < RDX_IPT; ++j) {
+        const uint64_t e = t0 + (uint64_t)j * RDX_NT + threadIdx.x;
+        if (e < n) atomicAdd(&h[(uint32_t)(keys[e] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one digit pass.  A tile is taken in 16 rounds of 256
+// consecutive rows; a row's rank is the rows of its digit in earlier rounds,
+// in earlier waves of its round and in earlier lanes of its wave.
+__global__ void __launch_bounds__(RDX_NT) k_rdx_scatter(const uint64_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ perm, uint64_t n, int shift,
+                                                       uint32_t nblocks, const uint64_t* __restrict__ offs,
+                                                       uint64_t* __restrict__ keys_out,
+                                                       uint32_t* __restrict__ perm_out) {
+    __shared__ uint32_t cnt[256];
+    __shared__ uint32_t wc[RDX_NT / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    cnt[tid] = 0;
+    for (int q = 0; q < RDX_NT / 64; ++q) wc[q][tid] = 0;
+    __syncthreads();
+    const uint64_t t0 = (uint64_t)blockIdx.x * RDX_TILE;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (int j = 0; j < RDX_IPT; ++j) {
+        const uint64_t e = t0 + (uint64_t)j * RDX_NT + tid;
+        const bool ok = e < n;
+        const uint64_t key = ok ? keys[e] : 0;
+        const uint32_t p = ok ? (perm ? perm[e] : (uint32_t)e) : 0u;
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint64_t match = wave_match(d, 8, __ballot(ok));
+        const uint32_t before = (uint32_t)__popcll(match & lt);
+        if (ok && before == 0) wc[w][d] = (uint32_t)__popcll(match);
+        __syncthreads();
+        if (ok) {
+            uint32_t r = cnt[d] + before;
+            for (int q = 0; q < w; ++q) r += wc[q][d];
+            const uint64_t pos = offs[(uint64_t)d * nblocks + blockIdx.x] + r;
+            keys_out[pos] = key;
+            perm_out[pos] = p;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int q = 0; q < RDX_NT / 64; ++q) {
+            add += wc[q][tid];
+            wc[q][tid] = 0;
+        }
+        cnt[tid] += add;
+        __syncthreads();
+    }
+}
+
+// Offset-value code of every row of the sorted stream against its
+// predecessor (the first row: offset 0, against a base that differs in the
+// first column); heads[i] = 1 when the offset is below K.  Column values
+// compared are summed into *compares.
+__global__ void __launch_bounds__(256) k_ovc(const int64_t* const* __restrict__ cols, uint32_t K,
+                                             const uint32_t* __restrict__ perm, uint64_t n,
+                                             uint32_t* __restrict__ heads, uint32_t* __restrict__ code_off,
+                                             int64_t* __restrict__ code_val,
+                                             unsigned long long* __restrict__ compares) {
+    uint64_t acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        const uint32_t a = perm ? perm[i] : (uint32_t)i;
+        uint32_t off = 0;
+        if (i > 0) {
+            const uint32_t b = perm ? perm[i - 1] : (uint32_t)(i - 1);
+            while (off < K && cols[off][a] == cols[off][b]) ++off;
+            acc += off < K ? off + 1 : K;
+        }
+        heads[i] = off < K ? 1u : 0u;
+        if (code_off) code_off[i] = off;
+        if (code_val) code_val[i] = off < K ? cols[off][a] : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(compares, (unsigned long long)acc);
+}
+
+// group number of every sorted row (heads scanned: offs exclusive), the
+// sorted position of each group's first row, and the value column in
+// sorted order
+__global__ void k_group_ids(const uint32_t* __restrict__ heads, const uint64_t* __restrict__ offs,
+                            const uint32_t* __restrict__ perm, const int64_t* __restrict__ v, uint64_t n,
+                            uint64_t* __restrict__ gid, uint64_t* __restrict__ head_pos,
+                            int64_t* __restrict__ v_sorted) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t g = offs[i] + heads[i] - 1;
+        gid[i] = g;
+        if (heads[i]) head_pos[g] = i;
+        if (v) v_sorted[i] = v[perm ? perm[i] : i];
+    }
+}
+
+// key columns of every group from its first row
+__global__ void k_group_keys(const int64_t* const* __restrict__ cols, uint32_t K, const uint32_t* __restrict__ perm,
+                             const uint64_t* __restrict__ head_pos, uint64_t groups,
+                             int64_t* const* __restrict__ out_cols) {
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t r = perm ? perm[head_pos[g]] : (uint32_t)head_pos[g];
+        for (uint32_t c = 0; c < K; ++c) out_cols[c][g] = cols[c][r];
+    }
+}
+
+static dim3 grid_of(uint64_t n, uint64_t cap) {
+    uint64_t g = (n + 255) / 256;
+    if (g > cap) g = cap;
+    return dim3((uint32_t)(g ? g : 1));
+}
+
+uint64_t rdx_blocks(uint64_t n) { return (n + RDX_TILE - 1) / RDX_TILE; }
+void launch_col_minmax(const int64_t* col, uint64_t n, uint64_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_col_minmax, grid_of(n, 2048), dim3(256), 0, st, col, n, (unsigned long long*)out);
+}
+void launch_col_keys(const int64_t* col, const uint32_t* perm, uint64_t n, uint64_t lo, uint64_t* keys,
+                     hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_col_keys, grid_of(n, 16384), dim3(256), 0, st, col, perm, n, lo, keys);
+}
+void launch_rdx_hist(const uint64_t* keys, uint64_t n, int shift, uint32_t* hist, hipStream_t st) {
+    const uint64_t nb = rdx_blocks(n);
+    if (!nb) return;
+    hipLaunchKernelGGL(k_rdx_hist, dim3((uint32_t)nb), dim3(RDX_NT), 0, st, keys, n, shift, (uint32_t)nb, hist);
+}
+void launch_rdx_scatter(const uint64_t* keys, const uint32_t* perm, uint64_t n, int shift, const uint64_t* offs,
+                        uint64_t* keys_out, uint32_t* perm_out, hipStream_t st) {
+    const uint64_t nb = rdx_blocks(n);
+    if (!nb) return;
+    hipLaunchKernelGGL(k_rdx_scatter, dim3((uint32_t)nb), dim3(RDX_NT), 0, st, keys, perm, n, shift, (uint32_t)nb,
+                       offs, keys_out, perm_out);
+}
+void launch_ovc(const int64_t* const* cols, uint32_t K, const uint32_t* perm, uint64_t n, uint32_t* heads,
+                uint32_t* code_off, int64_t* code_val, uint64_t* compares, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_ovc, grid_of(n, 16384), dim3(256), 0, st, cols, K, perm, n, heads, code_off, code_val,
+                       (unsigned long long*)compares);
+}
+void launch_group_ids(const uint32_t* heads, const uint64_t* offs, const uint32_t* perm, const int64_t* v,
+                      uint64_t n, uint64_t* gid, uint64_t* head_pos, int64_t* v_sorted, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_group_ids, grid_of(n, 16384), dim3(256), 0, st, heads, offs, perm, v, n, gid, head_pos,
+                       v_sorted);
+}
+void launch_group_keys(const int64_t* const* cols, uint32_t K, const uint32_t* perm, const uint64_t* head_pos,
+                       uint64_t groups, int64_t* const* out_cols, hipStream_t st) {
+    if (!groups) return;
+    hipLaunchKernelGGL(k_group_keys, grid_of(groups, 16384), dim3(256), 0, st, cols, K, perm, head_pos, groups,
+                       out_cols);
 }
 
 // ---------------------------------------------------------------------------

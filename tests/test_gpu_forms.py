@@ -106,7 +106,7 @@ def test_tuning_changes_speed_not_results(ctx, cfg):
     dev = [(to_dev(k), to_dev(v), None) for k, v, f in insts]
     ctx.set_tuning(**cfg)
     try:
-        assert ctx.get_tuning() == cfg
+        assert ctx.get_tuning() == dict(isa.Context.default_tuning(), **cfg)
         res, status = isa.batch_run(ctx, dev, aggs=isa.ISA_INT_AGGS, mem_budget=512 << 20)
         for i, (k, v, f) in enumerate(insts):
             compare(np_out(res[i]), k, v, None, isa.ISA_INT_AGGS, "inst %d" % i)
@@ -119,7 +119,8 @@ def test_tuning_changes_speed_not_results(ctx, cfg):
 
 
 def test_tuning_rejects_out_of_range(ctx):
-    for bad in [dict(leaf_rows=100), dict(leaf_rows=4096), dict(chunk_split=8), dict(graph=2)]:
+    for bad in [dict(leaf_rows=100), dict(leaf_rows=4096), dict(chunk_split=8), dict(graph=2),
+                dict(merge_fanin=1), dict(merge_fanin=65537)]:
         with pytest.raises(isa.InsortError) as e:
             ctx.set_tuning(**bad)
         assert e.value.status == isa.ISA_EINVAL

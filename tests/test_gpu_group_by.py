@@ -278,3 +278,29 @@ def test_truncation_while_spilling(ctx, monkeypatch, redo):
         assert status == isa.ISA_ETRUNC and g == G
         for col in ("keys", "count", "sum_i64", "min_i64", "max_i64"):
             assert np.array_equal(got[col], ref[col][:cap]), (cap, col)
+
+
+@pytest.mark.parametrize("fanin", [3, 4])
+def test_preliminary_merges_before_the_wide_merge(ctx, fanin):
+    # with a merge fan-in below the run count, the smallest runs are merged
+    # first (Section 4, Example 4) so that the final wide merge takes at most
+    # `fanin` runs; the output equals the oracle's, and the steps, the rows
+    # they write and the runs left equal the exact simulation of the same plan.
+    # Merged runs are state rows beside the compact initial runs, so the
+    # temporary storage is sized above one state row per input row.
+    say("case preliminary merges fan-in %d" % fanin)
+    n = 1_500_000
+    k, v, f = datagen.plain_input(5, n, 400_000, 0.0, with_f64=True)
+    ctx.set_tuning(merge_fanin=fanin)
+    try:
+        got, st, status, g = run_gpu(ctx, k, v, f, budget=16 << 20, spill_bytes=3 * n * 48)
+    finally:
+        ctx.set_tuning()
+    compare(got, k, v, f, isa.ISA_ALL, "preliminary merges")
+    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"], keep_runs=True)
+    assert st["runs"] == sim["runs"] and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
+    plan = spillsim.preliminary_merges_exact(sim["run_keys"], fanin)
+    assert len(plan["counts"]) - 1 >= 2                     # at least two steps
+    assert st["merge_steps"] == len(plan["counts"]) - 1, (st, plan["counts"])
+    assert st["merge_rows"] == plan["written_rows"], (st, plan)
+    assert st["windows"] >= 1

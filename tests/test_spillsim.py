@@ -202,3 +202,92 @@ def test_hybrid_plan_in_memory_case(O_over_M):
     # O <= M: no fan-out, nothing spills
     h = spillsim.hybrid_plan(1e9, 1e5, O_over_M * 1e5, 10)
     assert h["f"] == 0 and h["spilled_rows"] == 0.0 and h["runs"] == 0.0
+
+
+def test_preliminary_merges_exact_on_disjoint_runs_follows_the_plan():
+    # runs with disjoint keys: every merge writes the sum of its inputs, so the
+    # exact steps reproduce the size-only plan (Example 4's counts)
+    rng = np.random.default_rng(3)
+    keys = rng.permutation(500 * 40).astype(np.uint64)
+    runs = [np.sort(keys[i * 40:(i + 1) * 40]) for i in range(500)]
+    ex = spillsim.preliminary_merges_exact(runs, 100)
+    plan = spillsim.preliminary_merges([40] * 500, 100, float("inf"))
+    assert ex["counts"] == plan["counts"] == [500, 496, 397, 298, 199, 100]
+    assert ex["written_rows"] == plan["written_rows"]
+    assert sum(ex["final_run_sizes"]) == 500 * 40
+
+
+def test_preliminary_merges_exact_combines_equal_keys():
+    # hand-worked: fan-in 2 over runs {1,2}, {2,3,4}, {1,5}, {9}: each step
+    # takes 2 runs, the smallest: {9} (1 row) and {1,2} (2 rows, written
+    # before {1,5}) -> {1,2,9}; then {1,5} (2 rows) and {2,3,4} (3 rows,
+    # written before {1,2,9} of the same size) -> {1,2,3,4,5}
+    runs = [np.array([1, 2]), np.array([2, 3, 4]), np.array([1, 5]), np.array([9])]
+    ex = spillsim.preliminary_merges_exact(runs, 2)
+    assert ex["counts"] == [4, 3, 2]
+    assert ex["step_rows"] == [3, 5]
+    assert ex["final_run_sizes"] == [3, 5]
+
+
+def test_simulate_keeps_run_keys():
+    keys = np.array([5, 1, 5, 2, 7, 8, 9, 1, 3, 4], dtype=np.uint64)
+    sim = spillsim.simulate(keys, 2, 3, keep_runs=True)
+    assert [r.shape[0] for r in sim["run_keys"]] == sim["run_sizes"]
+    for r in sim["run_keys"]:
+        assert (np.diff(r.astype(np.int64)) > 0).all()
+    # every key is in a run or in the final index; runs hold each key once
+    seen = np.concatenate(sim["run_keys"]) if sim["run_keys"] else np.empty(0, np.uint64)
+    assert seen.shape[0] == sim["spilled_rows"]
+
+
+def test_hybrid_without_a_resident_index_is_read_sort_write():
+    # no memory for the resident index (f = F): every key goes to runs, and
+    # the runs are those of read-sort-write cycles
+    k = datagen.plain_input(21, 60_000, 9_000, 0.5)[0]
+    h = spillsim.simulate_hybrid(k, 1_000, 0, 3_000)
+    r = spillsim.simulate(k, 1_000, 3_000)
+    assert h["runs"] == r["runs"] and h["run_sizes"] == r["run_sizes"]
+    assert h["resident_rows"] == 0 and h["final_index_rows"] == r["final_index_rows"]
+
+
+def test_hybrid_output_fits_the_resident_index():
+    # O <= resident capacity (f = 0): in-memory duplicate removal, no run
+    k = datagen.plain_input(22, 50_000, 2_000, 0.0)[0]
+    h = spillsim.simulate_hybrid(k, 1_000, 4_000, 1_000)
+    assert h["runs"] == 0 and h["spilled_rows"] == 0
+    assert h["resident_rows"] == np.unique(k).shape[0] and h["cut"] == 1 << 64
+
+
+def test_hybrid_hand_worked():
+    # batches of 2 rows, resident capacity 4 (keeps 3), run capacity 2
+    keys = np.array([10, 20, 30, 40, 50, 5, 60, 70, 35, 80], dtype=np.uint64)
+    h = spillsim.simulate_hybrid(keys, 2, 4, 2)
+    # b1 {10,20} -> R {10,20}; b2 {30,40} -> R {10,20,30,40}; b3 {5,50} ->
+    # R {5,10,20,30,40,50}: 6 > 4, demote {30,40,50}, cut 30, R {5,10,20};
+    # b4 {60,70} -> gen {60,70}; b5 {35,80} -> gen {35,60,70,80} > 2: run
+    # {60,70}, gen {35,80}
+    assert h["run_sizes"] == [3, 2] and h["run_kinds"] == ["demotion", "run"]
+    assert h["cut"] == 30 and h["resident_rows"] == 3 and h["final_index_rows"] == 5
+
+
+def test_hybrid_scale_of_the_model():
+    # Section 5's example scaled down: M = 10,000 rows, F = 10, O = 2.75 M,
+    # I = 100 O, f = 2: an index of 8/10 of memory and runs from the other
+    # 2/10.  The resident index keeps 3/4 of its capacity after a demotion,
+    # so it absorbs 0.75 * 8,000 of the output's keys for good; the spilled
+    # rows approach (1 - 6,000 / 27,500) of the input, less the duplicates
+    # each run absorbs (about 5% for runs of 2,000 of the remaining ~21,500
+    # keys: -D ln(1 - 2,000 / D) rows per run of 2,000 keys)
+    M, O = 10_000, 27_500
+    I = 100 * O
+    h0 = spillsim.hybrid_plan(I, M, O, 10)
+    assert h0["f"] == 2
+    k = datagen.plain_input(23, I, O, 0.0)[0]
+    Kr, Kw = int((1 - h0["f"] / 10) * M), int(h0["f"] / 10 * M)
+    h = spillsim.simulate_hybrid(k, 500, Kr, Kw)
+    D = O - 0.75 * Kr
+    absorb = 1.0 - Kw / (-D * np.log(1 - Kw / D))
+    expect = (1 - 0.75 * Kr / O) * I * (1 - absorb)
+    assert abs(h["spilled_rows"] - expect) <= 0.05 * expect, (h["spilled_rows"], expect)
+    assert h["spilled_rows"] < I
+    assert abs(h["resident_rows"] - 0.75 * Kr) <= 0.25 * Kr
