@@ -98,17 +98,11 @@ def bench_batch(args, lo, hi):
     if tuned:
         ctx.set_tuning(**tuned)
     else:
-        # a stratified sample across the instance-size range: instances taken
-        # in order of size at even steps until about 1e8 rows
-        order = np.argsort(rows, kind="stable")
-        pick, acc = [], 0
-        step = max(1, count // 400)
-        for j in range(0, count, step):
-            i = int(order[j])
-            if acc + int(rows[i]) > 100_000_000:
-                continue
-            pick.append(i)
-            acc += int(rows[i])
+        # an unbiased sample of the whole workload: every instance at a fixed
+        # stride (sizes are drawn independently per instance), about 2e8 rows
+        stride = max(1, int(np.ceil(float(rows.sum()) / 2e8)))
+        pick = list(range(0, count, stride))
+        acc = int(rows[pick].sum())
         n_s = len(pick)
         keys_s = torch.empty(acc, dtype=torch.int64, device="cuda")
         vals_s = torch.empty(acc, dtype=torch.int64, device="cuda")
