@@ -308,6 +308,20 @@ __device__ void block_minmax(uint64_t& mn, uint64_t& mx, uint64_t* s_tmp /* 2*NT
     __syncthreads();
 }
 
+// Row at the middle of stratum q of S equal strata of n rows:
+// floor((2q + 1) n / (2S)).  The product fits 64 bits for every n below 2^48
+// (q < S <= 2^15), and a power-of-two S divides by a shift; otherwise the
+// library's 64-bit or, beyond 2^48 rows, 128-bit division (slow on the GPU)
+// is used.
+__device__ __forceinline__ uint64_t stratum_row(uint64_t q, uint64_t n, uint64_t S) {
+    const uint64_t den = 2 * S;
+    if (n < (1ull << 48)) {
+        const uint64_t num = (2 * q + 1) * n;
+        return (den & (den - 1)) == 0 ? num >> __builtin_ctzll(den) : num / den;
+    }
+    return (uint64_t)(((unsigned __int128)(2 * q + 1) * n) / den);
+}
+
 // ---------------------------------------------------------------------------
 // Splitter selection: one workgroup per region sorts a stratified sample of
 // SAMPLE_N keys and takes nb-1 quantiles as splitters.  A key that fills
@@ -332,7 +346,7 @@ __global__ void __launch_bounds__(LEAF_NT) k_sample(const Region* __restrict__ r
         const uint64_t q = (uint64_t)(w * 64 * IPT + j * 64 + lane);
         v[j] = (uint16_t)q;
         if (q < S) {
-            const uint64_t pos = (uint64_t)(((unsigned __int128)(2 * q + 1) * R.n) / (2 * S));
+            const uint64_t pos = stratum_row(q, R.n, S);
             k[j] = R.src.key[pos * R.src.stride];
             mn = k[j] < mn ? k[j] : mn;
             mx = k[j] > mx ? k[j] : mx;
@@ -702,7 +716,7 @@ __global__ void k_extract_keys(const uint64_t* __restrict__ rows, uint64_t n, ui
 // Stratified key sample: key of row floor((2q+1) n / 2S) for q < S.
 __global__ void k_sample_keys(ColView src, uint64_t n, uint64_t S, uint64_t* __restrict__ out) {
     for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < S; q += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t pos = (uint64_t)(((unsigned __int128)(2 * q + 1) * n) / (2 * S));
+        const uint64_t pos = stratum_row(q, n, S);
         out[q] = src.key[pos * src.stride];
     }
 }
