@@ -283,7 +283,8 @@ struct Node {
     ColView src;
     uint64_t n, pos, lo, hi;
     uint32_t inst;
-    std::vector<int> kids;
+    // an expanded region's buckets: pool[first_kid, first_kid + n_kids), in key order
+    int first_kid = 0, n_kids = 0;
 };
 
 }  // namespace
@@ -427,7 +428,10 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
     const uint64_t src_row_bytes = (uint64_t)L.words * 8;
     std::vector<uint64_t> totals(dests.size(), 0);
     std::vector<Node> pool;
-    pool.reserve(1024);
+    uint64_t rows_all = 0;
+    for (const Instance& x : inst) rows_all += x.n;
+    // about one node per leaf of half a leaf's rows, plus the regions
+    pool.reserve(inst.size() + 2 * (rows_all / (uint64_t)LEAF_CAP) * 2 + 1024);
     std::vector<int> roots(inst.size(), -1);
     uint64_t N = 0;
     bool need_part = false;
@@ -549,7 +553,7 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
             const uint64_t* sp = spl.data() + ri * (MAX_BUCKETS - 1);
             const uint64_t* bs = bstart.data() + bsb[ri];
             if (bs[r.nb] != r.n) throw Fail{ISA_EDEVICE, "partition lost rows"};
-            std::vector<int> kids;
+            const int first_kid = (int)pool.size();
             for (uint32_t b = 0; b < r.nb; ++b) {
                 const uint64_t size = bs[b + 1] - bs[b];
                 if (!size) continue;
@@ -565,11 +569,11 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
                 c.hi = hi;
                 c.inst = pool[id].inst;
                 c.kind = size <= (uint64_t)LEAF_CAP ? 0 : (lo == hi ? 1 : 2);
-                kids.push_back((int)pool.size());
                 if (c.kind == 2) next.push_back((int)pool.size());
                 pool.push_back(c);
             }
-            pool[id].kids = kids;
+            pool[id].first_kid = first_kid;
+            pool[id].n_kids = (int)pool.size() - first_kid;
             pool[id].kind = 3;
         }
         pending.swap(next);
@@ -579,6 +583,8 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
     // Leaves in output order: instances in order, keys ascending within each.
     std::vector<Leaf> leaves;
     std::vector<uint32_t> leaf_dest;
+    leaves.reserve(pool.size());
+    leaf_dest.reserve(pool.size());
     std::vector<SinglePiece> pieces;
     std::vector<uint32_t> first_seg(dests.size() + 1, 0);
     std::vector<int> stack;
@@ -592,7 +598,7 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
             stack.pop_back();
             const Node& nd = pool[id];
             if (nd.kind == 3) {
-                for (auto it = nd.kids.rbegin(); it != nd.kids.rend(); ++it) stack.push_back(*it);
+                for (int c = nd.first_kid + nd.n_kids - 1; c >= nd.first_kid; --c) stack.push_back(c);
                 continue;
             }
             Leaf lf;
