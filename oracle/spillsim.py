@@ -25,10 +25,17 @@ from __future__ import annotations
 import numpy as np
 
 
-def simulate(keys, batch_rows: int, capacity: int, keep_runs: bool = False):
+def simulate(keys, batch_rows: int, capacity: int, keep_runs: bool = False, absorb_first: bool = False):
     """Read-sort-write cycles at batch granularity (see the module docstring).
     With ``keep_runs`` the result also holds ``run_keys``: each run's sorted
-    keys, in the order the runs were written."""
+    keys, in the order the runs were written.
+
+    ``absorb_first`` is the other batch-granular reading of "memory is full":
+    every batch is absorbed, and as soon as the index then holds more than
+    ``capacity`` keys it is written whole as one run (up to capacity plus a
+    batch) and the next index starts empty; the memory holds up to capacity
+    plus one batch of keys.  This is the rule of an index that absorbs a batch
+    in place, where the index before the absorb no longer exists."""
     if batch_rows <= 0 or capacity <= 0 or batch_rows > capacity:
         raise ValueError("need 0 < batch_rows <= capacity")
     keys = np.asarray(keys, dtype=np.uint64)
@@ -40,6 +47,11 @@ def simulate(keys, batch_rows: int, capacity: int, keep_runs: bool = False):
         merged = np.union1d(index, batch)
         if merged.shape[0] <= capacity:
             index = merged
+        elif absorb_first:
+            run_sizes.append(int(merged.shape[0]))
+            if keep_runs:
+                run_keys.append(merged)
+            index = np.empty(0, np.uint64)
         else:
             run_sizes.append(int(index.shape[0]))
             if keep_runs:

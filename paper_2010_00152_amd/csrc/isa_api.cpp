@@ -139,11 +139,18 @@ uint64_t merge_scratch_bytes(uint64_t rows) {
 // three batch runs (one being sorted, one being absorbed, one kept until the
 // previous absorb is decided), the merge's scratch, the batch program and the
 // compact-run split's scratch.
-uint64_t rungen_bytes(uint64_t Bt, uint64_t K, const Cols& k) {
+// In-place absorption (read-sort-write): one index buffer of K + Bt rows
+// absorbs each batch in place, and a spare area of a little over half of it
+// receives a compacted run before its copy to host memory.
+constexpr uint64_t SPARE_NUM = 11, SPARE_DEN = 20;
+uint64_t spare_rows(uint64_t buf_rows) { return buf_rows * SPARE_NUM / SPARE_DEN + 64; }
+
+uint64_t rungen_bytes(uint64_t Bt, uint64_t K, const Cols& k, bool inplace = false) {
     const uint64_t sw = (uint64_t)state_layout(k).words * 8;
     const uint64_t split_scratch = ((K + Bt) / 4096 + 4) * 24 + 1024;
-    return 2 * (K + Bt) * sw + 3 * Bt * sw + merge_scratch_bytes(K + 2 * Bt) + batch_program_bytes(Bt, k) +
-           split_scratch + MERGE_MARGIN + 16 * 256 + (MAX_BUCKETS - 1) * 8;
+    const uint64_t index = inplace ? ((K + Bt) + spare_rows(K + Bt)) * sw : 2 * (K + Bt) * sw;
+    return index + 3 * Bt * sw + merge_scratch_bytes(K + 2 * Bt) + batch_program_bytes(Bt, k) + split_scratch +
+           MERGE_MARGIN + 16 * 256 + (MAX_BUCKETS - 1) * 8;
 }
 
 // Share of the budget given to the batch area (1/share); the rest holds the
@@ -154,18 +161,20 @@ uint64_t batch_share() {
     return v >= 2 && v <= 64 ? (uint64_t)v : 4;
 }
 
-bool plan_batches(uint64_t ws, uint64_t n, const Cols& k, Plan& p) {
+bool plan_batches(uint64_t ws, uint64_t n, const Cols& k, Plan& p, bool inplace = false) {
     const uint64_t sw = (uint64_t)state_layout(k).words * 8;
     uint64_t Bt = ws / batch_share() / (sort_reduce_bytes(1, 0, k, false) - (4u << 20) + sw);
     // a batch is sorted by the flat plan
     Bt = std::min<uint64_t>(std::min<uint64_t>(Bt, n), FLAT_MAX);
     if (Bt < MIN_BATCH) Bt = MIN_BATCH;
     for (;;) {
-        const uint64_t fixed = rungen_bytes(Bt, 0, k);
+        const uint64_t fixed = rungen_bytes(Bt, 0, k, inplace);
         if (fixed < ws) {
-            // K from the remaining bytes: 2*K*sw plus merge scratch growth
+            // K from the remaining bytes: 2*K*sw (in place: about 1.55*K*sw)
+            // plus merge scratch growth
             uint64_t K = (ws - fixed) / (2 * sw + 1);
-            while (K > 0 && rungen_bytes(Bt, K, k) > ws) K -= std::max<uint64_t>(1, K / 64);
+            if (inplace) K = K * 2 * SPARE_DEN / (SPARE_DEN + SPARE_NUM);
+            while (K > 0 && rungen_bytes(Bt, K, k, inplace) > ws) K -= std::max<uint64_t>(1, K / 64);
             // K >= 2 Bt: an index made of one batch always absorbs the next batch
             if (K >= 2 * Bt) {
                 p.batch_rows = Bt;
@@ -858,12 +867,22 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             }
         } else {
             Plan p;
-            if (!plan_batches(ws.bytes, n, k, p)) return ISA_EBUDGET;
+            const bool rs = ctx->rungen == ISA_RUNGEN_REPLACEMENT;
+            const bool hy = ctx->rungen == ISA_RUNGEN_HYBRID;
+            // compact runs need a count column and a raw row narrower than a state row
+            const Layout Rl = raw_layout(k);
+            const bool compact = S.cnt >= 0 && Rl.words < S.words;
+            // read-sort-write absorbs every batch into one index buffer in
+            // place when a compacted run of mostly count-1 rows fits a spare
+            // area of about half the index (a raw row at most half a state
+            // row); replacement selection and hybrid run generation keep the
+            // old index while the merged one is decided (two buffers)
+            const bool inplace = !rs && !hy && compact && 2 * Rl.words <= S.words;
+            if (!plan_batches(ws.bytes, n, k, p, inplace)) return ISA_EBUDGET;
             // Hybrid run generation: the index memory is shared by a resident
             // index (Kr keys) and a run-generation index (Kw keys, at least a
             // batch), and runs are compacted in a staging area of their own
             // (a run-generation index and a demotion at most).
-            const bool hy = ctx->rungen == ISA_RUNGEN_HYBRID;
             uint64_t Kr = 0, Kw = 0, st_rows = 0;
             if (hy) {
                 // plan with the staging area set aside, until the plan and
@@ -888,7 +907,10 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             const uint64_t buf_bytes = buf_rows * sw * 8;
             uint64_t* idx[2];
             idx[0] = A.take_n<uint64_t>(buf_rows * sw);
-            idx[1] = A.take_n<uint64_t>(buf_rows * sw);
+            idx[1] = inplace ? nullptr : A.take_n<uint64_t>(buf_rows * sw);
+            // in place: the area a compacted run is written to before its copy
+            const uint64_t spare_words = inplace ? spare_rows(buf_rows) * sw : 0;
+            uint64_t* spare = inplace ? A.take_n<uint64_t>(spare_words) : nullptr;
             uint64_t* brun[3];
             for (int j = 0; j < 3; ++j) brun[j] = A.take_n<uint64_t>(p.batch_rows * sw);
             const uint64_t mscr_parts = merge_parts(buf_rows, p.batch_rows) + 1;
@@ -903,7 +925,6 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             m_ctl2[1] = m_ctl2[0] + mctl_words;
             launch_fill(m_ctl2[0], 2 * mctl_words, 0, E.stream);
             // replacement selection: the cursor key and its past-the-end flag
-            const bool rs = ctx->rungen == ISA_RUNGEN_REPLACEMENT;
             uint64_t* rs_cur = A.take_n<uint64_t>(2);
             launch_fill(rs_cur, 2, 0, E.stream);
             // hybrid: the cut below which keys stay resident, in the same two
@@ -911,9 +932,6 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             if (hy && Kr) launch_fill(rs_cur + 1, 1, 1, E.stream);
             uint64_t* m_splits = A.take_n<uint64_t>(2 * (mscr_parts + 1));
             uint64_t* hy_stage = hy ? A.take_n<uint64_t>(st_rows * sw) : nullptr;
-            // compact runs need a count column and a raw row narrower than a state row
-            const Layout Rl = raw_layout(k);
-            const bool compact = S.cnt >= 0 && Rl.words < S.words;
             const uint64_t sp_blocks = split_blocks(buf_rows) + 1;
             uint32_t* sp_counts = A.take_n<uint32_t>(sp_blocks);
             uint64_t* sp_offs = A.take_n<uint64_t>(sp_blocks + 1);
@@ -954,7 +972,9 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             // The index is `ip` (n_idx rows): one of the two index buffers, or,
             // right after a spill or at the first batch, the batch run that
             // starts it (K >= 2 Bt guarantees that the next merge absorbs it,
-            // before its buffer is reused).
+            // before its buffer is reused).  In place, the index lies at the
+            // head of the one index buffer or at its tail (ending at row
+            // buf_rows), and is empty (ip null) after a spill.
             const uint64_t* ip = nullptr;
             uint64_t n_idx = 0;
             std::vector<RunInfo> runs;
@@ -964,6 +984,9 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             // from byte pend_lo to its end
             int pend_buf = -1;
             uint64_t pend_lo = 0;
+            // in place: a run is being copied to host memory from the index
+            // buffer itself (pend_idx), or from the spare area (spare_busy)
+            bool pend_idx = false, spare_busy = false;
             hipStream_t cs = E.copier();
             // runs are written to the pinned spill buffer through its device mapping
             char* spill_dev = nullptr;
@@ -980,6 +1003,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             // the index buffer the next merge writes: not the index itself, and
             // preferably not the one whose tail holds a run being copied out
             auto merge_target = [&]() -> int {
+                if (inplace) return 0;
                 if (ip == idx[0]) return 1;
                 if (ip == idx[1]) return 0;
                 return pend_buf == 0 ? 1 : 0;
@@ -989,6 +1013,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             struct {
                 bool active = false;
                 int buf = 0;
+                const uint64_t* src = nullptr;  // in place: the run's state rows
                 uint64_t rows = 0;
             } deferred;
             auto flush_copy = [&]() {
@@ -996,11 +1021,23 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 deferred.active = false;
                 ck(hipEventSynchronize(E.sync_event(2)), "hipEventSynchronize(split count)");
                 const uint64_t n_run = deferred.rows;
-                const uint64_t n_single = ((const uint64_t*)E.ring_slot(16))[0];
-                const bool narrow = ((const uint64_t*)E.ring_slot(16))[1] != 0;
-                const uint64_t bytes = single_bytes(n_single, Rl, narrow) + (n_run - n_single) * sw * 8;
+                uint64_t n_single = ((const uint64_t*)E.ring_slot(16))[0];
+                bool narrow = ((const uint64_t*)E.ring_slot(16))[1] != 0;
+                uint64_t bytes = single_bytes(n_single, Rl, narrow) + (n_run - n_single) * sw * 8;
+                const char* run_src = inplace ? (const char*)spare : (const char*)idx[deferred.buf] + buf_bytes - bytes;
+                if (inplace && bytes / 8 > spare_words) {
+                    // the split wrote nothing (the compacted run exceeds the
+                    // spare area): the run's state rows go out as they are, and
+                    // the index buffer stays read until the copy ends
+                    n_single = 0;
+                    narrow = false;
+                    bytes = n_run * sw * 8;
+                    run_src = (const char*)deferred.src;
+                    pend_idx = true;
+                } else if (inplace) {
+                    spare_busy = true;
+                }
                 if (spill_used + bytes > spill.bytes) throw Fail{ISA_ESPILL, "spill buffer too small"};
-                const char* run_src = (const char*)idx[deferred.buf] + buf_bytes - bytes;
                 ck(hipStreamWaitEvent(cs, E.sync_event(2), 0), "hipStreamWaitEvent");
                 E.pbegin("spill_d2h", cs);
                 ck(hipMemcpyAsync(spill_dev + spill_used, run_src, bytes, hipMemcpyDeviceToDeviceNoCU, cs),
@@ -1016,7 +1053,15 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 spill_used += bytes;
                 spilled += n_run;
                 spilled_bytes += bytes;
-                pend_lo = buf_bytes - bytes;
+                if (!inplace) pend_lo = buf_bytes - bytes;
+            };
+            // in place: order the stream after a copy that reads the index buffer
+            auto guard_idx = [&]() {
+                flush_copy();
+                if (pend_idx) {
+                    ck(hipStreamWaitEvent(E.stream, E.sync_event(1), 0), "hipStreamWaitEvent");
+                    pend_idx = false;
+                }
             };
             // order the stream after the pending run's copy when [0, end) of
             // idx[buf] is about to be written over it
@@ -1084,6 +1129,27 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 pend_buf = own;
                 pend_lo = 0;
                 n_idx = 0;
+            };
+            // memory is full, in place: the merged index U (m rows, more than
+            // K) is written whole as one run, and the next index starts with
+            // the next batch run.  The run is compacted into the spare area
+            // (after the spare area's last copy) and copied to host memory by
+            // flush_copy; a compacted run larger than the spare area is not
+            // written there, and flush_copy copies U's state rows instead.
+            auto spill_inplace = [&](const uint64_t* U, uint64_t m) {
+                flush_copy();
+                if (!spill.host_pinned) throw Fail{ISA_ESPILL, "spill buffer too small"};
+                if (spare_busy) {
+                    ck(hipStreamWaitEvent(E.stream, E.sync_event(1), 0), "hipStreamWaitEvent");
+                    spare_busy = false;
+                }
+                launch_split(U, m, S, Rl, sp_counts, sp_tiles, sp_offs, spare, 0, E.stream, spare_words);
+                ck(hipMemcpyAsync(E.ring_slot(16), sp_offs + split_blocks(m), 16, hipMemcpyDeviceToHost, E.stream),
+                   "hipMemcpyAsync(split count)");
+                ck(hipEventRecord(E.sync_event(2), E.stream), "hipEventRecord");
+                deferred.active = true;
+                deferred.src = U;
+                deferred.rows = m;
             };
             // replacement selection: the open run starts at rs_off in the
             // spill buffer and holds rs_rows rows so far
@@ -1235,11 +1301,24 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 n_res = q;
                 n_idx = q + nw;
             };
-            auto decide = [&](uint64_t j, uint64_t gj, int target) {
+            auto decide = [&](uint64_t j, uint64_t gj, int target, bool rev) {
                 if (hy) return decide_hybrid(j, gj, target);
                 const uint64_t* h = (const uint64_t*)rb_merge(j);
                 if (h[0] >> 32) throw Fail{ISA_EDEVICE, "merge placement wait timed out"};
                 const uint64_t m = h[1];
+                if (inplace) {
+                    // a reverse merge leaves the index at the buffer's tail
+                    uint64_t* U = rev ? idx[0] + (buf_rows - m) * sw : idx[0];
+                    if (m <= p.capacity) {
+                        ip = U;
+                        n_idx = m;
+                    } else {
+                        spill_inplace(U, m);
+                        ip = nullptr;
+                        n_idx = 0;
+                    }
+                    return;
+                }
                 if (m <= p.capacity) {
                     ip = idx[target];
                     n_idx = m;
@@ -1274,6 +1353,8 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             bool merge_out = false;  // a merge whose absorb is not decided yet
             uint64_t merge_batch = 0, merge_g = 0;
             int merge_tgt = 0;
+            bool merge_rev = false;
+            uint64_t n_merges = 0;
             for (uint64_t i = 0; i < bp.batches; ++i) {
                 const uint32_t slot = (uint32_t)(i % 3);
                 if (i + 1 < bp.batches) sort_batch(i + 1);
@@ -1301,7 +1382,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 }
                 ++batches;
                 if (merge_out) {
-                    decide(merge_batch, merge_g, merge_tgt);
+                    decide(merge_batch, merge_g, merge_tgt, merge_rev);
                     merge_out = false;
                 }
                 if (!ip) {
@@ -1313,15 +1394,25 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     continue;
                 }
                 const int tgt = merge_target();
-                guard(tgt, (n_idx + g) * sw * 8);
+                // in place: an index at the buffer's head is merged backwards,
+                // ending at the buffer's end; one at its tail (or a batch run)
+                // forwards, from the buffer's start
+                const bool rev = inplace && ip == idx[0];
+                if (inplace)
+                    guard_idx();
+                else
+                    guard(tgt, (n_idx + g) * sw * 8);
                 ck(hipStreamWaitEvent(E.stream, ev_sort(i), 0), "hipStreamWaitEvent");
-                uint64_t* m_ctl = m_ctl2[i % 2];
+                // merges alternate between the two control blocks (a batch
+                // that starts an index after a spill makes no merge)
+                uint64_t* m_ctl = m_ctl2[n_merges % 2];
                 E.pbegin("k_merge");
                 // the merge's last partition (and the probe) write the result
                 // words straight to the pinned readback slot
                 uint64_t* rb_dev = E.ring_dev_of(rb_merge(i));
                 launch_merge(ip, n_idx, brun[slot], g, idx[tgt], S, m_splits, m_ctl + 3, (uint32_t*)m_ctl, m_ctl + 1,
-                             E.stream, m_ctl2[(i + 1) % 2], (uint32_t)mctl_words, rb_dev);
+                             E.stream, m_ctl2[(n_merges + 1) % 2], (uint32_t)mctl_words, rb_dev, rev ? buf_rows : 0);
+                ++n_merges;
                 E.pend(n_idx + g, (n_idx + g) * sw * 8);
                 if (rs) launch_rs_probe(idx[tgt], m_ctl + 1, (uint32_t)sw, rs_cur, rb_dev + 2, E.stream);
                 if (hy) {
@@ -1340,10 +1431,11 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 merge_batch = i;
                 merge_g = g;
                 merge_tgt = tgt;
+                merge_rev = rev;
             }
             if (merge_out) {
                 ck(hipEventSynchronize(ev_merge(merge_batch)), "hipEventSynchronize");
-                decide(merge_batch, merge_g, merge_tgt);
+                decide(merge_batch, merge_g, merge_tgt, merge_rev);
             }
             flush_copy();
             if (rs_rows) runs.push_back(RunInfo{rs_off, 0, rs_rows});
@@ -1371,7 +1463,19 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             } else {
                 // keep only the live index, at the front; everything after it
                 // is merge space
-                if (ip != idx[0]) launch_copy_words(ip, idx[0], n_idx * sw, E.stream);
+                if (ip && ip != idx[0]) {
+                    // an index at the buffer's tail moves down in pieces no
+                    // longer than the distance (at least a batch)
+                    if (inplace && ip > idx[0] && ip < idx[0] + buf_rows * sw) {
+                        const uint64_t dist = (uint64_t)(ip - idx[0]) / sw;
+                        for (uint64_t c = 0; c < n_idx; c += dist) {
+                            const uint64_t len = std::min(dist, n_idx - c);
+                            launch_copy_words(ip + c * sw, idx[0] + c * sw, len * sw, E.stream);
+                        }
+                    } else {
+                        launch_copy_words(ip, idx[0], n_idx * sw, E.stream);
+                    }
+                }
                 const uint64_t idx_off = (uint64_t)((char*)idx[0] - A.base);
                 A.off = idx_off + n_idx * sw * 8;
                 // Preliminary merge steps (Section 4, Example 4): the smallest

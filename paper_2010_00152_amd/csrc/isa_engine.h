@@ -54,9 +54,13 @@ void launch_single_partial(const Leaf* leaves, const SinglePiece* pieces, uint32
 size_t single_partial_bytes();
 uint64_t merge_parts(uint64_t na, uint64_t nb);
 // next_ctl (optional): next_words words cleared by the merge for the next one.
+// rev_cap > 0: the merged rows end at row rev_cap of out (reverse order of
+// partitions); A may then occupy the start of out.  With rev_cap == 0, A may
+// occupy the tail of out (in-place absorption; see the kernel).
 void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb, uint64_t* out, Layout L,
                   uint64_t* splits, uint64_t* status, uint32_t* ctl, uint64_t* total_out, hipStream_t st,
-                  uint64_t* next_ctl = nullptr, uint32_t next_words = 0, uint64_t* host_out = nullptr);
+                  uint64_t* next_ctl = nullptr, uint32_t next_words = 0, uint64_t* host_out = nullptr,
+                  uint64_t rev_cap = 0);
 // Replacement selection: cursor position in the merged index (*p_out) and
 // eviction of rows [p, p+a) and [0, b) (see the kernels).
 void launch_rs_probe(const uint64_t* U, const uint64_t* m_ptr, uint32_t w, const uint64_t* cur, uint64_t* p_out,
@@ -64,8 +68,9 @@ void launch_rs_probe(const uint64_t* U, const uint64_t* m_ptr, uint32_t w, const
 void launch_rs_evict(const uint64_t* U, uint64_t m, uint32_t w, uint64_t p, uint64_t a, uint64_t b, uint64_t* out,
                      uint64_t* cur, hipStream_t st);
 uint64_t split_blocks(uint64_t n);
+// cap_words > 0: the run is written only if it takes at most that many words.
 void launch_split(const uint64_t* rows, uint64_t n, Layout S, Layout R, uint32_t* counts, uint64_t* tiles,
-                  uint64_t* offs, uint64_t* out, uint64_t end_words, hipStream_t st);
+                  uint64_t* offs, uint64_t* out, uint64_t end_words, hipStream_t st, uint64_t cap_words = 0);
 void launch_gather(const GatherTask* tasks, uint32_t n_tasks, Layout R, Layout S, uint64_t* dst, hipStream_t st);
 void launch_copy_rows(ColView src, uint64_t n, OutView dst, uint64_t cap, hipStream_t st);
 uint64_t scan_tiles(uint64_t n);

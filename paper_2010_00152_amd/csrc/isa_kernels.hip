@@ -1305,13 +1305,27 @@ __device__ __forceinline__ void combine_rows(uint64_t* o, const uint64_t* a, con
 
 // next_ctl (optional, next_words words): the control block of the next merge
 // on the stream, cleared here so that it needs no launch of its own.
-__global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A, uint64_t na,
+//
+// In place.  A may lie in the output buffer itself: partitions are taken in
+// ticket order, and a partition stages all its input in LDS before it
+// publishes its count, so when a partition writes, every partition of an
+// earlier ticket has read its input.
+//  - Forward (rev_cap == 0): out is written from its start; A may occupy the
+//    tail of a buffer of at least na + nb rows ending where A ends.  A write
+//    of partition p ends before diagonal d_{p+1} <= ia_{p+1} + nb, which is
+//    not beyond where the A rows of later partitions start.
+//  - Reverse (rev_cap = C > 0): partitions are taken from the last key down
+//    and the merged rows end at row C of out (C >= na + nb); A may occupy
+//    rows [0, na) of out.  A write of partition p starts at or after
+//    C - (na - ia_p) - (nb - ja_p) >= ia_p, beyond the A rows of every
+//    partition taken later.
+__global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* A, uint64_t na,
                                                  const uint64_t* __restrict__ B, uint64_t nb,
-                                                 const uint64_t* __restrict__ splits, uint64_t* __restrict__ out,
+                                                 const uint64_t* __restrict__ splits, uint64_t* out,
                                                  Layout L, uint64_t* __restrict__ status, uint32_t* __restrict__ ctl,
                                                  uint64_t* __restrict__ total_out, uint64_t* __restrict__ next_ctl,
                                                  uint32_t next_words, uint32_t nparts,
-                                                 uint64_t* __restrict__ host_out) {
+                                                 uint64_t* __restrict__ host_out, uint64_t rev_cap) {
     __shared__ uint64_t s_in[(MG_D + 2) * MG_MAXW];
     __shared__ uint32_t s_li[MG_NT + 1], s_lj[MG_NT + 1];
     __shared__ uint32_t s_tmp[MG_NT / 64 + 1];
@@ -1324,8 +1338,9 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
     for (;;) {
         if (tid == 0) s_part = atomicAdd(&ctl[0], 1u);
         __syncthreads();
-        const uint32_t part = s_part;
-        if (part >= nparts) break;
+        const uint32_t ticket = s_part;
+        if (ticket >= nparts) break;
+        const uint32_t part = rev_cap ? nparts - 1 - ticket : ticket;
         const uint64_t ia0 = splits[2 * part], ja0 = splits[2 * part + 1];
         const uint64_t ia1 = splits[2 * part + 2], ja1 = splits[2 * part + 3];
         const uint32_t la = (uint32_t)(ia1 - ia0), lb = (uint32_t)(ja1 - ja0);
@@ -1396,10 +1411,10 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
         uint32_t tot;
         const uint32_t off = block_exclusive_scan<MG_NT>(c, s_tmp, tot);  // synchronises: the input is dead
         if (tid < 64) {
-            const uint64_t pre = chained_prefix(status, part, 0, tot, &ctl[1]);
+            const uint64_t pre = chained_prefix(status, ticket, 0, tot, &ctl[1]);
             if (tid == 0) {
                 s_pre = pre;
-                if (part == nparts - 1) {
+                if (ticket == nparts - 1) {
                     *total_out = pre + tot;
                     if (host_out) {
                         __threadfence();
@@ -1419,7 +1434,7 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* __restrict__ A,
             }
         }
         __syncthreads();
-        uint64_t* const ob = out + s_pre * W;
+        uint64_t* const ob = out + (rev_cap ? rev_cap - s_pre - tot : s_pre) * W;
         for (uint32_t x = tid; x < tot * W; x += MG_NT) ob[x] = s_in[x];
         __syncthreads();  // the LDS input and s_part are reused by the next partition
     }
@@ -1997,7 +2012,8 @@ constexpr int SPLIT_TILE = 1024;
 constexpr int SPLIT_MAXW = 6;
 __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict__ rows, uint64_t n, Layout S,
                                                      Layout R, const uint64_t* __restrict__ offs, uint64_t nblocks,
-                                                     uint64_t* __restrict__ out, uint64_t end_words) {
+                                                     uint64_t* __restrict__ out, uint64_t end_words,
+                                                     uint64_t cap_words) {
     __shared__ uint64_t s_rows[SPLIT_TILE * SPLIT_MAXW];
     __shared__ uint16_t s_msrc[SPLIT_TILE];
     __shared__ uint32_t s_wave[4];
@@ -2007,6 +2023,9 @@ __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict_
     const uint64_t n_single = offs[nblocks];
     const bool narrow = offs[nblocks + 1] != 0;
     const uint64_t s_words = single_bytes(n_single, R, narrow) / 8;
+    // a run larger than the room it is written into is not written at all
+    // (the caller sees its size and copies the rows some other way)
+    if (cap_words && s_words + (n - n_single) * S.words > cap_words) return;
     if (end_words) out += end_words - (s_words + (n - n_single) * S.words);
     uint64_t* key_c = out;
     uint64_t* fs_c = out + n_single;
@@ -2269,7 +2288,7 @@ uint64_t merge_parts(uint64_t na, uint64_t nb) { return (na + nb + MG_D - 1) / M
 // status: parts words and ctl: 2 words, both zeroed.
 void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb, uint64_t* out, Layout L,
                   uint64_t* splits, uint64_t* status, uint32_t* ctl, uint64_t* total_out, hipStream_t st,
-                  uint64_t* next_ctl, uint32_t next_words, uint64_t* host_out) {
+                  uint64_t* next_ctl, uint32_t next_words, uint64_t* host_out, uint64_t rev_cap) {
     const uint64_t parts = merge_parts(na, nb);
     if (parts == 0) return;
     hipLaunchKernelGGL(k_merge_splits, dim3((uint32_t)((parts + 1 + 255) / 256)), dim3(256), 0, st, A, na, B, nb,
@@ -2278,7 +2297,7 @@ void launch_merge(const uint64_t* A, uint64_t na, const uint64_t* B, uint64_t nb
     // sort running beside the merge
     const uint32_t grid = (uint32_t)(parts < MG_GRID ? parts : MG_GRID);
     hipLaunchKernelGGL(k_merge, dim3(grid), dim3(MG_NT), 0, st, A, na, B, nb, splits, out, L, status, ctl, total_out,
-                       next_ctl, next_words, (uint32_t)parts, host_out);
+                       next_ctl, next_words, (uint32_t)parts, host_out, rev_cap);
 }
 void launch_rs_probe(const uint64_t* U, const uint64_t* m_ptr, uint32_t w, const uint64_t* cur, uint64_t* p_out,
                      hipStream_t st) {
@@ -2296,14 +2315,15 @@ uint64_t split_blocks(uint64_t n) { return (n + SPLIT_T - 1) / SPLIT_T; }
 // counts: split_blocks(n) words; tiles as for launch_scan; offs: split_blocks(n) + 2
 // words (the scan, then the narrow flag of the count-1 part).
 void launch_split(const uint64_t* rows, uint64_t n, Layout S, Layout R, uint32_t* counts, uint64_t* tiles,
-                  uint64_t* offs, uint64_t* out, uint64_t end_words, hipStream_t st) {
+                  uint64_t* offs, uint64_t* out, uint64_t end_words, hipStream_t st, uint64_t cap_words) {
     const uint64_t nb = split_blocks(n);
     if (!nb) return;
     // offs[nb + 1] (beyond the scan's entries) holds the narrow flag
     launch_fill(offs + nb + 1, 1, 1, st);
     hipLaunchKernelGGL(k_split_count, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, counts, offs + nb + 1);
     launch_scan(counts, nb, tiles, offs, st);
-    hipLaunchKernelGGL(k_split_write, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, R, offs, nb, out, end_words);
+    hipLaunchKernelGGL(k_split_write, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, R, offs, nb, out, end_words,
+                       cap_words);
 }
 void launch_gather(const GatherTask* tasks, uint32_t n_tasks, Layout R, Layout S, uint64_t* dst, hipStream_t st) {
     if (!n_tasks) return;

@@ -90,8 +90,10 @@ def test_spilling_100m_rows_full_size(ctx, s, seed, policy):
     assert not bad.any(), (int(bad.sum()), float((err / np.maximum(absum, 1e-300)).max()))
     del ref, absum, err
 
-    simulate = spillsim.simulate_replacement if policy == "rs" else spillsim.simulate
-    sim = simulate(k, st["batch_rows"], st["index_capacity"])
+    if policy == "rs":
+        sim = spillsim.simulate_replacement(k, st["batch_rows"], st["index_capacity"])
+    else:
+        sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"], absorb_first=True)
     assert st["runs"] == sim["runs"] and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
     assert st["spilled_rows"] <= n
     assert st["peak_ws_bytes"] <= 256 << 20

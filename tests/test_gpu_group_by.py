@@ -103,7 +103,7 @@ def test_spilling_matches_oracle_and_simulator(ctx, s, seed, budget_mib):
     k, v, f = datagen.plain_input(seed, n, 400_000, s, with_f64=True)
     got, st, status, g = run_gpu(ctx, k, v, f, budget=budget_mib << 20)
     compare(got, k, v, f, isa.ISA_ALL, "spill")
-    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"])
+    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"], absorb_first=True)
     assert st["runs"] == sim["runs"] and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
     assert st["spilled_rows"] <= n
     if s < 1.2:
@@ -211,7 +211,7 @@ def test_spilling_with_extreme_keys(ctx):
     got, st, status, g = run_gpu(ctx, k, v, f, budget=16 << 20)
     compare(got, k, v, f, isa.ISA_ALL, "spill extremes")
     assert st["runs"] > 0
-    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"])
+    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"], absorb_first=True)
     assert st["runs"] == sim["runs"] and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
 
 
@@ -297,10 +297,39 @@ def test_preliminary_merges_before_the_wide_merge(ctx, fanin):
     finally:
         ctx.set_tuning()
     compare(got, k, v, f, isa.ISA_ALL, "preliminary merges")
-    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"], keep_runs=True)
+    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"], keep_runs=True, absorb_first=True)
     assert st["runs"] == sim["runs"] and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
     plan = spillsim.preliminary_merges_exact(sim["run_keys"], fanin)
     assert len(plan["counts"]) - 1 >= 2                     # at least two steps
     assert st["merge_steps"] == len(plan["counts"]) - 1, (st, plan["counts"])
     assert st["merge_rows"] == plan["written_rows"], (st, plan)
     assert st["windows"] >= 1
+
+
+def test_inplace_runs_compacted_or_as_state_rows(ctx):
+    # read-sort-write absorbs batches in place and compacts each run into a
+    # spare area of about half the index; a run whose compacted form would not
+    # fit (few count-1 rows, wide values) goes out as state rows instead.
+    # Both give the oracle's output and the simulator's runs and rows.
+    n = 1_200_000
+    sw = 48
+    # many count-1 rows and 32-bit values: every run compacted
+    say("case in-place compacted runs")
+    k, v, f = datagen.plain_input(51, n, 600_000, 0.0, with_f64=True)
+    got, st, status, g = run_gpu(ctx, k, v, f, budget=16 << 20)
+    compare(got, k, v, f, isa.ISA_ALL, "in-place compacted")
+    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"], absorb_first=True)
+    assert st["runs"] == sim["runs"] > 1 and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
+    assert st["spilled_bytes"] < 0.6 * sw * st["spilled_rows"]
+    # a key domain near the index capacity and 64-bit values: more than half
+    # of each run's keys repeat, and no compacted run fits the spare area
+    say("case in-place state-row runs")
+    rng = np.random.default_rng(52)
+    k = datagen.key_of_rank(rng.integers(0, 80_000, n).astype(np.uint64))
+    v = rng.integers(-(1 << 40), 1 << 40, n).astype(np.int64)
+    f = rng.standard_normal(n)
+    got, st, status, g = run_gpu(ctx, k, v, f, budget=16 << 20)
+    compare(got, k, v, f, isa.ISA_ALL, "in-place state rows")
+    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"], absorb_first=True)
+    assert st["runs"] == sim["runs"] > 1 and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
+    assert st["spilled_bytes"] == sw * st["spilled_rows"]

@@ -291,3 +291,40 @@ def test_hybrid_scale_of_the_model():
     assert abs(h["spilled_rows"] - expect) <= 0.05 * expect, (h["spilled_rows"], expect)
     assert h["spilled_rows"] < I
     assert abs(h["resident_rows"] - 0.75 * Kr) <= 0.25 * Kr
+
+
+def test_absorb_first_hand_worked():
+    # batches of 2 rows, capacity 3: {5,1} -> index {1,5}; {5,2} -> {1,2,5};
+    # {7,8} -> {1,2,5,7,8} > 3: written whole (5 rows), index empty;
+    # {9,1} -> {1,9}; {3,4} -> {1,3,4,9} > 3: written (4 rows), index empty
+    keys = np.array([5, 1, 5, 2, 7, 8, 9, 1, 3, 4], dtype=np.uint64)
+    r = spillsim.simulate(keys, 2, 3, absorb_first=True)
+    assert r["run_sizes"] == [5, 4] and r["final_index_rows"] == 0
+
+
+@pytest.mark.parametrize("nb,m", [(1000, 3), (700, 5), (512, 2)])
+def test_absorb_first_all_distinct_closed_form(nb, m):
+    # all keys distinct: the index grows by a batch until it holds more than
+    # m batches, then (m + 1) batches are written: runs of (m + 1) * Bt rows
+    n = nb * (m + 1) * 7 + nb * 2
+    keys = datagen.key_of_rank(np.arange(n, dtype=np.uint64))
+    r = spillsim.simulate(keys, nb, m * nb, absorb_first=True)
+    assert r["run_sizes"] == [(m + 1) * nb] * 7
+    assert r["final_index_rows"] == 2 * nb
+
+
+@pytest.mark.parametrize("s", [0.0, 0.8, 1.2])
+def test_absorb_first_bounds(s):
+    # no run while the output fits the capacity; runs never exceed capacity
+    # plus a batch, and spilled rows never exceed the input rows; the index
+    # after a run starts empty, so each run holds more than capacity keys
+    k = datagen.plain_input(31, 200_000, 20_000, s)[0]
+    o = np.unique(k).shape[0]
+    assert spillsim.simulate(k, 1_000, o, absorb_first=True)["runs"] == 0
+    r = spillsim.simulate(k, 1_000, 4_000, absorb_first=True)
+    assert all(4_000 < x <= 5_000 for x in r["run_sizes"])
+    assert r["spilled_rows"] <= k.shape[0]
+    sim_old = spillsim.simulate(k, 1_000, 4_000)
+    # writing the memory whole as soon as it is full: about as many rows per
+    # run as the other reading with one batch more of memory
+    assert r["runs"] <= sim_old["runs"]
