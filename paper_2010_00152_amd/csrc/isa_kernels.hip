@@ -177,14 +177,39 @@ struct CSortSmem {
     static constexpr int NP = N + N / 16;
     uint64_t key[NP];
     uint16_t val[NP];
-    uint16_t cnt[CNT_DIGITS * NT];
+    alignas(16) uint16_t cnt[CNT_DIGITS * NT];
     uint32_t tmp[NT / 64 + 1];
 };
 
-template <int NT, int IPT>
+// Exclusive block scan with one barrier: every thread sums the wave totals
+// itself.  s_tmp (NT/64 words) must not be rewritten before a later barrier.
+template <int NT>
+__device__ __forceinline__ uint32_t block_exclusive_scan_1b(uint32_t x, uint32_t* s_tmp, uint32_t& total) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t inc = wave_inclusive_scan(x);
+    if (lane == 63) s_tmp[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const uint32_t t = s_tmp[i];
+        before += i < w ? t : 0u;
+        all += t;
+    }
+    total = all;
+    return before + inc - x;
+}
+
+// IPTC <= IPT items per thread take part (thread t: items t*IPTC ..
+// t*IPTC+IPTC-1).  The count is a compile-time constant so that every loop
+// over the items is straight-line code: a wave's LDS operations of all its
+// items are in flight together instead of one item per round trip.
+template <int NT, int IPT, int IPTC = IPT>
 __device__ void block_sort_cnt(uint64_t (&k)[IPT], uint16_t (&v)[IPT], int lo_bit, int hi_bit,
-                               CSortSmem<NT, IPT>& s, int ipt = IPT) {
-    // ipt <= IPT items per thread take part (thread t: items t*ipt .. t*ipt+ipt-1)
+                               CSortSmem<NT, IPT>& s) {
+    static_assert(IPTC <= IPT, "active items per thread");
+    constexpr int ipt = IPTC;
     static_assert((CNT_DIGITS * NT * 2) % (16 * NT) == 0, "counter zeroing layout");
     constexpr int ZERO4 = CNT_DIGITS * NT * 2 / 16 / NT;  // uint4 stores per thread
     constexpr int SEG = CNT_DIGITS;                       // counters scanned per thread
@@ -201,6 +226,10 @@ __device__ void block_sort_cnt(uint64_t (&k)[IPT], uint16_t (&v)[IPT], int lo_bi
         return;
     }
     uint4* c4 = reinterpret_cast<uint4*>(s.cnt);
+    // thread t's counter of digit d, cnt[d*NT + t], is half (t & 1) of a word
+    uint32_t* cw = reinterpret_cast<uint32_t*>(s.cnt);
+    const uint32_t half = (uint32_t)(tid & 1) * 16u;
+    static_assert(NT % 2 == 0 && SEG % 8 == 0, "counter word and vector layout");
     for (int shift = lo_bit; shift < hi_bit; shift += CNT_BITS) {
         const int dbits = hi_bit - shift < CNT_BITS ? hi_bit - shift : CNT_BITS;
         const uint32_t mask = (1u << dbits) - 1u;
@@ -208,33 +237,45 @@ __device__ void block_sort_cnt(uint64_t (&k)[IPT], uint16_t (&v)[IPT], int lo_bi
 #pragma unroll
         for (int i = 0; i < ZERO4; ++i) c4[i * NT + tid] = make_uint4(0, 0, 0, 0);
         __syncthreads();
-        uint16_t loc[IPT];
-        uint32_t dg[IPT];
+        // the item's rank among the thread's earlier items of its digit: the
+        // counter's old value, from LDS atomics issued back to back (a
+        // wave's LDS operations complete in order)
+        uint32_t loc[IPT], dg[IPT];
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
             if (j < ipt) {
                 const uint32_t d = (uint32_t)(k[j] >> shift) & mask;
                 dg[j] = d;
-                const uint16_t c = s.cnt[d * NT + tid];
-                loc[j] = c;
-                s.cnt[d * NT + tid] = (uint16_t)(c + 1);
+                loc[j] = (atomicAdd(&cw[(d * NT + tid) >> 1], 1u << half) >> half) & 0xffffu;
             }
         }
         __syncthreads();
-        // scan the counters in memory order (digit-major, thread-minor)
-        uint16_t seg[SEG];
+        // scan the counters in memory order (digit-major, thread-minor),
+        // eight per 16-byte load
+        uint4* seg4 = reinterpret_cast<uint4*>(s.cnt + tid * SEG);
+        uint4 q[SEG / 8];
         uint32_t sum = 0;
 #pragma unroll
-        for (int i = 0; i < SEG; ++i) {
-            seg[i] = s.cnt[tid * SEG + i];
-            sum += seg[i];
+        for (int i = 0; i < SEG / 8; ++i) {
+            q[i] = seg4[i];
+            const uint32_t h = q[i].x + q[i].y + q[i].z + q[i].w;  // two 16-bit sums, no carry (<= N)
+            sum += (h & 0xffffu) + (h >> 16);
         }
         uint32_t total;
-        uint32_t run = block_exclusive_scan<NT>(sum, s.tmp, total);
+        uint32_t run = block_exclusive_scan_1b<NT>(sum, s.tmp, total);
+        auto pre2 = [&](uint32_t& wd) {
+            // the word's two counters become their exclusive prefixes
+            const uint32_t lo = wd & 0xffffu, hi = wd >> 16;
+            wd = run | ((run + lo) << 16);
+            run += lo + hi;
+        };
 #pragma unroll
-        for (int i = 0; i < SEG; ++i) {
-            s.cnt[tid * SEG + i] = (uint16_t)run;
-            run += seg[i];
+        for (int i = 0; i < SEG / 8; ++i) {
+            pre2(q[i].x);
+            pre2(q[i].y);
+            pre2(q[i].z);
+            pre2(q[i].w);
+            seg4[i] = q[i];
         }
         __syncthreads();
 #pragma unroll
@@ -262,8 +303,9 @@ __device__ void block_sort_cnt(uint64_t (&k)[IPT], uint16_t (&v)[IPT], int lo_bi
 // w*64*IPT + j*64 + l) into blocked order (thread t holds rows t*IPT ..
 // t*IPT+IPT-1) through LDS, so the first sort pass sees rows in row order and
 // padding rows (beyond n) stay after every real row.
-template <int NT, int IPT>
-__device__ void striped_to_blocked(uint64_t (&k)[IPT], uint16_t (&v)[IPT], CSortSmem<NT, IPT>& s, int ipt = IPT) {
+template <int NT, int IPT, int IPTC = IPT>
+__device__ void striped_to_blocked(uint64_t (&k)[IPT], uint16_t (&v)[IPT], CSortSmem<NT, IPT>& s) {
+    constexpr int ipt = IPTC;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
@@ -854,13 +896,17 @@ __device__ __forceinline__ void flush_stage(const uint64_t* st, uint32_t rows, i
     col(o.fs);
 }
 
-// Sort, reduce and place one leaf of at most LEAF_CAP rows (workgroup-wide).
+// Sort, reduce and place one leaf of at most LEAF_CAP rows (workgroup-wide),
+// with IPTC sorted positions per thread (IPTC * LEAF_NT >= n).
 // li is the leaf's ticket, [first, last] the tickets of its destination d.
-__device__ __forceinline__ void leaf_sort_reduce(const ColView& V, const uint32_t n, const Dest& D, const uint32_t li,
-                                                 const uint32_t first, const uint32_t last, const uint32_t d,
-                                                 uint64_t* __restrict__ status, uint64_t* __restrict__ totals,
-                                                 uint32_t* __restrict__ ctl, LeafSmem& s, uint64_t& s_pre) {
+template <int IPTC>
+__device__ __forceinline__ void leaf_sort_reduce_t(const ColView& V, const uint32_t n, const Dest& D,
+                                                   const uint32_t li, const uint32_t first, const uint32_t last,
+                                                   const uint32_t d, uint64_t* __restrict__ status,
+                                                   uint64_t* __restrict__ totals, uint32_t* __restrict__ ctl,
+                                                   LeafSmem& s, uint64_t& s_pre) {
     constexpr int NT = LEAF_NT, IPT = LEAF_IPT;
+    constexpr int ipt = IPTC;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     uint64_t k[IPT];
     uint16_t v[IPT];
@@ -887,10 +933,9 @@ __device__ __forceinline__ void leaf_sort_reduce(const ColView& V, const uint32_
     }
     const int nbits = bit_length(range);
     const int lo_bit = nbits > LEAF_TRUNC ? nbits - LEAF_TRUNC : 0;
-    // only the slots the leaf fills take part in the sort
-    const int ipt = (int)((n + NT - 1) / NT);
-    striped_to_blocked<NT, IPT>(k, v, s.sort, ipt);
-    block_sort_cnt<NT, IPT>(k, v, lo_bit, nbits, s.sort, ipt);
+    // only the slots of the leaf's rows (and their padding) take part
+    striped_to_blocked<NT, IPT, IPTC>(k, v, s.sort);
+    block_sort_cnt<NT, IPT, IPTC>(k, v, lo_bit, nbits, s.sort);
     if (lo_bit > 0) {
         bool clash = false;
 #pragma unroll
@@ -910,7 +955,7 @@ __device__ __forceinline__ void leaf_sort_reduce(const ColView& V, const uint32_
                 }
             }
             __syncthreads();
-            block_sort_cnt<NT, IPT>(k, v, 0, nbits, s.sort, ipt);
+            block_sort_cnt<NT, IPT, IPTC>(k, v, 0, nbits, s.sort);
         }
     }
 
@@ -962,7 +1007,7 @@ __device__ __forceinline__ void leaf_sort_reduce(const ColView& V, const uint32_
     bool have_head = false;
     uint32_t h = 0;
 #pragma unroll
-    for (int r0 = 0; r0 < IPT; r0 += LEAF_ROUND) {
+    for (int r0 = 0; r0 < ipt; r0 += LEAF_ROUND) {
         Agg pay[LEAF_ROUND];
 #pragma unroll
         for (int j = 0; j < LEAF_ROUND; ++j)
@@ -1021,6 +1066,20 @@ __device__ __forceinline__ void leaf_sort_reduce(const ColView& V, const uint32_
     const uint64_t room = D.capacity > pre0 ? D.capacity - pre0 : 0;
     flush_stage(s.stage, (uint64_t)staged < room ? staged : (uint32_t)room, W, row_major, D.out, pre0);
     if (tid == 0 && li == last) totals[d] = pre0 + total;
+}
+
+// A leaf of n <= LEAF_CAP rows: the sort's positions per thread rounded up to
+// 4, 8 or 16.
+__device__ __forceinline__ void leaf_sort_reduce(const ColView& V, const uint32_t n, const Dest& D, const uint32_t li,
+                                                 const uint32_t first, const uint32_t last, const uint32_t d,
+                                                 uint64_t* __restrict__ status, uint64_t* __restrict__ totals,
+                                                 uint32_t* __restrict__ ctl, LeafSmem& s, uint64_t& s_pre) {
+    if (n <= 4u * LEAF_NT)
+        leaf_sort_reduce_t<4>(V, n, D, li, first, last, d, status, totals, ctl, s, s_pre);
+    else if (n <= 8u * LEAF_NT)
+        leaf_sort_reduce_t<8>(V, n, D, li, first, last, d, status, totals, ctl, s, s_pre);
+    else
+        leaf_sort_reduce_t<LEAF_IPT>(V, n, D, li, first, last, d, status, totals, ctl, s, s_pre);
 }
 
 // Reduce all rows of a single-key range of any size in one workgroup
