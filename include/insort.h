@@ -318,7 +318,7 @@ typedef struct {
     uint32_t leaf_rows;    /* target rows per sort leaf (buckets per partition = rows / leaf_rows,
                               2..256); 256..2048 */
     uint32_t chunk_split;  /* partition chunks per region: chunk rows = rows / chunk_split, clamped
-                              to 4096..16384; 64..4096 */
+                              to 4096..16384 (2048..16384 for the batches of isa_group_by); 64..4096 */
     uint32_t graph;        /* 1: a wave of small batched instances launches as one captured HIP
                               graph; 0: direct launches */
     uint32_t merge_fanin;  /* runs one merge step of isa_group_by may take (Section 4's merge

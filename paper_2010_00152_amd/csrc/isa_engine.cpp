@@ -297,11 +297,11 @@ uint32_t buckets_for(const Engine& E, uint64_t n) {
     return (uint32_t)nb;
 }
 
-// Rows per partition chunk: one sub-tile for small regions (more
-// workgroups), up to four sub-tiles for large ones.
-uint64_t chunk_rows(const Engine& E, uint64_t n) {
-    const uint64_t crow = (n / E.tune.chunk_split + PART_TILE - 1) / PART_TILE * PART_TILE;
-    return std::max<uint64_t>(PART_TILE, std::min<uint64_t>(PART_CHUNK, crow));
+// Rows per partition chunk: at least min_rows (a multiple of PART_CHUNK_MIN)
+// for small regions (more workgroups), up to four tiles for large ones.
+uint64_t chunk_rows(const Engine& E, uint64_t n, uint64_t min_rows) {
+    const uint64_t crow = (n / E.tune.chunk_split + min_rows - 1) / min_rows * min_rows;
+    return std::max<uint64_t>(min_rows, std::min<uint64_t>(PART_CHUNK, crow));
 }
 
 // Splitters for every batch of one input, from a stratified sample of
@@ -476,7 +476,7 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
             r.n = nd.n;
             r.out_pos = nd.pos;
             r.nb = buckets_for(E, nd.n);
-            const uint64_t crow = chunk_rows(E, nd.n);
+            const uint64_t crow = chunk_rows(E, nd.n, PART_TILE);
             r.n_chunks = (uint32_t)((nd.n + crow - 1) / crow);
             r.hist_base = hist_total;
             hist_total += (uint64_t)r.nb * r.n_chunks;
@@ -713,7 +713,7 @@ bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, co
         r.n = in.n;
         r.out_pos = N;
         r.nb = (hint && hint->dev && inst.size() == 1) ? hint->nb : buckets_for(E, in.n);
-        const uint64_t crow = chunk_rows(E, in.n);
+        const uint64_t crow = chunk_rows(E, in.n, PART_TILE);
         r.n_chunks = (uint32_t)((in.n + crow - 1) / crow);
         r.hist_base = hist_total;
         hist_total += (uint64_t)r.nb * r.n_chunks;
@@ -839,7 +839,7 @@ constexpr uint32_t BP_CTL_RING = 8;  // control blocks reused round-robin
 }  // namespace
 
 uint64_t batch_program_bytes(uint64_t Bt, const Cols& k) {
-    const uint64_t ch = (Bt + PART_TILE - 1) / PART_TILE;  // the most chunks any tuning gives
+    const uint64_t ch = (Bt + PART_CHUNK_MIN - 1) / PART_CHUNK_MIN;  // the most chunks any tuning gives
     const uint64_t hist = (uint64_t)MAX_BUCKETS * ch;
     const uint64_t pieces = (Bt + SINGLE_CHUNK - 1) / SINGLE_CHUNK;
     const uint64_t desc = BP_CTL_RING * sizeof(Region) + 2 * ch * sizeof(Chunk) + MAX_BUCKETS * sizeof(FlatSlot) +
@@ -860,7 +860,9 @@ void BatchProgram::setup(Engine& E, Arena& A, const ColView& src_rows, uint64_t 
     L = raw_layout(k);
     src = src_rows;
     splitters = hint.dev;
-    const uint64_t crow = chunk_rows(E, Bt);
+    // a batch is one region: chunks of PART_CHUNK_MIN rows give every
+    // compute unit a workgroup of the partition passes
+    const uint64_t crow = chunk_rows(E, Bt, PART_CHUNK_MIN);
     chunks_full = (uint32_t)((Bt + crow - 1) / crow);
     const uint64_t last_n = n - (batches - 1) * Bt;
     chunks_last = (uint32_t)((last_n + crow - 1) / crow);

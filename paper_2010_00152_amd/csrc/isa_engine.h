@@ -148,7 +148,7 @@ struct ProfRec {
 // Launch configuration of the sort-reduce plans (the autotuner's search space).
 struct Tuning {
     uint32_t leaf_rows = 2048;  // target rows per leaf bucket (buckets = rows / leaf_rows, 2..MAX_BUCKETS)
-    uint32_t chunk_split = 512; // partition chunks per region: chunk rows = rows / chunk_split, in [PART_TILE, PART_CHUNK]
+    uint32_t chunk_split = 512; // partition chunks per region: chunk rows = rows / chunk_split, in [PART_TILE, PART_CHUNK] (batches of run generation: from PART_CHUNK_MIN)
     uint32_t graph = 1;         // batched waves of small instances launch as one captured graph
     uint32_t merge_fanin = 0;   // runs per merge step of a spilling group-by (0: all in one wide merge)
 };
@@ -253,7 +253,7 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
                                   const std::vector<Dest>& dests, const Cols& k, bool state_rows,
                                   const SplitterHint* hint = nullptr);
 uint32_t buckets_for(const Engine& E, uint64_t n);
-uint64_t chunk_rows(const Engine& E, uint64_t n);
+uint64_t chunk_rows(const Engine& E, uint64_t n, uint64_t min_rows);
 
 // Device-to-host copy into pinned staging; valid after the next sync().
 const void* download_async(Engine& E, const void* dev, uint64_t bytes);

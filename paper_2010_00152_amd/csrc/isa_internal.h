@@ -15,6 +15,9 @@ constexpr int PART_NT = 256;
 constexpr int PART_IPT = 16;
 constexpr int PART_TILE = PART_NT * PART_IPT;
 constexpr int PART_CHUNK = 4 * PART_TILE;
+// smallest partition chunk (one workgroup's rows): a 524288-row batch spans
+// 256 chunks, one per compute unit
+constexpr int PART_CHUNK_MIN = PART_TILE / 2;
 // Buckets per partition level (8-bit digit of the splitter rank).
 constexpr int MAX_BUCKETS = 256;
 // Keys sampled per region to choose its splitters.

@@ -170,6 +170,11 @@ constexpr int CNT_DIGITS = 1 << CNT_BITS;
 // Key bits (below the range's top) that leaf sorts and splitter samples order
 // first; a leaf re-sorts at full width when two distinct keys share them.
 constexpr int LEAF_TRUNC = 30;
+// Key bits (below the range's top) that a leaf sorts on; distinct keys that
+// share them are put in order afterwards in runs of at most LEAF_FIX_MAX rows.
+constexpr int LEAF_SORT_BITS = 25;
+constexpr int LEAF_FIX_MAX = 1024;
+constexpr int LEAF_FIX_RUNS = 32;
 
 template <int NT, int IPT>
 struct CSortSmem {
@@ -812,8 +817,9 @@ __global__ void __launch_bounds__(256) k_single_partial(const Leaf* __restrict__
 // destination; a leaf's groups go straight to its destination at the chained
 // prefix of the group counts of the destination's earlier leaves.
 // Kind 0: at most LEAF_CAP rows, loaded, sorted in LDS (ordered on their top
-// LEAF_TRUNC bits relative to the leaf minimum, re-sorted on all bits if two
-// distinct keys share those bits) and reduced.  Kind 1: a single key, whose
+// LEAF_SORT_BITS bits relative to the leaf minimum; runs of distinct keys that
+// share those bits are then ordered by rank, or, if such runs are long or
+// many, the leaf is re-sorted on all bits) and reduced.  Kind 1: a single key, whose
 // pieces were reduced by k_single_partial; combined here with a fixed tree.
 // ---------------------------------------------------------------------------
 
@@ -932,30 +938,97 @@ __device__ __forceinline__ void leaf_sort_reduce_t(const ColView& V, const uint3
         k[j] = q < n ? k[j] - mn : range;  // padding sorts last
     }
     const int nbits = bit_length(range);
-    const int lo_bit = nbits > LEAF_TRUNC ? nbits - LEAF_TRUNC : 0;
+    const int lo_bit = nbits > LEAF_SORT_BITS ? nbits - LEAF_SORT_BITS : 0;
     // only the slots of the leaf's rows (and their padding) take part
     striped_to_blocked<NT, IPT, IPTC>(k, v, s.sort);
     block_sort_cnt<NT, IPT, IPTC>(k, v, lo_bit, nbits, s.sort);
     if (lo_bit > 0) {
-        bool clash = false;
+        // Distinct keys that share the sorted top bits (a clash) are still in
+        // input order.  Each run of equal top bits around a clash (found by
+        // binary search: the top bits are sorted) is put in order by the
+        // whole workgroup: every row's rank in the run is its count of
+        // smaller keys plus equal keys before it.  More than LEAF_FIX_RUNS
+        // clashes, or a run longer than LEAF_FIX_MAX rows, sends the leaf
+        // through a full-width sort instead.
+        auto top = [&](uint32_t p) { return s.sort.key[pad16((int)p)] >> lo_bit; };
+        uint32_t cl = 0;  // bit j: positions p-1 and p clash (p = tid*ipt + j)
 #pragma unroll
-        for (int j = 0; j < IPT; ++j) {
+        for (int j = 0; j < ipt; ++j) {
             const int p = tid * ipt + j;
-            if (j < ipt && p > 0 && p < (int)n) {
+            if (p > 0 && p < (int)n) {
                 const uint64_t a = s.sort.key[pad16(p - 1)], b = s.sort.key[pad16(p)];
-                clash |= (a != b) && ((a >> lo_bit) == (b >> lo_bit));
+                if (a != b && (a >> lo_bit) == (b >> lo_bit)) cl |= 1u << j;
             }
         }
-        if (__syncthreads_or(clash)) {
-#pragma unroll
-            for (int j = 0; j < IPT; ++j) {
-                if (j < ipt) {
-                    k[j] = s.sort.key[pad16(tid * ipt + j)];
-                    v[j] = s.sort.val[pad16(tid * ipt + j)];
+        uint32_t* runs = s.pre_flags;  // [0]: clashes seen, then (lo, hi) per clash
+        if (tid == 0) runs[0] = 0;
+        if (__syncthreads_or(cl != 0)) {
+            for (int j = 0; j < ipt; ++j) {
+                if (!(cl & (1u << j))) continue;
+                const uint32_t p = (uint32_t)(tid * ipt + j);
+                const uint64_t t = top(p);
+                uint32_t a = 0, b = p;
+                while (a < b) {
+                    const uint32_t m = (a + b) >> 1;
+                    if (top(m) < t) a = m + 1;
+                    else b = m;
+                }
+                const uint32_t lo = a;
+                a = p;
+                b = n;
+                while (a < b) {
+                    const uint32_t m = (a + b) >> 1;
+                    if (top(m) <= t) a = m + 1;
+                    else b = m;
+                }
+                const uint32_t slot = atomicAdd(&runs[0], 1u);
+                if (slot < (uint32_t)LEAF_FIX_RUNS) {
+                    runs[1 + 2 * slot] = lo;
+                    runs[2 + 2 * slot] = a;
                 }
             }
             __syncthreads();
-            block_sort_cnt<NT, IPT, IPTC>(k, v, 0, nbits, s.sort);
+            const uint32_t nc = runs[0];
+            bool redo = nc > (uint32_t)LEAF_FIX_RUNS;
+            for (uint32_t r = 0; r < nc && !redo; ++r) redo = runs[2 + 2 * r] - runs[1 + 2 * r] > (uint32_t)LEAF_FIX_MAX;
+            if (redo) {
+#pragma unroll
+                for (int j = 0; j < IPT; ++j) {
+                    if (j < ipt) {
+                        k[j] = s.sort.key[pad16(tid * ipt + j)];
+                        v[j] = s.sort.val[pad16(tid * ipt + j)];
+                    }
+                }
+                __syncthreads();
+                block_sort_cnt<NT, IPT, IPTC>(k, v, 0, nbits, s.sort);
+            } else {
+                // the counter area holds a run's rows in rank order
+                uint64_t* tk = reinterpret_cast<uint64_t*>(s.sort.cnt);
+                uint16_t* tv = reinterpret_cast<uint16_t*>(tk + LEAF_FIX_MAX);
+                for (uint32_t r = 0; r < nc; ++r) {
+                    const uint32_t lo = runs[1 + 2 * r], hi = runs[2 + 2 * r];
+                    bool seen = false;  // clashes of one run name it once each
+                    for (uint32_t q = 0; q < r; ++q) seen |= runs[1 + 2 * q] == lo;
+                    if (seen) continue;
+                    const uint32_t L = hi - lo;
+                    for (uint32_t i = tid; i < L; i += NT) {
+                        const uint64_t kx = s.sort.key[pad16((int)(lo + i))];
+                        uint32_t rank = 0;
+                        for (uint32_t q = 0; q < L; ++q) {
+                            const uint64_t kq = s.sort.key[pad16((int)(lo + q))];
+                            rank += (kq < kx || (kq == kx && q < i)) ? 1u : 0u;
+                        }
+                        tk[rank] = kx;
+                        tv[rank] = s.sort.val[pad16((int)(lo + i))];
+                    }
+                    __syncthreads();
+                    for (uint32_t i = tid; i < L; i += NT) {
+                        s.sort.key[pad16((int)(lo + i))] = tk[i];
+                        s.sort.val[pad16((int)(lo + i))] = tv[i];
+                    }
+                    __syncthreads();
+                }
+            }
         }
     }
 
