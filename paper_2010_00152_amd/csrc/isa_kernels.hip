@@ -2226,11 +2226,15 @@ __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict_
 // small persistent grid walks the window's tasks (run slices of at most
 // GATHER_ROWS rows), reading pinned host memory through its device mapping
 // (or device memory) with contiguous word loads, eight in flight per thread.
-// The grid is kept small on purpose: the loads wait on the host link, and
-// the window being reduced meanwhile needs the compute units.  Raw slices
-// (count-1 rows) are staged in LDS and expanded to state rows on the way out.
+// The grid is kept small on purpose: its host reads hold memory-request
+// slots for the whole link latency, and the window being reduced meanwhile
+// slows down with every such read in flight (its kernels run about three
+// times slower beside a gather than alone).  32 workgroups, four per XCD,
+// still fill the link (measured: 24 read slower, 48 slow the reduction).
+// Raw slices (count-1 rows) are staged in LDS and expanded to state rows on
+// the way out.
 constexpr int GATHER_NT = 256;
-constexpr uint32_t GATHER_GRID = 48;
+constexpr uint32_t GATHER_GRID = 32;
 __global__ void __launch_bounds__(GATHER_NT) k_gather(const GatherTask* __restrict__ tasks, uint32_t n_tasks,
                                                       Layout R, Layout S, uint64_t* __restrict__ dst) {
     __shared__ uint64_t s_raw[GATHER_ROWS * 3];
