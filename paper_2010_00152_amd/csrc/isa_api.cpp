@@ -147,7 +147,7 @@ uint64_t spare_rows(uint64_t buf_rows) { return buf_rows * SPARE_NUM / SPARE_DEN
 
 uint64_t rungen_bytes(uint64_t Bt, uint64_t K, const Cols& k, bool inplace = false) {
     const uint64_t sw = (uint64_t)state_layout(k).words * 8;
-    const uint64_t split_scratch = ((K + Bt) / 4096 + 4) * 24 + 1024;
+    const uint64_t split_scratch = ((K + Bt) / 4096 + 4) * 48 + 1024;
     const uint64_t index = inplace ? ((K + Bt) + spare_rows(K + Bt)) * sw : 2 * (K + Bt) * sw;
     return index + 3 * Bt * sw + merge_scratch_bytes(K + 2 * Bt) + batch_program_bytes(Bt, k) + split_scratch +
            MERGE_MARGIN + 16 * 256 + (MAX_BUCKETS - 1) * 8;
@@ -188,14 +188,15 @@ bool plan_batches(uint64_t ws, uint64_t n, const Cols& k, Plan& p, bool inplace 
 }
 
 // A run in the spill buffer: n_single count-1 rows stored column by column
-// (single_bytes) followed by n_multi rows in state layout, both sorted on the
-// key.  Runs written without count information hold only state rows
-// (n_single = 0).
+// (single_bytes), then n_packed packed rows (packed_words), then n_multi rows
+// in state layout, each part sorted on the key.  Runs written without count
+// information hold only state rows (n_single = n_packed = 0).
 struct RunInfo {
     uint64_t byte_off;
     uint64_t n_single;
     uint64_t n_multi;
     bool narrow = false;  // the count-1 part's integer values take 4 bytes
+    uint64_t n_packed = 0;
 };
 
 // First row of [pos, n) whose key is >= x in a strided host array.
@@ -268,7 +269,9 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
         uint64_t stride, n;
         const uint64_t* rows;
         bool raw, narrow;
+        bool packed = false;
     };
+    const uint64_t pw = (uint64_t)packed_words(S);
     std::vector<Src> src;
     auto on_dev = [&](const uint64_t* hp) { return (const uint64_t*)(host_dev + ((const char*)hp - host)); };
     uint64_t total = 0;
@@ -276,9 +279,11 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
         const uint64_t* base = (const uint64_t*)(host + r.byte_off);
         // the count-1 part is stored column by column, keys first
         if (r.n_single) src.push_back(Src{base, 1, r.n_single, on_dev(base), true, r.narrow});
-        const uint64_t* mb = base + single_bytes(r.n_single, Rl, r.narrow) / 8;
+        const uint64_t* pb = base + single_bytes(r.n_single, Rl, r.narrow) / 8;
+        if (r.n_packed) src.push_back(Src{pb, pw, r.n_packed, on_dev(pb), false, false, true});
+        const uint64_t* mb = pb + r.n_packed * pw;
         if (r.n_multi) src.push_back(Src{mb, sw, r.n_multi, on_dev(mb), false, false});
-        total += r.n_single + r.n_multi;
+        total += r.n_single + r.n_packed + r.n_multi;
     }
     if (n_idx) src.push_back(Src{idx_keys.data(), 1, n_idx, idx, false, false});
     total += n_idx;
@@ -431,8 +436,9 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
             for (size_t s = 0; s < ns; ++s) {
                 const Src& q = src[s];
                 // host bytes per row; a count-1 part's columns
-                const uint64_t row_bytes =
-                    q.raw ? 8 + (Rl.fs >= 0 ? 8 : 0) + (Rl.sum >= 0 ? (q.narrow ? 4 : 8) : 0) : sw * 8;
+                const uint64_t row_bytes = q.raw      ? 8 + (Rl.fs >= 0 ? 8 : 0) + (Rl.sum >= 0 ? (q.narrow ? 4 : 8) : 0)
+                                           : q.packed ? pw * 8
+                                                      : sw * 8;
                 const uint64_t* fs_c = q.rows + q.n;
                 const uint64_t* int_c = q.rows + q.n * (Rl.fs >= 0 ? 2 : 1);
                 for (uint64_t r = pos[s]; r < end[s]; r += GATHER_ROWS) {
@@ -450,10 +456,10 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
                                           : (const void*)(int_c + r);
                         t.raw = q.narrow ? 2u : 1u;
                     } else {
-                        t.src = q.rows + r * sw;
+                        t.src = q.rows + r * (q.packed ? pw : sw);
                         t.fv = nullptr;
                         t.iv = nullptr;
-                        t.raw = 0;
+                        t.raw = q.packed ? 3u : 0u;
                     }
                     at += len;
                     if (s + 1 < ns || !n_idx) hb += len * row_bytes;
@@ -933,8 +939,8 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             uint64_t* m_splits = A.take_n<uint64_t>(2 * (mscr_parts + 1));
             uint64_t* hy_stage = hy ? A.take_n<uint64_t>(st_rows * sw) : nullptr;
             const uint64_t sp_blocks = split_blocks(buf_rows) + 1;
-            uint32_t* sp_counts = A.take_n<uint32_t>(sp_blocks);
-            uint64_t* sp_offs = A.take_n<uint64_t>(sp_blocks + 1);
+            uint32_t* sp_counts = A.take_n<uint32_t>(2 * sp_blocks);
+            uint64_t* sp_offs = A.take_n<uint64_t>(2 * sp_blocks + 4);
             uint64_t* sp_tiles = A.take_n<uint64_t>(scan_tiles(sp_blocks) + 1);
             // splitters for every batch, chosen once from a sample of the whole
             // input (batches are slices of one input)
@@ -1023,13 +1029,15 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 const uint64_t n_run = deferred.rows;
                 uint64_t n_single = ((const uint64_t*)E.ring_slot(16))[0];
                 bool narrow = ((const uint64_t*)E.ring_slot(16))[1] != 0;
-                uint64_t bytes = single_bytes(n_single, Rl, narrow) + (n_run - n_single) * sw * 8;
+                uint64_t n_packed = ((const uint64_t*)E.ring_slot(16))[2];
+                uint64_t bytes = compact_bytes(n_single, n_packed, n_run - n_single - n_packed, Rl, S, narrow);
                 const char* run_src = inplace ? (const char*)spare : (const char*)idx[deferred.buf] + buf_bytes - bytes;
                 if (inplace && bytes / 8 > spare_words) {
                     // the split wrote nothing (the compacted run exceeds the
                     // spare area): the run's state rows go out as they are, and
                     // the index buffer stays read until the copy ends
                     n_single = 0;
+                    n_packed = 0;
                     narrow = false;
                     bytes = n_run * sw * 8;
                     run_src = (const char*)deferred.src;
@@ -1047,7 +1055,8 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 RunInfo ri;
                 ri.byte_off = spill_used;
                 ri.n_single = n_single;
-                ri.n_multi = n_run - n_single;
+                ri.n_packed = n_packed;
+                ri.n_multi = n_run - n_single - n_packed;
                 ri.narrow = narrow;
                 runs.push_back(ri);
                 spill_used += bytes;
@@ -1094,7 +1103,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 if (compact) {
                     launch_split(ip, n_idx, S, Rl, sp_counts, sp_tiles, sp_offs, idx[spare], buf_rows * sw, E.stream);
                     // the count-1 rows and the narrow flag
-                    ck(hipMemcpyAsync(E.ring_slot(16), sp_offs + split_blocks(n_idx), 16, hipMemcpyDeviceToHost,
+                    ck(hipMemcpyAsync(E.ring_slot(16), sp_offs + split_blocks(n_idx), 24, hipMemcpyDeviceToHost,
                                       E.stream),
                        "hipMemcpyAsync(split count)");
                     ck(hipEventRecord(E.sync_event(2), E.stream), "hipEventRecord");
@@ -1144,7 +1153,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     spare_busy = false;
                 }
                 launch_split(U, m, S, Rl, sp_counts, sp_tiles, sp_offs, spare, 0, E.stream, spare_words);
-                ck(hipMemcpyAsync(E.ring_slot(16), sp_offs + split_blocks(m), 16, hipMemcpyDeviceToHost, E.stream),
+                ck(hipMemcpyAsync(E.ring_slot(16), sp_offs + split_blocks(m), 24, hipMemcpyDeviceToHost, E.stream),
                    "hipMemcpyAsync(split count)");
                 ck(hipEventRecord(E.sync_event(2), E.stream), "hipEventRecord");
                 deferred.active = true;
@@ -1221,7 +1230,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     if (compact) {
                         launch_split(rr[r].first, rr[r].second, S, Rl, sp_counts, sp_tiles, sp_offs,
                                      hy_stage + at, 0, E.stream);
-                        ck(hipMemcpyAsync(E.ring_slot(16 + r), sp_offs + split_blocks(rr[r].second), 16,
+                        ck(hipMemcpyAsync(E.ring_slot(16 + r), sp_offs + split_blocks(rr[r].second), 24,
                                           hipMemcpyDeviceToHost, E.stream),
                            "hipMemcpyAsync(split count)");
                     } else {
@@ -1234,12 +1243,13 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 ck(hipStreamWaitEvent(cs, E.sync_event(2), 0), "hipStreamWaitEvent");
                 for (size_t r = 0; r < rr.size(); ++r) {
                     const uint64_t n_run = rr[r].second;
-                    uint64_t n_single = 0, bytes = n_run * sw * 8;
+                    uint64_t n_single = 0, n_packed = 0, bytes = n_run * sw * 8;
                     bool narrow = false;
                     if (compact) {
                         n_single = ((const uint64_t*)E.ring_slot(16 + r))[0];
                         narrow = ((const uint64_t*)E.ring_slot(16 + r))[1] != 0;
-                        bytes = single_bytes(n_single, Rl, narrow) + (n_run - n_single) * sw * 8;
+                        n_packed = ((const uint64_t*)E.ring_slot(16 + r))[2];
+                        bytes = compact_bytes(n_single, n_packed, n_run - n_single - n_packed, Rl, S, narrow);
                     }
                     if (spill_used + bytes > spill.bytes) throw Fail{ISA_ESPILL, "spill buffer too small"};
                     E.pbegin("spill_d2h", cs);
@@ -1250,7 +1260,8 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     RunInfo ri;
                     ri.byte_off = spill_used;
                     ri.n_single = n_single;
-                    ri.n_multi = n_run - n_single;
+                    ri.n_packed = n_packed;
+                    ri.n_multi = n_run - n_single - n_packed;
                     ri.narrow = narrow;
                     runs.push_back(ri);
                     spill_used += bytes;
@@ -1487,9 +1498,9 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 std::vector<uint64_t> run_seq(runs.size());
                 for (size_t j = 0; j < runs.size(); ++j) run_seq[j] = j;
                 uint64_t next_seq = runs.size(), merge_steps = 0, merge_rows = 0;
-                auto run_rows = [](const RunInfo& r) { return r.n_single + r.n_multi; };
+                auto run_rows = [](const RunInfo& r) { return r.n_single + r.n_packed + r.n_multi; };
                 auto run_bytes = [&](const RunInfo& r) {
-                    return single_bytes(r.n_single, Rl, r.narrow) + r.n_multi * sw * 8;
+                    return compact_bytes(r.n_single, r.n_packed, r.n_multi, Rl, S, r.narrow);
                 };
                 // space of the spill buffer given back by merged runs (offset ->
                 // bytes), reused first fit; new space comes after spill_used

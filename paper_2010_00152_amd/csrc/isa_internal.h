@@ -69,6 +69,22 @@ __host__ __device__ inline uint64_t single_bytes(uint64_t n, const Layout& R, bo
     return (b + 7) & ~7ull;
 }
 
+// Compact run format, packed part: the rows of count above 1 whose count
+// fits in 32 bits and whose integer sum, min and max fit in 32-bit signed
+// values, each as the key, the f64 sum (when present) and then the 32-bit
+// fields count, sum, min, max (those present), two to a word, low half first.
+// Used when narrower than a state row (packed_words(S) < S.words).
+__host__ __device__ inline int packed_words(const Layout& S) {
+    const int nf = (S.cnt >= 0 ? 1 : 0) + (S.sum >= 0 ? 3 : 0);
+    return 1 + (S.fs >= 0 ? 1 : 0) + (nf + 1) / 2;
+}
+__host__ __device__ inline bool has_packed(const Layout& S) { return S.cnt >= 0 && packed_words(S) < S.words; }
+// Bytes of a compact run: its count-1 part, packed part and state rows.
+__host__ __device__ inline uint64_t compact_bytes(uint64_t n_single, uint64_t n_packed, uint64_t n_state,
+                                                  const Layout& R, const Layout& S, bool narrow) {
+    return single_bytes(n_single, R, narrow) + (n_packed * (uint64_t)packed_words(S) + n_state * (uint64_t)S.words) * 8;
+}
+
 // One region being partitioned at the current level.
 struct Region {
     ColView src;        // its rows are src[0, n)
@@ -152,7 +168,8 @@ struct GatherTask {
     uint64_t dst_row;     // first state row written in the staging buffer
     uint32_t n;           // rows, at most GATHER_ROWS
     uint32_t raw;         // 0: state rows; count-1 rows, expanded to state rows,
-                          // with 8-byte (1) or 4-byte (2) integer values
+                          // with 8-byte (1) or 4-byte (2) integer values;
+                          // 3: packed rows (packed_words), expanded
 };
 
 // A span of gapped output copied into its final place.

@@ -2100,104 +2100,144 @@ __global__ void __launch_bounds__(256) k_seg_write(const int32_t* __restrict__ a
 
 // ---------------------------------------------------------------------------
 // Compact run format.  A state row whose count is 1 holds a single input row,
-// so key plus raw value columns describe it; a run is written as the sorted
-// sub-run of such rows, column by column (single_bytes), followed by the
-// sorted sub-run of the other rows in state layout (stable split, two
-// passes).  The integer column of the count-1 part takes 4 bytes per value
-// when every value in it fits in 32 bits.
+// so key plus raw value columns describe it; a row whose count and integer
+// aggregates fit in 32 bits is packed (packed_words).  A run is written as
+// the sorted sub-run of count-1 rows, column by column (single_bytes), then
+// the sorted sub-run of packed rows, then the sorted sub-run of the other
+// rows in state layout (a stable three-way split, two passes).  The integer
+// column of the count-1 part takes 4 bytes per value when every value in it
+// fits in 32 bits.
 // ---------------------------------------------------------------------------
 
 constexpr int SPLIT_T = 4096;  // rows per workgroup
 
 __device__ __forceinline__ bool fits_i32(uint64_t v) { return (int64_t)v == (int64_t)(int32_t)(int64_t)v; }
 
-// counts[b]: count-1 rows of block b.  *narrow (set to 1 beforehand) is
-// cleared when a count-1 row's integer value needs more than 32 bits.
+// A state row (count above 1) that the packed format holds exactly.
+__device__ __forceinline__ bool packable(const uint64_t* q, const Layout& S) {
+    if (!has_packed(S) || (q[S.cnt] >> 32) != 0) return false;
+    return S.sum < 0 || (fits_i32(q[S.sum]) && fits_i32(q[S.mn]) && fits_i32(q[S.mx]));
+}
+
+// counts[b]: count-1 rows of block b, counts[nblk + b]: its packed rows.
+// *narrow (set to 1 beforehand) is cleared when a count-1 row's integer value
+// needs more than 32 bits.
 __global__ void __launch_bounds__(256) k_split_count(const uint64_t* __restrict__ rows, uint64_t n, Layout S,
-                                                     uint32_t* __restrict__ counts, uint64_t* __restrict__ narrow) {
+                                                     uint32_t* __restrict__ counts, uint64_t nblk,
+                                                     uint64_t* __restrict__ narrow) {
     __shared__ uint32_t s_tmp[256 / 64 + 1];
     const uint64_t r0 = (uint64_t)blockIdx.x * SPLIT_T;
-    uint32_t c = 0;
+    uint32_t c = 0, cp = 0;
     bool wide = false;
     for (uint32_t i = threadIdx.x; i < SPLIT_T; i += 256) {
         const uint64_t r = r0 + i;
-        if (r < n && rows[r * S.words + S.cnt] == 1) {
+        if (r >= n) continue;
+        const uint64_t* q = rows + r * S.words;
+        if (q[S.cnt] == 1) {
             ++c;
-            if (S.sum >= 0) wide |= !fits_i32(rows[r * S.words + S.sum]);
+            if (S.sum >= 0) wide |= !fits_i32(q[S.sum]);
+        } else if (packable(q, S)) {
+            ++cp;
         }
     }
-    uint32_t tot;
+    uint32_t tot, totp;
     block_exclusive_scan<256>(c, s_tmp, tot);
+    block_exclusive_scan<256>(cp, s_tmp, totp);
     if (__syncthreads_or(wide) && threadIdx.x == 0) *narrow = 0;
-    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+    if (threadIdx.x == 0) {
+        counts[blockIdx.x] = tot;
+        counts[nblk + blockIdx.x] = totp;
+    }
 }
 
-// offs: exclusive scan of the counts (offs[nblocks] = all count-1 rows),
-// offs[nblocks + 1]: the narrow flag.  The run starts at out[0], or ends at
-// out[end_words] when end_words is nonzero.
+// offs[0..nblocks]: exclusive scan of the count-1 counts (offs[nblocks] = all
+// count-1 rows), offs[nblocks + 1]: the narrow flag, offs[nblocks + 2]: all
+// packed rows (written here), offs[nblocks + 3 ..]: the scan of the packed
+// counts.  The run starts at out[0], or ends at out[end_words] when
+// end_words is nonzero.
 // A workgroup takes its SPLIT_T rows in tiles of SPLIT_TILE rows: a tile is
 // loaded into LDS with consecutive threads on consecutive words, each thread
 // then ranks the rows of its stripes (rows t, t + 256, ...) by ballots, the
-// count-1 rows' columns leave in contiguous stores, and the other rows are
-// copied word by word from LDS into their contiguous span of the run.
+// count-1 rows' columns and the packed rows leave in contiguous stores, and
+// the other rows are copied word by word from LDS into their contiguous span
+// of the run.
 constexpr int SPLIT_TILE = 1024;
 constexpr int SPLIT_MAXW = 6;
 __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict__ rows, uint64_t n, Layout S,
-                                                     Layout R, const uint64_t* __restrict__ offs, uint64_t nblocks,
+                                                     Layout R, uint64_t* __restrict__ offs, uint64_t nblocks,
                                                      uint64_t* __restrict__ out, uint64_t end_words,
                                                      uint64_t cap_words) {
     __shared__ uint64_t s_rows[SPLIT_TILE * SPLIT_MAXW];
     __shared__ uint16_t s_msrc[SPLIT_TILE];
-    __shared__ uint32_t s_wave[4];
+    __shared__ uint32_t s_wave[8];
     constexpr int STRIPES = SPLIT_TILE / 256;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const uint32_t W = (uint32_t)S.words;
-    const uint64_t n_single = offs[nblocks];
+    const uint32_t W = (uint32_t)S.words, PW = (uint32_t)packed_words(S);
+    const uint64_t* offs_p = offs + nblocks + 3;
+    const uint64_t n_single = offs[nblocks], n_packed = offs_p[nblocks];
     const bool narrow = offs[nblocks + 1] != 0;
+    if (blockIdx.x == 0 && tid == 0) offs[nblocks + 2] = n_packed;
     const uint64_t s_words = single_bytes(n_single, R, narrow) / 8;
+    const uint64_t n_words = s_words + n_packed * PW + (n - n_single - n_packed) * W;
     // a run larger than the room it is written into is not written at all
     // (the caller sees its size and copies the rows some other way)
-    if (cap_words && s_words + (n - n_single) * S.words > cap_words) return;
-    if (end_words) out += end_words - (s_words + (n - n_single) * S.words);
+    if (cap_words && n_words > cap_words) return;
+    if (end_words) out += end_words - n_words;
     uint64_t* key_c = out;
     uint64_t* fs_c = out + n_single;
     void* int_c = out + n_single * (R.fs >= 0 ? 2 : 1);
-    uint64_t* multi = out + s_words;
+    uint64_t* packed = out + s_words;
+    uint64_t* multi = packed + n_packed * PW;
     const uint64_t blk0 = (uint64_t)blockIdx.x * SPLIT_T;
-    uint64_t so = offs[blockIdx.x];  // count-1 rows before the current tile
+    uint64_t so = offs[blockIdx.x];     // count-1 rows before the current tile
+    uint64_t sop = offs_p[blockIdx.x];  // packed rows before the current tile
     for (uint64_t t0 = blk0; t0 < blk0 + SPLIT_T && t0 < n; t0 += SPLIT_TILE) {
         const uint32_t tn = (uint32_t)(n - t0 < (uint64_t)SPLIT_TILE ? n - t0 : (uint64_t)SPLIT_TILE);
         const uint64_t* src = rows + t0 * W;
         for (uint32_t x = tid; x < tn * W; x += 256) s_rows[x] = src[x];
         __syncthreads();
-        // ranks of the count-1 rows, stripe by stripe (row order is stripe-major)
-        uint32_t srank[STRIPES];
-        bool single[STRIPES];
-        uint32_t before = 0;  // count-1 rows of the tile in earlier stripes
+        // ranks of the count-1 and of the packed rows, stripe by stripe (row
+        // order is stripe-major)
+        uint32_t srank[STRIPES], prank[STRIPES];
+        uint8_t kind[STRIPES];  // 1: count-1, 2: packed, 0: state row (or none)
+        uint32_t before = 0, before_p = 0;  // rows of each kind in earlier stripes
 #pragma unroll
         for (int i = 0; i < STRIPES; ++i) {
             const uint32_t r = (uint32_t)(i * 256 + tid);
-            single[i] = r < tn && s_rows[r * W + S.cnt] == 1;
-            const uint64_t bal = __ballot(single[i]);
-            if (lane == 0) s_wave[wv] = (uint32_t)__popcll(bal);
+            uint8_t kd = 0;
+            if (r < tn) {
+                const uint64_t* q = s_rows + r * W;
+                kd = q[S.cnt] == 1 ? 1 : packable(q, S) ? 2 : 0;
+            }
+            kind[i] = kd;
+            const uint64_t bal = __ballot(kd == 1), balp = __ballot(kd == 2);
+            if (lane == 0) {
+                s_wave[wv] = (uint32_t)__popcll(bal);
+                s_wave[4 + wv] = (uint32_t)__popcll(balp);
+            }
             __syncthreads();
-            uint32_t wbase = 0, stot = 0;
+            uint32_t wbase = 0, stot = 0, wbase_p = 0, stot_p = 0;
             for (int q = 0; q < 4; ++q) {
                 wbase += q < wv ? s_wave[q] : 0u;
                 stot += s_wave[q];
+                wbase_p += q < wv ? s_wave[4 + q] : 0u;
+                stot_p += s_wave[4 + q];
             }
-            srank[i] = before + wbase + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+            const uint64_t lt = (1ull << lane) - 1ull;
+            srank[i] = before + wbase + (uint32_t)__popcll(bal & lt);
+            prank[i] = before_p + wbase_p + (uint32_t)__popcll(balp & lt);
             before += stot;
+            before_p += stot_p;
             __syncthreads();
         }
-        const uint32_t t_single = before;
-        // columns of the count-1 rows: consecutive ranks of a stripe are
-        // consecutive rows, so a wave's stores are contiguous
+        const uint32_t t_single = before, t_packed = before_p;
+        // consecutive ranks of a stripe are consecutive rows of their part, so
+        // a wave's stores are contiguous
 #pragma unroll
         for (int i = 0; i < STRIPES; ++i) {
             const uint32_t r = (uint32_t)(i * 256 + tid);
-            if (single[i]) {
-                const uint64_t* q = s_rows + r * W;
+            const uint64_t* q = s_rows + r * W;
+            if (kind[i] == 1) {
                 const uint64_t o = so + srank[i];
                 key_c[o] = q[0];
                 if (R.fs >= 0) fs_c[o] = q[S.fs];
@@ -2205,19 +2245,34 @@ __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict_
                     if (narrow) ((int32_t*)int_c)[o] = (int32_t)(int64_t)q[S.sum];
                     else ((uint64_t*)int_c)[o] = q[S.sum];
                 }
+            } else if (kind[i] == 2) {
+                uint64_t* pr = packed + (sop + prank[i]) * PW;
+                uint64_t fld[4];
+                int nf = 0;
+                if (S.cnt >= 0) fld[nf++] = q[S.cnt] & 0xffffffffull;
+                if (S.sum >= 0) {
+                    fld[nf++] = q[S.sum] & 0xffffffffull;
+                    fld[nf++] = q[S.mn] & 0xffffffffull;
+                    fld[nf++] = q[S.mx] & 0xffffffffull;
+                }
+                int wd = 0;
+                pr[wd++] = q[0];
+                if (S.fs >= 0) pr[wd++] = q[S.fs];
+                for (int f = 0; f < nf; f += 2) pr[wd++] = fld[f] | (f + 1 < nf ? fld[f + 1] << 32 : 0ull);
             } else if (r < tn) {
-                s_msrc[r - srank[i]] = (uint16_t)r;  // its rank among the other rows
+                s_msrc[r - srank[i] - prank[i]] = (uint16_t)r;  // its rank among the state rows
             }
         }
         __syncthreads();
-        // the other rows, word by word from LDS into their contiguous span
-        const uint32_t t_multi = tn - t_single;
-        uint64_t* md = multi + (t0 - so) * W;  // rows before the tile that are not count-1
+        // the state rows, word by word from LDS into their contiguous span
+        const uint32_t t_multi = tn - t_single - t_packed;
+        uint64_t* md = multi + (t0 - so - sop) * W;  // rows before the tile that stay state rows
         for (uint32_t x = tid; x < t_multi * W; x += 256) {
             const uint32_t j = x / W, wd = x - j * W;
             md[x] = s_rows[(uint32_t)s_msrc[j] * W + wd];
         }
         so += t_single;
+        sop += t_packed;
         __syncthreads();  // the tile's LDS is reused by the next tile
     }
 }
@@ -2237,12 +2292,56 @@ constexpr int GATHER_NT = 256;
 constexpr uint32_t GATHER_GRID = 32;
 __global__ void __launch_bounds__(GATHER_NT) k_gather(const GatherTask* __restrict__ tasks, uint32_t n_tasks,
                                                       Layout R, Layout S, uint64_t* __restrict__ dst) {
-    __shared__ uint64_t s_raw[GATHER_ROWS * 3];
+    __shared__ uint64_t s_raw[GATHER_ROWS * 4];
     const uint32_t sw = (uint32_t)S.words, rw = (uint32_t)R.words;
     for (uint32_t ti = blockIdx.x; ti < n_tasks; ti += gridDim.x) {
         const GatherTask t = tasks[ti];
         uint64_t* __restrict__ out = dst + t.dst_row * sw;
         const uint64_t* __restrict__ in = t.src;
+        if (t.raw == 3) {
+            // packed rows: loaded into LDS with eight loads in flight per
+            // thread, then widened to state rows
+            const uint32_t pw = (uint32_t)packed_words(S);
+            const uint32_t words = t.n * pw;
+            for (uint32_t i = threadIdx.x; i < words; i += 8 * GATHER_NT) {
+                uint64_t r[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const uint32_t x = i + q * GATHER_NT;
+                    if (x < words) r[q] = in[x];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const uint32_t x = i + q * GATHER_NT;
+                    if (x < words) s_raw[x] = r[q];
+                }
+            }
+            __syncthreads();
+            const uint32_t base = S.fs >= 0 ? 2u : 1u;
+            const uint32_t owords = t.n * sw;
+            for (uint32_t o = threadIdx.x; o < owords; o += GATHER_NT) {
+                const uint32_t r = o / sw, c = o - r * sw;
+                const uint64_t* x = s_raw + r * pw;
+                // field number of a 32-bit column: count, sum, min, max
+                int f = -1;
+                if ((int)c == S.cnt) f = 0;
+                else if ((int)c == S.sum) f = S.cnt >= 0 ? 1 : 0;
+                else if ((int)c == S.mn) f = S.cnt >= 0 ? 2 : 1;
+                else if ((int)c == S.mx) f = S.cnt >= 0 ? 3 : 2;
+                uint64_t v;
+                if (c == 0) {
+                    v = x[0];
+                } else if ((int)c == S.fs) {
+                    v = x[1];
+                } else {
+                    const uint32_t h = (uint32_t)(x[base + (uint32_t)f / 2] >> (32 * (f & 1)));
+                    v = (int)c == S.cnt ? (uint64_t)h : (uint64_t)(int64_t)(int32_t)h;
+                }
+                out[o] = v;
+            }
+            __syncthreads();  // s_raw is refilled by the next task
+            continue;
+        }
         if (!t.raw) {
             const uint32_t words = t.n * sw;
             uint32_t i = threadIdx.x;
@@ -2448,16 +2547,18 @@ void launch_rs_evict(const uint64_t* U, uint64_t m, uint32_t w, uint64_t p, uint
 }
 void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* offs, hipStream_t st);
 uint64_t split_blocks(uint64_t n) { return (n + SPLIT_T - 1) / SPLIT_T; }
-// counts: split_blocks(n) words; tiles as for launch_scan; offs: split_blocks(n) + 2
-// words (the scan, then the narrow flag of the count-1 part).
+// counts: 2 * split_blocks(n) words; tiles as for launch_scan; offs:
+// 2 * split_blocks(n) + 4 words (the count-1 scan, the narrow flag, the packed
+// rows' total, the packed scan; see k_split_write).
 void launch_split(const uint64_t* rows, uint64_t n, Layout S, Layout R, uint32_t* counts, uint64_t* tiles,
                   uint64_t* offs, uint64_t* out, uint64_t end_words, hipStream_t st, uint64_t cap_words) {
     const uint64_t nb = split_blocks(n);
     if (!nb) return;
     // offs[nb + 1] (beyond the scan's entries) holds the narrow flag
     launch_fill(offs + nb + 1, 1, 1, st);
-    hipLaunchKernelGGL(k_split_count, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, counts, offs + nb + 1);
+    hipLaunchKernelGGL(k_split_count, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, counts, nb, offs + nb + 1);
     launch_scan(counts, nb, tiles, offs, st);
+    launch_scan(counts + nb, nb, tiles, offs + nb + 3, st);
     hipLaunchKernelGGL(k_split_write, dim3((uint32_t)nb), dim3(256), 0, st, rows, n, S, R, offs, nb, out, end_words,
                        cap_words);
 }
