@@ -1341,16 +1341,19 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     n_idx = gj;
                 }
             };
-            // Batches are sorted on a stream of their own, so that the sort of
-            // batch i+1 runs beside the absorb of batch i.  A sort waits for the
-            // last absorb that reads the batch-run buffer it overwrites (as the
-            // batch run, or as the index that a spill left in it); the first
-            // sorts wait for everything enqueued on the main stream before
-            // them.  An absorb waits for its batch's sort.
-            hipStream_t ss = E.side(1);
+            // Batches are sorted on two streams of their own (batch b on
+            // ss2[b % 2], with the batch program's scratch set b % 2), so that
+            // the sorts of batches i and i+1 overlap each other and the absorb
+            // of batch i.  A sort waits for the last absorb that reads the
+            // batch-run buffer it overwrites (as the batch run, or as the index
+            // that a spill left in it); the first sorts wait for everything
+            // enqueued on the main stream before them.  An absorb waits for its
+            // batch's sort.
+            hipStream_t ss2[2] = {E.side(1), E.side(2)};
             int64_t last_reader[3] = {-1, -1, -1};
             bool merged = false;
             auto sort_batch = [&](uint64_t b) {
+                hipStream_t ss = ss2[b % 2];
                 if (!merged) {
                     ck(hipEventRecord(E.sync_event(24), E.stream), "hipEventRecord");
                     ck(hipStreamWaitEvent(ss, E.sync_event(24), 0), "hipStreamWaitEvent");
@@ -1375,9 +1378,9 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                 if (!bp.result(rb_sort(i), g)) {
                     // a bucket was too large for a leaf: redo the batch with the
                     // general plan in the batch program's scratch, once the sort
-                    // stream (the scratch's other user) is idle; later sorts wait
-                    // for the main stream
-                    ck(hipStreamSynchronize(ss), "hipStreamSynchronize(sort)");
+                    // streams (the scratch's other users) are idle; later sorts
+                    // wait for the main stream
+                    for (hipStream_t ss : ss2) ck(hipStreamSynchronize(ss), "hipStreamSynchronize(sort)");
                     A.off = bp.scratch_off;
                     std::vector<Instance> inst(1);
                     inst[0].src = bp.batch_src(i);
@@ -1389,7 +1392,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     // hybrid policy's probe of the batch run)
                     ((uint64_t*)rb_sort(i))[1] = g;
                     ck(hipEventRecord(E.sync_event(25), E.stream), "hipEventRecord");
-                    ck(hipStreamWaitEvent(ss, E.sync_event(25), 0), "hipStreamWaitEvent");
+                    for (hipStream_t ss : ss2) ck(hipStreamWaitEvent(ss, E.sync_event(25), 0), "hipStreamWaitEvent");
                 }
                 ++batches;
                 if (merge_out) {
@@ -1451,7 +1454,7 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             flush_copy();
             if (rs_rows) runs.push_back(RunInfo{rs_off, 0, rs_rows});
             if (!runs.empty()) ck(hipStreamSynchronize(cs), "hipStreamSynchronize(copy)");
-            ck(hipStreamSynchronize(ss), "hipStreamSynchronize(sort)");
+            for (hipStream_t ss : ss2) ck(hipStreamSynchronize(ss), "hipStreamSynchronize(sort)");
             E.sync();
             const double t1 = now_ms();
             if (stats) {

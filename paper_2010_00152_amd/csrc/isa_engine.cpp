@@ -844,11 +844,11 @@ uint64_t batch_program_bytes(uint64_t Bt, const Cols& k) {
     const uint64_t pieces = (Bt + SINGLE_CHUNK - 1) / SINGLE_CHUNK;
     const uint64_t desc = BP_CTL_RING * sizeof(Region) + 2 * ch * sizeof(Chunk) + MAX_BUCKETS * sizeof(FlatSlot) +
                           16 + 3 * sizeof(Dest) + BP_CTL_RING * (2 + MAX_BUCKETS) * 8 + 2 * MAX_BUCKETS * 4 +
-                          (uint64_t)MAX_BUCKETS * pieces * single_partial_bytes() + 4 * 256;
-    const uint64_t scratch = Bt * (uint64_t)raw_layout(k).words * 8 + hist * 4 + (hist + 1) * 8 +
-                             (scan_tiles(hist) + 1) * 8 + 8 * 256;
+                          BatchProgram::SETS * ((uint64_t)MAX_BUCKETS * pieces * single_partial_bytes() + 256) +
+                          4 * 256;
+    const uint64_t scratch = Bt * (uint64_t)raw_layout(k).words * 8 + hist * 4 + (hist + 1) * 8 + 8 * 256;
     // the scratch area also serves the general plan when a batch falls back
-    return desc + 8 * 256 + std::max(scratch, sort_reduce_bytes(Bt, 1, k, false));
+    return desc + 8 * 256 + std::max(BatchProgram::SETS * scratch, sort_reduce_bytes(Bt, 1, k, false));
 }
 
 void BatchProgram::setup(Engine& E, Arena& A, const ColView& src_rows, uint64_t n_rows, uint64_t batch_rows,
@@ -908,7 +908,8 @@ void BatchProgram::setup(Engine& E, Arena& A, const ColView& src_rows, uint64_t 
     char* d = up.commit(E, A);
     d_single_list = n_single ? (uint32_t*)(d + o_sl) : nullptr;
     d_single_of = n_single ? (uint32_t*)(d + o_so) : nullptr;
-    d_partials = n_single ? A.take((uint64_t)n_single * max_pieces * single_partial_bytes()) : nullptr;
+    for (int z = 0; z < SETS; ++z)
+        d_partials[z] = n_single ? A.take((uint64_t)n_single * max_pieces * single_partial_bytes()) : nullptr;
     d_chunks_full = (Chunk*)(d + o_cf);
     d_chunks_last = (Chunk*)(d + o_cl);
     d_slots = (FlatSlot*)(d + o_slots);
@@ -918,10 +919,11 @@ void BatchProgram::setup(Engine& E, Arena& A, const ColView& src_rows, uint64_t 
     d_ctl = A.take_n<uint64_t>(BP_CTL_RING * ctl_words());
     scratch_off = A.off;
     const uint64_t hist = (uint64_t)nb * chunks_full;
-    part = A.take_n<uint64_t>((Bt < n ? Bt : n) * (uint64_t)L.words);
-    d_hist = A.take_n<uint32_t>(hist + 1);
-    d_offs = A.take_n<uint64_t>(hist + 1);
-    d_tiles = A.take_n<uint64_t>(scan_tiles(hist) + 1);
+    for (int z = 0; z < SETS; ++z) {
+        part[z] = A.take_n<uint64_t>((Bt < n ? Bt : n) * (uint64_t)L.words);
+        d_hist[z] = A.take_n<uint32_t>(hist + 1);
+        d_offs[z] = A.take_n<uint64_t>(hist + 1);
+    }
 }
 
 ColView BatchProgram::batch_src(uint64_t i) const {
@@ -947,22 +949,24 @@ void BatchProgram::enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback,
     r.n_chunks = nch;
     Region* reg = d_regs + (i % BP_CTL_RING);
     uint64_t* ctl = d_ctl + (i % BP_CTL_RING) * ctl_words();
+    const int z = (int)(i % SETS);
     E.pbegin("k_hist", st);
-    launch_hist_batch(r, reg, ctl, (uint32_t)ctl_words(), ch, nch, splitters, d_hist, st);
+    launch_hist_batch(r, reg, ctl, (uint32_t)ctl_words(), ch, nch, splitters, d_hist[z], st);
     E.pend(bn, bn * 8, st);
     E.pbegin("k_scatter", st);
-    launch_scatter(reg, ch, nch, splitters, d_offs, part, L, st, d_hist, d_offs);
+    launch_scatter(reg, ch, nch, splitters, d_offs[z], part[z], L, st, d_hist[z], d_offs[z]);
     E.pend(bn, bn * (uint64_t)L.words * 8, st);
     if (n_single) {
         E.pbegin("k_single_partial", st);
-        launch_flat_single_partial(reg, d_offs, part, L, d_single_list, n_single, max_pieces, d_partials, st);
+        launch_flat_single_partial(reg, d_offs[z], part[z], L, d_single_list, n_single, max_pieces, d_partials[z],
+                                   st);
         E.pend(bn, 0, st);
     }
     E.pbegin("k_leaf", st);
     // the last leaf writes the control word and the group count straight to
     // the pinned readback slot (no copy after the launch)
-    launch_leaf_flat(d_slots, nb, nullptr, reg, splitters, d_offs, part, L, d_first, d_dests + slot, ctl + 2, ctl + 1,
-                     (uint32_t*)ctl, st, d_single_of, d_partials, max_pieces, E.ring_dev_of(readback));
+    launch_leaf_flat(d_slots, nb, nullptr, reg, splitters, d_offs[z], part[z], L, d_first, d_dests + slot, ctl + 2,
+                     ctl + 1, (uint32_t*)ctl, st, d_single_of, d_partials[z], max_pieces, E.ring_dev_of(readback));
     E.pend(bn, bn * (uint64_t)L.words * 8, st);
 }
 

@@ -294,16 +294,19 @@ struct BatchProgram {
     Dest* d_dests = nullptr;
     uint64_t* d_ctl = nullptr;  // ring of per-batch [ticket|error, total, status x nb]
     uint64_t scratch_off = 0;   // arena offset of the per-batch scratch (reusable by a fallback)
-    uint64_t* part = nullptr;
-    uint32_t* d_hist = nullptr;
-    uint64_t* d_offs = nullptr;
-    uint64_t* d_tiles = nullptr;
+    // Two batches are sorted at once (on two streams), batch i with scratch
+    // set i % SETS: a sort's kernels wait on memory with one workgroup per
+    // compute unit, and a second batch fills the gaps.
+    static constexpr int SETS = 2;
+    uint64_t* part[SETS] = {};
+    uint32_t* d_hist[SETS] = {};
+    uint64_t* d_offs[SETS] = {};
     // single-key buckets (known from the splitters): their pieces are reduced
     // in parallel before the leaves combine them
     uint32_t n_single = 0, max_pieces = 0;
     uint32_t* d_single_list = nullptr;  // bucket of each single-key bucket
     uint32_t* d_single_of = nullptr;    // per bucket: its index in the list, or ~0
-    void* d_partials = nullptr;
+    void* d_partials[SETS] = {};
     uint64_t ctl_words() const { return 2 + (uint64_t)nb; }
     void setup(Engine& E, Arena& A, const ColView& src, uint64_t n_rows, uint64_t batch_rows, const Cols& k,
                const SplitterHint& hint, const std::vector<Dest>& dests);
