@@ -636,7 +636,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="spill_100M_zipf0.8", choices=sorted(WORKLOADS) + list(FORMS))
     ap.add_argument("--only", action="store_true",
                     help="the named workload alone (default for the headline: every configuration)")

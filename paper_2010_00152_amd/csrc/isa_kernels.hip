@@ -2280,16 +2280,20 @@ __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict_
 // Gather of a wide-merge window into one staging buffer of state rows.  A
 // small persistent grid walks the window's tasks (run slices of at most
 // GATHER_ROWS rows), reading pinned host memory through its device mapping
-// (or device memory) with contiguous word loads, eight in flight per thread.
-// The grid is kept small on purpose: its host reads hold memory-request
-// slots for the whole link latency, and the window being reduced meanwhile
-// slows down with every such read in flight (its kernels run about three
-// times slower beside a gather than alone).  32 workgroups, four per XCD,
-// still fill the link (measured: 24 read slower, 48 slow the reduction).
-// Raw slices (count-1 rows) are staged in LDS and expanded to state rows on
-// the way out.
+// (or device memory) with contiguous word loads, GATHER_LOADS in flight per
+// thread.
+// The reads in flight are kept few on purpose: a host read holds a
+// memory-request slot for the whole link latency, and the window being
+// reduced meanwhile slows down with every such read (its kernels run about
+// three times slower beside a gather of 48 workgroups with eight loads in
+// flight per thread than alone).  48 workgroups, six per XCD, with four
+// loads in flight per thread still fill the link (measured over repeated
+// calls: 1.5 ms per call faster than 32 workgroups with eight, and than 96
+// with two).  Raw slices (count-1 rows) are staged in LDS and expanded to
+// state rows on the way out.
 constexpr int GATHER_NT = 256;
-constexpr uint32_t GATHER_GRID = 32;
+constexpr uint32_t GATHER_GRID = 48;
+constexpr int GATHER_LOADS = 4;
 __global__ void __launch_bounds__(GATHER_NT) k_gather(const GatherTask* __restrict__ tasks, uint32_t n_tasks,
                                                       Layout R, Layout S, uint64_t* __restrict__ dst) {
     __shared__ uint64_t s_raw[GATHER_ROWS * 4];
@@ -2299,19 +2303,19 @@ __global__ void __launch_bounds__(GATHER_NT) k_gather(const GatherTask* __restri
         uint64_t* __restrict__ out = dst + t.dst_row * sw;
         const uint64_t* __restrict__ in = t.src;
         if (t.raw == 3) {
-            // packed rows: loaded into LDS with eight loads in flight per
+            // packed rows: loaded into LDS with GATHER_LOADS loads in flight per
             // thread, then widened to state rows
             const uint32_t pw = (uint32_t)packed_words(S);
             const uint32_t words = t.n * pw;
-            for (uint32_t i = threadIdx.x; i < words; i += 8 * GATHER_NT) {
-                uint64_t r[8];
+            for (uint32_t i = threadIdx.x; i < words; i += GATHER_LOADS * GATHER_NT) {
+                uint64_t r[GATHER_LOADS];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < GATHER_LOADS; ++q) {
                     const uint32_t x = i + q * GATHER_NT;
                     if (x < words) r[q] = in[x];
                 }
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < GATHER_LOADS; ++q) {
                     const uint32_t x = i + q * GATHER_NT;
                     if (x < words) s_raw[x] = r[q];
                 }
@@ -2345,19 +2349,19 @@ __global__ void __launch_bounds__(GATHER_NT) k_gather(const GatherTask* __restri
         if (!t.raw) {
             const uint32_t words = t.n * sw;
             uint32_t i = threadIdx.x;
-            for (; i + 7 * GATHER_NT < words; i += 8 * GATHER_NT) {
-                uint64_t r[8];
+            for (; i + (GATHER_LOADS - 1) * GATHER_NT < words; i += GATHER_LOADS * GATHER_NT) {
+                uint64_t r[GATHER_LOADS];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) r[q] = in[i + q * GATHER_NT];
+                for (int q = 0; q < GATHER_LOADS; ++q) r[q] = in[i + q * GATHER_NT];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) out[i + q * GATHER_NT] = r[q];
+                for (int q = 0; q < GATHER_LOADS; ++q) out[i + q * GATHER_NT] = r[q];
             }
             for (; i < words; i += GATHER_NT) out[i] = in[i];
             continue;
         }
         // count-1 rows: the key column, the f64 column and the integer
         // column of the slice, loaded into raw rows in LDS with 8-byte loads,
-        // eight in flight per thread.  A 4-byte integer column is read in
+        // GATHER_LOADS in flight per thread.  A 4-byte integer column is read in
         // 8-byte words; a slice that starts at an odd row starts in the upper
         // half of its first word (column starts are 8-byte aligned).
         const uint32_t n = t.n;
@@ -2366,15 +2370,15 @@ __global__ void __launch_bounds__(GATHER_NT) k_gather(const GatherTask* __restri
         const uint64_t* iw = (const uint64_t*)((const char*)t.iv - 4 * odd);
         const uint32_t e0 = n, e1 = e0 + (R.fs >= 0 ? n : 0u);
         const uint32_t e2 = e1 + (R.sum < 0 ? 0u : nar ? (n + odd + 1) / 2 : n);
-        for (uint32_t i = threadIdx.x; i < e2; i += 8 * GATHER_NT) {
-            uint64_t r[8];
+        for (uint32_t i = threadIdx.x; i < e2; i += GATHER_LOADS * GATHER_NT) {
+            uint64_t r[GATHER_LOADS];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < GATHER_LOADS; ++q) {
                 const uint32_t x = i + q * GATHER_NT;
                 if (x < e2) r[q] = x < e0 ? in[x] : x < e1 ? t.fv[x - e0] : iw[x - e1];
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < GATHER_LOADS; ++q) {
                 const uint32_t x = i + q * GATHER_NT;
                 if (x >= e2) continue;
                 if (x < e0) {
