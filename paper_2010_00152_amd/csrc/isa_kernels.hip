@@ -2287,9 +2287,9 @@ __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict_
 // reduced meanwhile slows down with every such read (its kernels run about
 // three times slower beside a gather of 48 workgroups with eight loads in
 // flight per thread than alone).  48 workgroups, six per XCD, with four
-// loads in flight per thread still fill the link (measured over repeated
-// calls: 1.5 ms per call faster than 32 workgroups with eight, and than 96
-// with two).  Raw slices (count-1 rows) are staged in LDS and expanded to
+// loads in flight per thread still fill the link (measured: as fast as 32
+// workgroups with eight, faster than 96 with two, 24 or fewer read too
+// slowly).  Raw slices (count-1 rows) are staged in LDS and expanded to
 // state rows on the way out.
 constexpr int GATHER_NT = 256;
 constexpr uint32_t GATHER_GRID = 48;
