@@ -300,7 +300,7 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     auto win_task_bound = [&](uint64_t w) { return w / GATHER_ROWS + (ns + 1) * (w / (PIECE_CAP / 2) + 2) + 16; };
     auto need = [&](uint64_t w) {
         const uint64_t pieces = w / (PIECE_CAP / 2) + 2;
-        return (sink ? 4 : 3) * w * sw * 8 + 3 * win_task_bound(w) * sizeof(GatherTask) +
+        return (sink ? 4 : 3) * w * sw * 8 +
                std::max(flat_bytes(w, pieces, k, true), std::min(piece_fallback, sort_reduce_bytes(w, 1, k, true)));
     };
     // every window but the last holds at least 3/4 W rows (fences every P rows)
@@ -414,12 +414,15 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     // issued, so that the host plans while earlier windows are read.  A
     // window's gather tasks lay its pieces out one after the other in the
     // staging buffer; they are written to a pinned table (all windows, kept
-    // for a second pass) and uploaded ahead of the gather into one of three
-    // device tables, used in turn like the staging buffers.
+    // for a second pass) that the gather reads through its device mapping.
+    // (An upload of each window's tasks cost the host about 0.2 ms per
+    // window in the runtime, which made the host loop the merge's
+    // bottleneck.)
     const uint64_t max_tasks = task_bound(W);
     const uint64_t win_tasks = win_task_bound(W);
     GatherTask* h_tasks = (GatherTask*)E.table_buf((max_tasks + 1) * sizeof(GatherTask));
-    GatherTask* d_tasks = A.take_n<GatherTask>(3 * win_tasks);
+    GatherTask* h_tasks_dev = nullptr;
+    ck(hipHostGetDevicePointer((void**)&h_tasks_dev, h_tasks, 0), "hipHostGetDevicePointer(task table)");
     uint64_t n_tasks = 0;
     std::vector<uint64_t> task_first(1, 0);
     std::vector<uint64_t> win_rows, win_host_bytes;
@@ -488,26 +491,12 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     uint64_t* d_cur = A.take_n<uint64_t>(2);
     const uint64_t mark = A.off;
     hipStream_t gs = E.side(0);
-    // task uploads run on a stream of their own: a copy queued on the gather
-    // stream would wait for the gather ahead of it and then hold up the next
-    hipStream_t us = E.side(1);
     auto ev_gather = [&](size_t w) { return E.sync_event(5 + (w % 3)); };
-    auto ev_upload = [&](size_t w) { return E.sync_event(9 + (w % 3)); };
     auto ev_reduce = [&](size_t w) { return E.sync_event(12 + (w % 3)); };
     auto issue = [&](size_t w) {
         const uint64_t t0 = task_first[w], nt = task_first[w + 1] - task_first[w];
-        GatherTask* dt = d_tasks + (w % 3) * win_tasks;
-        if (nt) {
-            // the device table's last reader: the gather of window w-3, whose
-            // completion event this window's gather records anew
-            ck(hipStreamWaitEvent(us, ev_gather(w), 0), "hipStreamWaitEvent");
-            ck(hipMemcpyAsync(dt, h_tasks + t0, nt * sizeof(GatherTask), hipMemcpyHostToDevice, us),
-               "hipMemcpyAsync(gather tasks)");
-            ck(hipEventRecord(ev_upload(w), us), "hipEventRecord");
-            ck(hipStreamWaitEvent(gs, ev_upload(w), 0), "hipStreamWaitEvent");
-        }
         E.pbegin("merge_h2d", gs);
-        launch_gather(dt, (uint32_t)nt, Rl, S, stage[w % 3], gs);
+        launch_gather(h_tasks_dev + t0, (uint32_t)nt, Rl, S, stage[w % 3], gs);
         E.pend(win_rows[w], win_host_bytes[w], gs);
         ck(hipEventRecord(ev_gather(w), gs), "hipEventRecord");
     };
@@ -572,7 +561,6 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
             sink->rows += g;
         }
         ck(hipStreamSynchronize(gs), "hipStreamSynchronize(gather)");
-        ck(hipStreamSynchronize(us), "hipStreamSynchronize(upload)");
         A.off = mark;
         n_groups = sink->rows;
         return;
@@ -607,7 +595,6 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     }
     const uint64_t* h_end = (const uint64_t*)download_async(E, d_cur + ((nw + 1) % 2), 8);
     ck(hipStreamSynchronize(gs), "hipStreamSynchronize(gather)");
-    ck(hipStreamSynchronize(us), "hipStreamSynchronize(upload)");
     ck(hipStreamSynchronize(E.stream), "hipStreamSynchronize");
     bool redo = false;
     for (const uint64_t* hc : win_ctl) {
@@ -652,7 +639,6 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
             ck(hipEventRecord(ev_reduce(w), E.stream), "hipEventRecord");
         }
         ck(hipStreamSynchronize(gs), "hipStreamSynchronize(gather)");
-        ck(hipStreamSynchronize(us), "hipStreamSynchronize(upload)");
     }
     A.off = mark;
     n_groups = cursor;
