@@ -75,6 +75,104 @@ __device__ __forceinline__ void empty_agg(Agg& a) {
     a.fs = 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Segmented scan of per-thread aggregates across a workgroup, for groups that
+// span threads.  Thread t contributes y_t; a thread with `start` set begins a
+// segment.  Inside a wave the inclusive scan R_t = start_t ? y_t :
+// R_{t-1} + y_t takes DPP lane moves (row shifts by 1, 2, 4 and 8 lanes, then
+// the broadcasts of lanes 15 and 31 to the rows after them); across waves the
+// waves' last lanes go through LDS.  Each thread gets R_{t-1}, the open
+// segment's aggregate at the end of the thread before it (empty for t = 0),
+// and R_t.  The combination order is fixed, so results repeat exactly.
+// ---------------------------------------------------------------------------
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROW_MASK, 0xf, false);
+    return (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_agg(const Agg& r, uint32_t f, Agg& t, uint32_t& tf) {
+    t.cnt = dpp_u64<CTRL, ROW_MASK>(r.cnt);
+    t.sum = dpp_u64<CTRL, ROW_MASK>(r.sum);
+    t.mn = (int64_t)dpp_u64<CTRL, ROW_MASK>((uint64_t)r.mn);
+    t.mx = (int64_t)dpp_u64<CTRL, ROW_MASK>((uint64_t)r.mx);
+    t.fs = __longlong_as_double((long long)dpp_u64<CTRL, ROW_MASK>((uint64_t)__double_as_longlong(r.fs)));
+    tf = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)f, CTRL, ROW_MASK, 0xf, false);
+}
+
+// One step: lanes with `take` add the moved partial (the lanes before them)
+// to their own unless their segment already started.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void seg_step(Agg& r, uint32_t& f, bool take) {
+    Agg t;
+    uint32_t tf;
+    dpp_agg<CTRL, ROW_MASK>(r, f, t, tf);
+    if (take) {
+        if (!f) {
+            combine(t, r);
+            r.cnt = t.cnt;
+            r.sum = t.sum;
+            r.mn = t.mn;
+            r.mx = t.mx;
+            r.fs = t.fs;
+        }
+        f |= tf;
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void seg_scan_agg(const Agg& y, bool start, Agg& prev, Agg& incl, Agg* s_w,
+                                             uint32_t* s_wf) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, rl = lane & 15;
+    Agg r = y;
+    uint32_t f = start ? 1u : 0u;
+    // DPP controls (gfx9): row_shr:n = 0x110 + n, wave_shr:1 = 0x138,
+    // row_bcast:15 = 0x142 (rows 1 and 3), row_bcast:31 = 0x143 (rows 2 and 3)
+    seg_step<0x111, 0xf>(r, f, rl >= 1);
+    seg_step<0x112, 0xf>(r, f, rl >= 2);
+    seg_step<0x114, 0xf>(r, f, rl >= 4);
+    seg_step<0x118, 0xf>(r, f, rl >= 8);
+    seg_step<0x142, 0xa>(r, f, (lane & 31) >= 16);
+    seg_step<0x143, 0xc>(r, f, lane >= 32);
+    if (lane == 63) {
+        s_w[w] = r;
+        s_wf[w] = f;
+    }
+    // the thread before: one lane down the wave (lane 0 takes the waves before)
+    Agg p;
+    uint32_t pf;
+    dpp_agg<0x138, 0xf>(r, f, p, pf);
+    __syncthreads();
+    // a segment open at the wave's start continues from the waves before
+    Agg c;
+    empty_agg(c);
+    for (int w2 = w - 1; w2 >= 0; --w2) {
+        Agg t = s_w[w2];
+        combine(t, c);
+        c = t;
+        if (s_wf[w2]) break;
+    }
+    if (!f) {
+        Agg t = c;
+        combine(t, r);
+        r = t;
+    }
+    if (lane == 0) {
+        p = c;
+    } else if (!pf) {
+        Agg t = c;
+        combine(t, p);
+        p = t;
+    }
+    prev = p;
+    incl = r;
+    __syncthreads();  // s_w is reused by the next call
+}
+
 __device__ __forceinline__ void store_agg(const OutView& o, uint64_t i, const Agg& a) {
     const uint64_t p = i * o.stride;
     o.key[p] = a.key;
@@ -834,12 +932,9 @@ struct LeafSmem {
         uint64_t stage[LEAF_STAGE_WORDS];
     };
     uint64_t mm[2 * LEAF_NT / 64];
-    uint64_t pre_cnt[LEAF_NT];
-    uint64_t pre_sum[LEAF_NT];
-    int64_t pre_mn[LEAF_NT];
-    int64_t pre_mx[LEAF_NT];
-    double pre_fs[LEAF_NT];
-    uint32_t pre_flags[LEAF_NT];  // bit0: thread has a head, bit1: thread has rows
+    Agg seg_w[LEAF_NT / 64];  // the segmented scan's wave partials
+    uint32_t seg_wf[LEAF_NT / 64];
+    uint32_t fix_runs[1 + 2 * 32];  // the clash fix-up's runs (count, then lo/hi pairs)
     uint32_t scan_tmp[LEAF_NT / 64 + 1];
 };
 
@@ -960,7 +1055,7 @@ __device__ __forceinline__ void leaf_sort_reduce_t(const ColView& V, const uint3
                 if (a != b && (a >> lo_bit) == (b >> lo_bit)) cl |= 1u << j;
             }
         }
-        uint32_t* runs = s.pre_flags;  // [0]: clashes seen, then (lo, hi) per clash
+        uint32_t* runs = s.fix_runs;  // [0]: clashes seen, then (lo, hi) per clash
         if (tid == 0) runs[0] = 0;
         if (__syncthreads_or(cl != 0)) {
             for (int j = 0; j < ipt; ++j) {
@@ -1038,8 +1133,10 @@ __device__ __forceinline__ void leaf_sort_reduce_t(const ColView& V, const uint3
     uint16_t rw[IPT];
     uint32_t heads = 0;  // bit j: position p0+j starts a group
     int nrows = 0;
+    uint64_t key_before = 0;  // the key (less the minimum) of position p0 - 1
     {
         uint64_t prev = p0 > 0 ? s.sort.key[pad16(p0 - 1)] : 0;
+        key_before = prev;
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
             const int p = p0 + j;
@@ -1075,8 +1172,9 @@ __device__ __forceinline__ void leaf_sort_reduce_t(const ColView& V, const uint3
         }
     };
 
-    Agg acc;
+    Agg acc, pre_a;  // the thread's open group; its rows before its first head
     empty_agg(acc);
+    empty_agg(pre_a);
     bool have_head = false;
     uint32_t h = 0;
 #pragma unroll
@@ -1092,11 +1190,7 @@ __device__ __forceinline__ void leaf_sort_reduce_t(const ColView& V, const uint3
             r.key = kk[r0 + j] + mn;
             if (heads & (1u << (r0 + j))) {
                 if (!have_head) {
-                    s.pre_cnt[tid] = acc.cnt;
-                    s.pre_sum[tid] = acc.sum;
-                    s.pre_mn[tid] = acc.mn;
-                    s.pre_mx[tid] = acc.mx;
-                    s.pre_fs[tid] = acc.fs;
+                    pre_a = acc;
                     have_head = true;
                 } else {
                     put(obase + h - 1, acc);
@@ -1108,31 +1202,21 @@ __device__ __forceinline__ void leaf_sort_reduce_t(const ColView& V, const uint3
             }
         }
     }
-    if (!have_head) {
-        s.pre_cnt[tid] = acc.cnt;
-        s.pre_sum[tid] = acc.sum;
-        s.pre_mn[tid] = acc.mn;
-        s.pre_mx[tid] = acc.mx;
-        s.pre_fs[tid] = acc.fs;
+    // Groups that span threads: a segmented scan over the threads' open
+    // groups (a thread with a head starts a segment).  The group open at the
+    // end of the thread before ends with this thread's rows before its first
+    // head: this thread places it, as group obase - 1; the last thread with
+    // rows places the leaf's last group.
+    Agg before, incl;
+    seg_scan_agg<NT>(acc, have_head, before, incl, s.seg_w, s.seg_wf);
+    if (have_head && tid > 0) {
+        combine(before, pre_a);
+        before.key = key_before + mn;
+        put(obase - 1, before);
     }
-    s.pre_flags[tid] = (have_head ? 1u : 0u) | (nrows > 0 ? 2u : 0u);
-    __syncthreads();
-    if (have_head) {
-        // the last group of this thread continues into following threads up
-        // to the next thread that starts a group
-        for (int u = tid + 1; u < NT; ++u) {
-            const uint32_t f = s.pre_flags[u];
-            if (!(f & 2u)) break;
-            Agg b;
-            b.cnt = s.pre_cnt[u];
-            b.sum = s.pre_sum[u];
-            b.mn = s.pre_mn[u];
-            b.mx = s.pre_mx[u];
-            b.fs = s.pre_fs[u];
-            combine(acc, b);
-            if (f & 1u) break;
-        }
-        put(obase + h - 1, acc);
+    if (nrows > 0 && (uint32_t)tid == (n - 1) / (uint32_t)ipt) {
+        incl.key = have_head ? acc.key : key_before + mn;
+        put(total - 1, incl);
     }
     __syncthreads();
     const uint32_t staged = total < stage_rows ? total : stage_rows;
