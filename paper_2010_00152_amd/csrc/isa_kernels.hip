@@ -1802,12 +1802,8 @@ __global__ void k_sorted_align(ColView V, uint64_t n, int shift, uint64_t m, uin
 
 struct SortedSmem {
     uint64_t col[SORTED_CAP];  // one column of the range, for the striped-to-blocked transpose
-    uint64_t pre_cnt[SORTED_NT];
-    uint64_t pre_sum[SORTED_NT];
-    int64_t pre_mn[SORTED_NT];
-    int64_t pre_mx[SORTED_NT];
-    double pre_fs[SORTED_NT];
-    uint32_t pre_flags[SORTED_NT];
+    Agg seg_w[SORTED_NT / 64];  // the segmented scan's wave partials
+    uint32_t seg_wf[SORTED_NT / 64];
     uint32_t tmp[SORTED_NT / 64 + 1];
 };
 
@@ -1869,8 +1865,9 @@ __device__ uint32_t sorted_reduce_range(const ColView& V, int shift, uint64_t s,
     }
     uint32_t total;
     const uint32_t obase = block_exclusive_scan<SORTED_NT>(nh, sm.tmp, total);
-    Agg acc;
+    Agg acc, pre_a;  // the thread's open group; its rows before its first head
     empty_agg(acc);
+    empty_agg(pre_a);
     bool have_head = false;
     uint32_t h = 0;
     uint64_t prev = first_prev;
@@ -1887,11 +1884,7 @@ __device__ uint32_t sorted_reduce_range(const ColView& V, int shift, uint64_t s,
         r.fs = V.fs ? __longlong_as_double((long long)ff[j]) : 0.0;
         if (p == 0 || r.key != prev) {
             if (!have_head) {
-                sm.pre_cnt[tid] = acc.cnt;
-                sm.pre_sum[tid] = acc.sum;
-                sm.pre_mn[tid] = acc.mn;
-                sm.pre_mx[tid] = acc.mx;
-                sm.pre_fs[tid] = acc.fs;
+                pre_a = acc;
                 have_head = true;
             } else {
                 const uint64_t pos = g + obase + h - 1;
@@ -1904,32 +1897,20 @@ __device__ uint32_t sorted_reduce_range(const ColView& V, int shift, uint64_t s,
         }
         prev = r.key;
     }
-    if (!have_head) {
-        sm.pre_cnt[tid] = acc.cnt;
-        sm.pre_sum[tid] = acc.sum;
-        sm.pre_mn[tid] = acc.mn;
-        sm.pre_mx[tid] = acc.mx;
-        sm.pre_fs[tid] = acc.fs;
+    // groups that span threads: the segmented scan of the leaf kernels
+    Agg before, incl;
+    seg_scan_agg<SORTED_NT>(acc, have_head, before, incl, sm.seg_w, sm.seg_wf);
+    if (have_head && tid > 0) {
+        combine(before, pre_a);
+        before.key = first_prev;
+        const uint64_t pos = g + obase - 1;
+        if (pos < cap) store_agg(out, pos, before);
     }
-    sm.pre_flags[tid] = (have_head ? 1u : 0u) | (p1 > p0 ? 2u : 0u);
-    __syncthreads();
-    if (have_head) {
-        for (int u = tid + 1; u < SORTED_NT; ++u) {
-            const uint32_t f = sm.pre_flags[u];
-            if (!(f & 2u)) break;
-            Agg b;
-            b.cnt = sm.pre_cnt[u];
-            b.sum = sm.pre_sum[u];
-            b.mn = sm.pre_mn[u];
-            b.mx = sm.pre_mx[u];
-            b.fs = sm.pre_fs[u];
-            combine(acc, b);
-            if (f & 1u) break;
-        }
-        const uint64_t pos = g + obase + h - 1;
-        if (pos < cap) store_agg(out, pos, acc);
+    if (p1 > p0 && (uint32_t)tid == (n - 1) / ipt) {
+        incl.key = have_head ? acc.key : first_prev;
+        const uint64_t pos = g + total - 1;
+        if (pos < cap) store_agg(out, pos, incl);
     }
-    __syncthreads();
     return total;
 }
 
