@@ -333,3 +333,28 @@ def test_inplace_runs_compacted_or_as_state_rows(ctx):
     sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"], absorb_first=True)
     assert st["runs"] == sim["runs"] > 1 and st["spilled_rows"] == sim["spilled_rows"], (st, sim)
     assert st["spilled_bytes"] == sw * st["spilled_rows"]
+
+
+@pytest.mark.parametrize("aggs", [0, isa.ISA_COUNT, isa.ISA_SUM_F64, isa.ISA_MIN_I64,
+                                  isa.ISA_MAX_I64 | isa.ISA_SUM_I64, isa.ISA_COUNT | isa.ISA_SUM_F64])
+def test_spilling_aggregate_subsets(ctx, aggs):
+    # Aggregate sets without a count column write their runs as state rows
+    # and keep two index buffers (the other batch-granular rule of R8); a
+    # count with an f64 sum alone compacts its runs but keeps two buffers (its
+    # raw row is more than half a state row); a count alone absorbs in place.
+    # Every form: the oracle's output and the simulator's runs and rows.
+    say("case spilling aggs=%d" % aggs)
+    n = 1_200_000
+    k, v, f = datagen.plain_input(61, n, 400_000, 0.4, with_f64=True)
+    vv = v if aggs & (isa.ISA_SUM_I64 | isa.ISA_MIN_I64 | isa.ISA_MAX_I64) else None
+    ff = f if aggs & isa.ISA_SUM_F64 else None
+    got, st, status, g = run_gpu(ctx, k, vv, ff, aggs=aggs, budget=16 << 20)
+    compare(got, k, vv, ff, aggs, "spilling aggs %d" % aggs)
+    in_place = aggs in (isa.ISA_COUNT,)
+    sim = spillsim.simulate(k, st["batch_rows"], st["index_capacity"], absorb_first=in_place)
+    assert st["runs"] == sim["runs"] > 0 and st["spilled_rows"] == sim["spilled_rows"], (aggs, st, sim)
+    row_b = isa.lib().isa_state_row_bytes(aggs)
+    if not aggs & isa.ISA_COUNT:
+        assert st["spilled_bytes"] == row_b * st["spilled_rows"]      # state rows only
+    else:
+        assert st["spilled_bytes"] < row_b * st["spilled_rows"]       # compacted
