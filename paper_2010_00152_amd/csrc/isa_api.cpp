@@ -248,18 +248,6 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     if (hipHostGetDevicePointer(&hdev, (void*)host, 0) != hipSuccess || !hdev)
         throw Fail{ISA_EINVAL, "spill buffer is not device-mapped pinned memory"};
     const char* host_dev = (const char*)hdev;
-    // index keys on the host (one strided D2H copy)
-    std::vector<uint64_t> idx_keys(n_idx);
-    if (n_idx) {
-        const uint64_t mark0 = A.off;
-        uint64_t* d_keys = A.take_n<uint64_t>(n_idx);
-        launch_extract_keys(idx, n_idx, (uint32_t)sw, d_keys, E.stream);
-        void* p = E.pinned_buf(n_idx * 8);
-        ck(hipMemcpyAsync(p, d_keys, n_idx * 8, hipMemcpyDeviceToHost, E.stream), "hipMemcpyAsync(index keys)");
-        E.sync();
-        std::memcpy(idx_keys.data(), p, n_idx * 8);
-        A.off = mark0;
-    }
     // Sources: every run contributes its count-1 sub-run (columns) and its
     // other rows (state rows); the last source is the index (state rows,
     // device).  keys: host view of the keys, strided; rows: device-visible
@@ -285,7 +273,8 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
         if (r.n_multi) src.push_back(Src{mb, sw, r.n_multi, on_dev(mb), false, false});
         total += r.n_single + r.n_packed + r.n_multi;
     }
-    if (n_idx) src.push_back(Src{idx_keys.data(), 1, n_idx, idx, false, false});
+    // the index's keys are read on the host from the pinned table (below)
+    if (n_idx) src.push_back(Src{nullptr, 1, n_idx, idx, false, false});
     total += n_idx;
     const size_t ns = src.size();
     std::vector<uint64_t> pos(ns, 0);
@@ -312,6 +301,20 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     const char* force = std::getenv("ISA_FORCE_INDEX_SPILL");
     if (W < 2 * (ns + 1) || need(W) > avail0 || (n_idx && force && force[0] == '1'))
         throw Fail{ISA_ESPILL, "workspace too small for a single wide merge of all runs"};
+    // One pinned table holds the index's keys for the host's planning (a
+    // kernel writes them there through the table's device mapping: no copy,
+    // no staging) followed by the gather tasks of every window.
+    const uint64_t max_tasks = task_bound(W);
+    const uint64_t win_tasks = win_task_bound(W);
+    const uint64_t keys_bytes = (n_idx * 8 + 255) & ~(uint64_t)255;
+    char* h_table = (char*)E.table_buf(keys_bytes + (max_tasks + 1) * sizeof(GatherTask));
+    char* h_table_dev = nullptr;
+    ck(hipHostGetDevicePointer((void**)&h_table_dev, h_table, 0), "hipHostGetDevicePointer(task table)");
+    if (n_idx) {
+        launch_extract_keys(idx, n_idx, (uint32_t)sw, (uint64_t*)h_table_dev, E.stream);
+        E.sync();
+        src.back().keys = (const uint64_t*)h_table;
+    }
     // Fences: the key of every P-th row of each source, merged in key order.
     // A cut at key x ends source s at lb_s(x) = its first row >= x; with c_s
     // of its fences below x, lb_s(x) lies in [c_s P, (c_s + 1) P], so the
@@ -418,11 +421,8 @@ void wide_merge(Engine& E, Arena& A, const Cols& k, uint32_t aggs, const std::ve
     // (An upload of each window's tasks cost the host about 0.2 ms per
     // window in the runtime, which made the host loop the merge's
     // bottleneck.)
-    const uint64_t max_tasks = task_bound(W);
-    const uint64_t win_tasks = win_task_bound(W);
-    GatherTask* h_tasks = (GatherTask*)E.table_buf((max_tasks + 1) * sizeof(GatherTask));
-    GatherTask* h_tasks_dev = nullptr;
-    ck(hipHostGetDevicePointer((void**)&h_tasks_dev, h_tasks, 0), "hipHostGetDevicePointer(task table)");
+    GatherTask* h_tasks = (GatherTask*)(h_table + keys_bytes);
+    GatherTask* const h_tasks_dev = (GatherTask*)(h_table_dev + keys_bytes);
     uint64_t n_tasks = 0;
     std::vector<uint64_t> task_first(1, 0);
     std::vector<uint64_t> win_rows, win_host_bytes;
