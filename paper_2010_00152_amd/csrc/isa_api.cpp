@@ -1391,6 +1391,10 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
                     ip = brun[slot];
                     n_idx = g;
                     n_res = hy && Kr ? g : 0;
+                    // a run split just before (the batch after a spill) is
+                    // copied out now: waiting for the next absorb would leave
+                    // the host link idle for a batch
+                    flush_copy();
                     continue;
                 }
                 const int tgt = merge_target();
