@@ -594,9 +594,20 @@ __device__ __forceinline__ void hist_chunk(const Region& R, const Chunk& C, cons
     __syncthreads();
     const uint64_t* kp = R.src.key;
     const uint64_t st = R.src.stride;
-    for (uint32_t i = tid; i < C.n; i += PART_NT) {
-        const uint64_t key = kp[(C.start + i) * st];
-        atomicAdd(&s_hist[bucket_of(s_spl, key, R.nb)], 1u);
+    // eight keys in flight per thread
+    constexpr int HL = 8;
+    for (uint32_t i0 = tid; i0 < C.n; i0 += PART_NT * HL) {
+        uint64_t kk[HL];
+#pragma unroll
+        for (int q = 0; q < HL; ++q) {
+            const uint32_t i = i0 + (uint32_t)q * PART_NT;
+            if (i < C.n) kk[q] = kp[(C.start + i) * st];
+        }
+#pragma unroll
+        for (int q = 0; q < HL; ++q) {
+            const uint32_t i = i0 + (uint32_t)q * PART_NT;
+            if (i < C.n) atomicAdd(&s_hist[bucket_of(s_spl, kk[q], R.nb)], 1u);
+        }
     }
     __syncthreads();
     for (uint32_t b = tid; b < R.nb; b += PART_NT)
@@ -1474,6 +1485,29 @@ __global__ void __launch_bounds__(LEAF_NT) k_leaf_flat(const FlatSlot* __restric
 // contiguous stores at the chained prefix of the partitions' group counts.
 // ---------------------------------------------------------------------------
 
+// Copies na words of a and then nb words of b to dst[0, na + nb) in LDS,
+// NT threads with LOADS loads in flight each.  (A loop of one load and one
+// LDS store per trip waits for each load before the next is issued: one
+// memory latency per trip.)
+template <int NT, int LOADS>
+__device__ __forceinline__ void stage_words(uint64_t* dst, const uint64_t* __restrict__ a, uint32_t na,
+                                            const uint64_t* __restrict__ b, uint32_t nb) {
+    const uint32_t n = na + nb;
+    for (uint32_t base = threadIdx.x; base < n; base += NT * LOADS) {
+        uint64_t r[LOADS];
+#pragma unroll
+        for (int q = 0; q < LOADS; ++q) {
+            const uint32_t x = base + (uint32_t)q * NT;
+            if (x < n) r[q] = x < na ? a[x] : b[x - na];
+        }
+#pragma unroll
+        for (int q = 0; q < LOADS; ++q) {
+            const uint32_t x = base + (uint32_t)q * NT;
+            if (x < n) dst[x] = r[q];
+        }
+    }
+}
+
 constexpr int MG_NT = 512;
 constexpr int MG_PER = 2;
 constexpr int MG_D = MG_NT * MG_PER;
@@ -1560,8 +1594,8 @@ __global__ void __launch_bounds__(MG_NT) k_merge(const uint64_t* A, uint64_t na,
         const uint64_t ia0 = splits[2 * part], ja0 = splits[2 * part + 1];
         const uint64_t ia1 = splits[2 * part + 2], ja1 = splits[2 * part + 3];
         const uint32_t la = (uint32_t)(ia1 - ia0), lb = (uint32_t)(ja1 - ja0);
-        for (uint32_t x = tid; x < la * W; x += MG_NT) s_in[x] = A[ia0 * W + x];
-        for (uint32_t x = tid; x < lb * W; x += MG_NT) s_in[la * W + x] = B[ja0 * W + x];
+        // a partition is about MG_D rows: 12 words per thread in one round
+        stage_words<MG_NT, 12>(s_in, A + ia0 * W, la * W, B + ja0 * W, lb * W);
         __syncthreads();
         const uint64_t* a = s_in;
         const uint64_t* b = s_in + la * W;
@@ -2194,15 +2228,37 @@ __global__ void __launch_bounds__(256) k_split_count(const uint64_t* __restrict_
     const uint64_t r0 = (uint64_t)blockIdx.x * SPLIT_T;
     uint32_t c = 0, cp = 0;
     bool wide = false;
-    for (uint32_t i = threadIdx.x; i < SPLIT_T; i += 256) {
-        const uint64_t r = r0 + i;
-        if (r >= n) continue;
-        const uint64_t* q = rows + r * S.words;
-        if (q[S.cnt] == 1) {
-            ++c;
-            if (S.sum >= 0) wide |= !fits_i32(q[S.sum]);
-        } else if (packable(q, S)) {
-            ++cp;
+    // the words a row is classified by, four rows' worth in flight per thread
+    constexpr int G = 4;
+    const bool pk = has_packed(S);
+    for (uint32_t i0 = threadIdx.x; i0 < SPLIT_T; i0 += 256 * G) {
+        uint64_t cv[G], sv[G], lo[G], hi[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint64_t r = r0 + i0 + (uint32_t)g * 256;
+            cv[g] = 0;
+            sv[g] = lo[g] = hi[g] = 0;
+            if (r < n) {
+                const uint64_t* q = rows + r * S.words;
+                cv[g] = q[S.cnt];
+                if (S.sum >= 0) {
+                    sv[g] = q[S.sum];
+                    lo[g] = q[S.mn];
+                    hi[g] = q[S.mx];
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint64_t r = r0 + i0 + (uint32_t)g * 256;
+            if (r >= n) continue;
+            if (cv[g] == 1) {
+                ++c;
+                if (S.sum >= 0) wide |= !fits_i32(sv[g]);
+            } else if (pk && (cv[g] >> 32) == 0 &&
+                       (S.sum < 0 || (fits_i32(sv[g]) && fits_i32(lo[g]) && fits_i32(hi[g])))) {
+                ++cp;
+            }
         }
     }
     uint32_t tot, totp;
@@ -2258,8 +2314,7 @@ __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict_
     uint64_t sop = offs_p[blockIdx.x];  // packed rows before the current tile
     for (uint64_t t0 = blk0; t0 < blk0 + SPLIT_T && t0 < n; t0 += SPLIT_TILE) {
         const uint32_t tn = (uint32_t)(n - t0 < (uint64_t)SPLIT_TILE ? n - t0 : (uint64_t)SPLIT_TILE);
-        const uint64_t* src = rows + t0 * W;
-        for (uint32_t x = tid; x < tn * W; x += 256) s_rows[x] = src[x];
+        stage_words<256, 12>(s_rows, rows + t0 * W, tn * W, nullptr, 0);
         __syncthreads();
         // ranks of the count-1 and of the packed rows, stripe by stripe (row
         // order is stripe-major)
