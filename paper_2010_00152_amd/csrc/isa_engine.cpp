@@ -304,11 +304,6 @@ uint64_t chunk_rows(const Engine& E, uint64_t n, uint64_t min_rows) {
     return std::max<uint64_t>(min_rows, std::min<uint64_t>(PART_CHUNK, crow));
 }
 
-// Splitters for every batch of one input, from a stratified sample of
-// WIDE_SAMPLE keys sorted on the host.  A heavy key (at least one bucket's
-// share of the sample) gets a bucket of its own, [key, key+1); the light keys
-// share the remaining buckets evenly by sample count.  A bucket boundary never
-// falls inside a run of equal keys.
 // Least-significant-digit radix sort of host keys, 8 bits a pass; a pass
 // whose digit is the same in every key is skipped.  (The splitter sample is
 // sorted on the host before the first batch can start: about three times
@@ -334,6 +329,11 @@ static void sort_keys_host(std::vector<uint64_t>& a) {
     }
 }
 
+// Splitters for every batch of one input, from a stratified sample of
+// WIDE_SAMPLE keys sorted on the host.  A heavy key (at least one bucket's
+// share of the sample) gets a bucket of its own, [key, key+1); the light keys
+// share the remaining buckets evenly by sample count.  A bucket boundary never
+// falls inside a run of equal keys.
 void choose_splitters(Engine& E, Arena& A, const ColView& src, uint64_t n, uint32_t nb, uint64_t* dev_out,
                       std::vector<uint64_t>& host_out, std::vector<double>* share, double* light_share) {
     constexpr uint64_t WIDE_SAMPLE = 32768;
@@ -887,7 +887,7 @@ void BatchProgram::setup(Engine& E, Arena& A, const ColView& src_rows, uint64_t 
     splitters = hint.dev;
     // a batch is one region: chunks of PART_CHUNK_MIN rows give every
     // compute unit a workgroup of the partition passes
-    const uint64_t crow = chunk_rows(E, Bt, PART_CHUNK_MIN);
+    crow = chunk_rows(E, Bt, PART_CHUNK_MIN);
     chunks_full = (uint32_t)((Bt + crow - 1) / crow);
     const uint64_t last_n = n - (batches - 1) * Bt;
     chunks_last = (uint32_t)((last_n + crow - 1) / crow);
@@ -979,7 +979,7 @@ void BatchProgram::enqueue(Engine& E, uint64_t i, uint32_t slot, char* readback,
     launch_hist_batch(r, reg, ctl, (uint32_t)ctl_words(), ch, nch, splitters, d_hist[z], st);
     E.pend(bn, bn * 8, st);
     E.pbegin("k_scatter", st);
-    launch_scatter(reg, ch, nch, splitters, d_offs[z], part[z], L, st, d_hist[z], d_offs[z]);
+    launch_scatter(reg, ch, nch, splitters, d_offs[z], part[z], L, st, d_hist[z], d_offs[z], crow);
     E.pend(bn, bn * (uint64_t)L.words * 8, st);
     if (n_single) {
         E.pbegin("k_single_partial", st);

@@ -17,10 +17,11 @@ void launch_hist(const Region* regions, const Chunk* chunks, uint32_t n_chunks, 
                  uint32_t* hist, hipStream_t st);
 // hist_self (optional, one region only): the raw histogram; the scatter then
 // derives the chunk offsets itself (no scan launch) and writes them to
-// offs_out for the launches after it.
+// offs_out for the launches after it.  max_chunk_rows: the largest chunk's
+// rows when known (it picks the tile size), else 0.
 void launch_scatter(const Region* regions, const Chunk* chunks, uint32_t n_chunks, const uint64_t* splitters,
                     const uint64_t* offs, uint64_t* dst, Layout L, hipStream_t st,
-                    const uint32_t* hist_self = nullptr, uint64_t* offs_out = nullptr);
+                    const uint32_t* hist_self = nullptr, uint64_t* offs_out = nullptr, uint64_t max_chunk_rows = 0);
 void launch_bucket_starts(const Region* regions, uint32_t n_regions, const uint64_t* offs, const uint64_t* bs_base,
                           uint64_t* bstart, hipStream_t st);
 void launch_fill(uint64_t* p, uint64_t n, uint64_t value, hipStream_t st);
@@ -283,6 +284,7 @@ bool sort_reduce_flat(Engine& E, Arena& A, const std::vector<Instance>& inst, co
 struct BatchProgram {
     uint64_t n = 0, Bt = 0, batches = 0;
     uint32_t nb = 0, chunks_full = 0, chunks_last = 0;
+    uint64_t crow = 0;  // rows per partition chunk
     Layout L{};
     ColView src{};
     const uint64_t* splitters = nullptr;

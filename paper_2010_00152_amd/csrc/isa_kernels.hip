@@ -2545,12 +2545,19 @@ void launch_hist(const Region* regions, const Chunk* chunks, uint32_t n_chunks, 
 }
 void launch_scatter(const Region* regions, const Chunk* chunks, uint32_t n_chunks, const uint64_t* splitters,
                     const uint64_t* offs, uint64_t* dst, Layout L, hipStream_t st, const uint32_t* hist_self,
-                    uint64_t* offs_out) {
-    // rows of up to 3 words: tiles of 2048 rows staged in LDS; up to 6 words
-    // (state rows): tiles of 1024 rows (48 KB either way, two workgroups per CU)
-    if (L.words <= 3)
+                    uint64_t* offs_out, uint64_t max_chunk_rows) {
+    // Rows of up to 3 words: a chunk of at most 2048 rows is one tile of 2048
+    // rows staged in LDS (48 KB, two workgroups per CU); longer chunks go in
+    // tiles of 1536 rows (36 KB and 129 VGPRs, three workgroups per CU, so
+    // that one workgroup's loads overlap another's ranking and stores: the
+    // 100M-row partition passes run about 7% faster).  Up to 6 words (state
+    // rows): tiles of 1024 rows.
+    if (L.words <= 3 && max_chunk_rows && max_chunk_rows <= (uint64_t)(PART_NT * PART_IPT / 2))
         hipLaunchKernelGGL((k_scatter<3, PART_IPT / 2>), dim3(n_chunks), dim3(PART_NT), 0, st, regions, chunks,
                            splitters, offs, dst, L, hist_self, offs_out);
+    else if (L.words <= 3)
+        hipLaunchKernelGGL((k_scatter<3, 6>), dim3(n_chunks), dim3(PART_NT), 0, st, regions, chunks, splitters,
+                           offs, dst, L, hist_self, offs_out);
     else if (L.words <= 6)
         hipLaunchKernelGGL((k_scatter<6, PART_IPT / 4>), dim3(n_chunks), dim3(PART_NT), 0, st, regions, chunks,
                            splitters, offs, dst, L, hist_self, offs_out);
