@@ -182,6 +182,29 @@ def test_leaf_max_key_ties_with_padding(ctx, n):
     compare(got, k, v, None, isa.ISA_INT_AGGS, "ties %d" % n)
 
 
+# Keys in clusters: every key of a cluster is its centre plus a low part
+# below 2^20, and centres are multiples of 2^51, so within any leaf the keys
+# of one cluster agree on every bit a leaf sorts before its clash fix-up
+# (the top 24 or so bits of the leaf's key range) and differ only below.
+# Cases: a few short clusters in one leaf (ranked in place), clusters longer
+# than the fix-up takes, more clusters than it takes (both re-sorted at full
+# width), and a 200K-row input whose buckets each hold several clusters (the
+# single-level plan's leaves).  Low parts repeat, so groups have many rows.
+@pytest.mark.parametrize("n, clusters, pool", [(3000, 8, 200), (3500, 2, 100_000), (3000, 40, 40),
+                                               (4096, 32, 2000), (200_000, 2000, 60)])
+def test_leaf_key_clashes(ctx, n, clusters, pool):
+    say("case clashes n=%d clusters=%d pool=%d" % (n, clusters, pool))
+    rng = np.random.default_rng(n + clusters)
+    centres = np.sort(rng.choice(1 << 13, clusters, replace=False)).astype(np.uint64) << np.uint64(51)
+    lows = rng.integers(0, 1 << 20, size=(clusters, pool)).astype(np.uint64)
+    c = rng.integers(0, clusters, n)
+    k = centres[c] + lows[c, rng.integers(0, pool, n)]
+    v = rng.integers(-(1 << 40), 1 << 40, n).astype(np.int64)
+    f = rng.standard_normal(n)
+    got, st, status, g = run_gpu(ctx, k, v, f, budget=256 << 20)
+    compare(got, k, v, f, isa.ISA_ALL, "clashes %d/%d" % (n, clusters))
+
+
 def test_flat_plan_falls_back_on_oversized_bucket(ctx):
     # every row the splitter sample reads holds the same key, all other rows
     # are distinct: the sampled splitters isolate that key and leave two huge
