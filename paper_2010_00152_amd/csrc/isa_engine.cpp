@@ -566,17 +566,16 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
         const uint64_t* h_rb = (const uint64_t*)download_async(E, fixed ? d_bstart : d_rb,
                                                                ((fixed ? 0 : spl_words) + bs_total) * sizeof(uint64_t));
         E.sync();
+        // read in place: the staging stays valid until the next sync
         const uint64_t* h_bs = fixed ? h_rb : h_rb + spl_words;
         const uint64_t* h_sp = fixed ? hint->host : h_rb;
-        std::vector<uint64_t> bstart(h_bs, h_bs + bs_total);
-        std::vector<uint64_t> spl(h_sp, h_sp + spl_words);
         A.off = mark;
         std::vector<int> next;
         for (size_t ri = 0; ri < pending.size(); ++ri) {
             const int id = pending[ri];
             const Region& r = regs[ri];
-            const uint64_t* sp = spl.data() + ri * (MAX_BUCKETS - 1);
-            const uint64_t* bs = bstart.data() + bsb[ri];
+            const uint64_t* sp = h_sp + ri * (MAX_BUCKETS - 1);
+            const uint64_t* bs = h_bs + bsb[ri];
             if (bs[r.nb] != r.n) throw Fail{ISA_EDEVICE, "partition lost rows"};
             const int first_kid = (int)pool.size();
             for (uint32_t b = 0; b < r.nb; ++b) {
@@ -606,16 +605,17 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
     }
 
     // Leaves in output order: instances in order, keys ascending within each.
-    std::vector<Leaf> leaves;
-    std::vector<uint32_t> leaf_dest;
-    leaves.reserve(pool.size());
-    leaf_dest.reserve(pool.size());
+    // They are written straight into pinned staging (at most one per node)
+    // and uploaded from there.
+    Leaf* const leaves = (Leaf*)E.pinned_buf(pool.size() * sizeof(Leaf));
+    uint32_t* const leaf_dest = (uint32_t*)E.pinned_buf(pool.size() * sizeof(uint32_t));
+    uint64_t nl = 0;
     std::vector<SinglePiece> pieces;
     std::vector<uint32_t> first_seg(dests.size() + 1, 0);
     std::vector<int> stack;
     uint32_t cur_dest = 0;
     for (size_t i = 0; i < inst.size(); ++i) {
-        while (cur_dest < inst[i].dest) first_seg[++cur_dest] = (uint32_t)leaves.size();
+        while (cur_dest < inst[i].dest) first_seg[++cur_dest] = (uint32_t)nl;
         if (roots[i] < 0) continue;
         stack.assign(1, roots[i]);
         while (!stack.empty()) {
@@ -638,7 +638,7 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
                 lf.single_first = (uint32_t)pieces.size();
                 for (uint64_t s = 0; s < nd.n; s += SINGLE_CHUNK) {
                     SinglePiece p;
-                    p.leaf = (uint32_t)leaves.size();
+                    p.leaf = (uint32_t)nl;
                     p.slot = (uint32_t)pieces.size();
                     p.start = s;
                     p.n = (uint32_t)std::min<uint64_t>(SINGLE_CHUNK, nd.n - s);
@@ -647,22 +647,25 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
                 }
                 lf.single_count = (uint32_t)pieces.size() - lf.single_first;
             }
-            leaves.push_back(lf);
-            leaf_dest.push_back(inst[i].dest);
+            leaves[nl] = lf;
+            leaf_dest[nl] = inst[i].dest;
+            ++nl;
         }
     }
-    while (cur_dest < dests.size()) first_seg[++cur_dest] = (uint32_t)leaves.size();
+    while (cur_dest < dests.size()) first_seg[++cur_dest] = (uint32_t)nl;
 
-    const uint64_t nl = leaves.size();
+    Leaf* d_leaves = A.take_n<Leaf>(nl ? nl : 1);
+    uint32_t* d_ldest = A.take_n<uint32_t>(nl ? nl : 1);
+    if (nl) {
+        ck(hipMemcpyAsync(d_leaves, leaves, nl * sizeof(Leaf), hipMemcpyHostToDevice, E.stream), "hipMemcpyAsync(leaves)");
+        ck(hipMemcpyAsync(d_ldest, leaf_dest, nl * sizeof(uint32_t), hipMemcpyHostToDevice, E.stream),
+           "hipMemcpyAsync(leaf destinations)");
+    }
     UpPack up;
-    const uint64_t o_leaves = up.add(leaves.data(), nl * sizeof(Leaf));
-    const uint64_t o_ldest = up.add(leaf_dest.data(), nl * sizeof(uint32_t));
     const uint64_t o_first = up.add(first_seg.data(), first_seg.size() * sizeof(uint32_t));
     const uint64_t o_dests = up.add(dests.data(), dests.size() * sizeof(Dest));
     const uint64_t o_pieces = up.add(pieces.data(), pieces.size() * sizeof(SinglePiece));
     char* d_up = up.commit(E, A);
-    Leaf* d_leaves = (Leaf*)(d_up + o_leaves);
-    uint32_t* d_ldest = (uint32_t*)(d_up + o_ldest);
     uint32_t* d_first = (uint32_t*)(d_up + o_first);
     Dest* d_dests = (Dest*)(d_up + o_dests);
     SinglePiece* d_pieces = pieces.empty() ? nullptr : (SinglePiece*)(d_up + o_pieces);
@@ -673,7 +676,7 @@ std::vector<uint64_t> sort_reduce(Engine& E, Arena& A, const std::vector<Instanc
     void* d_partials = pieces.empty() ? nullptr : A.take(pieces.size() * single_partial_bytes());
     launch_fill(d_ctl, 1 + dests.size() + nl, 0, E.stream);
     uint64_t sort_rows = 0, single_rows = 0;
-    for (const Leaf& lf : leaves) (lf.kind == 0 ? sort_rows : single_rows) += lf.n;
+    for (uint64_t i = 0; i < nl; ++i) (leaves[i].kind == 0 ? sort_rows : single_rows) += leaves[i].n;
     const uint64_t leaf_bytes = need_part ? (uint64_t)L.words * 8 : src_row_bytes;
     if (!pieces.empty()) {
         E.pbegin("k_single");
