@@ -343,7 +343,8 @@ def bench_serve(args):
 
 # Profile labels of the library's launches -> kernel names in rocprofv3 output
 KERNELS_OF_LABEL = {"k_leaf": ["k_leaf_flat", "k_leaf"], "k_merge": ["k_merge"], "k_scatter": ["k_scatter"],
-                    "k_hist": ["k_hist", "k_hist_batch"], "k_sample": ["k_sample", "k_sample_keys"]}
+                    "k_hist": ["k_hist", "k_hist_batch"], "k_sample": ["k_sample", "k_sample_keys"],
+                    "merge_h2d": ["k_gather"]}
 # input generators: not part of a step, left out of the step's counter bytes
 GENERATORS = ("k_zipf_keys", "k_normal_f64", "k_uniform_i64", "k_uniform_ranks", "k_keys_uniform",
               "k_seg_", "k_zipf_approx")
@@ -604,11 +605,27 @@ def run_workload(args, workload, steps, warmup, detail):
             name, avg_us, per_step = dom
             label = next((lb for lb, ks in KERNELS_OF_LABEL.items() if name in ks), name)
             ev = kernels.get(label)
-            roofline["dominant_kernel"] = {
-                "name": name, "source": "committed rocprofv3 summary (same kernel source)",
-                "rocprof_avg_us": avg_us, "launches_per_step": round(per_step, 1),
-                "event_avg_us": ev["avg_us"] if ev else None,
-                "share_of_step": round(avg_us * per_step / (ms_per_step * 1e3), 3)}
+            dk = {"name": name, "source": "committed rocprofv3 summary (same kernel source)",
+                  "rocprof_avg_us": avg_us, "launches_per_step": round(per_step, 1),
+                  "event_avg_us": ev["avg_us"] if ev else None,
+                  "share_of_step": round(avg_us * per_step / (ms_per_step * 1e3), 3)}
+            # its HBM rate from the committed counters (FETCH_SIZE + WRITE_SIZE
+            # per launch over rocprof's average duration of the same source)
+            t = _profiles("hbm_traffic.json")
+            c = (t or {}).get("workloads", {}).get(workload, {}).get(name)
+            if c:
+                gbs = (c["fetch_bytes_per_launch"] + c["write_bytes_per_launch"]) / (avg_us * 1e-6) / 1e9
+                dk["counter_GBps"] = round(gbs, 1)
+                dk["counter_frac_of_hbm_peak"] = round(gbs / HBM_PEAK_GBS, 4)
+            # a kernel that reads host memory is bound by the link: its host
+            # bytes per launch (from the library's own launch records) over
+            # rocprof's average duration
+            if label in prof and label == "merge_h2d" and prof[label]["launches"]:
+                hb = prof[label]["bytes"] / prof[label]["launches"]
+                dk["host_bytes_per_launch"] = int(hb)
+                dk["link_GBps"] = round(hb / (avg_us * 1e-6) / 1e9, 1)
+                dk["link_frac"] = round(hb / (avg_us * 1e-6) / 1e9 / LINK_PEAK_GBS, 3)
+            roofline["dominant_kernel"] = dk
         if stats["spilled_rows"]:
             hl_ms = sum(prof[k]["total_ms"] for k in ("spill_d2h", "merge_h2d") if k in prof) / max(1, args.profile_steps)
             res["host_link"] = link_summary(stats["spilled_bytes"], hl_ms, ms_per_step)
