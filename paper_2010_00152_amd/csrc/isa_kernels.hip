@@ -2412,13 +2412,16 @@ __global__ void __launch_bounds__(256) k_split_write(const uint64_t* __restrict_
 // memory-request slot for the whole link latency, and the window being
 // reduced meanwhile slows down with every such read (its kernels run about
 // three times slower beside a gather of 48 workgroups with eight loads in
-// flight per thread than alone).  48 workgroups, six per XCD, with four
-// loads in flight per thread still fill the link (measured: as fast as 32
-// workgroups with eight, faster than 96 with two, 24 or fewer read too
-// slowly).  Raw slices (count-1 rows) are staged in LDS and expanded to
-// state rows on the way out.
+// flight per thread than alone).  64 workgroups, eight per XCD, with four
+// loads in flight per thread read the link fastest while the window keeps
+// up (measured on the 100M-row spilling merge: 0.5 ms faster than 48
+// workgroups; 72 to 96 workgroups, or eight loads in flight, slow the
+// window's reduction more than they speed the reads).  Each workgroup
+// alternates between loading a slice and expanding it, so a plain stream of
+// the same reads would run about 10% faster.  Raw slices (count-1 rows) are
+// staged in LDS and expanded to state rows on the way out.
 constexpr int GATHER_NT = 256;
-constexpr uint32_t GATHER_GRID = 48;
+constexpr uint32_t GATHER_GRID = 64;
 constexpr int GATHER_LOADS = 4;
 __global__ void __launch_bounds__(GATHER_NT) k_gather(const GatherTask* __restrict__ tasks, uint32_t n_tasks,
                                                       Layout R, Layout S, uint64_t* __restrict__ dst) {
