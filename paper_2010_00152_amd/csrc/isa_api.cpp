@@ -2016,6 +2016,92 @@ isa_status isa_group_by_segmented(isa_ctx* ctx, const int32_t* a, const int32_t*
         A.peak = 0;
         // segments are independent groupings on b; several run together per wave
         const uint64_t per_row = 16 + (sort_reduce_bytes(1, 0, k, false) - (4u << 20));
+        // the segments of one wave: [i0, i1) while they fit the workspace
+        auto wave_end = [&](uint64_t i0, uint64_t& rows) {
+            uint64_t i1 = i0;
+            rows = 0;
+            while (i1 < n_seg) {
+                const uint64_t r = starts[i1 + 1] - starts[i1];
+                const uint64_t need = (rows + r) * per_row + (i1 - i0 + 1) * 4608 + (5u << 20);
+                if (need > ws.bytes) break;
+                rows += r;
+                ++i1;
+            }
+            if (i1 == i0) throw Fail{ISA_EBUDGET, "one segment does not fit the workspace"};
+            return i1;
+        };
+        auto wave_instances = [&](uint64_t i0, uint64_t i1, const uint64_t* keys) {
+            std::vector<Instance> inst;
+            const uint64_t r0 = starts[i0];
+            for (uint64_t i = i0; i < i1; ++i) {
+                Instance in;
+                in.src.key = keys + (starts[i] - r0);
+                in.src.cnt = nullptr;
+                in.src.sum = in.src.mn = in.src.mx = k.v ? v + starts[i] : nullptr;
+                in.src.fs = nullptr;
+                in.src.stride = 1;
+                in.n = starts[i + 1] - starts[i];
+                in.dest = 0;
+                inst.push_back(in);
+            }
+            return inst;
+        };
+        uint64_t max_seg = 0;
+        for (uint64_t i = 0; i < n_seg; ++i) max_seg = std::max(max_seg, starts[i + 1] - starts[i]);
+        const char* sync_env = std::getenv("ISA_SEGMENTED_SYNC");
+        if (max_seg <= FLAT_MAX && !(sync_env && sync_env[0] == '1')) {
+            // Waves enqueued back to back, no host round trip between them:
+            // a wave's groups start at the output row that the previous
+            // wave's last leaf wrote to a device word (two words alternate),
+            // its normalized keys go to a buffer of its own (indexed from
+            // that row) and are unpacked from there; the flat plans' error
+            // words are read once at the end.  A plan that failed (a bucket
+            // too large for a leaf) sends the call through the waves below,
+            // one at a time.
+            uint64_t* d_cur = A.take_n<uint64_t>(2);
+            launch_fill(d_cur, 2, 0, E.stream);
+            const uint64_t mark = A.off;
+            std::vector<const uint64_t*> ctls;
+            uint64_t w = 0;
+            bool ok = true;
+            for (uint64_t i0 = 0; i0 < n_seg && ok; ++w) {
+                uint64_t rows = 0;
+                const uint64_t i1 = wave_end(i0, rows);
+                A.off = mark;
+                uint64_t* keys = A.take_n<uint64_t>(rows);
+                uint64_t* okeys = A.take_n<uint64_t>(rows);
+                launch_pack_pairs(a + starts[i0], b + starts[i0], rows, keys, E.stream);
+                Dest d;
+                d.out = output_view(*out, aggs, 0);
+                d.out.key = okeys;
+                d.capacity = out->capacity;
+                d.base = d_cur + ((w + 1) % 2);
+                d.key_local = 1;
+                std::vector<uint64_t> g;
+                const uint64_t* hc = nullptr;
+                sort_reduce_flat(E, A, wave_instances(i0, i1, keys), std::vector<Dest>(1, d), k, false, nullptr,
+                                 false, g, d_cur + (w % 2), &hc);
+                if (!hc) {
+                    ok = false;
+                    break;
+                }
+                ctls.push_back(hc);
+                launch_unpack_pairs_at(okeys, rows, d.base, d_cur + (w % 2), out->capacity, out_a, out_b, E.stream);
+                i0 = i1;
+            }
+            const uint64_t* h_end = (const uint64_t*)download_async(E, d_cur + ((w + 1) % 2), 8);
+            E.sync();
+            for (const uint64_t* hc : ctls) {
+                const uint64_t err = hc[0] >> 32;
+                if (err & 1) throw Fail{ISA_EDEVICE, "leaf placement wait timed out"};
+                if (err & 2) ok = false;
+            }
+            if (ok) {
+                const uint64_t total = *h_end;
+                out->n_groups = total;
+                return total > out->capacity ? ISA_ETRUNC : ISA_OK;
+            }
+        }
         uint64_t cursor = 0;
         uint64_t i0 = 0;
         while (i0 < n_seg) {

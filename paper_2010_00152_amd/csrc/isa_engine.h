@@ -79,6 +79,10 @@ void launch_scan(const uint32_t* in, uint64_t n, uint64_t* tile_sums, uint64_t* 
 void launch_pack_pairs(const int32_t* a, const int32_t* b, uint64_t n, uint64_t* keys, hipStream_t st);
 void launch_unpack_hi(const uint64_t* hi, uint64_t n, int32_t* a, hipStream_t st);
 void launch_unpack_pairs(const uint64_t* keys, uint64_t n, int32_t* a, int32_t* b, hipStream_t st);
+// Output rows [*lo, *hi) below cap (lo null: 0) from a launch-local key
+// buffer of at most max_n keys; the bounds are read on the device.
+void launch_unpack_pairs_at(const uint64_t* keys, uint64_t max_n, const uint64_t* lo, const uint64_t* hi,
+                            uint64_t cap, int32_t* a, int32_t* b, hipStream_t st);
 void launch_seg_count(const int32_t* a, uint64_t n, uint32_t chunk, uint32_t* counts, uint32_t* bad,
                       hipStream_t st);
 void launch_seg_write(const int32_t* a, uint64_t n, uint32_t chunk, const uint64_t* offs, uint64_t* starts,

@@ -154,6 +154,10 @@ struct Dest {
     // rows already in the destination, read on the device when the leaves
     // start (the end row an earlier launch wrote); nullptr means none
     const uint64_t* base = nullptr;
+    // nonzero: the key column is a buffer of this launch's own, indexed from
+    // the base row (its row 0 is the destination's row *base); the other
+    // columns are the destination's
+    uint64_t key_local = 0;
 };
 
 // Rows per gather task of the wide merge (a raw slice is staged in LDS).

@@ -956,6 +956,13 @@ struct LeafSmem {
 constexpr int LEAF_ROUND = 8;  // payload loads issued together
 
 __device__ __forceinline__ uint64_t dest_base(const Dest& D) { return D.base ? *D.base : 0ull; }
+// The destination's columns as the leaves index them (by output row); a
+// launch-local key column is shifted back by the base row.
+__device__ __forceinline__ OutView dest_out(const Dest& D) {
+    OutView o = D.out;
+    if (D.key_local && o.key) o.key -= dest_base(D) * o.stride;
+    return o;
+}
 
 // Words of one output row and whether the destination is row-major with the
 // fields in state order right after the key (then a leaf's rows form one
@@ -1185,7 +1192,7 @@ __device__ __forceinline__ void leaf_sort_reduce_t(const ColView& V, const uint3
             stage_agg(s.stage + (uint64_t)g * W, D.out, a);
         } else {
             const uint64_t pos = pre0 + g;
-            if (pos < D.capacity) store_agg(D.out, pos, a);
+            if (pos < D.capacity) store_agg(dest_out(D), pos, a);
         }
     };
 
@@ -1238,7 +1245,7 @@ __device__ __forceinline__ void leaf_sort_reduce_t(const ColView& V, const uint3
     __syncthreads();
     const uint32_t staged = total < stage_rows ? total : stage_rows;
     const uint64_t room = D.capacity > pre0 ? D.capacity - pre0 : 0;
-    flush_stage(s.stage, (uint64_t)staged < room ? staged : (uint32_t)room, W, row_major, D.out, pre0);
+    flush_stage(s.stage, (uint64_t)staged < room ? staged : (uint32_t)room, W, row_major, dest_out(D), pre0);
     if (tid == 0 && li == last) totals[d] = pre0 + total;
 }
 
@@ -1281,7 +1288,7 @@ __device__ __forceinline__ void leaf_single_stream(const ColView& V, const uint6
     if (tid == 0) {
         a.key = V.key[0];
         const uint64_t pos = s_pre;
-        if (pos < D.capacity) store_agg(D.out, pos, a);
+        if (pos < D.capacity) store_agg(dest_out(D), pos, a);
         if (li == last) totals[d] = pos + 1;
     }
 }
@@ -1318,7 +1325,7 @@ __global__ void __launch_bounds__(LEAF_NT, 3) k_leaf(const Leaf* __restrict__ le
         if (tid == 0) {
             a.key = partials[Lf.single_first].key;
             const uint64_t pos = s_pre;
-            if (pos < D.capacity) store_agg(D.out, pos, a);
+            if (pos < D.capacity) store_agg(dest_out(D), pos, a);
             if (li == last) totals[d] = pos + 1;
         }
         return;
@@ -1445,7 +1452,7 @@ __device__ __forceinline__ void leaf_flat_slot(const FlatSlot* __restrict__ slot
         block_reduce_agg<LEAF_NT>(a, red);
         if (tid == 0) {
             a.key = pa[0].key;
-            if (s_pre < D.capacity) store_agg(D.out, s_pre, a);
+            if (s_pre < D.capacity) store_agg(dest_out(D), s_pre, a);
             if (li == last) totals[d] = s_pre + 1;
         }
         return;
@@ -2159,6 +2166,20 @@ __global__ void k_unpack_pairs(const uint64_t* __restrict__ keys, uint64_t n, in
     }
 }
 
+// Rows [*lo, *hi) of the output (below cap) from a launch-local key buffer:
+// key i belongs to output row *lo + i.
+__global__ void k_unpack_pairs_at(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ lo,
+                                  const uint64_t* __restrict__ hi, uint64_t cap, int32_t* __restrict__ a,
+                                  int32_t* __restrict__ b) {
+    const uint64_t r0 = lo ? *lo : 0ull, r1 = *hi < cap ? *hi : cap;
+    const uint64_t n = r1 > r0 ? r1 - r0 : 0ull;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        const uint64_t k = keys[i];
+        a[r0 + i] = (int32_t)((uint32_t)(k >> 32) ^ 0x80000000u);
+        b[r0 + i] = (int32_t)((uint32_t)k ^ 0x80000000u);
+    }
+}
+
 // The int32 value held in the high half of a normalized pair key.
 __global__ void k_unpack_hi(const uint64_t* __restrict__ hi, uint64_t n, int32_t* __restrict__ a) {
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
@@ -2746,6 +2767,11 @@ void launch_unpack_hi(const uint64_t* hi, uint64_t n, int32_t* a, hipStream_t st
 void launch_unpack_pairs(const uint64_t* keys, uint64_t n, int32_t* a, int32_t* b, hipStream_t st) {
     if (!n) return;
     hipLaunchKernelGGL(k_unpack_pairs, grid_rows(n), dim3(256), 0, st, keys, n, a, b);
+}
+void launch_unpack_pairs_at(const uint64_t* keys, uint64_t max_n, const uint64_t* lo, const uint64_t* hi,
+                            uint64_t cap, int32_t* a, int32_t* b, hipStream_t st) {
+    if (!max_n) return;
+    hipLaunchKernelGGL(k_unpack_pairs_at, grid_rows(max_n), dim3(256), 0, st, keys, lo, hi, cap, a, b);
 }
 void launch_seg_count(const int32_t* a, uint64_t n, uint32_t chunk, uint32_t* counts, uint32_t* bad,
                       hipStream_t st) {

@@ -43,6 +43,32 @@ def test_segmented_matches_pair_oracle(ctx, n, n_a, b_per_a, budget_mib):
         assert np.array_equal(got[c], ref[c]), c
 
 
+# The waves of segments run back to back with device-side output rows by
+# default; ISA_SEGMENTED_SYNC=1 takes the loop that waits for every wave, and
+# a segment longer than the single-level plan takes (here 600K rows) sends
+# the call there by itself.  Both must give the oracle's result, also when
+# the output is truncated (the first rows, then ISA_ETRUNC).
+@pytest.mark.parametrize("sync", [False, True])
+@pytest.mark.parametrize("n,n_a,b_per_a,budget_mib,cap", [(2_000_000, 1000, 100_000, 32, None),
+                                                          (1_200_000, 2, 100_000, 128, None),
+                                                          (2_000_000, 1000, 100_000, 32, 700_000)])
+def test_segmented_wave_loops(ctx, monkeypatch, sync, n, n_a, b_per_a, budget_mib, cap):
+    say("case segmented waves sync=%d n=%d n_a=%d cap=%s" % (sync, n, n_a, cap))
+    if sync:
+        monkeypatch.setenv("ISA_SEGMENTED_SYNC", "1")
+    a, b, v = datagen.segmented_input(9, n, n_a, b_per_a)
+    res, status, g = isa.group_by_segmented(ctx, to_dev(a), to_dev(b), to_dev(v), aggs=isa.ISA_INT_AGGS,
+                                            mem_budget=budget_mib << 20, capacity=cap, check=False)
+    got = np_out(res)
+    ref = oracle.group_by_pairs(a, b, v)
+    G = ref["a"].shape[0]
+    assert g == G
+    m = G if cap is None else min(cap, G)
+    assert status == (isa.ISA_ETRUNC if m < G else isa.ISA_OK)
+    for c in ["a", "b", "count", "sum_i64", "min_i64", "max_i64"]:
+        assert np.array_equal(got[c], ref[c][:m]), c
+
+
 def test_segmented_rejects_unsorted_prefix(ctx):
     say("case segmented unsorted")
     a = np.array([1, 2, 1, 3] * 1000, np.int32)
