@@ -69,6 +69,28 @@ def test_segmented_wave_loops(ctx, monkeypatch, sync, n, n_a, b_per_a, budget_mi
         assert np.array_equal(got[c], ref[c][:m]), c
 
 
+def test_segmented_flat_plan_failure_falls_back(ctx):
+    # one 300K-row segment whose rows at the splitter sample's positions all
+    # hold the same B value, all other B values distinct: the sampled
+    # splitters isolate that value and leave two multi-key buckets far above
+    # a leaf, the pipelined wave's flat plan reports it, and the call must
+    # still give the exact result through the wave-at-a-time loop
+    say("case segmented flat fallback")
+    n, S = 300_000, 4096
+    a = np.zeros(n, np.int32)
+    b = (np.arange(n, dtype=np.int64) * 7919 % (1 << 30)).astype(np.int32)
+    pos = ((2 * np.arange(S, dtype=np.int64) + 1) * n) // (2 * S)
+    b[pos] = np.int32(123)
+    v = datagen.uniform_i64(19, n)
+    res, status, g = isa.group_by_segmented(ctx, to_dev(a), to_dev(b), to_dev(v), aggs=isa.ISA_INT_AGGS,
+                                            mem_budget=128 << 20)
+    got = np_out(res)
+    ref = oracle.group_by_pairs(a, b, v)
+    assert g == ref["a"].shape[0]
+    for c in ["a", "b", "count", "sum_i64", "min_i64", "max_i64"]:
+        assert np.array_equal(got[c], ref[c]), c
+
+
 def test_segmented_rejects_unsorted_prefix(ctx):
     say("case segmented unsorted")
     a = np.array([1, 2, 1, 3] * 1000, np.int32)
