@@ -1072,8 +1072,8 @@ isa_status isa_group_by(isa_ctx* ctx, const isa_input* in, uint32_t aggs, isa_wo
             // placed at the end of the other index buffer, and copied to host
             // memory on the copy stream while run generation continues.  The
             // copy's size depends on the split's count, so the copy is enqueued
-            // after the next absorb (flush_copy), which then need not wait for a
-            // host round trip.
+            // later (flush_copy: once the next batch has started the next
+            // index), when the count is in.
             auto spill_index = [&]() {
                 flush_copy();
                 // an index that fails to absorb a batch holds more than one
