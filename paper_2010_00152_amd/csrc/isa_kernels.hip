@@ -2204,23 +2204,36 @@ __global__ void __launch_bounds__(256) k_seg_count(const int32_t* __restrict__ a
     if (b) atomicOr(bad, 1u);
 }
 
+// The chunk is read in rows of 256 consecutive elements, one per thread
+// (coalesced, as in k_seg_count); a row holding segment starts places them
+// in order by wave ballots and the waves' counts, and a row without any is
+// skipped after one block-wide vote.  (A thread walking a contiguous
+// sub-range of its own made every load of a wave touch a different line:
+// 6.7 ms for 200M rows, against 0.4 ms for the count.)
 __global__ void __launch_bounds__(256) k_seg_write(const int32_t* __restrict__ a, uint64_t n, uint32_t chunk,
                                                    const uint64_t* __restrict__ offs, uint64_t* __restrict__ starts) {
-    __shared__ uint32_t s_tmp[256 / 64 + 1];
+    __shared__ uint32_t s_w[256 / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t c0 = (uint64_t)blockIdx.x * chunk;
     const uint64_t c1 = c0 + chunk < n ? c0 + chunk : n;
-    // thread t scans a contiguous sub-range so that starts come out in order
-    const uint64_t per = (chunk + 255) / 256;
-    const uint64_t t0 = c0 + threadIdx.x * per;
-    const uint64_t t1 = t0 + per < c1 ? t0 + per : c1;
-    uint32_t c = 0;
-    for (uint64_t i = t0; i < t1; ++i)
-        if (i == 0 || a[i] != a[i - 1]) ++c;
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<256>(c, s_tmp, tot);
-    uint64_t o = offs[blockIdx.x] + ex;
-    for (uint64_t i = t0; i < t1; ++i)
-        if (i == 0 || a[i] != a[i - 1]) starts[o++] = i;
+    uint64_t o = offs[blockIdx.x];  // starts before this chunk
+    for (uint64_t base = c0; base < c1; base += 256) {
+        const uint64_t i = base + (uint64_t)tid;
+        const bool f = i < c1 && (i == 0 || a[i] != a[i - 1]);
+        if (!__syncthreads_or(f)) continue;
+        const uint64_t bal = __ballot(f);
+        if (lane == 0) s_w[w] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < 256 / 64; ++q) {
+            before += q < w ? s_w[q] : 0u;
+            tot += s_w[q];
+        }
+        if (f) starts[o + before + (uint64_t)__popcll(bal & ((1ull << lane) - 1ull))] = i;
+        o += tot;
+        __syncthreads();  // s_w is rewritten by the next row with starts
+    }
 }
 
 
