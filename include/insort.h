@@ -247,7 +247,9 @@ isa_status isa_count_distinct(isa_ctx* ctx, const int32_t* g, const int32_t* x, 
  * Group on the pair (a, b) of int32 columns for input sorted on a only
  * (Section 1: with input sorted on a prefix of the grouping key, grouping
  * proceeds one segment at a time).  Each a-segment is grouped on b
- * independently; segments are processed together as one batch.  Output is
+ * independently; segments are processed together in waves that fit the
+ * workspace, enqueued on the stream one after another (output rows are
+ * carried between waves on the device).  Output is
  * ordered by (a, b), both signed, in out_a/out_b (device, capacity rows) and
  * the aggregate columns of out (out->keys is unused and may be NULL).
  * Requires a to be non-decreasing (ISA_EINVAL if a segment boundary check
